@@ -1,0 +1,219 @@
+"""Pins of the oracle's element operators against the structure the paper proves.
+
+The oracle builds every matrix by full 3D quadrature through the general
+Jacobian.  These tests rebuild the same matrices from the paper's
+closed-form statements (Lemma 1; the Kronecker forms of the mass, face
+mass, lift and derivative matrices in Sec. 4.2; the affine limit) from 1D
+and triangle pieces computed separately here, and require agreement to
+rounding.  A dropped term, wrong sign or transposed operand in the oracle
+breaks one of them.
+"""
+import numpy as np
+import pytest
+
+from oracle import basis as B
+from oracle import dg
+from oracle import geometry as G
+from paper_1607_03399_amd import inputs
+
+
+def _single_wedge_mesh(X):
+    verts = X.reshape(-1, 3)
+    return dg.Mesh(verts, np.arange(6, dtype=np.int64)[None, :], np.ones(1), np.ones(1), "rigid", "upwind")
+
+
+def _closed_form_factors(X):
+    """Lemma 1 closed forms (bi-unit reference) for one vertically mapped wedge."""
+    x, y = X[:3, 0], X[:3, 1]
+    zb, zt = X[:3, 2], X[3:, 2]
+    xr, xs = (x[1] - x[0]) / 2, (x[2] - x[0]) / 2
+    yr, ys = (y[1] - y[0]) / 2, (y[2] - y[0]) / 2
+    Jtri = xr * ys - xs * yr
+    h = zt - zb
+    return dict(xr=xr, xs=xs, yr=yr, ys=ys, Jtri=Jtri, h=h, zb=zb, zt=zt)
+
+
+def test_lemma1_geometric_factors():
+    Xs = inputs.random_vertical_wedges(6, seed=3)
+    rng = np.random.default_rng(1)
+    rs = rng.uniform(-1, 0, (9, 2))
+    ts = np.array([-1.0, -0.3, 0.4, 1.0])
+    for X in Xs:
+        cf = _closed_form_factors(X)
+        for (r, s) in rs:
+            xi = np.array([[r, s, t] for t in ts])
+            _, Jm = G.map_points("wedge", X[None], xi)
+            Jm = Jm[0]
+            J = np.linalg.det(Jm)
+            Ji = np.linalg.inv(Jm)  # rows: r, s, t ; columns x, y, z
+            # J constant in t; equals J_tri * sum_v L_v h_v / 2
+            L = np.array([-(r + s) / 2, (1 + r) / 2, (1 + s) / 2])
+            np.testing.assert_allclose(J, cf["Jtri"] * (L @ cf["h"]) / 2, rtol=1e-13)
+            # r_z = s_z = 0
+            np.testing.assert_allclose(Ji[:, 0, 2], 0, atol=1e-13)
+            np.testing.assert_allclose(Ji[:, 1, 2], 0, atol=1e-13)
+            # r_x, r_y, s_x, s_y constant, with the closed forms
+            np.testing.assert_allclose(Ji[:, 0, 0], cf["ys"] / cf["Jtri"], rtol=1e-12)
+            np.testing.assert_allclose(Ji[:, 0, 1], -cf["xs"] / cf["Jtri"], rtol=1e-12)
+            np.testing.assert_allclose(Ji[:, 1, 0], -cf["yr"] / cf["Jtri"], rtol=1e-12)
+            np.testing.assert_allclose(Ji[:, 1, 1], cf["xr"] / cf["Jtri"], rtol=1e-12)
+            # t_z J constant = J_tri ; t_x J, t_y J linear in t (general formulas)
+            np.testing.assert_allclose(Ji[:, 2, 2] * J, cf["Jtri"], rtol=1e-12)
+            txJ = Ji[:, 2, 0] * J
+            tyJ = Ji[:, 2, 1] * J
+            for q in (txJ, tyJ):
+                lin = q[0] + (q[-1] - q[0]) * (ts + 1) / 2
+                np.testing.assert_allclose(q, lin, atol=1e-12)
+            zr = ((cf["zb"][1] - cf["zb"][0]) * (1 - ts) + (cf["zt"][1] - cf["zt"][0]) * (1 + ts)) / 4
+            zs = ((cf["zb"][2] - cf["zb"][0]) * (1 - ts) + (cf["zt"][2] - cf["zt"][0]) * (1 + ts)) / 4
+            np.testing.assert_allclose(txJ, cf["yr"] * zs - zr * cf["ys"], atol=1e-12)
+            np.testing.assert_allclose(tyJ, zr * cf["xs"] - cf["xr"] * zs, atol=1e-12)
+
+
+def test_inverse_map_round_trip():
+    Xs = inputs.random_vertical_wedges(4, seed=5)
+    rng = np.random.default_rng(2)
+    xi = np.column_stack([rng.uniform(-1, -0.1, 20), rng.uniform(-1, -0.1, 20), rng.uniform(-1, 1, 20)])
+    xi[:, 1] = np.minimum(xi[:, 1], -xi[:, 0])
+    for X in Xs:
+        x, _ = G.map_points("wedge", X[None], xi)
+        back = G.inverse_map("wedge", np.repeat(X[None], len(xi), 0), x[0])
+        np.testing.assert_allclose(back, xi, atol=1e-13)
+
+
+class _Pieces:
+    """Triangle and 1D reference pieces, built here from the oracle's bases."""
+
+    def __init__(self, N):
+        self.N = N
+        self.W = B.Wedge(N)
+        T = self.W.tri
+        self.T = T
+        rq, sq, wq = B.tri_quadrature(N + 2)
+        self.rq, self.sq, self.wq = rq, sq, wq
+        self.Lq, _, _ = T.eval(rq, sq)
+        self.Mtri_hat = self.Lq.T @ (wq[:, None] * self.Lq)
+        tg, wg = B.gauss_nodes_weights(N + 2)
+        l1 = B.lagrange1d(self.W.tgll, tg)
+        self.M1d = l1.T @ (wg[:, None] * l1)
+        self.Dt = B.lagrange1d_deriv(self.W.tgll, self.W.tgll)
+        _, self.Dr, self.Ds = T.eval(T.r, T.s)
+
+    def Mtri_k(self, X):
+        cf = _closed_form_factors(X)
+        L = np.stack([-(self.rq + self.sq) / 2, (1 + self.rq) / 2, (1 + self.sq) / 2], 1)
+        J = cf["Jtri"] * (L @ cf["h"]) / 2
+        return self.Lq.T @ ((self.wq * J)[:, None] * self.Lq)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+def test_kronecker_mass_lift_and_derivatives(N):
+    P = _Pieces(N)
+    Nq = N + 1
+    for X in inputs.random_vertical_wedges(3, seed=10 + N):
+        mesh = _single_wedge_mesh(X)
+        ops = dg.build_operators(mesh, N)
+        cf = _closed_form_factors(X)
+        Mtk = P.Mtri_k(X)
+        Ltri = np.linalg.solve(Mtk, P.Mtri_hat)
+        # mass: M^k = M^{tri,k} (x) M^1D  (node n = j Np_tri + i -> kron(M1D, Mtri))
+        np.testing.assert_allclose(ops.M[0], np.kron(P.M1d, Mtk), rtol=1e-12, atol=1e-14)
+        # triangular-face lifts: J_f L^{tri,k} (x) (M^1D)^-1 e
+        Minv = ops.Minv[0]
+        for f, j in ((0, 0), (1, N)):
+            Mf = ops.Pown[f].T @ (ops.wJ[f][0][:, None] * ops.Pown[f])
+            e = np.zeros(Nq)
+            e[j] = 1.0
+            Jf = ops.wJ[f][0].sum() / 2.0  # face area / reference area 2
+            expect = np.kron(np.linalg.solve(P.M1d, np.outer(e, e)), Jf * Ltri)
+            np.testing.assert_allclose(Minv @ Mf, expect, atol=1e-11 * np.abs(expect).max())
+        # quadrilateral-face lifts: (M^{tri,k})^-1 Mtilde_edge (x) I  (block diagonal)
+        xg, wg = B.gauss_nodes_weights(N + 2)
+        edges = {2: (0, 1), 3: (1, 2), 4: (2, 0)}
+        vref = np.array([[-1, -1], [1, -1], [-1, 1]], float)
+        for f, (a, b) in edges.items():
+            Mf = ops.Pown[f].T @ (ops.wJ[f][0][:, None] * ops.Pown[f])
+            ell = np.linalg.norm(X[b, :2] - X[a, :2])
+            ha, hb = cf["h"][a], cf["h"][b]
+            pts = vref[a][None, :] * (1 - xg[:, None]) / 2 + vref[b][None, :] * (1 + xg[:, None]) / 2
+            Le, _, _ = P.T.eval(pts[:, 0], pts[:, 1])
+            Jf = ell * (ha * (1 - xg) / 2 + hb * (1 + xg) / 2) / 4
+            Medge = Le.T @ ((wg * Jf)[:, None] * Le)
+            expect = np.kron(np.eye(Nq), np.linalg.solve(Mtk, Medge))
+            np.testing.assert_allclose(Minv @ Mf, expect, atol=1e-11 * np.abs(expect).max())
+        # derivatives (Sec. 4.2): D_x = (r_x Dr + s_x Ds) (x) I + L^{tri,k} (x) diag(t_xJ) Dt
+        tg = P.W.tgll
+        zr = ((cf["zb"][1] - cf["zb"][0]) * (1 - tg) + (cf["zt"][1] - cf["zt"][0]) * (1 + tg)) / 4
+        zs = ((cf["zb"][2] - cf["zb"][0]) * (1 - tg) + (cf["zt"][2] - cf["zt"][0]) * (1 + tg)) / 4
+        Jt = cf["Jtri"]
+        rx, ry, sx, sy = cf["ys"] / Jt, -cf["xs"] / Jt, -cf["yr"] / Jt, cf["xr"] / Jt
+        txJ = cf["yr"] * zs - zr * cf["ys"]
+        tyJ = zr * cf["xs"] - cf["xr"] * zs
+        I1 = np.eye(Nq)
+        Dx = np.kron(I1, rx * P.Dr + sx * P.Ds) + np.kron(np.diag(txJ) @ P.Dt, Ltri)
+        Dy = np.kron(I1, ry * P.Dr + sy * P.Ds) + np.kron(np.diag(tyJ) @ P.Dt, Ltri)
+        Dz = np.kron(Jt * P.Dt, Ltri)
+        for d, Dk in enumerate((Dx, Dy, Dz)):
+            got = Minv @ ops.S[d][0]
+            np.testing.assert_allclose(got, Dk, atol=1e-10 * np.abs(Dk).max())
+
+
+def test_affine_limit_of_triangular_lift():
+    """Flat layers: J constant, so L^{tri,k} = (J^k)^{-1} I (reading of the
+    affine remark after the D_z formula in Sec. 4.2)."""
+    for N in (1, 2, 3):
+        P = _Pieces(N)
+        X = inputs.random_vertical_wedges(1, seed=4)[0]
+        X[:3, 2] = -0.2
+        X[3:, 2] = 0.7
+        cf = _closed_form_factors(X)
+        Ltri = np.linalg.solve(P.Mtri_k(X), P.Mtri_hat)
+        J = cf["Jtri"] * 0.9 / 2
+        np.testing.assert_allclose(Ltri * J, np.eye(P.T.Np), atol=1e-13)
+        # and the oracle's full mass matrix then is J (Mtri_hat (x) M1D)
+        ops = dg.build_operators(_single_wedge_mesh(X), N)
+        np.testing.assert_allclose(ops.M[0], J * np.kron(P.M1d, P.Mtri_hat), rtol=1e-12, atol=1e-15)
+
+
+def test_lift_spy_pattern():
+    """Column blocks of the concatenated lift (bottom, top, 3 quads): quad
+    blocks couple only nodes of the same slice; triangle blocks reach every
+    slice (Fig. ``lift``)."""
+    N = 3
+    X = inputs.random_vertical_wedges(1, seed=8)[0]
+    ops = dg.build_operators(_single_wedge_mesh(X), N)
+    Np_tri = (N + 1) * (N + 2) // 2
+    j = np.arange(ops.M.shape[1]) // Np_tri
+    for f in range(5):
+        Mf = ops.Pown[f].T @ (ops.wJ[f][0][:, None] * ops.Pown[f])
+        L = ops.Minv[0] @ Mf
+        big = np.abs(L) > 1e-12 * np.abs(L).max()
+        if f >= 2:
+            rows, cols = np.nonzero(big)
+            assert np.all(j[rows] == j[cols])
+        else:
+            src = 0 if f == 0 else N
+            rows, cols = np.nonzero(big)
+            assert np.all(j[cols] == src)
+            assert set(j[rows]) == set(range(N + 1))
+
+
+def test_volume_and_face_measures():
+    for X in inputs.random_vertical_wedges(4, seed=12):
+        ops = dg.build_operators(_single_wedge_mesh(X), 2)
+        cf = _closed_form_factors(X)
+        area = abs(cf["Jtri"]) * 2
+        vol = area * cf["h"].mean()
+        assert abs(np.ones(ops.M.shape[1]) @ ops.M[0] @ np.ones(ops.M.shape[1]) - vol) < 1e-13
+        for f, tri in ((0, X[:3]), (1, X[3:])):
+            a = 0.5 * np.linalg.norm(np.cross(tri[1] - tri[0], tri[2] - tri[0]))
+            assert abs(ops.wJ[f][0].sum() - a) < 1e-13
+            nexp = np.cross(tri[1] - tri[0], tri[2] - tri[0])
+            nexp = nexp / np.linalg.norm(nexp) * (-1 if f == 0 else 1)
+            np.testing.assert_allclose(ops.n[f][0], np.tile(nexp, (len(ops.wJ[f][0]), 1)), atol=1e-14)
+        for f, (a, b) in ((2, (0, 1)), (3, (1, 2)), (4, (2, 0))):
+            ell = np.linalg.norm(X[b, :2] - X[a, :2])
+            qa = ell * (cf["h"][a] + cf["h"][b]) / 2
+            assert abs(ops.wJ[f][0].sum() - qa) < 1e-13
+            nexp = np.array([X[b, 1] - X[a, 1], -(X[b, 0] - X[a, 0]), 0.0]) / ell
+            np.testing.assert_allclose(ops.n[f][0], np.tile(nexp, (len(ops.wJ[f][0]), 1)), atol=1e-14)
