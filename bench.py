@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput of the wedge DG solver on one MI355X.
+
+Workload (default): 64 x 64 base squares (8192 triangles) x 32 layers =
+262144 vertically mapped wedges with random smooth interfaces, N = 3
+(40 nodes per wedge), FP32, banded per-layer wave speed and density, rigid
+walls, upwind flux, Ricker point source at the centre, 200 steps of the
+five-stage low-storage Runge-Kutta scheme.  Inputs are synthetic (seeded).
+
+Prints one JSON line: DG node-updates per second per Runge-Kutta stage
+(elements x nodes x 5 x steps / wall time), the HBM-roofline fraction of the
+stage kernel (algorithmic bytes / average kernel time from HIP events on the
+solver stream) and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_bytes(N: int, bits: int, reads_res: bool) -> int:
+    """Algorithmic HBM bytes of one stage for one wedge.
+
+    State U read and U' written, residual written (and read after the first
+    stage): 4 fields x Np values each; per-element geometry record (32
+    values), triangular lift (Np_tri^2 padded to a multiple of 4) and
+    connectivity (8 int32).  Neighbour traces are counted as cache hits.
+    """
+    NT = (N + 1) * (N + 2) // 2
+    NP = NT * (N + 1)
+    ts = bits // 8
+    LS = (NT * NT + 3) // 4 * 4
+    state = 4 * NP * ts
+    return state * (3 + int(reads_res)) + 32 * ts + LS * ts + 8 * 4
+
+
+def cpu_baseline(mesh, N: int, dt: float, seconds: float, sample: int):
+    """The FP64 oracle on the first ``sample`` elements (a block of whole
+    columns) of the same workload: untimed setup, then Runge-Kutta stages
+    (right-hand side + update) until ``seconds`` have elapsed."""
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from oracle import dg, lsrk
+
+    om = dg.Mesh(mesh.verts, mesh.wedges, mesh.c, mesh.rho, "rigid", "upwind")
+    elems = np.arange(min(sample, mesh.K))
+    ops = dg.build_operators(om, N, elems=elems)
+    NP = ops.M.shape[1]
+    rng = np.random.default_rng(0)
+    U = rng.standard_normal((mesh.K, 4, NP))
+    res = np.zeros((len(elems), 4, NP))
+    stages = 0
+    c0 = time.process_time()
+    t0 = time.perf_counter()
+    while True:
+        s = stages % 5
+        res *= lsrk.A[s]
+        res += dt * dg.rhs(ops, U)
+        U[elems] += lsrk.B[s] * res
+        stages += 1
+        if time.perf_counter() - t0 >= seconds and s == 4:
+            break
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    return {
+        "value": len(elems) * NP * stages / wall,
+        "unit": "node-updates/s",
+        "cores": max(1, int(round(cpu / wall))),
+        "kind": "oracle",
+        "sample": f"first {len(elems)} wedges ({len(elems) // mesh.layers} whole columns) of the same mesh, "
+                  f"{stages} stages, {wall:.1f} s wall",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="cfg2", choices=["cfg2", "cfg5"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        if int(os.environ.get("RANK", "0")) == 0:
+            print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                       "not part of this build)", "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from paper_1607_03399_amd import inputs
+    from paper_1607_03399_amd import wdg
+
+    N, bits = 3, 32
+    mesh = inputs.cfg2_mesh() if args.config == "cfg2" else inputs.cfg5_mesh()
+    K = mesh.K
+    s = wdg.Solver(N, bits, device=0)
+    s.set_mesh(mesh.verts, mesh.wedges)
+    s.set_material(mesh.c, mesh.rho)
+    s.set_boundary("rigid")
+    s.set_flux("upwind")
+    s.add_ricker_source([0.5, 0.5, 0.5], 10.0, 0.1, 1.0)
+    s.set_fields(np.zeros((K, 4, s.Np)))
+    s.bind_torch()
+    dt = s.stable_dt(0.5)
+
+    s.step(args.warmup, dt)
+    s.synchronize()
+    torch.cuda.synchronize()
+    s.kernel_timing(True)
+    t0 = time.perf_counter()
+    s.step(args.steps, dt)
+    s.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, nlaunch = s.read_kernel_timing()
+    s.kernel_timing(False)
+    U = s.get_fields()
+    if not np.all(np.isfinite(U)):
+        raise RuntimeError("non-finite fields")
+
+    launches_expected = 5 * args.steps
+    assert nlaunch == launches_expected, (nlaunch, launches_expected)
+    bytes_total = K * args.steps * (stage_bytes(N, bits, False) + 4 * stage_bytes(N, bits, True))
+    avg_launch_s = kms / 1e3 / nlaunch
+    achieved = bytes_total / nlaunch / avg_launch_s / 1e9
+    value = K * s.Np * 5 * args.steps / wall
+
+    out = {
+        "metric": "DG node-updates/s per RK stage (wedge N=3, FP32)",
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.config}: layered vertically mapped wedges, {K} elements "
+                        f"({'64x64x32' if args.config == 'cfg2' else '128x128x16'}), N=3 (40 nodes/wedge), FP32, "
+                        "banded c and rho, rigid walls, upwind flux, Ricker source f0=10, LSRK(5,4), CFL 0.5",
+            "elements": K,
+            "order": N,
+            "nodes_per_element": s.Np,
+            "dt": dt,
+            "stage_kernel_avg_us": avg_launch_s * 1e6,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mesh, N, dt, args.cpu_seconds, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

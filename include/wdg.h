@@ -1,0 +1,172 @@
+/*
+ * wdg.h - C ABI of libwdg: reduced-storage nodal DG for first-order acoustics
+ * on meshes of vertically mapped wedges, on one AMD MI355X (gfx950).
+ *
+ * Method: Chan, Wang, Hewett, Warburton, "Reduced storage nodal discontinuous
+ * Galerkin methods on semi-structured prismatic meshes" (arXiv:1607.03399).
+ *   PDE and fluxes ................ Sec. 2, eq. (form), boundary reflection
+ *   nodal wedge basis ............. Sec. 3.1 (triangle Warp & Blend x GLL)
+ *   vertically mapped wedges ...... Sec. 3.2, Definition and Lemma 1
+ *   Kronecker mass/lift/derivative  Sec. 4.2, triangular lift L^{tri,k}
+ *   storage ....................... Sec. 4.3
+ *   layered meshes ................ Sec. 5
+ *
+ * Conventions
+ *   - All host pointers are caller-owned, read or written only during the
+ *     call and never retained.  Device pointers passed to
+ *     wdg_bind_device_state must stay valid while the context uses them.
+ *   - Every function returns WDG_OK (0) or a negative WDG_ERR_* code; the
+ *     context keeps a message readable with wdg_last_error.  No exception
+ *     crosses the ABI and nothing aborts.
+ *   - A context is not thread-safe.  Calls follow the state machine
+ *     create -> set_mesh -> set_material -> set_fields -> step*; a call made
+ *     too early returns WDG_ERR_STATE.
+ *   - Elements are numbered as given; wedge nodes are element-major and
+ *     within an element n = j * Np_tri + i (j: GLL level from the bottom,
+ *     i: triangle node), Np_tri = (N+1)(N+2)/2, Np = Np_tri (N+1).
+ *   - Reference domains are bi-unit (triangle r,s >= -1, r+s <= 0;
+ *     t in [-1,1]).
+ */
+#ifndef WDG_H
+#define WDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wdg_ctx wdg_ctx;
+
+enum {
+  WDG_OK = 0,
+  WDG_ERR_ARG = -1,           /* bad argument (null pointer, size, range) */
+  WDG_ERR_STATE = -2,         /* call out of order for the context state */
+  WDG_ERR_NOT_VERTICAL = -3,  /* a wedge violates the vertical-mapping definition (Sec. 3.2) */
+  WDG_ERR_JACOBIAN = -4,      /* non-positive Jacobian (zero-volume or inverted element) */
+  WDG_ERR_ORIENTATION = -5,   /* bottom triangle not counter-clockwise seen from above */
+  WDG_ERR_NONCONFORMING = -6, /* a face is shared by more than two elements */
+  WDG_ERR_OUTSIDE = -7,       /* source or receiver point not inside any element */
+  WDG_ERR_HIP = -8,           /* HIP runtime error (includes: no device) */
+  WDG_ERR_OOM = -9,           /* device allocation failed */
+  WDG_ERR_UNSTABLE = -10      /* non-finite values detected */
+};
+
+enum { WDG_BC_DIRICHLET_P0 = 0, WDG_BC_RIGID = 1 };
+enum { WDG_FLUX_UPWIND = 0, WDG_FLUX_CENTRAL = 1 };
+
+/* Create a context for polynomial order 1 <= order_N <= 5 computing in
+ * precision_bits = 32 (FP32 fields and operators; FP64 setup) or 64.
+ * device >= 0 selects a HIP device; device = -1 creates a host-only context
+ * that validates meshes and returns node coordinates but cannot step.
+ * Nothing touches the GPU before wdg_set_mesh. */
+int wdg_create(int order_N, int precision_bits, int device, wdg_ctx** out);
+int wdg_destroy(wdg_ctx* ctx);
+/* Message of the last failing call (never NULL; owned by the context). */
+const char* wdg_last_error(const wdg_ctx* ctx);
+
+/* Mesh upload (Sec. 3.2, Sec. 5).  vxyz: nv x 3 vertex coordinates.
+ * wedge_v: nw x 6 vertex ids; v1,v2,v3 form the bottom triangle,
+ * counter-clockwise seen from +z, and v4,v5,v6 lie directly above v1,v2,v3
+ * (vertex pairs (1,4),(2,5),(3,6) share x and y to 1e-12 relative to the
+ * element size, else WDG_ERR_NOT_VERTICAL).  Every vertical edge must have
+ * positive length (WDG_ERR_JACOBIAN).  tet_v: nt x 4 (tetrahedra; nt must be
+ * 0 in this version, else WDG_ERR_ARG).  Faces are matched through their
+ * vertex ids; unmatched faces are domain boundary.  On success the geometric
+ * factors and triangular lifts are built on the device in FP64 (host-only
+ * contexts build host data only).  Material defaults to c = rho = 1,
+ * boundary to rigid, flux to upwind, fields to zero. */
+int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const int64_t* wedge_v,
+                 int64_t nt, const int64_t* tet_v);
+
+/* Per-element wave speed c > 0 and density rho > 0 (Sec. 2; kappa = rho c^2),
+ * arrays of length nw + nt. */
+int wdg_set_material(wdg_ctx* ctx, const double* c, const double* rho);
+/* Boundary treatment: WDG_BC_DIRICHLET_P0 (p+ = -p-, u+ = u-; Sec. 2) or
+ * WDG_BC_RIGID (p+ = p-, u+ = u- - 2 (n.u-) n). */
+int wdg_set_boundary(wdg_ctx* ctx, int bc);
+/* Numerical flux: WDG_FLUX_UPWIND (tau_p = 1/{rho c}, tau_u = {rho c}; Sec. 2)
+ * or WDG_FLUX_CENTRAL (tau = 0; Sec. 4.1). */
+int wdg_set_flux(wdg_ctx* ctx, int flux);
+
+/* Total number of nodes (sum over elements of Np). */
+int wdg_num_nodes(const wdg_ctx* ctx, int64_t* n);
+/* Physical node coordinates, num_nodes x 3, in the node order above. */
+int wdg_get_node_coords(const wdg_ctx* ctx, double* xyz);
+
+/* Nodal values of p, u_x, u_y, u_z (each num_nodes), e.g. an initial
+ * condition by interpolation.  Resets the receiver history. */
+int wdg_set_fields(wdg_ctx* ctx, const double* p, const double* ux, const double* uy, const double* uz);
+int wdg_get_fields(const wdg_ctx* ctx, double* p, double* ux, double* uy, double* uz);
+
+/* Use caller-owned device memory for the state and a caller-owned HIP stream
+ * for every launch.  d_U: 2 * num_nodes * 4 values of the context precision
+ * (two ping-pong copies of the node-interleaved state), d_res: num_nodes * 4
+ * values; both 256-byte aligned.  Current fields are copied into d_U.  Pass
+ * NULL buffers to keep context-owned memory and only set the stream. */
+int wdg_bind_device_state(wdg_ctx* ctx, void* d_U, void* d_res, void* hip_stream);
+
+/* Point source s(t) delta(x - xs) in the pressure equation with the Ricker
+ * wavelet s(t) = amp (1 - 2 pi^2 f0^2 (t-t0)^2) exp(-pi^2 f0^2 (t-t0)^2).
+ * The lowest-numbered element containing xs (1e-12 tolerance in reference
+ * coordinates) receives kappa s(t) M^-1 l(xs).  At most 8 sources. */
+int wdg_add_ricker_source(wdg_ctx* ctx, const double xyz[3], double f0, double t0, double amp, int* id);
+/* Pressure receivers at n points (n x 3), sampled after every completed step;
+ * replaces earlier receivers and clears their history. */
+int wdg_set_receivers(wdg_ctx* ctx, int64_t n, const double* xyz);
+/* Copy the history (steps x n, row = step) into out; *steps receives the
+ * number of recorded steps.  out may be NULL to query *steps only. */
+int wdg_read_receivers(const wdg_ctx* ctx, double* out, int64_t* steps);
+
+/* Stable time step for a CFL number (reading of Sec. 6: trace inequality):
+ * dt = cfl / max_k [ c_k (N+1)(N+3)/3 max_f max J_f / min J ]. */
+int wdg_stable_dt(const wdg_ctx* ctx, double cfl, double* dt);
+/* Advance nsteps steps of the five-stage fourth-order 2N-storage
+ * Runge-Kutta scheme with step dt.  Asynchronous on the bound stream except
+ * when receivers are set (their history lives on the device and is read by
+ * wdg_read_receivers). */
+int wdg_step(wdg_ctx* ctx, int64_t nsteps, double dt);
+int wdg_get_time(const wdg_ctx* ctx, double* t);
+int wdg_set_time(wdg_ctx* ctx, double t);
+/* Wait for all work of the context. */
+int wdg_synchronize(wdg_ctx* ctx);
+
+/* Test hook: the semi-discrete right-hand side dU/dt at time t of the state
+ * in4 (4 * num_nodes: p block, u_x block, u_y block, u_z block), sources
+ * included, written to out4 (same layout).  The context state is unchanged. */
+int wdg_eval_rhs(wdg_ctx* ctx, double t, const double* in4, double* out4);
+/* E = 1/2 sum_k (p^T M^k p / kappa + rho u^T M^k u) (integrand of eq. estab),
+ * M^k = M^{tri,k} (x) M^1D (Sec. 4.2), evaluated on the device. */
+int wdg_energy(wdg_ctx* ctx, double* E);
+
+/* Per-launch timing of the stage kernel with HIP events on the context stream:
+ * enable = 1 starts collecting (and clears), 0 stops.  read returns the summed
+ * kernel time in milliseconds and the number of timed launches since the last
+ * read or enable, waiting for the stream first. */
+int wdg_kernel_timing(wdg_ctx* ctx, int enable);
+int wdg_read_kernel_timing(wdg_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Test hook: per-element data built on the device by the FP64 setup kernel,
+ * converted to double.  geo: nw x 32 values, slots
+ *   0 r_x, 1 r_y, 2 s_x, 3 s_y, 4 t_z J, 5 t_x J (t=-1), 6 t_x J (t=+1),
+ *   7 t_y J (t=-1), 8 t_y J (t=+1), 9 kappa, 10 1/rho, 11 rho c,
+ *   12..15 bottom face (J_f, n_x, n_y, n_z), 16..19 top face,
+ *   20+4e..23+4e quad face on edge e (J_f at its first and second vertex, n_x, n_y)
+ * (Lemma 1; face Jacobians and normals of Sec. 4.2).  lift: nw x Np_tri x
+ * Np_tri, the triangular lift L^{tri,k} = (M^{tri,k})^-1 M^tri (Sec. 4.2),
+ * row-major.  Either pointer may be NULL. */
+int wdg_get_element_data(const wdg_ctx* ctx, double* geo, double* lift);
+
+/* Host-side reference operators of order N (no context, no device), for
+ * inspection.  name: "r","s" (triangle nodes), "t" (GLL nodes), "Dr","Ds"
+ * (Np_tri x Np_tri), "Dt","M1" (Nq x Nq), "Mtri", "Mv0","Mv1","Mv2"
+ * (Np_tri x Np_tri, int l_a l_b lambda_v), "g0","gN" (Nq), "Ea0".."Ea2",
+ * "Eb0".."Eb2" (Np_tri x Nq), "edge0".."edge2" (N+1 node ids).  Writes at
+ * most cap values; *count receives the full size. */
+int wdg_reference_operator(int order_N, const char* name, double* out, int64_t cap, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WDG_H */

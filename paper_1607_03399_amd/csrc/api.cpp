@@ -1,0 +1,934 @@
+// Host runtime and C ABI of libwdg.
+//
+// Mesh validation (Definition of vertically mapped wedges, Sec. 3.2),
+// face matching, node coordinates, point location, sources/receivers and the
+// Runge-Kutta driver loop.  All arithmetic of the right-hand side runs in the
+// HIP kernels (kernels.hip); the host only prepares data and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "refops.hpp"
+#include "wdg.h"
+
+using wdg::RefOps;
+
+namespace {
+
+// five-stage fourth-order 2N-storage Runge-Kutta (Carpenter & Kennedy 1994)
+const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+const double kRkC[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
+                        2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
+
+struct Source {
+  double xyz[3];
+  double f0, t0, amp;
+  int64_t elem;
+  std::vector<double> vec;  // kappa (M^k)^-1 l(xs), NP values
+  double value(double t) const {
+    const double a = M_PI * M_PI * f0 * f0 * (t - t0) * (t - t0);
+    return amp * (1.0 - 2.0 * a) * std::exp(-a);
+  }
+};
+
+enum State { kCreated = 0, kMesh = 1, kMaterial = 2, kFields = 3 };
+
+}  // namespace
+
+struct wdg_ctx {
+  int N = 0, bits = 64, device = -1;
+  bool host_only = true;
+  std::unique_ptr<RefOps> ref;
+  mutable std::string err;
+  int state = kCreated;
+  int64_t K = 0;
+  std::vector<double> X;      // K x 6 x 3 vertex coordinates
+  std::vector<int32_t> conn;  // K x kConnStride
+  std::vector<double> c, rho;
+  int bc = WDG_BC_RIGID, flux = WDG_FLUX_UPWIND;
+  double time = 0.0;
+
+  hipStream_t stream = nullptr;
+  void* dU[2] = {nullptr, nullptr};
+  void* dRes = nullptr;
+  bool own_state = true;
+  int cur = 0;
+  void* dGeo = nullptr;
+  void* dL = nullptr;
+  void* dOps = nullptr;
+  void* dSrcVec = nullptr;
+  double* dAux = nullptr;
+  double* dMv = nullptr;
+  double* dM1 = nullptr;
+  double* dPartial = nullptr;
+  int32_t* dConn = nullptr;
+  std::vector<Source> src;
+  int64_t nrec = 0;
+  int* dRecElem = nullptr;
+  double* dRecRows = nullptr;
+  double* dRecBuf = nullptr;
+  int64_t rec_cap = 0, rec_steps = 0;
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t events_used = 0;
+
+  size_t tsize() const { return bits == 32 ? 4 : 8; }
+  int NT() const { return ref->NT; }
+  int NP() const { return ref->NP; }
+};
+
+namespace {
+
+int fail(const wdg_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                             \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) {                                                                      \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? WDG_ERR_OOM : WDG_ERR_HIP,                    \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                            \
+    }                                                                                            \
+  } while (0)
+
+template <typename P>
+void dfree(P*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+void release_device(wdg_ctx* ctx) {
+  if (ctx->host_only) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  if (ctx->own_state) {
+    dfree(ctx->dU[0]);
+    dfree(ctx->dU[1]);
+    dfree(ctx->dRes);
+  }
+  ctx->dU[0] = ctx->dU[1] = nullptr;
+  ctx->dRes = nullptr;
+  ctx->own_state = true;
+  dfree(ctx->dGeo);
+  dfree(ctx->dL);
+  dfree(ctx->dOps);
+  dfree(ctx->dSrcVec);
+  dfree(ctx->dAux);
+  dfree(ctx->dMv);
+  dfree(ctx->dM1);
+  dfree(ctx->dPartial);
+  dfree(ctx->dConn);
+  dfree(ctx->dRecElem);
+  dfree(ctx->dRecRows);
+  dfree(ctx->dRecBuf);
+  ctx->rec_cap = 0;
+  for (auto& ev : ctx->events) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  ctx->events.clear();
+  ctx->events_used = 0;
+}
+
+// reference coordinates of physical point x in wedge k (closed form for a
+// vertically mapped wedge: affine in (x, y), then linear in t along the vertical)
+void wedge_ref_coords(const double* Xk, const double* x, double& r, double& s, double& t) {
+  const double xr = 0.5 * (Xk[3] - Xk[0]), xs = 0.5 * (Xk[6] - Xk[0]);
+  const double yr = 0.5 * (Xk[4] - Xk[1]), ys = 0.5 * (Xk[7] - Xk[1]);
+  const double J = xr * ys - xs * yr;
+  const double dx = x[0] - Xk[0], dy = x[1] - Xk[1];
+  r = -1.0 + (ys * dx - xs * dy) / J;
+  s = -1.0 + (-yr * dx + xr * dy) / J;
+  const double lam[3] = {-(r + s) / 2.0, (1.0 + r) / 2.0, (1.0 + s) / 2.0};
+  double zb = 0, zt = 0;
+  for (int v = 0; v < 3; ++v) {
+    zb += lam[v] * Xk[3 * v + 2];
+    zt += lam[v] * Xk[3 * (v + 3) + 2];
+  }
+  t = 2.0 * (x[2] - zb) / (zt - zb) - 1.0;
+}
+
+int64_t locate(const wdg_ctx* ctx, const double* x, double& r, double& s, double& t) {
+  const double tol = 1e-12;
+  for (int64_t k = 0; k < ctx->K; ++k) {
+    double rr, ss, tt;
+    wedge_ref_coords(&ctx->X[k * 18], x, rr, ss, tt);
+    if (rr >= -1 - tol && ss >= -1 - tol && rr + ss <= tol && std::fabs(tt) <= 1 + tol) {
+      r = rr;
+      s = ss;
+      t = tt;
+      return k;
+    }
+  }
+  return -1;
+}
+
+// wedge basis l_{ij}(r,s,t) = l^tri_i(r,s) l^1D_j(t)
+void wedge_basis(const RefOps& R, double r, double s, double t, std::vector<double>& out) {
+  std::vector<double> lt(R.NT), l1(R.Nq);
+  R.tri_basis(r, s, lt.data());
+  R.line_basis(t, l1.data());
+  out.resize(R.NP);
+  for (int j = 0; j < R.Nq; ++j)
+    for (int i = 0; i < R.NT; ++i) out[j * R.NT + i] = lt[i] * l1[j];
+}
+
+// kappa (M^k)^-1 l with M^k = M^{tri,k} (x) M^1D (Sec. 4.2)
+std::vector<double> mass_inverse_times(const wdg_ctx* ctx, int64_t k, double kappa, double r, double s, double t) {
+  const RefOps& R = *ctx->ref;
+  const double* Xk = &ctx->X[k * 18];
+  const double xr = 0.5 * (Xk[3] - Xk[0]), xs = 0.5 * (Xk[6] - Xk[0]);
+  const double yr = 0.5 * (Xk[4] - Xk[1]), ys = 0.5 * (Xk[7] - Xk[1]);
+  const double Jt = xr * ys - xs * yr;
+  std::vector<double> Mt(R.NT * R.NT, 0.0);
+  for (int v = 0; v < 3; ++v) {
+    const double cw = 0.5 * Jt * (Xk[3 * (v + 3) + 2] - Xk[3 * v + 2]);
+    for (int i = 0; i < R.NT * R.NT; ++i) Mt[i] += cw * R.Mv[v][i];
+  }
+  std::vector<double> lt(R.NT), l1(R.Nq);
+  R.tri_basis(r, s, lt.data());
+  R.line_basis(t, l1.data());
+  wdg::solve_dense(R.NT, 1, Mt, lt);
+  wdg::solve_dense(R.Nq, 1, R.M1, l1);
+  std::vector<double> out(R.NP);
+  for (int j = 0; j < R.Nq; ++j)
+    for (int i = 0; i < R.NT; ++i) out[j * R.NT + i] = kappa * lt[i] * l1[j];
+  return out;
+}
+
+template <typename T>
+void to_interleaved(const wdg_ctx* ctx, const double* p, const double* ux, const double* uy, const double* uz,
+                    std::vector<unsigned char>& buf) {
+  const int64_t n = ctx->K * ctx->NP();
+  buf.resize(size_t(n) * 4 * sizeof(T));
+  T* o = reinterpret_cast<T*>(buf.data());
+  for (int64_t m = 0; m < n; ++m) {
+    o[4 * m] = T(p[m]);
+    o[4 * m + 1] = T(ux[m]);
+    o[4 * m + 2] = T(uy[m]);
+    o[4 * m + 3] = T(uz[m]);
+  }
+}
+
+template <typename T>
+void from_interleaved(const wdg_ctx* ctx, const std::vector<unsigned char>& buf, double* p, double* ux, double* uy,
+                      double* uz) {
+  const int64_t n = ctx->K * ctx->NP();
+  const T* o = reinterpret_cast<const T*>(buf.data());
+  for (int64_t m = 0; m < n; ++m) {
+    if (p) p[m] = double(o[4 * m]);
+    if (ux) ux[m] = double(o[4 * m + 1]);
+    if (uy) uy[m] = double(o[4 * m + 2]);
+    if (uz) uz[m] = double(o[4 * m + 3]);
+  }
+}
+
+int upload_state(wdg_ctx* ctx, void* dst, const double* p, const double* ux, const double* uy, const double* uz) {
+  std::vector<unsigned char> buf;
+  if (ctx->bits == 32) to_interleaved<float>(ctx, p, ux, uy, uz, buf);
+  else to_interleaved<double>(ctx, p, ux, uy, uz, buf);
+  HIPCHK(hipMemcpyAsync(dst, buf.data(), buf.size(), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return WDG_OK;
+}
+
+int download_state(const wdg_ctx* ctx, const void* src, double* p, double* ux, double* uy, double* uz) {
+  std::vector<unsigned char> buf(size_t(ctx->K * ctx->NP()) * 4 * ctx->tsize());
+  HIPCHK(hipMemcpyAsync(buf.data(), src, buf.size(), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ctx->bits == 32) from_interleaved<float>(ctx, buf, p, ux, uy, uz);
+  else from_interleaved<double>(ctx, buf, p, ux, uy, uz);
+  return WDG_OK;
+}
+
+int upload_sources(wdg_ctx* ctx) {
+  if (ctx->host_only || ctx->src.empty()) return WDG_OK;
+  const int NP = ctx->NP();
+  std::vector<unsigned char> buf(size_t(wdg::kMaxSources) * NP * ctx->tsize(), 0);
+  for (size_t s = 0; s < ctx->src.size(); ++s)
+    for (int n = 0; n < NP; ++n) {
+      if (ctx->bits == 32) reinterpret_cast<float*>(buf.data())[s * NP + n] = float(ctx->src[s].vec[n]);
+      else reinterpret_cast<double*>(buf.data())[s * NP + n] = ctx->src[s].vec[n];
+    }
+  HIPCHK(hipMemcpyAsync(ctx->dSrcVec, buf.data(), buf.size(), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return WDG_OK;
+}
+
+// one Runge-Kutta stage (or, with a = 0, dt = 1, no U write, a plain RHS)
+int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a, double b, double dt, double tstage,
+                 int flags) {
+  wdg::StageLaunch L{};
+  L.Uin = Uin;
+  L.Uout = Uout;
+  L.res = res;
+  L.geo = ctx->dGeo;
+  L.L = ctx->dL;
+  L.conn = ctx->dConn;
+  L.ops = ctx->dOps;
+  L.srcvec = ctx->dSrcVec;
+  L.nsrc = int(ctx->src.size());
+  for (int s = 0; s < L.nsrc; ++s) {
+    L.src_elem[s] = int(ctx->src[s].elem);
+    L.src_amp[s] = ctx->src[s].value(tstage);
+  }
+  L.a = a;
+  L.b = b;
+  L.dt = dt;
+  L.K = ctx->K;
+  L.flags = flags | (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
+            (ctx->flux == WDG_FLUX_CENTRAL ? wdg::kCentral : 0);
+  if (ctx->timing) {
+    if (ctx->events_used == ctx->events.size()) {
+      hipEvent_t a, b;
+      HIPCHK(hipEventCreate(&a));
+      HIPCHK(hipEventCreate(&b));
+      ctx->events.emplace_back(a, b);
+    }
+    auto& ev = ctx->events[ctx->events_used++];
+    HIPCHK(hipEventRecord(ev.first, ctx->stream));
+    HIPCHK(wdg::launch_stage(ctx->N, ctx->bits, L, ctx->stream));
+    HIPCHK(hipEventRecord(ev.second, ctx->stream));
+    return WDG_OK;
+  }
+  HIPCHK(wdg::launch_stage(ctx->N, ctx->bits, L, ctx->stream));
+  return WDG_OK;
+}
+
+int ensure_receiver_capacity(wdg_ctx* ctx, int64_t steps_needed) {
+  if (ctx->nrec == 0 || steps_needed <= ctx->rec_cap) return WDG_OK;
+  int64_t cap = std::max<int64_t>(steps_needed, 2 * ctx->rec_cap);
+  cap = std::max<int64_t>(cap, 64);
+  double* nb = nullptr;
+  HIPCHK(hipMalloc(&nb, size_t(cap * ctx->nrec) * sizeof(double)));
+  if (ctx->dRecBuf && ctx->rec_steps > 0)
+    HIPCHK(hipMemcpyAsync(nb, ctx->dRecBuf, size_t(ctx->rec_steps * ctx->nrec) * sizeof(double),
+                          hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  dfree(ctx->dRecBuf);
+  ctx->dRecBuf = nb;
+  ctx->rec_cap = cap;
+  return WDG_OK;
+}
+
+bool finite_all(const double* a, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wdg_create(int order_N, int precision_bits, int device, wdg_ctx** out) {
+  if (!out) return WDG_ERR_ARG;
+  *out = nullptr;
+  if (order_N < 1 || order_N > 5) return WDG_ERR_ARG;
+  if (precision_bits != 32 && precision_bits != 64) return WDG_ERR_ARG;
+  if (device < -1) return WDG_ERR_ARG;
+  wdg_ctx* ctx = new (std::nothrow) wdg_ctx();
+  if (!ctx) return WDG_ERR_OOM;
+  ctx->N = order_N;
+  ctx->bits = precision_bits;
+  ctx->device = device;
+  ctx->host_only = device < 0;
+  try {
+    ctx->ref = std::make_unique<RefOps>(order_N);
+  } catch (...) {
+    delete ctx;
+    return WDG_ERR_ARG;
+  }
+  *out = ctx;
+  return WDG_OK;
+}
+
+int wdg_destroy(wdg_ctx* ctx) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (!ctx->host_only && ctx->dGeo) {
+    (void)hipSetDevice(ctx->device);
+    release_device(ctx);
+  }
+  delete ctx;
+  return WDG_OK;
+}
+
+const char* wdg_last_error(const wdg_ctx* ctx) {
+  if (!ctx) return "null context";
+  return ctx->err.c_str();
+}
+
+int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const int64_t* wedge_v, int64_t nt,
+                 const int64_t* tet_v) {
+  if (!ctx) return WDG_ERR_ARG;
+  (void)tet_v;
+  if (nv <= 0 || !vxyz || nw <= 0 || !wedge_v || nt < 0) return fail(ctx, WDG_ERR_ARG, "bad mesh arguments");
+  if (nt > 0) return fail(ctx, WDG_ERR_ARG, "tetrahedra are not supported in this version");
+  if (nw > (int64_t(1) << 31) / 8) return fail(ctx, WDG_ERR_ARG, "too many elements");
+  for (int64_t i = 0; i < nv * 3; ++i)
+    if (!std::isfinite(vxyz[i])) return fail(ctx, WDG_ERR_ARG, "non-finite vertex coordinate");
+  const int64_t K = nw;
+  std::vector<double> X(size_t(K) * 18);
+  for (int64_t k = 0; k < K; ++k) {
+    for (int v = 0; v < 6; ++v) {
+      const int64_t id = wedge_v[k * 6 + v];
+      if (id < 0 || id >= nv) return fail(ctx, WDG_ERR_ARG, "vertex id out of range in wedge " + std::to_string(k));
+      for (int d = 0; d < 3; ++d) X[k * 18 + 3 * v + d] = vxyz[id * 3 + d];
+    }
+    const double* x = &X[k * 18];
+    double h = 0.0;
+    for (int a = 0; a < 6; ++a)
+      for (int b = a + 1; b < 6; ++b) {
+        double d2 = 0;
+        for (int d = 0; d < 3; ++d) d2 += (x[3 * a + d] - x[3 * b + d]) * (x[3 * a + d] - x[3 * b + d]);
+        h = std::max(h, std::sqrt(d2));
+      }
+    for (int v = 0; v < 3; ++v)
+      if (std::fabs(x[3 * v] - x[3 * (v + 3)]) > 1e-12 * h || std::fabs(x[3 * v + 1] - x[3 * (v + 3) + 1]) > 1e-12 * h)
+        return fail(ctx, WDG_ERR_NOT_VERTICAL, "wedge " + std::to_string(k) + " is not vertically mapped");
+    const double xr = 0.5 * (x[3] - x[0]), xs = 0.5 * (x[6] - x[0]);
+    const double yr = 0.5 * (x[4] - x[1]), ys = 0.5 * (x[7] - x[1]);
+    const double Jt = xr * ys - xs * yr;
+    if (std::fabs(Jt) <= 1e-14 * h * h) return fail(ctx, WDG_ERR_JACOBIAN, "wedge " + std::to_string(k) + " has a degenerate base");
+    if (Jt < 0) return fail(ctx, WDG_ERR_ORIENTATION, "wedge " + std::to_string(k) + " bottom triangle is clockwise");
+    for (int v = 0; v < 3; ++v)
+      if (x[3 * (v + 3) + 2] - x[3 * v + 2] <= 1e-14 * h)
+        return fail(ctx, WDG_ERR_JACOBIAN, "wedge " + std::to_string(k) + " has a non-positive vertical edge");
+  }
+
+  // face matching by sorted vertex ids
+  static const int kFaceVerts[5][4] = {{0, 1, 2, -1}, {3, 4, 5, -1}, {0, 1, 4, 3}, {1, 2, 5, 4}, {2, 0, 3, 5}};
+  struct FaceKey {
+    std::array<int64_t, 4> key;
+    int64_t id;  // k * 5 + f
+  };
+  std::vector<FaceKey> faces(size_t(K) * 5);
+  for (int64_t k = 0; k < K; ++k)
+    for (int f = 0; f < 5; ++f) {
+      std::array<int64_t, 4> kk{-1, -1, -1, -1};
+      const int nvf = f < 2 ? 3 : 4;
+      for (int m = 0; m < nvf; ++m) kk[m] = wedge_v[k * 6 + kFaceVerts[f][m]];
+      std::sort(kk.begin(), kk.begin() + nvf);
+      if (nvf == 3) kk = {-1, kk[0], kk[1], kk[2]};
+      faces[k * 5 + f] = {kk, k * 5 + f};
+    }
+  std::sort(faces.begin(), faces.end(), [](const FaceKey& a, const FaceKey& b) { return a.key < b.key; });
+  std::vector<int32_t> conn(size_t(K) * wdg::kConnStride, 0);
+  for (int64_t k = 0; k < K; ++k)
+    for (int f = 0; f < 5; ++f) conn[k * wdg::kConnStride + f] = -1;
+  for (size_t a = 0; a < faces.size();) {
+    size_t b = a + 1;
+    while (b < faces.size() && faces[b].key == faces[a].key) ++b;
+    if (b - a > 2) return fail(ctx, WDG_ERR_NONCONFORMING, "a face is shared by more than two elements");
+    if (b - a == 2) {
+      for (int side = 0; side < 2; ++side) {
+        const int64_t me = faces[a + side].id, other = faces[a + 1 - side].id;
+        const int64_t k1 = me / 5, k2 = other / 5;
+        const int f1 = int(me % 5), f2 = int(other % 5);
+        int32_t* cn = &conn[k1 * wdg::kConnStride];
+        cn[f1] = int32_t(k2);
+        if (f1 < 2) {
+          int pi[3];
+          for (int v = 0; v < 3; ++v) {
+            const int64_t gid = wedge_v[k1 * 6 + kFaceVerts[f1][v]];
+            pi[v] = -1;
+            for (int m = 0; m < 3; ++m)
+              if (wedge_v[k2 * 6 + kFaceVerts[f2][m]] == gid) pi[v] = m;
+          }
+          int code = -1;
+          for (int p = 0; p < 6; ++p)
+            if (wdg::kPerm[p][0] == pi[0] && wdg::kPerm[p][1] == pi[1] && wdg::kPerm[p][2] == pi[2]) code = p;
+          if (code < 0) return fail(ctx, WDG_ERR_NONCONFORMING, "triangular face vertex mismatch");
+          cn[5] |= code << (3 * f1);
+          if (f2 == 1) cn[5] |= 1 << (6 + f1);
+        } else {
+          const int e1 = f1 - 2, e2 = f2 - 2;
+          const int64_t A = wedge_v[k1 * 6 + e1], B = wedge_v[k1 * 6 + (e1 + 1) % 3];
+          const int64_t A2 = wedge_v[k2 * 6 + e2], B2 = wedge_v[k2 * 6 + (e2 + 1) % 3];
+          if (!(A2 == B && B2 == A))
+            return fail(ctx, WDG_ERR_NONCONFORMING, "quadrilateral face orientation mismatch");
+          cn[5] |= e2 << (8 + 2 * e1);
+        }
+      }
+    }
+    a = b;
+  }
+
+  // accept: replace any previous mesh
+  if (!ctx->host_only && ctx->dGeo) {
+    (void)hipSetDevice(ctx->device);
+    release_device(ctx);
+  }
+  ctx->K = K;
+  ctx->X.swap(X);
+  ctx->conn.swap(conn);
+  ctx->c.assign(size_t(K), 1.0);
+  ctx->rho.assign(size_t(K), 1.0);
+  ctx->src.clear();
+  ctx->nrec = 0;
+  ctx->rec_steps = 0;
+  ctx->time = 0.0;
+  ctx->cur = 0;
+  ctx->state = kMesh;
+
+  if (ctx->host_only) return WDG_OK;
+  ctx->state = kCreated;  // until the device side is complete
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= ctx->device)
+    return fail(ctx, WDG_ERR_HIP, "no HIP device " + std::to_string(ctx->device));
+  HIPCHK(hipSetDevice(ctx->device));
+  const RefOps& R = *ctx->ref;
+  const size_t ts = ctx->tsize();
+  const size_t nstate = size_t(K) * R.NP * 4 * ts;
+  const int LS = wdg::lift_stride(ctx->N);
+  HIPCHK(hipMalloc(&ctx->dU[0], nstate));
+  HIPCHK(hipMalloc(&ctx->dU[1], nstate));
+  HIPCHK(hipMalloc(&ctx->dRes, nstate));
+  HIPCHK(hipMalloc(&ctx->dGeo, size_t(K) * wdg::kGeoStride * ts));
+  HIPCHK(hipMalloc(&ctx->dL, size_t(K) * LS * ts));
+  HIPCHK(hipMalloc(&ctx->dAux, size_t(K) * wdg::kAuxStride * sizeof(double)));
+  HIPCHK(hipMalloc(&ctx->dConn, size_t(K) * wdg::kConnStride * sizeof(int32_t)));
+  HIPCHK(hipMalloc(&ctx->dOps, wdg::ops_bytes(ctx->N, ctx->bits)));
+  HIPCHK(hipMalloc(&ctx->dMv, 3 * size_t(R.NT) * R.NT * sizeof(double)));
+  HIPCHK(hipMalloc(&ctx->dM1, size_t(R.Nq) * R.Nq * sizeof(double)));
+  HIPCHK(hipMalloc(&ctx->dPartial, 1024 * sizeof(double)));
+  HIPCHK(hipMalloc(&ctx->dSrcVec, size_t(wdg::kMaxSources) * R.NP * ts));
+  HIPCHK(hipMemsetAsync(ctx->dU[0], 0, nstate, ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->dU[1], 0, nstate, ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->dRes, 0, nstate, ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->dSrcVec, 0, size_t(wdg::kMaxSources) * R.NP * ts, ctx->stream));
+
+  std::vector<unsigned char> ops(wdg::ops_bytes(ctx->N, ctx->bits));
+  const double* Ea[3] = {R.Ea[0].data(), R.Ea[1].data(), R.Ea[2].data()};
+  const double* Eb[3] = {R.Eb[0].data(), R.Eb[1].data(), R.Eb[2].data()};
+  wdg::fill_ops(ctx->N, ctx->bits, ops.data(), R.Dr.data(), R.Ds.data(), Ea, Eb, R.Dt.data(), R.g0.data(),
+                R.gN.data(), R.t.data(), R.perm.data());
+  std::vector<double> Mv(3 * size_t(R.NT) * R.NT);
+  for (int v = 0; v < 3; ++v) std::copy(R.Mv[v].begin(), R.Mv[v].end(), Mv.begin() + v * R.NT * R.NT);
+  double *dX = nullptr, *dMtri = nullptr;
+  HIPCHK(hipMalloc(&dX, ctx->X.size() * sizeof(double)));
+  HIPCHK(hipMalloc(&dMtri, R.Mtri.size() * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(ctx->dOps, ops.data(), ops.size(), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->dMv, Mv.data(), Mv.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->dM1, R.M1.data(), R.M1.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(dX, ctx->X.data(), ctx->X.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(dMtri, R.Mtri.data(), R.Mtri.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->dConn, ctx->conn.data(), ctx->conn.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                        ctx->stream));
+  HIPCHK(wdg::launch_setup(ctx->N, ctx->bits, K, dX, ctx->dMv, dMtri, ctx->dGeo, ctx->dL, ctx->dAux, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipFree(dX));
+  HIPCHK(hipFree(dMtri));
+  ctx->state = kMesh;
+  return WDG_OK;
+}
+
+int wdg_set_material(wdg_ctx* ctx, const double* c, const double* rho) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "set_material before set_mesh");
+  if (!c || !rho) return fail(ctx, WDG_ERR_ARG, "null material array");
+  for (int64_t k = 0; k < ctx->K; ++k)
+    if (!(c[k] > 0) || !(rho[k] > 0) || !std::isfinite(c[k]) || !std::isfinite(rho[k]))
+      return fail(ctx, WDG_ERR_ARG, "material must be positive and finite");
+  ctx->c.assign(c, c + ctx->K);
+  ctx->rho.assign(rho, rho + ctx->K);
+  for (auto& s : ctx->src) {
+    double r, ss, t;
+    wedge_ref_coords(&ctx->X[s.elem * 18], s.xyz, r, ss, t);
+    s.vec = mass_inverse_times(ctx, s.elem, ctx->rho[s.elem] * ctx->c[s.elem] * ctx->c[s.elem], r, ss, t);
+  }
+  if (!ctx->host_only) {
+    HIPCHK(hipSetDevice(ctx->device));
+    double *dc = nullptr, *dr = nullptr;
+    HIPCHK(hipMalloc(&dc, ctx->K * sizeof(double)));
+    HIPCHK(hipMalloc(&dr, ctx->K * sizeof(double)));
+    HIPCHK(hipMemcpyAsync(dc, c, ctx->K * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(dr, rho, ctx->K * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(wdg::launch_material(ctx->bits, ctx->K, dc, dr, ctx->dGeo, ctx->dAux, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipFree(dc));
+    HIPCHK(hipFree(dr));
+    int rc = upload_sources(ctx);
+    if (rc) return rc;
+  }
+  ctx->state = std::max(ctx->state, int(kMaterial));
+  return WDG_OK;
+}
+
+int wdg_set_boundary(wdg_ctx* ctx, int bc) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (bc != WDG_BC_DIRICHLET_P0 && bc != WDG_BC_RIGID) return fail(ctx, WDG_ERR_ARG, "unknown boundary condition");
+  ctx->bc = bc;
+  return WDG_OK;
+}
+
+int wdg_set_flux(wdg_ctx* ctx, int flux) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (flux != WDG_FLUX_UPWIND && flux != WDG_FLUX_CENTRAL) return fail(ctx, WDG_ERR_ARG, "unknown flux");
+  ctx->flux = flux;
+  return WDG_OK;
+}
+
+int wdg_num_nodes(const wdg_ctx* ctx, int64_t* n) {
+  if (!ctx || !n) return WDG_ERR_ARG;
+  if (ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "no mesh");
+  *n = ctx->K * ctx->NP();
+  return WDG_OK;
+}
+
+int wdg_get_node_coords(const wdg_ctx* ctx, double* xyz) {
+  if (!ctx || !xyz) return WDG_ERR_ARG;
+  if (ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "no mesh");
+  const RefOps& R = *ctx->ref;
+  for (int64_t k = 0; k < ctx->K; ++k) {
+    const double* x = &ctx->X[k * 18];
+    for (int j = 0; j < R.Nq; ++j)
+      for (int i = 0; i < R.NT; ++i) {
+        const double r = R.r[i], s = R.s[i], t = R.t[j];
+        const double lam[3] = {-(r + s) / 2.0, (1.0 + r) / 2.0, (1.0 + s) / 2.0};
+        double* o = xyz + 3 * (k * R.NP + j * R.NT + i);
+        for (int d = 0; d < 3; ++d) {
+          double acc = 0;
+          for (int v = 0; v < 3; ++v) acc += lam[v] * (x[3 * v + d] * (1 - t) / 2 + x[3 * (v + 3) + d] * (1 + t) / 2);
+          o[d] = acc;
+        }
+      }
+  }
+  return WDG_OK;
+}
+
+int wdg_set_fields(wdg_ctx* ctx, const double* p, const double* ux, const double* uy, const double* uz) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (ctx->state < kMaterial) return fail(ctx, WDG_ERR_STATE, "set_fields before set_material");
+  if (!p || !ux || !uy || !uz) return fail(ctx, WDG_ERR_ARG, "null field array");
+  if (ctx->host_only) return fail(ctx, WDG_ERR_STATE, "host-only context cannot hold fields");
+  const int64_t n = ctx->K * ctx->NP();
+  if (!finite_all(p, n) || !finite_all(ux, n) || !finite_all(uy, n) || !finite_all(uz, n))
+    return fail(ctx, WDG_ERR_UNSTABLE, "non-finite field values");
+  HIPCHK(hipSetDevice(ctx->device));
+  int rc = upload_state(ctx, ctx->dU[ctx->cur], p, ux, uy, uz);
+  if (rc) return rc;
+  ctx->rec_steps = 0;
+  ctx->state = kFields;
+  return WDG_OK;
+}
+
+int wdg_get_fields(const wdg_ctx* ctx, double* p, double* ux, double* uy, double* uz) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (ctx->state < kFields) return fail(ctx, WDG_ERR_STATE, "no fields");
+  HIPCHK(hipSetDevice(ctx->device));
+  return download_state(ctx, ctx->dU[ctx->cur], p, ux, uy, uz);
+}
+
+int wdg_bind_device_state(wdg_ctx* ctx, void* d_U, void* d_res, void* hip_stream) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (ctx->host_only || ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "bind before set_mesh");
+  if ((d_U == nullptr) != (d_res == nullptr)) return fail(ctx, WDG_ERR_ARG, "bind both state buffers or none");
+  if ((reinterpret_cast<uintptr_t>(d_U) | reinterpret_cast<uintptr_t>(d_res)) & 255)
+    return fail(ctx, WDG_ERR_ARG, "state buffers must be 256-byte aligned");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  if (!d_U) return WDG_OK;
+  const size_t nstate = size_t(ctx->K) * ctx->NP() * 4 * ctx->tsize();
+  HIPCHK(hipMemcpyAsync(d_U, ctx->dU[ctx->cur], nstate, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(d_res, ctx->dRes, nstate, hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ctx->own_state) {
+    dfree(ctx->dU[0]);
+    dfree(ctx->dU[1]);
+    dfree(ctx->dRes);
+  }
+  ctx->dU[0] = d_U;
+  ctx->dU[1] = static_cast<unsigned char*>(d_U) + nstate;
+  ctx->dRes = d_res;
+  ctx->cur = 0;
+  ctx->own_state = false;
+  return WDG_OK;
+}
+
+int wdg_add_ricker_source(wdg_ctx* ctx, const double xyz[3], double f0, double t0, double amp, int* id) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "source before set_mesh");
+  if (!xyz || !(f0 > 0) || !std::isfinite(t0) || !std::isfinite(amp)) return fail(ctx, WDG_ERR_ARG, "bad source");
+  if (ctx->src.size() >= size_t(wdg::kMaxSources)) return fail(ctx, WDG_ERR_ARG, "too many sources");
+  double r, s, t;
+  const int64_t k = locate(ctx, xyz, r, s, t);
+  if (k < 0) return fail(ctx, WDG_ERR_OUTSIDE, "source outside the mesh");
+  Source S;
+  std::copy(xyz, xyz + 3, S.xyz);
+  S.f0 = f0;
+  S.t0 = t0;
+  S.amp = amp;
+  S.elem = k;
+  S.vec = mass_inverse_times(ctx, k, ctx->rho[k] * ctx->c[k] * ctx->c[k], r, s, t);
+  ctx->src.push_back(S);
+  if (id) *id = int(ctx->src.size()) - 1;
+  if (!ctx->host_only) {
+    HIPCHK(hipSetDevice(ctx->device));
+    return upload_sources(ctx);
+  }
+  return WDG_OK;
+}
+
+int wdg_set_receivers(wdg_ctx* ctx, int64_t n, const double* xyz) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "receivers before set_mesh");
+  if (n < 0 || (n > 0 && !xyz)) return fail(ctx, WDG_ERR_ARG, "bad receivers");
+  const RefOps& R = *ctx->ref;
+  std::vector<int> el(static_cast<size_t>(n));
+  std::vector<double> rows(static_cast<size_t>(n) * R.NP);
+  for (int64_t q = 0; q < n; ++q) {
+    double r, s, t;
+    const int64_t k = locate(ctx, xyz + 3 * q, r, s, t);
+    if (k < 0) return fail(ctx, WDG_ERR_OUTSIDE, "receiver " + std::to_string(q) + " outside the mesh");
+    el[q] = int(k);
+    std::vector<double> b;
+    wedge_basis(R, r, s, t, b);
+    std::copy(b.begin(), b.end(), rows.begin() + q * R.NP);
+  }
+  ctx->rec_steps = 0;
+  if (ctx->host_only) {
+    ctx->nrec = n;
+    return WDG_OK;
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  dfree(ctx->dRecElem);
+  dfree(ctx->dRecRows);
+  dfree(ctx->dRecBuf);
+  ctx->rec_cap = 0;
+  ctx->nrec = n;
+  if (n == 0) return WDG_OK;
+  HIPCHK(hipMalloc(&ctx->dRecElem, el.size() * sizeof(int)));
+  HIPCHK(hipMalloc(&ctx->dRecRows, rows.size() * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(ctx->dRecElem, el.data(), el.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->dRecRows, rows.data(), rows.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return WDG_OK;
+}
+
+int wdg_read_receivers(const wdg_ctx* ctx, double* out, int64_t* steps) {
+  if (!ctx || !steps) return WDG_ERR_ARG;
+  *steps = ctx->rec_steps;
+  if (!out || ctx->rec_steps == 0 || ctx->nrec == 0) return WDG_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipMemcpyAsync(out, ctx->dRecBuf, size_t(ctx->rec_steps * ctx->nrec) * sizeof(double),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return WDG_OK;
+}
+
+int wdg_stable_dt(const wdg_ctx* ctx, double cfl, double* dt) {
+  if (!ctx || !dt) return WDG_ERR_ARG;
+  if (ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "no mesh");
+  if (!(cfl > 0)) return fail(ctx, WDG_ERR_ARG, "cfl must be positive");
+  const int N = ctx->N;
+  double worst = 0.0;
+  for (int64_t k = 0; k < ctx->K; ++k) {
+    const double* x = &ctx->X[k * 18];
+    const double xr = 0.5 * (x[3] - x[0]), xs = 0.5 * (x[6] - x[0]);
+    const double yr = 0.5 * (x[4] - x[1]), ys = 0.5 * (x[7] - x[1]);
+    const double Jt = xr * ys - xs * yr;
+    double h[3], Jmin = 1e300, Jf = 0.0;
+    for (int v = 0; v < 3; ++v) {
+      h[v] = x[3 * (v + 3) + 2] - x[3 * v + 2];
+      Jmin = std::min(Jmin, 0.5 * Jt * h[v]);
+    }
+    for (int face = 0; face < 2; ++face) {
+      const int o = face == 0 ? 0 : 9;
+      const double ax = x[o + 3] - x[o], ay = x[o + 4] - x[o + 1], az = x[o + 5] - x[o + 2];
+      const double bx = x[o + 6] - x[o], by = x[o + 7] - x[o + 1], bz = x[o + 8] - x[o + 2];
+      const double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
+      Jf = std::max(Jf, 0.25 * std::sqrt(cx * cx + cy * cy + cz * cz));
+    }
+    for (int e = 0; e < 3; ++e) {
+      const int a = e, b = (e + 1) % 3;
+      const double ell = std::hypot(x[3 * b] - x[3 * a], x[3 * b + 1] - x[3 * a + 1]);
+      Jf = std::max(Jf, 0.25 * ell * std::max(h[a], h[b]));
+    }
+    worst = std::max(worst, ctx->c[k] * (N + 1.0) * (N + 3.0) / 3.0 * Jf / Jmin);
+  }
+  *dt = cfl / worst;
+  return WDG_OK;
+}
+
+int wdg_step(wdg_ctx* ctx, int64_t nsteps, double dt) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (ctx->state < kFields) return fail(ctx, WDG_ERR_STATE, "step before set_fields");
+  if (nsteps < 0 || !(dt > 0) || !std::isfinite(dt)) return fail(ctx, WDG_ERR_ARG, "bad step arguments");
+  HIPCHK(hipSetDevice(ctx->device));
+  int rc = ensure_receiver_capacity(ctx, ctx->rec_steps + nsteps);
+  if (rc) return rc;
+  const double t0 = ctx->time;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    const double tn = t0 + double(n) * dt;
+    for (int s = 0; s < 5; ++s) {
+      const int flags = (s == 0 ? 0 : wdg::kReadRes) | wdg::kWriteU;
+      rc = launch_stage(ctx, ctx->dU[ctx->cur], ctx->dU[1 - ctx->cur], ctx->dRes, kRkA[s], kRkB[s], dt,
+                        tn + kRkC[s] * dt, flags);
+      if (rc) return rc;
+      ctx->cur = 1 - ctx->cur;
+    }
+    if (ctx->nrec > 0) {
+      HIPCHK(wdg::launch_receivers(ctx->bits, ctx->NP(), int(ctx->nrec), ctx->dU[ctx->cur], ctx->dRecElem,
+                                   ctx->dRecRows, ctx->dRecBuf + ctx->rec_steps * ctx->nrec, ctx->stream));
+      ctx->rec_steps += 1;
+    }
+  }
+  ctx->time = t0 + double(nsteps) * dt;
+  return WDG_OK;
+}
+
+int wdg_get_time(const wdg_ctx* ctx, double* t) {
+  if (!ctx || !t) return WDG_ERR_ARG;
+  *t = ctx->time;
+  return WDG_OK;
+}
+
+int wdg_set_time(wdg_ctx* ctx, double t) {
+  if (!ctx || !std::isfinite(t)) return WDG_ERR_ARG;
+  ctx->time = t;
+  return WDG_OK;
+}
+
+int wdg_synchronize(wdg_ctx* ctx) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (ctx->host_only || ctx->state < kMesh) return WDG_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return WDG_OK;
+}
+
+int wdg_eval_rhs(wdg_ctx* ctx, double t, const double* in4, double* out4) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (ctx->state < kMaterial || ctx->host_only) return fail(ctx, WDG_ERR_STATE, "eval_rhs before set_material");
+  if (!in4 || !out4) return fail(ctx, WDG_ERR_ARG, "null array");
+  HIPCHK(hipSetDevice(ctx->device));
+  const int64_t n = ctx->K * ctx->NP();
+  const size_t nstate = size_t(n) * 4 * ctx->tsize();
+  void *dIn = nullptr, *dOut = nullptr;
+  HIPCHK(hipMalloc(&dIn, nstate));
+  HIPCHK(hipMalloc(&dOut, nstate));
+  int rc = upload_state(ctx, dIn, in4, in4 + n, in4 + 2 * n, in4 + 3 * n);
+  if (!rc) rc = launch_stage(ctx, dIn, nullptr, dOut, 0.0, 0.0, 1.0, t, 0);
+  if (!rc) rc = download_state(ctx, dOut, out4, out4 + n, out4 + 2 * n, out4 + 3 * n);
+  (void)hipFree(dIn);
+  (void)hipFree(dOut);
+  return rc;
+}
+
+int wdg_energy(wdg_ctx* ctx, double* E) {
+  if (!ctx || !E) return WDG_ERR_ARG;
+  if (ctx->state < kFields) return fail(ctx, WDG_ERR_STATE, "energy before set_fields");
+  HIPCHK(hipSetDevice(ctx->device));
+  int nb = 0;
+  HIPCHK(wdg::launch_energy(ctx->N, ctx->bits, ctx->K, ctx->dU[ctx->cur], ctx->dAux, ctx->dMv, ctx->dM1,
+                            ctx->dPartial, &nb, ctx->stream));
+  std::vector<double> part(nb);
+  HIPCHK(hipMemcpyAsync(part.data(), ctx->dPartial, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double acc = 0.0;
+  for (double v : part) acc += v;
+  *E = acc;
+  return WDG_OK;
+}
+
+int wdg_kernel_timing(wdg_ctx* ctx, int enable) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (ctx->host_only || ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "timing needs a device mesh");
+  ctx->timing = enable != 0;
+  ctx->events_used = 0;
+  return WDG_OK;
+}
+
+int wdg_read_kernel_timing(wdg_ctx* ctx, double* total_ms, int64_t* launches) {
+  if (!ctx || !total_ms || !launches) return WDG_ERR_ARG;
+  if (ctx->host_only || ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "timing needs a device mesh");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double acc = 0.0;
+  for (size_t i = 0; i < ctx->events_used; ++i) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->events[i].first, ctx->events[i].second));
+    acc += ms;
+  }
+  *total_ms = acc;
+  *launches = int64_t(ctx->events_used);
+  ctx->events_used = 0;
+  return WDG_OK;
+}
+
+int wdg_get_element_data(const wdg_ctx* ctx, double* geo, double* lift) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (ctx->host_only || ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "no device mesh");
+  HIPCHK(hipSetDevice(ctx->device));
+  const int NT = ctx->NT();
+  const int LS = wdg::lift_stride(ctx->N);
+  auto fetch = [&](const void* src, size_t count, double* dst, int stride, int used) -> int {
+    std::vector<unsigned char> buf(count * ctx->tsize());
+    HIPCHK(hipMemcpyAsync(buf.data(), src, buf.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int64_t k = 0; k < ctx->K; ++k)
+      for (int i = 0; i < used; ++i) {
+        const size_t m = size_t(k) * stride + i;
+        dst[k * used + i] = ctx->bits == 32 ? double(reinterpret_cast<float*>(buf.data())[m])
+                                            : reinterpret_cast<double*>(buf.data())[m];
+      }
+    return WDG_OK;
+  };
+  if (geo) {
+    int rc = fetch(ctx->dGeo, size_t(ctx->K) * wdg::kGeoStride, geo, wdg::kGeoStride, wdg::kGeoStride);
+    if (rc) return rc;
+  }
+  if (lift) {
+    int rc = fetch(ctx->dL, size_t(ctx->K) * LS, lift, LS, NT * NT);
+    if (rc) return rc;
+  }
+  return WDG_OK;
+}
+
+int wdg_reference_operator(int order_N, const char* name, double* out, int64_t cap, int64_t* count) {
+  if (!name || !count || order_N < 1 || order_N > 5 || cap < 0) return WDG_ERR_ARG;
+  RefOps R(order_N);
+  std::vector<double> v;
+  const std::string n(name);
+  if (n == "r") v = R.r;
+  else if (n == "s") v = R.s;
+  else if (n == "t") v = R.t;
+  else if (n == "Dr") v = R.Dr;
+  else if (n == "Ds") v = R.Ds;
+  else if (n == "Dt") v = R.Dt;
+  else if (n == "M1") v = R.M1;
+  else if (n == "Mtri") v = R.Mtri;
+  else if (n == "g0") v = R.g0;
+  else if (n == "gN") v = R.gN;
+  else if (n.size() == 3 && (n.substr(0, 2) == "Mv" || n.substr(0, 2) == "Ea" || n.substr(0, 2) == "Eb") &&
+           n[2] >= '0' && n[2] <= '2') {
+    const int e = n[2] - '0';
+    v = n[0] == 'M' ? R.Mv[e] : (n[1] == 'a' ? R.Ea[e] : R.Eb[e]);
+  } else if (n.size() == 5 && n.substr(0, 4) == "edge" && n[4] >= '0' && n[4] <= '2') {
+    for (int id : R.edge_nodes[n[4] - '0']) v.push_back(id);
+  } else {
+    return WDG_ERR_ARG;
+  }
+  *count = int64_t(v.size());
+  if (out) std::copy(v.begin(), v.begin() + std::min<int64_t>(cap, int64_t(v.size())), out);
+  return WDG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,270 @@
+"""Thin ctypes binding of libwdg (C ABI in include/wdg.h).
+
+Only argument marshalling lives here: every step of the solver runs in the
+HIP library.  Arrays of nodal values use the layout (K, 4, Np) with fields
+(p, u_x, u_y, u_z) and node n = j * Np_tri + i inside an element.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwdg.so")
+
+OK = 0
+ERRORS = {
+    -1: "WDG_ERR_ARG", -2: "WDG_ERR_STATE", -3: "WDG_ERR_NOT_VERTICAL", -4: "WDG_ERR_JACOBIAN",
+    -5: "WDG_ERR_ORIENTATION", -6: "WDG_ERR_NONCONFORMING", -7: "WDG_ERR_OUTSIDE", -8: "WDG_ERR_HIP",
+    -9: "WDG_ERR_OOM", -10: "WDG_ERR_UNSTABLE",
+}
+BC = {"dirichlet": 0, "rigid": 1}
+FLUX = {"upwind": 0, "central": 1}
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+_i64p = C.POINTER(C.c_int64)
+
+
+class WdgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+def load_library() -> C.CDLL:
+    """Load libwdg.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1607_03399_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    sig = {
+        "wdg_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.POINTER(vp)]),
+        "wdg_destroy": (C.c_int, [vp]),
+        "wdg_last_error": (C.c_char_p, [vp]),
+        "wdg_set_mesh": (C.c_int, [vp, C.c_int64, _dp, C.c_int64, _i64p, C.c_int64, _i64p]),
+        "wdg_set_material": (C.c_int, [vp, _dp, _dp]),
+        "wdg_set_boundary": (C.c_int, [vp, C.c_int]),
+        "wdg_set_flux": (C.c_int, [vp, C.c_int]),
+        "wdg_num_nodes": (C.c_int, [vp, _i64p]),
+        "wdg_get_node_coords": (C.c_int, [vp, _dp]),
+        "wdg_set_fields": (C.c_int, [vp, _dp, _dp, _dp, _dp]),
+        "wdg_get_fields": (C.c_int, [vp, _dp, _dp, _dp, _dp]),
+        "wdg_bind_device_state": (C.c_int, [vp, vp, vp, vp]),
+        "wdg_add_ricker_source": (C.c_int, [vp, _dp, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int)]),
+        "wdg_set_receivers": (C.c_int, [vp, C.c_int64, _dp]),
+        "wdg_read_receivers": (C.c_int, [vp, _dp, _i64p]),
+        "wdg_stable_dt": (C.c_int, [vp, C.c_double, _dp]),
+        "wdg_step": (C.c_int, [vp, C.c_int64, C.c_double]),
+        "wdg_get_time": (C.c_int, [vp, _dp]),
+        "wdg_set_time": (C.c_int, [vp, C.c_double]),
+        "wdg_synchronize": (C.c_int, [vp]),
+        "wdg_eval_rhs": (C.c_int, [vp, C.c_double, _dp, _dp]),
+        "wdg_energy": (C.c_int, [vp, _dp]),
+        "wdg_get_element_data": (C.c_int, [vp, _dp, _dp]),
+        "wdg_kernel_timing": (C.c_int, [vp, C.c_int]),
+        "wdg_read_kernel_timing": (C.c_int, [vp, _dp, _i64p]),
+        "wdg_reference_operator": (C.c_int, [C.c_int, C.c_char_p, _dp, C.c_int64, _i64p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray, ctype=C.c_double):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def reference_operator(N: int, name: str) -> np.ndarray:
+    """Host-built reference operator of the library (see wdg_reference_operator)."""
+    lib = load_library()
+    n = C.c_int64()
+    rc = lib.wdg_reference_operator(N, name.encode(), None, 0, C.byref(n))
+    if rc:
+        raise WdgError(rc, f"reference operator {name}")
+    out = np.zeros(n.value)
+    lib.wdg_reference_operator(N, name.encode(), _ptr(out), n.value, C.byref(n))
+    return out
+
+
+class Solver:
+    """One solver context (one device, one polynomial order, one precision)."""
+
+    def __init__(self, N: int, precision: int = 32, device: int = 0):
+        self._lib = load_library()
+        self.N = N
+        self.precision = precision
+        self.NT = (N + 1) * (N + 2) // 2
+        self.Np = self.NT * (N + 1)
+        self.K = 0
+        h = C.c_void_p()
+        rc = self._lib.wdg_create(N, precision, device, C.byref(h))
+        if rc:
+            raise WdgError(rc, "wdg_create")
+        self._h = h
+        self._bound = None
+
+    # -- plumbing ----------------------------------------------------------
+    def _check(self, rc: int, what: str):
+        if rc:
+            msg = self._lib.wdg_last_error(self._h)
+            raise WdgError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.wdg_destroy(self._h)
+            self._h = None
+        self._bound = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- setup -------------------------------------------------------------
+    def set_mesh(self, verts, wedges, tets=None):
+        v = np.ascontiguousarray(verts, dtype=np.float64)
+        w = np.ascontiguousarray(wedges, dtype=np.int64)
+        t = np.ascontiguousarray(np.zeros((0, 4)) if tets is None else tets, dtype=np.int64)
+        self._check(self._lib.wdg_set_mesh(self._h, len(v), _ptr(v), len(w), _ptr(w, C.c_int64), len(t),
+                                           _ptr(t, C.c_int64)), "set_mesh")
+        self.K = len(w) + len(t)
+
+    def set_material(self, c, rho):
+        c = np.ascontiguousarray(np.broadcast_to(c, (self.K,)), dtype=np.float64)
+        r = np.ascontiguousarray(np.broadcast_to(rho, (self.K,)), dtype=np.float64)
+        self._check(self._lib.wdg_set_material(self._h, _ptr(c), _ptr(r)), "set_material")
+
+    def set_boundary(self, bc: str):
+        self._check(self._lib.wdg_set_boundary(self._h, BC[bc]), "set_boundary")
+
+    def set_flux(self, flux: str):
+        self._check(self._lib.wdg_set_flux(self._h, FLUX[flux]), "set_flux")
+
+    def num_nodes(self) -> int:
+        n = C.c_int64()
+        self._check(self._lib.wdg_num_nodes(self._h, C.byref(n)), "num_nodes")
+        return n.value
+
+    def node_coords(self) -> np.ndarray:
+        out = np.zeros((self.num_nodes(), 3))
+        self._check(self._lib.wdg_get_node_coords(self._h, _ptr(out)), "get_node_coords")
+        return out.reshape(self.K, self.Np, 3)
+
+    # -- state -------------------------------------------------------------
+    def set_fields(self, U):
+        U = np.asarray(U, dtype=np.float64).reshape(self.K, 4, self.Np)
+        f = [np.ascontiguousarray(U[:, i, :]) for i in range(4)]
+        self._check(self._lib.wdg_set_fields(self._h, *[_ptr(a) for a in f]), "set_fields")
+
+    def get_fields(self) -> np.ndarray:
+        f = [np.zeros((self.K, self.Np)) for _ in range(4)]
+        self._check(self._lib.wdg_get_fields(self._h, *[_ptr(a) for a in f]), "get_fields")
+        return np.stack(f, axis=1)
+
+    def bind_torch(self, device=None, stream=None):
+        """Allocate the state as torch tensors on the current HIP device and run
+        every launch on the given (or current) torch stream."""
+        import torch
+
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        dtype = torch.float32 if self.precision == 32 else torch.float64
+        n = self.num_nodes() * 4
+        U = torch.empty(2 * n, dtype=dtype, device=dev)
+        res = torch.empty(n, dtype=dtype, device=dev)
+        st = torch.cuda.current_stream(dev) if stream is None else stream
+        self._check(self._lib.wdg_bind_device_state(self._h, C.c_void_p(U.data_ptr()), C.c_void_p(res.data_ptr()),
+                                                    C.c_void_p(st.cuda_stream)), "bind_device_state")
+        self._bound = (U, res, st)
+        return self._bound
+
+    def set_stream(self, stream):
+        self._check(self._lib.wdg_bind_device_state(self._h, None, None, C.c_void_p(stream.cuda_stream)),
+                    "bind_device_state")
+
+    # -- sources and receivers --------------------------------------------
+    def add_ricker_source(self, xyz, f0: float, t0: float, amp: float = 1.0) -> int:
+        x = np.ascontiguousarray(xyz, dtype=np.float64)
+        sid = C.c_int()
+        self._check(self._lib.wdg_add_ricker_source(self._h, _ptr(x), f0, t0, amp, C.byref(sid)), "add_ricker_source")
+        return sid.value
+
+    def set_receivers(self, xyz):
+        x = np.ascontiguousarray(np.atleast_2d(xyz), dtype=np.float64)
+        self._nrec = len(x)
+        self._check(self._lib.wdg_set_receivers(self._h, len(x), _ptr(x)), "set_receivers")
+
+    def read_receivers(self) -> np.ndarray:
+        n = C.c_int64()
+        self._check(self._lib.wdg_read_receivers(self._h, None, C.byref(n)), "read_receivers")
+        out = np.zeros((n.value, getattr(self, "_nrec", 0)))
+        if out.size:
+            self._check(self._lib.wdg_read_receivers(self._h, _ptr(out), C.byref(n)), "read_receivers")
+        return out
+
+    # -- stepping ----------------------------------------------------------
+    def stable_dt(self, cfl: float) -> float:
+        dt = C.c_double()
+        self._check(self._lib.wdg_stable_dt(self._h, cfl, C.byref(dt)), "stable_dt")
+        return dt.value
+
+    def step(self, nsteps: int, dt: float):
+        self._check(self._lib.wdg_step(self._h, int(nsteps), float(dt)), "step")
+
+    @property
+    def time(self) -> float:
+        t = C.c_double()
+        self._check(self._lib.wdg_get_time(self._h, C.byref(t)), "get_time")
+        return t.value
+
+    @time.setter
+    def time(self, t: float):
+        self._check(self._lib.wdg_set_time(self._h, float(t)), "set_time")
+
+    def synchronize(self):
+        self._check(self._lib.wdg_synchronize(self._h), "synchronize")
+
+    def eval_rhs(self, U, t: float = 0.0) -> np.ndarray:
+        U = np.asarray(U, dtype=np.float64).reshape(self.K, 4, self.Np)
+        inp = np.ascontiguousarray(np.transpose(U, (1, 0, 2)))  # field blocks
+        out = np.zeros_like(inp)
+        self._check(self._lib.wdg_eval_rhs(self._h, float(t), _ptr(inp), _ptr(out)), "eval_rhs")
+        return np.ascontiguousarray(np.transpose(out, (1, 0, 2)))
+
+    def energy(self) -> float:
+        E = C.c_double()
+        self._check(self._lib.wdg_energy(self._h, C.byref(E)), "energy")
+        return E.value
+
+    def kernel_timing(self, enable: bool):
+        self._check(self._lib.wdg_kernel_timing(self._h, int(bool(enable))), "kernel_timing")
+
+    def read_kernel_timing(self):
+        """(summed stage-kernel milliseconds, number of timed launches)."""
+        ms = C.c_double()
+        n = C.c_int64()
+        self._check(self._lib.wdg_read_kernel_timing(self._h, C.byref(ms), C.byref(n)), "read_kernel_timing")
+        return ms.value, n.value
+
+    def element_data(self):
+        """(geo (K,32), lift (K,Np_tri,Np_tri)) built by the device setup kernel."""
+        geo = np.zeros((self.K, 32))
+        lift = np.zeros((self.K, self.NT, self.NT))
+        self._check(self._lib.wdg_get_element_data(self._h, _ptr(geo), _ptr(lift)), "get_element_data")
+        return geo, lift
