@@ -336,15 +336,20 @@ def node_coords(mesh: Mesh, N: int) -> np.ndarray:
 
 def locate(mesh: Mesh, x: np.ndarray, tol: float = 1e-12):
     """Lowest-index element containing point x and its reference coordinates."""
+    x = np.asarray(x, float)
     X = mesh.verts[mesh.wedges]
-    xi = G.inverse_map("wedge", X, np.repeat(np.asarray(x, float)[None, :], mesh.K, axis=0))
+    # only elements whose bounding box holds the point can contain it
+    pad = 1e-9 * (np.abs(X).max() + 1.0)
+    cand = np.nonzero(np.all((X.min(axis=1) - pad <= x) & (x <= X.max(axis=1) + pad), axis=1))[0]
+    if len(cand) == 0:
+        raise ValueError("point outside the mesh")
+    xi = G.inverse_map("wedge", X[cand], np.repeat(x[None, :], len(cand), axis=0))
     r, s, t = xi[:, 0], xi[:, 1], xi[:, 2]
     inside = (r >= -1 - tol) & (s >= -1 - tol) & (r + s <= tol) & (np.abs(t) <= 1 + tol)
     hits = np.nonzero(inside)[0]
     if len(hits) == 0:
         raise ValueError("point outside the mesh")
-    k = int(hits[0])
-    return k, xi[k]
+    return int(cand[hits[0]]), xi[hits[0]]
 
 
 def point_basis(N: int, xi: np.ndarray) -> np.ndarray:

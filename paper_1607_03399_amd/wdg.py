@@ -42,6 +42,12 @@ def load_library() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1607_03399_amd.build`")
+    # torch ships its own HIP runtime under the same soname; loading torch first
+    # makes the library and torch share that one runtime (streams, memory)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     vp = C.c_void_p
     sig = {
