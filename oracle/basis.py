@@ -213,6 +213,12 @@ class Wedge:
     Basis function n = j * Np_tri + i is l^tri_i(r, s) l^1D_j(t).
     """
 
+    kind = "wedge"
+    nfaces = 5
+    # local vertex ids of the faces: bottom, top, quads on edges v1v2, v2v3, v3v1
+    face_verts = [(0, 1, 2), (3, 4, 5), (0, 1, 4, 3), (1, 2, 5, 4), (2, 0, 3, 5)]
+    ref_verts = np.array([[-1, -1, -1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1], [1, -1, 1], [-1, 1, 1]], float)
+
     def __init__(self, N: int):
         self.N = N
         self.tri = Triangle(N)
@@ -255,3 +261,159 @@ class Wedge:
         T = np.tile(tq, len(rq))
         W = np.repeat(wq, len(tq)) * np.tile(wt, len(rq))
         return R, S, T, W
+
+
+# ---------------------------------------------------------------------------
+# Tetrahedron
+# ---------------------------------------------------------------------------
+
+# equilateral tetrahedron (edge length 2) used by the 3D Warp & Blend construction
+_EQ_TET = np.array([[-1.0, -1.0 / math.sqrt(3.0), -1.0 / math.sqrt(6.0)],
+                    [1.0, -1.0 / math.sqrt(3.0), -1.0 / math.sqrt(6.0)],
+                    [0.0, 2.0 / math.sqrt(3.0), -1.0 / math.sqrt(6.0)],
+                    [0.0, 0.0, 3.0 / math.sqrt(6.0)]])
+_BIUNIT_TET = np.array([[-1.0, -1.0, -1.0], [1.0, -1.0, -1.0], [-1.0, 1.0, -1.0], [-1.0, -1.0, 1.0]])
+# faces of the tetrahedron: (opposite vertex, the three face vertices)
+_TET_FACES = [(3, (0, 1, 2)), (2, (0, 1, 3)), (0, (1, 2, 3)), (1, (0, 2, 3))]
+
+
+def tet_nodes(N: int):
+    """Warp & Blend nodes (alpha = 0) on the bi-unit tetrahedron.
+
+    Equispaced lattice (a, b, c), a+b+c <= N, barycentrics lambda2 = a/N,
+    lambda3 = b/N, lambda4 = c/N (c outer, then b, then a).  Every face adds
+    its 2D warp (the triangle construction of ``tri_nodes`` evaluated with the
+    face's barycentrics), weighted by the face blend
+        beta = l_b l_c l_d / ((l_b + l_a/2)(l_c + l_a/2)(l_d + l_a/2)),
+    l_a the barycentric of the opposite vertex; beta = 1 on the face.  Nodes on
+    an edge get the 1D GLL warp of that edge only.  Face nodes therefore equal
+    the triangle nodes and edge nodes the GLL points.
+    """
+    lam = []
+    for c in range(N + 1):
+        for b in range(N + 1 - c):
+            for a in range(N + 1 - b - c):
+                lam.append((1.0 - (a + b + c) / N, a / N, b / N, c / N))
+    lam = np.array(lam)
+    X = lam @ _EQ_TET
+    tol = 1e-10
+    nonzero = (lam > tol).sum(axis=1)
+    shift = np.zeros_like(X)
+    for a, (b, c, d) in _TET_FACES:
+        w = np.zeros_like(X)
+        for (u, v) in ((b, c), (c, d), (d, b)):
+            e = _EQ_TET[v] - _EQ_TET[u]
+            e = e / np.linalg.norm(e)
+            amt = 4.0 * lam[:, u] * lam[:, v] * _warp_1d(N, lam[:, v] - lam[:, u])
+            w += amt[:, None] * e[None, :]
+        la, lb, lc, ld = lam[:, a], lam[:, b], lam[:, c], lam[:, d]
+        denom = (lb + 0.5 * la) * (lc + 0.5 * la) * (ld + 0.5 * la)
+        beta = np.where(denom > tol, lb * lc * ld / np.where(denom > tol, denom, 1.0), 0.0)
+        shift += beta[:, None] * w
+        # edge nodes of this face: exactly the edge warp
+        on_edge = (la < tol) & (nonzero == 2)
+        shift[on_edge] = w[on_edge]
+    X = X + shift
+    T = np.vstack([_EQ_TET.T, np.ones(4)])
+    bary = np.linalg.solve(T, np.vstack([X.T, np.ones(len(X))]))
+    rst = bary.T @ _BIUNIT_TET
+    return rst[:, 0].copy(), rst[:, 1].copy(), rst[:, 2].copy()
+
+
+def tet_modes(N: int):
+    return [(a, b, c) for a in range(N + 1) for b in range(N + 1 - a) for c in range(N + 1 - a - b)]
+
+
+def tet_poly_basis(N: int, r, s, t):
+    """P_a(r) P_b(s) P_c(t), a+b+c <= N, and its gradient at points."""
+    r, s, t = (np.atleast_1d(x).astype(np.float64) for x in (r, s, t))
+    modes = tet_modes(N)
+    P = np.zeros((len(r), len(modes)))
+    G = np.zeros((len(r), len(modes), 3))
+    for m, (a, b, c) in enumerate(modes):
+        la, dla = _leg(a, r)
+        lb, dlb = _leg(b, s)
+        lc, dlc = _leg(c, t)
+        P[:, m] = la * lb * lc
+        G[:, m, 0] = dla * lb * lc
+        G[:, m, 1] = la * dlb * lc
+        G[:, m, 2] = la * lb * dlc
+    return P, G
+
+
+def tet_quadrature(n: int):
+    """Collapsed-coordinate rule on the bi-unit tetrahedron, n Gauss points per
+    direction: r = (1+a)(1-b)(1-c)/4 - 1, s = (1+b)(1-c)/2 - 1, t = c, Jacobian
+    (1-b)/2 ((1-c)/2)^2; exact to total degree 2n - 3.  sum(w) = 4/3."""
+    x, w = gauss_nodes_weights(n)
+    A, Bq, Cq = np.meshgrid(x, x, x, indexing="ij")
+    WA, WB, WC = np.meshgrid(w, w, w, indexing="ij")
+    r = (1 + A) * (1 - Bq) * (1 - Cq) / 4 - 1
+    s = (1 + Bq) * (1 - Cq) / 2 - 1
+    t = Cq
+    ww = WA * WB * WC * (1 - Bq) / 2 * ((1 - Cq) / 2) ** 2
+    return r.ravel(), s.ravel(), t.ravel(), ww.ravel()
+
+
+class Tet:
+    """Nodal P^N tetrahedron (Warp & Blend nodes, alpha = 0)."""
+
+    kind = "tet"
+    nfaces = 4
+    # local vertex ids of the faces: bottom (t=-1), front (s=-1), slanted, left (r=-1)
+    face_verts = [(0, 1, 2), (0, 1, 3), (1, 2, 3), (0, 2, 3)]
+    ref_verts = _BIUNIT_TET
+
+    def __init__(self, N: int):
+        self.N = N
+        self.r, self.s, self.t = tet_nodes(N)
+        self.Np = len(self.r)
+        V, _ = tet_poly_basis(N, self.r, self.s, self.t)
+        self.Vinv = np.linalg.inv(V)
+
+    def eval(self, r, s, t):
+        P, G = tet_poly_basis(self.N, r, s, t)
+        return P @ self.Vinv, np.einsum("qmd,mj->qjd", G, self.Vinv)
+
+    def volume_quadrature(self, lumped: bool = False):
+        return tet_quadrature(self.N + 2)
+
+    def face_rules(self, lumped: bool = False):
+        """(xi (nq,3), w (nq,), dxi/da, dxi/db) for every face; the reference
+        triangle (a, b) maps through the face's vertices by barycentrics."""
+        ra, sa, wa = tri_quadrature(self.N + 2)
+        l1, l2, l3 = -(ra + sa) / 2, (1 + ra) / 2, (1 + sa) / 2
+        rules = []
+        for fv in self.face_verts:
+            P, Q, R = (self.ref_verts[v] for v in fv)
+            xi = l1[:, None] * P + l2[:, None] * Q + l3[:, None] * R
+            rules.append((xi, wa, (Q - P) / 2, (R - P) / 2))
+        return rules
+
+
+def _wedge_face_rules(self, lumped: bool = False):
+    """(xi (nq,3), w (nq,), dxi/da, dxi/db) for the five wedge faces.
+
+    Triangles: Duffy rule with N+2 points per direction at t = -1 / +1.
+    Quadrilaterals: Gauss (N+2) along the edge times Gauss (N+2) in t (GLL
+    N+1 in t when lumped); edge parameter u in [-1,1] from the edge's first
+    vertex to its second.
+    """
+    N = self.N
+    ra, sa, wa = tri_quadrature(N + 2)
+    xg, wg = gauss_nodes_weights(N + 2)
+    xt, wt = gll_nodes_weights(N) if lumped else (xg, wg)
+    U, T = np.meshgrid(xg, xt, indexing="ij")
+    WU, WT = np.meshgrid(wg, wt, indexing="ij")
+    u, t, wq = U.ravel(), T.ravel(), (WU * WT).ravel()
+    one = np.ones_like(ra)
+    return [
+        (np.stack([ra, sa, -one], 1), wa, np.array([1.0, 0, 0]), np.array([0, 1.0, 0])),
+        (np.stack([ra, sa, one], 1), wa, np.array([1.0, 0, 0]), np.array([0, 1.0, 0])),
+        (np.stack([u, -np.ones_like(u), t], 1), wq, np.array([1.0, 0, 0]), np.array([0, 0, 1.0])),
+        (np.stack([-u, u, t], 1), wq, np.array([-1.0, 1.0, 0]), np.array([0, 0, 1.0])),
+        (np.stack([-np.ones_like(u), -u, t], 1), wq, np.array([0, -1.0, 0]), np.array([0, 0, 1.0])),
+    ]
+
+
+Wedge.face_rules = _wedge_face_rules

@@ -22,6 +22,11 @@ through the general 3x3 Jacobian at each point; face integrals use
 quadrature on each face with the neighbour trace evaluated at the physical
 quadrature point through the neighbour's inverse map.  No node maps,
 orientation codes or Kronecker factorisations are used.
+
+Meshes mix wedges (elements 0..nw-1) and tetrahedra (nw..nw+nt-1), joined
+through triangular faces (Sec. 3.1).  Nodal arrays are (K, 4, Np) with Np
+the largest element size; a tetrahedron uses its first Np_tet entries and
+the rest stay zero (see ``node_mask``).
 """
 from __future__ import annotations
 
@@ -32,19 +37,15 @@ import numpy as np
 from . import basis as B
 from . import geometry as G
 
-# ---------------------------------------------------------------------------
-# Mesh description
-# ---------------------------------------------------------------------------
-
-# local faces of the wedge: vertex ids and reference parametrisation
-WEDGE_FACE_VERTS = [(0, 1, 2), (3, 4, 5), (0, 1, 4, 3), (1, 2, 5, 4), (2, 0, 3, 5)]
+NFACE = 5  # face slots per element (tetrahedra leave the last one empty)
 
 
 @dataclass
 class Mesh:
-    """Wedge mesh: vertices (nv,3), wedges (nw,6) with v1..v3 the bottom
-    triangle and v4..v6 above them, per-element wave speed c and density rho.
-    bc in {'dirichlet', 'rigid'}, flux in {'upwind', 'central'}."""
+    """Vertices (nv,3); wedges (nw,6) with v1..v3 the bottom triangle and
+    v4..v6 above them; tetrahedra (nt,4); per-element wave speed c and
+    density rho (wedges first).  bc in {'dirichlet','rigid'}, flux in
+    {'upwind','central'}."""
 
     verts: np.ndarray
     wedges: np.ndarray
@@ -52,71 +53,84 @@ class Mesh:
     rho: np.ndarray
     bc: str = "rigid"
     flux: str = "upwind"
+    tets: np.ndarray = None
+
+    @property
+    def nw(self) -> int:
+        return len(self.wedges)
+
+    @property
+    def nt(self) -> int:
+        return 0 if self.tets is None else len(self.tets)
 
     @property
     def K(self) -> int:
-        return len(self.wedges)
+        return self.nw + self.nt
+
+    def kinds(self) -> np.ndarray:
+        """0 for wedges, 1 for tetrahedra."""
+        return np.concatenate([np.zeros(self.nw, int), np.ones(self.nt, int)])
+
+
+def references(N: int, mesh: Mesh):
+    refs = [B.Wedge(N)]
+    if mesh is not None and mesh.nt:
+        refs.append(B.Tet(N))
+    return refs
+
+
+def node_mask(mesh: Mesh, N: int) -> np.ndarray:
+    """(K, Np) True on the nodes an element actually has."""
+    refs = references(N, mesh)
+    Np = max(r.Np for r in refs)
+    mask = np.zeros((mesh.K, Np), bool)
+    for kind, ref in enumerate(refs):
+        mask[mesh.kinds() == kind, :ref.Np] = True
+    return mask
+
+
+def _vertices(mesh: Mesh, kind: int, ids: np.ndarray) -> np.ndarray:
+    if kind == 0:
+        return mesh.verts[mesh.wedges[ids]]
+    return mesh.verts[mesh.tets[np.asarray(ids) - mesh.nw]]
 
 
 def face_connectivity(mesh: Mesh):
-    """Neighbour element and neighbour local face for every (element, face).
+    """Neighbour element and its local face for every (element, face slot).
 
-    Faces are matched by their sets of global vertex ids.  Returns
-    nbr (K, 5) int64 (-1 on the boundary) and nbr_face (K, 5).
+    Faces are matched by their sets of global vertex ids.  Returns nbr (K, 5)
+    (-1 on the boundary, -2 for the empty fifth slot of a tetrahedron) and
+    nbr_face (K, 5).
     """
     K = mesh.K
-    keys = np.full((K, 5, 4), -1, dtype=np.int64)
-    for f, fv in enumerate(WEDGE_FACE_VERTS):
-        ids = np.sort(mesh.wedges[:, list(fv)], axis=1)
-        keys[:, f, 4 - len(fv):] = ids
+    keys = np.full((K, NFACE, 4), -1, dtype=np.int64)
+    present = np.zeros((K, NFACE), bool)
+    kinds = mesh.kinds()
+    for kind, ref in enumerate([B.Wedge, B.Tet][: 2 if mesh.nt else 1]):
+        ids = np.nonzero(kinds == kind)[0]
+        conn = mesh.wedges if kind == 0 else mesh.tets
+        for f, fv in enumerate(ref.face_verts):
+            v = np.sort(conn[:, list(fv)], axis=1)
+            keys[ids, f, 4 - len(fv):] = v
+            present[ids, f] = True
     flat = keys.reshape(-1, 4)
-    order = np.lexsort(flat.T[::-1])
+    slot_ok = present.reshape(-1)
+    cand = np.nonzero(slot_ok)[0]
+    order = cand[np.lexsort(flat[cand].T[::-1])]
     sk = flat[order]
     same = np.all(sk[1:] == sk[:-1], axis=1)
-    nbr = np.full(K * 5, -1, dtype=np.int64)
-    a = order[:-1][same]
-    b = order[1:][same]
-    nbr[a] = b // 5
-    nbr[b] = a // 5
-    nbr_face = np.full(K * 5, -1, dtype=np.int64)
-    nbr_face[a] = b % 5
-    nbr_face[b] = a % 5
-    # a face shared by more than two elements is not a valid conforming mesh
     if np.any(same[1:] & same[:-1]):
         raise ValueError("face shared by more than two elements")
-    return nbr.reshape(K, 5), nbr_face.reshape(K, 5)
-
-
-# ---------------------------------------------------------------------------
-# Face quadrature on the reference wedge
-# ---------------------------------------------------------------------------
-
-
-def wedge_face_rules(N: int, lumped: bool = False):
-    """Reference face rules for the five wedge faces.
-
-    Returns a list of (xi (nq,3), w (nq,), dxi_da (3,), dxi_db (3,)): points
-    in volume reference coordinates, face weights, and the constant
-    derivatives of the face parametrisation.  Triangles use the Duffy rule
-    with N+2 points per direction; quads Gauss (N+2) along the edge times
-    Gauss (N+2) in t (GLL N+1 in t when lumped).
-    """
-    ra, sa, wa = B.tri_quadrature(N + 2)
-    xg, wg = B.gauss_nodes_weights(N + 2)
-    if lumped:
-        xt, wt = B.gll_nodes_weights(N)
-    else:
-        xt, wt = xg, wg
-    U, T = np.meshgrid(xg, xt, indexing="ij")
-    WU, WT = np.meshgrid(wg, wt, indexing="ij")
-    u, t, wq = U.ravel(), T.ravel(), (WU * WT).ravel()
-    rules = []
-    rules.append((np.stack([ra, sa, -np.ones_like(ra)], 1), wa, np.array([1.0, 0, 0]), np.array([0, 1.0, 0])))
-    rules.append((np.stack([ra, sa, np.ones_like(ra)], 1), wa, np.array([1.0, 0, 0]), np.array([0, 1.0, 0])))
-    rules.append((np.stack([u, -np.ones_like(u), t], 1), wq, np.array([1.0, 0, 0]), np.array([0, 0, 1.0])))
-    rules.append((np.stack([-u, u, t], 1), wq, np.array([-1.0, 1.0, 0]), np.array([0, 0, 1.0])))
-    rules.append((np.stack([-np.ones_like(u), -u, t], 1), wq, np.array([0, -1.0, 0]), np.array([0, 0, 1.0])))
-    return rules
+    nbr = np.full(K * NFACE, -1, dtype=np.int64)
+    nbr_face = np.full(K * NFACE, -1, dtype=np.int64)
+    a = order[:-1][same]
+    b = order[1:][same]
+    nbr[a] = b // NFACE
+    nbr[b] = a // NFACE
+    nbr_face[a] = b % NFACE
+    nbr_face[b] = a % NFACE
+    nbr[~slot_ok] = -2
+    return nbr.reshape(K, NFACE), nbr_face.reshape(K, NFACE)
 
 
 # ---------------------------------------------------------------------------
@@ -126,18 +140,20 @@ def wedge_face_rules(N: int, lumped: bool = False):
 
 @dataclass
 class Operators:
-    """Dense per-element operators for a subset ``elems`` of the mesh."""
+    """Dense per-element operators for a subset ``elems`` of the mesh.
+
+    Nodal dimension Np is the largest element size (zero padding)."""
 
     N: int
     elems: np.ndarray
-    M: np.ndarray          # (K, Np, Np)
-    Minv: np.ndarray       # (K, Np, Np)
+    M: np.ndarray          # (K, Np, Np), zero padding
+    Minv: np.ndarray       # (K, Np, Np), zero padding
     S: np.ndarray          # (3, K, Np, Np)  (S_d)_ij = int l_i d_d l_j
-    Pown: list             # per face (nq, Np)
-    wJ: list               # per face (K, nq)   weight * surface Jacobian
-    n: list                # per face (K, nq, 3) outward unit normal
-    nbr: np.ndarray        # (K, 5) global neighbour id, -1 on the boundary
-    Pnbr: list             # per face (K, nq, Np) neighbour basis at the points
+    Pown: list             # per face slot (K, nq, Np) own basis at the face points
+    wJ: list               # per face slot (K, nq) weight * surface Jacobian (0: no face)
+    n: list                # per face slot (K, nq, 3) outward unit normal
+    nbr: np.ndarray        # (K, 5) global neighbour id, -1 boundary, -2 no face
+    Pnbr: list             # per face slot (K, nq, Np) neighbour basis at the points
     tau_p: np.ndarray      # (K, 5)
     tau_u: np.ndarray      # (K, 5)
     kappa: np.ndarray      # (K,)
@@ -146,21 +162,14 @@ class Operators:
     extra: dict = field(default_factory=dict)
 
 
-def element_vertices(mesh: Mesh, elems: np.ndarray) -> np.ndarray:
-    return mesh.verts[mesh.wedges[elems]]
-
-
 def build_operators(mesh: Mesh, N: int, elems=None, lumped: bool = False, chunk: int = 256) -> Operators:
     """Build the dense operators of the elements ``elems`` (default: all)."""
-    K_all = mesh.K
-    elems = np.arange(K_all) if elems is None else np.asarray(elems, dtype=np.int64)
-    ref = B.Wedge(N)
-    Np = ref.Np
-    R, S_, T, W = ref.volume_quadrature(lumped)
-    xi_v = np.stack([R, S_, T], 1)
-    Bv, Bg = ref.eval(R, S_, T)
-    rules = wedge_face_rules(N, lumped)
-    Pown = [ref.eval(*rule[0].T)[0] for rule in rules]
+    elems = np.arange(mesh.K) if elems is None else np.asarray(elems, dtype=np.int64)
+    refs = references(N, mesh)
+    Np = max(r.Np for r in refs)
+    kinds_all = mesh.kinds()
+    rules = [r.face_rules(lumped) for r in refs]
+    nq = max(len(rule[1]) for rr in rules for rule in rr)
 
     nbr_all, _ = face_connectivity(mesh)
     kappa_all = mesh.rho * mesh.c ** 2
@@ -168,47 +177,63 @@ def build_operators(mesh: Mesh, N: int, elems=None, lumped: bool = False, chunk:
 
     K = len(elems)
     M = np.zeros((K, Np, Np))
+    Minv = np.zeros((K, Np, Np))
     Sd = np.zeros((3, K, Np, Np))
-    wJ = [np.zeros((K, len(r[1]))) for r in rules]
-    nn = [np.zeros((K, len(r[1]), 3)) for r in rules]
-    Pnbr = [np.zeros((K, len(r[1]), Np)) for r in rules]
-    for c0 in range(0, K, chunk):
-        ids = elems[c0:c0 + chunk]
-        sl = slice(c0, c0 + len(ids))
-        X = element_vertices(mesh, ids)
-        # volume: general Jacobian at every quadrature point
-        _, Jm = G.map_points("wedge", X, xi_v)
-        detJ = np.linalg.det(Jm)
-        if np.any(detJ <= 0):
-            raise ValueError("non-positive Jacobian")
-        Jinv = np.linalg.inv(Jm)  # Jinv[..., c, d] = d xi_c / d x_d
-        Gp = np.einsum("qjc,kqcd->kqjd", Bg, Jinv)
-        wdet = W[None, :] * detJ
-        M[sl] = np.einsum("kq,qi,qj->kij", wdet, Bv, Bv)
-        for d in range(3):
-            Sd[d, sl] = np.einsum("kq,qi,kqj->kij", wdet, Bv, Gp[..., d])
-        centroid = X.mean(axis=1)
-        for f, (xi_f, w_f, da, db) in enumerate(rules):
-            xq, Jf = G.map_points("wedge", X, xi_f)
-            t1 = np.einsum("kqdc,c->kqd", Jf, da)
-            t2 = np.einsum("kqdc,c->kqd", Jf, db)
-            cr = np.cross(t1, t2)
-            area = np.linalg.norm(cr, axis=-1)
-            nvec = cr / area[..., None]
-            sign = np.sign(np.einsum("kqd,kqd->k", xq - centroid[:, None, :], nvec))
-            nn[f][sl] = nvec * sign[:, None, None]
-            wJ[f][sl] = w_f[None, :] * area
-            nb = nbr_all[ids, f]
-            inner = np.nonzero(nb >= 0)[0]
-            if len(inner):
-                nq = len(w_f)
-                Xn = element_vertices(mesh, nb[inner])
-                Xrep = np.repeat(Xn, nq, axis=0)
-                xi_n = G.inverse_map("wedge", Xrep, xq[inner].reshape(-1, 3))
-                vals, _ = ref.eval(xi_n[:, 0], xi_n[:, 1], xi_n[:, 2])
-                Pnbr[f][c0 + inner] = vals.reshape(len(inner), nq, Np)
+    Pown = [np.zeros((K, nq, Np)) for _ in range(NFACE)]
+    wJ = [np.zeros((K, nq)) for _ in range(NFACE)]
+    nn = [np.zeros((K, nq, 3)) for _ in range(NFACE)]
+    Pnbr = [np.zeros((K, nq, Np)) for _ in range(NFACE)]
+    for kind, ref in enumerate(refs):
+        sel = np.nonzero(kinds_all[elems] == kind)[0]
+        if len(sel) == 0:
+            continue
+        n_k = ref.Np
+        R, S_, T, W = ref.volume_quadrature(lumped)
+        xi_v = np.stack([R, S_, T], 1)
+        Bv, Bg = ref.eval(R, S_, T)
+        own_face = [ref.eval(*rule[0].T)[0] for rule in rules[kind]]
+        for c0 in range(0, len(sel), chunk):
+            loc = sel[c0:c0 + chunk]
+            ids = elems[loc]
+            X = _vertices(mesh, kind, ids)
+            # volume: general Jacobian at every quadrature point
+            _, Jm = G.map_points(ref.kind, X, xi_v)
+            detJ = np.linalg.det(Jm)
+            if np.any(detJ <= 0):
+                raise ValueError("non-positive Jacobian")
+            Jinv = np.linalg.inv(Jm)  # Jinv[..., c, d] = d xi_c / d x_d
+            Gp = np.einsum("qjc,kqcd->kqjd", Bg, Jinv)
+            wdet = W[None, :] * detJ
+            Mk = np.einsum("kq,qi,qj->kij", wdet, Bv, Bv)
+            M[loc, :n_k, :n_k] = Mk
+            Minv[loc, :n_k, :n_k] = np.linalg.inv(Mk)
+            for d in range(3):
+                Sd[d, loc, :n_k, :n_k] = np.einsum("kq,qi,kqj->kij", wdet, Bv, Gp[..., d])
+            centroid = X.mean(axis=1)
+            for f, (xi_f, w_f, da, db) in enumerate(rules[kind]):
+                m_f = len(w_f)
+                Pown[f][loc, :m_f, :n_k] = own_face[f][None]
+                xq, Jf = G.map_points(ref.kind, X, xi_f)
+                t1 = np.einsum("kqdc,c->kqd", Jf, da)
+                t2 = np.einsum("kqdc,c->kqd", Jf, db)
+                cr = np.cross(t1, t2)
+                area = np.linalg.norm(cr, axis=-1)
+                nvec = cr / area[..., None]
+                sign = np.sign(np.einsum("kqd,kqd->k", xq - centroid[:, None, :], nvec))
+                nn[f][loc, :m_f] = nvec * sign[:, None, None]
+                wJ[f][loc, :m_f] = w_f[None, :] * area
+                nb = nbr_all[ids, f]
+                for nkind, nref in enumerate(refs):
+                    inner = np.nonzero((nb >= 0) & (kinds_all[np.maximum(nb, 0)] == nkind))[0]
+                    if len(inner) == 0:
+                        continue
+                    Xn = _vertices(mesh, nkind, nb[inner])
+                    Xrep = np.repeat(Xn, m_f, axis=0)
+                    xi_n = G.inverse_map(nref.kind, Xrep, xq[inner].reshape(-1, 3))
+                    vals, _ = nref.eval(xi_n[:, 0], xi_n[:, 1], xi_n[:, 2])
+                    Pnbr[f][loc[inner], :m_f, :nref.Np] = vals.reshape(len(inner), m_f, nref.Np)
     nbr = nbr_all[elems]
-    Zm = Z_all[elems][:, None] * np.ones((1, 5))
+    Zm = Z_all[elems][:, None] * np.ones((1, NFACE))
     Zp = np.where(nbr >= 0, Z_all[np.maximum(nbr, 0)], Zm)
     if mesh.flux == "upwind":
         tau_p = 2.0 / (Zm + Zp)
@@ -218,7 +243,6 @@ def build_operators(mesh: Mesh, N: int, elems=None, lumped: bool = False, chunk:
         tau_u = np.zeros_like(Zm)
     else:
         raise ValueError(mesh.flux)
-    Minv = np.linalg.inv(M)
     return Operators(N=N, elems=elems, M=M, Minv=Minv, S=Sd, Pown=Pown, wJ=wJ, n=nn, nbr=nbr,
                      Pnbr=Pnbr, tau_p=tau_p, tau_u=tau_u, kappa=kappa_all[elems], rho=mesh.rho[elems],
                      bc=mesh.bc)
@@ -236,8 +260,8 @@ def face_traces(ops: Operators, U: np.ndarray, f: int):
     """
     Uk = U[..., ops.elems, :, :]
     P = ops.Pown[f]
-    pm = np.einsum("qj,...kj->...kq", P, Uk[..., 0, :])
-    um = np.einsum("qj,...kdj->...kdq", P, Uk[..., 1:4, :])
+    pm = np.einsum("kqj,...kj->...kq", P, Uk[..., 0, :])
+    um = np.einsum("kqj,...kdj->...kdq", P, Uk[..., 1:4, :])
     nb = ops.nbr[:, f]
     Un = U[..., np.maximum(nb, 0), :, :]
     pp = np.einsum("kqj,...kj->...kq", ops.Pnbr[f], Un[..., 0, :])
@@ -266,7 +290,7 @@ def rhs(ops: Operators, U: np.ndarray) -> np.ndarray:
         vol[..., 0, :] -= np.einsum("kij,...kj->...ki", ops.S[d], Uk[..., d + 1, :])
         vol[..., d + 1, :] = -np.einsum("kij,...kj->...ki", ops.S[d], p)
     surf = np.zeros_like(Uk)
-    for f in range(5):
+    for f in range(NFACE):
         pm, um, pp, up = face_traces(ops, U, f)
         n = ops.n[f]
         jp = pp - pm
@@ -274,9 +298,9 @@ def rhs(ops: Operators, U: np.ndarray) -> np.ndarray:
         Fp = 0.5 * (ops.tau_p[:, f, None] * jp - jun)
         Fu = 0.5 * (ops.tau_u[:, f, None] * jun - jp)
         P = ops.Pown[f]
-        surf[..., 0, :] += np.einsum("qj,...kq->...kj", P, ops.wJ[f] * Fp)
+        surf[..., 0, :] += np.einsum("kqj,...kq->...kj", P, ops.wJ[f] * Fp)
         for d in range(3):
-            surf[..., d + 1, :] += np.einsum("qj,...kq->...kj", P, ops.wJ[f] * n[..., d] * Fu)
+            surf[..., d + 1, :] += np.einsum("kqj,...kq->...kj", P, ops.wJ[f] * n[..., d] * Fu)
     out = np.einsum("kij,...kfj->...kfi", ops.Minv, vol + surf)
     out[..., 0, :] *= ops.kappa[:, None]
     out[..., 1:, :] *= (1.0 / ops.rho)[:, None, None]
@@ -301,7 +325,7 @@ def energy_rate_from_jumps(ops: Operators, U: np.ndarray) -> float:
     Requires ops built for all elements.
     """
     total = 0.0
-    for f in range(5):
+    for f in range(NFACE):
         pm, um, pp, up = face_traces(ops, U, f)
         n = ops.n[f]
         jp = pp - pm
@@ -327,36 +351,59 @@ def energy_rate(ops: Operators, U: np.ndarray, dUdt: np.ndarray) -> float:
 
 
 def node_coords(mesh: Mesh, N: int) -> np.ndarray:
-    """Physical node coordinates (K, Np, 3)."""
-    ref = B.Wedge(N)
-    xi = np.stack([ref.r, ref.s, ref.t], 1)
-    x, _ = G.map_points("wedge", mesh.verts[mesh.wedges], xi)
-    return x
+    """Physical node coordinates (K, Np, 3); padding entries are zero."""
+    refs = references(N, mesh)
+    Np = max(r.Np for r in refs)
+    out = np.zeros((mesh.K, Np, 3))
+    kinds = mesh.kinds()
+    for kind, ref in enumerate(refs):
+        ids = np.nonzero(kinds == kind)[0]
+        if len(ids) == 0:
+            continue
+        xi = np.stack([ref.r, ref.s, ref.t], 1)
+        x, _ = G.map_points(ref.kind, _vertices(mesh, kind, ids), xi)
+        out[ids, :ref.Np] = x
+    return out
+
+
+def _inside(kind: int, xi: np.ndarray, tol: float) -> np.ndarray:
+    r, s, t = xi[:, 0], xi[:, 1], xi[:, 2]
+    if kind == 0:
+        return (r >= -1 - tol) & (s >= -1 - tol) & (r + s <= tol) & (np.abs(t) <= 1 + tol)
+    return (r >= -1 - tol) & (s >= -1 - tol) & (t >= -1 - tol) & (r + s + t <= -1 + tol)
 
 
 def locate(mesh: Mesh, x: np.ndarray, tol: float = 1e-12):
     """Lowest-index element containing point x and its reference coordinates."""
     x = np.asarray(x, float)
-    X = mesh.verts[mesh.wedges]
-    # only elements whose bounding box holds the point can contain it
-    pad = 1e-9 * (np.abs(X).max() + 1.0)
-    cand = np.nonzero(np.all((X.min(axis=1) - pad <= x) & (x <= X.max(axis=1) + pad), axis=1))[0]
-    if len(cand) == 0:
+    kinds = mesh.kinds()
+    best = None
+    for kind in range(2 if mesh.nt else 1):
+        ids = np.nonzero(kinds == kind)[0]
+        X = _vertices(mesh, kind, ids)
+        # only elements whose bounding box holds the point can contain it
+        pad = 1e-9 * (np.abs(X).max() + 1.0)
+        cand = np.nonzero(np.all((X.min(axis=1) - pad <= x) & (x <= X.max(axis=1) + pad), axis=1))[0]
+        if len(cand) == 0:
+            continue
+        xi = G.inverse_map(["wedge", "tet"][kind], X[cand], np.repeat(x[None, :], len(cand), axis=0))
+        hits = np.nonzero(_inside(kind, xi, tol))[0]
+        if len(hits) and (best is None or ids[cand[hits[0]]] < best[0]):
+            best = (int(ids[cand[hits[0]]]), xi[hits[0]])
+    if best is None:
         raise ValueError("point outside the mesh")
-    xi = G.inverse_map("wedge", X[cand], np.repeat(x[None, :], len(cand), axis=0))
-    r, s, t = xi[:, 0], xi[:, 1], xi[:, 2]
-    inside = (r >= -1 - tol) & (s >= -1 - tol) & (r + s <= tol) & (np.abs(t) <= 1 + tol)
-    hits = np.nonzero(inside)[0]
-    if len(hits) == 0:
-        raise ValueError("point outside the mesh")
-    return int(cand[hits[0]]), xi[hits[0]]
+    return best
 
 
-def point_basis(N: int, xi: np.ndarray) -> np.ndarray:
-    """Wedge Lagrange basis values at one reference point (Np,)."""
-    ref = B.Wedge(N)
+def point_basis(N: int, xi: np.ndarray, mesh: Mesh = None, elem: int = 0) -> np.ndarray:
+    """Lagrange basis of the element's kind at one reference point (Np_max,)."""
+    refs = references(N, mesh)
+    kind = 0 if mesh is None else int(mesh.kinds()[elem])
+    ref = refs[kind]
     v, _ = ref.eval(np.array([xi[0]]), np.array([xi[1]]), np.array([xi[2]]))
-    return v[0]
+    out = np.zeros(max(r.Np for r in refs))
+    out[:ref.Np] = v[0]
+    return out
 
 
 def ricker(t, f0: float, t0: float, amp: float = 1.0):
@@ -383,7 +430,7 @@ class PointSource:
 def make_point_source(mesh: Mesh, N: int, xs, f0: float, t0: float, amp: float = 1.0) -> PointSource:
     k, xi = locate(mesh, xs)
     ops = build_operators(mesh, N, elems=[k])
-    lvec = point_basis(N, xi)
+    lvec = point_basis(N, xi, mesh, k)
     vec = ops.kappa[0] * (ops.Minv[0] @ lvec)
     return PointSource(k, vec, f0, t0, amp)
 
@@ -394,7 +441,7 @@ def make_receivers(mesh: Mesh, N: int, xr: np.ndarray):
     for x in np.atleast_2d(xr):
         k, xi = locate(mesh, x)
         elems.append(k)
-        rows.append(point_basis(N, xi))
+        rows.append(point_basis(N, xi, mesh, k))
     return np.array(elems), np.array(rows)
 
 
@@ -408,23 +455,26 @@ def stable_dt(mesh: Mesh, N: int, cfl: float) -> float:
 
     The paper takes the step from trace and Markov inequality constants
     without printing the formula (Sec. 6); this reading uses the 3D trace
-    constant (N+1)(N+3)/3 and the face-to-volume Jacobian ratio.
-
-    J is the volume Jacobian (bi-unit reference), J_f the face Jacobian; both
-    are linear on vertically mapped wedges, so their extremes are taken over
-    the reference vertices.
+    constant (N+1)(N+3)/3 and the face-to-volume Jacobian ratio.  J and J_f
+    are linear on vertically mapped wedges (constant on tetrahedra), so their
+    extremes are taken over the reference vertices.
     """
-    X = mesh.verts[mesh.wedges]
-    vref = np.array([[-1, -1, -1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1], [1, -1, 1], [-1, 1, 1]], float)
-    _, Jm = G.map_points("wedge", X, vref)
-    Jmin = np.linalg.det(Jm).min(axis=1)
-    rules = wedge_face_rules(N)
-    Jfmax = np.zeros(mesh.K)
-    face_ref_verts = [vref[list(fv)] for fv in WEDGE_FACE_VERTS]
-    for f, (_, _, da, db) in enumerate(rules):
-        _, Jf = G.map_points("wedge", X, face_ref_verts[f])
-        t1 = np.einsum("kqdc,c->kqd", Jf, da)
-        t2 = np.einsum("kqdc,c->kqd", Jf, db)
-        Jfmax = np.maximum(Jfmax, np.linalg.norm(np.cross(t1, t2), axis=-1).max(axis=1))
-    rate = mesh.c * ((N + 1) * (N + 3) / 3.0) * Jfmax / Jmin
+    refs = references(N, mesh)
+    kinds = mesh.kinds()
+    ratio = np.zeros(mesh.K)
+    for kind, ref in enumerate(refs):
+        ids = np.nonzero(kinds == kind)[0]
+        if len(ids) == 0:
+            continue
+        X = _vertices(mesh, kind, ids)
+        _, Jm = G.map_points(ref.kind, X, ref.ref_verts)
+        Jmin = np.linalg.det(Jm).min(axis=1)
+        Jfmax = np.zeros(len(ids))
+        for f, (_, _, da, db) in enumerate(ref.face_rules()):
+            _, Jf = G.map_points(ref.kind, X, ref.ref_verts[list(ref.face_verts[f])])
+            t1 = np.einsum("kqdc,c->kqd", Jf, da)
+            t2 = np.einsum("kqdc,c->kqd", Jf, db)
+            Jfmax = np.maximum(Jfmax, np.linalg.norm(np.cross(t1, t2), axis=-1).max(axis=1))
+        ratio[ids] = Jfmax / Jmin
+    rate = mesh.c * ((N + 1) * (N + 3) / 3.0) * ratio
     return cfl / float(rate.max())

@@ -256,3 +256,54 @@ def standing_mode_rigid(x: np.ndarray, t: float):
     p = cx * cy * cz * np.cos(w * t)
     k = np.sin(w * t) / np.sqrt(3.0)
     return np.stack([p, sx * cy * cz * k, cx * sy * cz * k, cx * cy * sz * k], axis=-2)
+
+
+# ---------------------------------------------------------------------------
+# Hybrid wedge / tetrahedron meshes
+# ---------------------------------------------------------------------------
+
+
+def prism_to_tets(prism, verts):
+    """Split a prism (a, b, c bottom; d, e, f above them) into 3 tetrahedra.
+
+    Each quadrilateral face is cut along the diagonal through its lowest
+    global vertex id, so neighbouring split prisms share their diagonals
+    (the standard conforming rule for prisms).  The prism is first relabelled
+    so that its lowest vertex id is a; the diagonal of the face opposite a then
+    decides the split.  Tetrahedra are returned positively oriented.
+    """
+    a, b, c, d, e, f = (int(v) for v in prism)
+    # rotations (and the bottom/top flip) that keep the prism structure
+    labels = [(a, b, c, d, e, f), (b, c, a, e, f, d), (c, a, b, f, d, e),
+              (d, f, e, a, c, b), (e, d, f, b, a, c), (f, e, d, c, b, a)]
+    a, b, c, d, e, f = min(labels, key=lambda L: L[0])
+    if min(b, f) < min(c, e):
+        tets = [(a, b, c, f), (a, b, f, e), (a, e, f, d)]
+    else:
+        tets = [(a, b, c, e), (a, e, c, f), (a, e, f, d)]
+    out = []
+    for t in tets:
+        p = verts[list(t)]
+        vol = np.dot(np.cross(p[1] - p[0], p[2] - p[0]), p[3] - p[0])
+        out.append(t if vol > 0 else (t[0], t[2], t[1], t[3]))
+    return out
+
+
+def split_layers(mesh: WedgeMesh, tet_layers: int):
+    """Hybrid mesh: the wedges of the lowest ``tet_layers`` layers become 3
+    tetrahedra each; wedges and tetrahedra meet only across triangular faces.
+    Returns (verts, wedges, tets, c, rho) with material per element (wedges
+    first, then tetrahedra in the order of the split wedges)."""
+    lay = np.arange(mesh.K) % mesh.layers
+    split = lay < tet_layers
+    tets, tc, tr = [], [], []
+    for k in np.nonzero(split)[0]:
+        for t in prism_to_tets(mesh.wedges[k], mesh.verts):
+            tets.append(t)
+            tc.append(mesh.c[k])
+            tr.append(mesh.rho[k])
+    keep = ~split
+    wedges = mesh.wedges[keep]
+    c = np.concatenate([mesh.c[keep], np.array(tc)])
+    rho = np.concatenate([mesh.rho[keep], np.array(tr)])
+    return mesh.verts, wedges, np.array(tets, dtype=np.int64).reshape(-1, 4), c, rho

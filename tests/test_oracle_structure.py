@@ -121,7 +121,7 @@ def test_kronecker_mass_lift_and_derivatives(N):
         # triangular-face lifts: J_f L^{tri,k} (x) (M^1D)^-1 e
         Minv = ops.Minv[0]
         for f, j in ((0, 0), (1, N)):
-            Mf = ops.Pown[f].T @ (ops.wJ[f][0][:, None] * ops.Pown[f])
+            Mf = ops.Pown[f][0].T @ (ops.wJ[f][0][:, None] * ops.Pown[f][0])
             e = np.zeros(Nq)
             e[j] = 1.0
             Jf = ops.wJ[f][0].sum() / 2.0  # face area / reference area 2
@@ -132,7 +132,7 @@ def test_kronecker_mass_lift_and_derivatives(N):
         edges = {2: (0, 1), 3: (1, 2), 4: (2, 0)}
         vref = np.array([[-1, -1], [1, -1], [-1, 1]], float)
         for f, (a, b) in edges.items():
-            Mf = ops.Pown[f].T @ (ops.wJ[f][0][:, None] * ops.Pown[f])
+            Mf = ops.Pown[f][0].T @ (ops.wJ[f][0][:, None] * ops.Pown[f][0])
             ell = np.linalg.norm(X[b, :2] - X[a, :2])
             ha, hb = cf["h"][a], cf["h"][b]
             pts = vref[a][None, :] * (1 - xg[:, None]) / 2 + vref[b][None, :] * (1 + xg[:, None]) / 2
@@ -185,7 +185,7 @@ def test_lift_spy_pattern():
     Np_tri = (N + 1) * (N + 2) // 2
     j = np.arange(ops.M.shape[1]) // Np_tri
     for f in range(5):
-        Mf = ops.Pown[f].T @ (ops.wJ[f][0][:, None] * ops.Pown[f])
+        Mf = ops.Pown[f][0].T @ (ops.wJ[f][0][:, None] * ops.Pown[f][0])
         L = ops.Minv[0] @ Mf
         big = np.abs(L) > 1e-12 * np.abs(L).max()
         if f >= 2:
