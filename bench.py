@@ -78,6 +78,26 @@ def cpu_baseline(mesh, N: int, dt: float, seconds: float, sample: int):
     }
 
 
+def copy_bandwidth(nbytes: int = 512 << 20, reps: int = 10) -> float:
+    """Device-to-device copy of nbytes (read + write) timed with events."""
+    import torch
+
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) / 1e3 / reps
+    del x, y
+    return 2 * nbytes / sec / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +107,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="time a plain 512 MiB device copy first (HBM reference for counters and roofline)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -101,6 +123,10 @@ def main():
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
     from paper_1607_03399_amd import inputs
     from paper_1607_03399_amd import wdg
+
+    copy_gbs = None
+    if args.copy_calibration:
+        copy_gbs = copy_bandwidth()
 
     N, bits = 3, 32
     mesh = inputs.cfg2_mesh() if args.config == "cfg2" else inputs.cfg5_mesh()
@@ -167,6 +193,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
+            "measured_copy_GBs": copy_gbs,
         },
     }
     s.close()

@@ -147,11 +147,13 @@ int wdg_kernel_timing(wdg_ctx* ctx, int enable);
 int wdg_read_kernel_timing(wdg_ctx* ctx, double* total_ms, int64_t* launches);
 
 /* Test hook: per-element data built on the device by the FP64 setup kernel,
- * converted to double.  geo: nw x 32 values, slots
+ * converted to double.  geo: nw x 40 values, slots
  *   0 r_x, 1 r_y, 2 s_x, 3 s_y, 4 t_z J, 5 t_x J (t=-1), 6 t_x J (t=+1),
  *   7 t_y J (t=-1), 8 t_y J (t=+1), 9 kappa, 10 1/rho, 11 rho c,
  *   12..15 bottom face (J_f, n_x, n_y, n_z), 16..19 top face,
- *   20+4e..23+4e quad face on edge e (J_f at its first and second vertex, n_x, n_y)
+ *   20+4e..23+4e quad face on edge e (J_f at its first and second vertex, n_x, n_y),
+ *   32..36 rho c of the element plus rho c across each face (bottom, top, quads),
+ *   37..39 unused
  * (Lemma 1; face Jacobians and normals of Sec. 4.2).  lift: nw x Np_tri x
  * Np_tri, the triangular lift L^{tri,k} = (M^{tri,k})^-1 M^tri (Sec. 4.2),
  * row-major.  Either pointer may be NULL. */

@@ -30,7 +30,7 @@ def hipcc() -> str:
 
 
 def common_flags(opt: str = "-O3"):
-    return [opt, "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-I", os.path.join(ROOT, "include"),
+    return [opt, "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", BUILD,
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function"]
 
 
@@ -46,8 +46,23 @@ def _run(cmd, verbose):
         print(out)
 
 
+def generate_tables(verbose: bool = False) -> None:
+    """Compile and run gen_tables (host C++ only) to write ref_tables.inc, the
+    reference operators that the stage kernels compile in as literals."""
+    gen = os.path.join(BUILD, "gen_tables")
+    cxx = shutil.which("g++") or "g++"
+    _run([cxx, "-O2", "-std=c++17", os.path.join(CSRC, "gen_tables.cpp"), os.path.join(CSRC, "refops.cpp"),
+          "-I", CSRC, "-o", gen], verbose)
+    proc = subprocess.run([gen], stdout=subprocess.PIPE, text=True, check=True)
+    out = os.path.join(BUILD, "ref_tables.inc")
+    with open(out + ".tmp", "w") as fh:
+        fh.write(proc.stdout)
+    os.replace(out + ".tmp", out)
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    generate_tables(verbose)
     cc = hipcc()
     jobs = []
     objs = []

@@ -216,11 +216,11 @@ void to_interleaved(const wdg_ctx* ctx, const double* p, const double* ux, const
   const int64_t n = ctx->K * ctx->NP();
   buf.resize(size_t(n) * 4 * sizeof(T));
   T* o = reinterpret_cast<T*>(buf.data());
-  for (int64_t m = 0; m < n; ++m) {
+  for (int64_t m = 0; m < n; ++m) {  // device node layout: (p, u_z, u_x, u_y)
     o[4 * m] = T(p[m]);
-    o[4 * m + 1] = T(ux[m]);
-    o[4 * m + 2] = T(uy[m]);
-    o[4 * m + 3] = T(uz[m]);
+    o[4 * m + 1] = T(uz[m]);
+    o[4 * m + 2] = T(ux[m]);
+    o[4 * m + 3] = T(uy[m]);
   }
 }
 
@@ -231,9 +231,9 @@ void from_interleaved(const wdg_ctx* ctx, const std::vector<unsigned char>& buf,
   const T* o = reinterpret_cast<const T*>(buf.data());
   for (int64_t m = 0; m < n; ++m) {
     if (p) p[m] = double(o[4 * m]);
-    if (ux) ux[m] = double(o[4 * m + 1]);
-    if (uy) uy[m] = double(o[4 * m + 2]);
-    if (uz) uz[m] = double(o[4 * m + 3]);
+    if (uz) uz[m] = double(o[4 * m + 1]);
+    if (ux) ux[m] = double(o[4 * m + 2]);
+    if (uy) uy[m] = double(o[4 * m + 3]);
   }
 }
 
@@ -502,7 +502,7 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
   HIPCHK(hipMalloc(&ctx->dL, size_t(K) * LS * ts));
   HIPCHK(hipMalloc(&ctx->dAux, size_t(K) * wdg::kAuxStride * sizeof(double)));
   HIPCHK(hipMalloc(&ctx->dConn, size_t(K) * wdg::kConnStride * sizeof(int32_t)));
-  HIPCHK(hipMalloc(&ctx->dOps, wdg::ops_bytes(ctx->N, ctx->bits)));
+  HIPCHK(hipMalloc(&ctx->dOps, wdg::ops_bytes(ctx->N)));
   HIPCHK(hipMalloc(&ctx->dMv, 3 * size_t(R.NT) * R.NT * sizeof(double)));
   HIPCHK(hipMalloc(&ctx->dM1, size_t(R.Nq) * R.Nq * sizeof(double)));
   HIPCHK(hipMalloc(&ctx->dPartial, 1024 * sizeof(double)));
@@ -512,11 +512,8 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
   HIPCHK(hipMemsetAsync(ctx->dRes, 0, nstate, ctx->stream));
   HIPCHK(hipMemsetAsync(ctx->dSrcVec, 0, size_t(wdg::kMaxSources) * R.NP * ts, ctx->stream));
 
-  std::vector<unsigned char> ops(wdg::ops_bytes(ctx->N, ctx->bits));
-  const double* Ea[3] = {R.Ea[0].data(), R.Ea[1].data(), R.Ea[2].data()};
-  const double* Eb[3] = {R.Eb[0].data(), R.Eb[1].data(), R.Eb[2].data()};
-  wdg::fill_ops(ctx->N, ctx->bits, ops.data(), R.Dr.data(), R.Ds.data(), Ea, Eb, R.Dt.data(), R.g0.data(),
-                R.gN.data(), R.t.data(), R.perm.data());
+  std::vector<unsigned char> ops(wdg::ops_bytes(ctx->N));
+  wdg::fill_ops(ctx->N, ops.data(), R.perm.data());
   std::vector<double> Mv(3 * size_t(R.NT) * R.NT);
   for (int v = 0; v < 3; ++v) std::copy(R.Mv[v].begin(), R.Mv[v].end(), Mv.begin() + v * R.NT * R.NT);
   double *dX = nullptr, *dMtri = nullptr;
@@ -558,7 +555,7 @@ int wdg_set_material(wdg_ctx* ctx, const double* c, const double* rho) {
     HIPCHK(hipMalloc(&dr, ctx->K * sizeof(double)));
     HIPCHK(hipMemcpyAsync(dc, c, ctx->K * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(dr, rho, ctx->K * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(wdg::launch_material(ctx->bits, ctx->K, dc, dr, ctx->dGeo, ctx->dAux, ctx->stream));
+    HIPCHK(wdg::launch_material(ctx->bits, ctx->K, dc, dr, ctx->dConn, ctx->dGeo, ctx->dAux, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     HIPCHK(hipFree(dc));
     HIPCHK(hipFree(dr));

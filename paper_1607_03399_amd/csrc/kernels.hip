@@ -11,6 +11,7 @@
 #include <cstring>
 
 #include "kernels.hpp"
+#include "ref_tables.inc"
 
 namespace wdg {
 namespace {
@@ -30,57 +31,100 @@ __host__ __device__ constexpr int edge_node(int N, int e, int q) {
   return e == 0 ? tri_idx(N, q, 0) : (e == 1 ? tri_idx(N, N - q, q) : tri_idx(N, 0, N - q));
 }
 
-template <int N, typename T>
-struct Ops {
-  static constexpr int NT = Dim<N>::NT, Nq = Dim<N>::Nq;
-  T Dr[NT * NT];
-  T Ds[NT * NT];
-  T Ea[3][NT * Nq];
-  T Eb[3][NT * Nq];
-  T Dt[Nq * Nq];
-  T g0[Nq];
-  T gN[Nq];
-  T tlo[Nq];  // (1 - t_j) / 2
-  T thi[Nq];  // (1 + t_j) / 2
-  int perm[6 * NT];
+// Vertex permutations of the triangle nodes across a shared triangular face
+// (6 permutations x NT nodes), the only operator data the stage kernel loads.
+template <int N>
+struct FacePerm {
+  int perm[6 * Dim<N>::NT];
 };
 
+// Node-interleaved state: one 4-vector per node in the order (p, u_z, u_x, u_y),
+// so that each of the two lane roles below owns one contiguous half.
 template <typename T>
 struct alignas(4 * sizeof(T)) V4 {
-  T x, y, z, w;
+  T p, uz, ux, uy;
+};
+template <typename T>
+struct alignas(2 * sizeof(T)) V2 {
+  T a, b;
 };
 
-// Block size: 256 threads unless the staged state would exceed 64 KiB of LDS.
+// Launch shape.  A wavefront holds EPW elements x Nq levels; a block has 4
+// wavefronts (2 if the staged state would not fit in 48 KiB of LDS): the first
+// half computes the (p, u_z) equations of its elements, the second half the
+// (u_x, u_y) equations of the same elements.
+#ifndef WDG_STAGE_WAVES
+#define WDG_STAGE_WAVES 4
+#endif
 template <int N, typename T>
 struct Cfg {
   static constexpr int NT = Dim<N>::NT, Nq = Dim<N>::Nq, NP = Dim<N>::NP;
-  static constexpr int lds(int bs) {
-    return (bs / Nq) * NP * 4 * int(sizeof(T)) + (bs / Nq) * 2 * NT * 2 * int(sizeof(T));
-  }
-  static constexpr int BS = lds(256) <= 65536 ? 256 : (lds(128) <= 65536 ? 128 : 64);
-  static constexpr int EPB = BS / Nq;
+  // LDS bytes of one element: staged state, fluxes, lift, geometry, connectivity
+  static constexpr int per_elem =
+      (NP * 4 + 2 * NT * 2 + Dim<N>::LS + kGeoStride) * int(sizeof(T)) + kConnStride * 4;
+  static constexpr int EPW_FULL = 64 / Nq;
+  static constexpr int WAVES = (WDG_STAGE_WAVES == 4 && EPW_FULL * 2 * per_elem <= 49152) ? 4 : 2;
+  // with two wavefronts, shrink the wavefront's element count until LDS fits 60 KiB
+  static constexpr int EPW = (WAVES == 4 || EPW_FULL * per_elem <= 61440) ? EPW_FULL : 61440 / per_elem;
+  static constexpr int BS = 64 * WAVES;
+  static constexpr int EPB = EPW * (WAVES / 2);
 };
+
+// acc1 += c x1; acc2 += c x2 for a reference-operator entry c known at
+// compile time; exact zeros of the operator cost nothing
+template <typename T>
+__device__ __forceinline__ void constexpr_or_skip(double c, T& acc1, T x1, T& acc2, T x2) {
+  if (c != 0.0) {
+    acc1 += T(c) * x1;
+    acc2 += T(c) * x2;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void constexpr_or_skip(double c, T& acc, T x) {
+  if (c != 0.0) acc += T(c) * x;
+}
+
+// entry of a reference table selected by the lane's level j (j < Nq)
+template <int Nq, typename T>
+__device__ __forceinline__ T pick(const double* tab, int j, int stride, int col) {
+  T v = T(tab[col]);
+#pragma unroll
+  for (int jj = 1; jj < Nq; ++jj) v = (j == jj) ? T(tab[jj * stride + col]) : v;
+  return v;
+}
 
 // ---------------------------------------------------------------------------
 // Fused stage kernel
 //
-// Lane (element, level j) owns the triangular slice j of its element: the
-// reference triangle operators are then the same for every lane (scalar
-// operands), and only the vertical derivative and the triangle-face lift
-// couple lanes of one element, through LDS.
+// Lane (element, level j, role) owns the triangular slice j of its element for
+// two of the four equations: role 0 the pressure and u_z equations, role 1
+// the u_x and u_y equations (role is uniform per wavefront).  The reference
+// triangle and 1D operators are compile-time constants (instruction
+// literals).  The element's state is staged in LDS: the vertical derivative
+// and the triangle-face lifts couple the levels of one element through it.
+//   phase 1: B = -W (vertical part of D_x, D_y, D_z, before L^{tri,k}) plus the
+//            quadrilateral-face lifts of this level; triangular-face fluxes
+//   phase 2: B += triangular-face lifts; R = L^{tri,k} B + H (horizontal part);
+//            scale by kappa, 1/rho; sources; low-storage Runge-Kutta update
 // ---------------------------------------------------------------------------
+#ifndef WDG_STAGE_WAVES_PER_EU
+#define WDG_STAGE_WAVES_PER_EU 1
+#endif
 template <int N, typename T>
-__global__ void __launch_bounds__((Cfg<N, T>::BS)) wedge_stage(StageLaunch A) {
+__global__ void __launch_bounds__((Cfg<N, T>::BS), WDG_STAGE_WAVES_PER_EU) wedge_stage(StageLaunch A) {
   using C = Cfg<N, T>;
-  constexpr int NT = C::NT, Nq = C::Nq, NP = C::NP, EPB = C::EPB, BS = C::BS;
+  using RT = gen::RefTables<N>;
+  constexpr int NT = C::NT, Nq = C::Nq, NP = C::NP, EPW = C::EPW, EPB = C::EPB, BS = C::BS;
+  constexpr int HALF = C::WAVES / 2;
   constexpr int LS = Dim<N>::LS;
   __shared__ V4<T> sU[EPB * NP];
+  __shared__ V4<T> sL[EPB * LS / 4];
+  __shared__ V4<T> sG[EPB * kGeoStride / 4];
+  __shared__ int4 sC[EPB * kConnStride / 4];
   __shared__ T sF[EPB * 2 * NT * 2];
 
-  const Ops<N, T>* __restrict__ op = static_cast<const Ops<N, T>*>(A.ops);
+  const FacePerm<N>* __restrict__ fp = static_cast<const FacePerm<N>*>(A.ops);
   const V4<T>* __restrict__ Uin = static_cast<const V4<T>*>(A.Uin);
-  V4<T>* __restrict__ Uout = static_cast<V4<T>*>(A.Uout);
-  V4<T>* __restrict__ res = static_cast<V4<T>*>(A.res);
   const T* __restrict__ geo = static_cast<const T*>(A.geo);
   const T* __restrict__ Lm = static_cast<const T*>(A.L);
   const int* __restrict__ conn = A.conn;
@@ -95,268 +139,320 @@ __global__ void __launch_bounds__((Cfg<N, T>::BS)) wedge_stage(StageLaunch A) {
   const int nE = left < EPB ? int(left) : EPB;
   const int tid = threadIdx.x;
 
+  // stage the chunk's state, triangular lifts, geometry and connectivity in
+  // LDS with coalesced 16-byte loads; lanes then read them by broadcast
   {
     const V4<T>* src = Uin + e0 * NP;
     for (int idx = tid; idx < nE * NP; idx += BS) sU[idx] = src[idx];
+    const V4<T>* Ls = reinterpret_cast<const V4<T>*>(Lm + e0 * LS);
+    for (int idx = tid; idx < nE * (LS / 4); idx += BS) sL[idx] = Ls[idx];
+    const V4<T>* Gs = reinterpret_cast<const V4<T>*>(geo + e0 * kGeoStride);
+    for (int idx = tid; idx < nE * (kGeoStride / 4); idx += BS) sG[idx] = Gs[idx];
+    const int4* Cs = reinterpret_cast<const int4*>(conn + e0 * kConnStride);
+    for (int idx = tid; idx < nE * (kConnStride / 4); idx += BS) sC[idx] = Cs[idx];
   }
   __syncthreads();
 
-  const int le = tid / Nq;
-  const int j = tid - le * Nq;
-  const bool active = le < nE;
+  const int wv = tid >> 6, ln = tid & 63;
+  const int role = wv / HALF;  // uniform per wavefront
+  const int le = (wv % HALF) * EPW + ln / Nq;
+  const int j = ln % Nq;
+  const bool active = ln < EPW * Nq && le < nE;
   const int64_t e = e0 + le;
-  const bool dirichlet = (A.flags & kDirichlet) != 0;
-  const bool central = (A.flags & kCentral) != 0;
+  const T bsign = (A.flags & kDirichlet) ? T(-1) : T(1);
+  const T tau_on = (A.flags & kCentral) ? T(0) : T(1);
+  const V4<T>* el = sU + le * NP;
 
-  T Bp[NT], Bx[NT], By[NT], Bz[NT];
+  // role 0: (B0, B1) = (p, u_z) equations; role 1: (u_x, u_y)
+  T B0[NT], B1[NT];
 
+  const T* g = reinterpret_cast<const T*>(sG) + le * kGeoStride;
   if (active) {
-    const T* g = geo + e * kGeoStride;
     const T tzJ = g[4];
-    const T tlo = op->tlo[j], thi = op->thi[j];
-    const T txJ = g[5] * tlo + g[6] * thi;
-    const T tyJ = g[7] * tlo + g[8] * thi;
-    const T Zm = g[11];
-    const V4<T>* el = sU + le * NP;
+    const T tl = T(0.5) * (T(1) - pick<Nq, T>(RT::t, j, 1, 0));
+    const T th = T(0.5) * (T(1) + pick<Nq, T>(RT::t, j, 1, 0));
+    const T txJ = g[5] * tl + g[6] * th;
+    const T tyJ = g[7] * tl + g[8] * th;
+    T dtr[Nq];
+#pragma unroll
+    for (int m = 0; m < Nq; ++m) dtr[m] = pick<Nq, T>(RT::Dt, j, Nq, m);
 
-    T p[NT], ux[NT], uy[NT], uz[NT];
+    // vertical part: W = t_dJ(t_j) (D_t U)(level j)
+    if (role == 0) {
 #pragma unroll
-    for (int i = 0; i < NT; ++i) {
-      V4<T> v = el[j * NT + i];
-      p[i] = v.x;
-      ux[i] = v.y;
-      uy[i] = v.z;
-      uz[i] = v.w;
-    }
-
-    // vertical part of D_x, D_y, D_z (before L^{tri,k}): W = t_dJ(t_j) D_t U
-    T dtrow[Nq];
+      for (int i = 0; i < NT; ++i) {
+        T dP = 0, dX = 0, dY = 0, dZ = 0;
 #pragma unroll
-    for (int m = 0; m < Nq; ++m) dtrow[m] = op->Dt[j * Nq + m];
-#pragma unroll
-    for (int i = 0; i < NT; ++i) {
-      T dP = 0, dX = 0, dY = 0, dZ = 0;
-#pragma unroll
-      for (int m = 0; m < Nq; ++m) {
-        V4<T> v = el[m * NT + i];
-        dP += dtrow[m] * v.x;
-        dX += dtrow[m] * v.y;
-        dY += dtrow[m] * v.z;
-        dZ += dtrow[m] * v.w;
+        for (int m = 0; m < Nq; ++m) {
+          const V4<T> v = el[m * NT + i];
+          dP += dtr[m] * v.p;
+          dX += dtr[m] * v.ux;
+          dY += dtr[m] * v.uy;
+          dZ += dtr[m] * v.uz;
+        }
+        T w = txJ * dX;
+        w += tyJ * dY;
+        w += tzJ * dZ;
+        B0[i] = -w;
+        B1[i] = -(tzJ * dP);
       }
-      Bp[i] = -(txJ * dX + tyJ * dY + tzJ * dZ);
-      Bx[i] = -txJ * dP;
-      By[i] = -tyJ * dP;
-      Bz[i] = -tzJ * dP;
+    } else {
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        T dP = 0;
+#pragma unroll
+        for (int m = 0; m < Nq; ++m) dP += dtr[m] * el[m * NT + i].p;
+        B0[i] = -(txJ * dP);
+        B1[i] = -(tyJ * dP);
+      }
     }
 
-    const int* cn = conn + e * kConnStride;
+    const int* cn = reinterpret_cast<const int*>(sC) + le * kConnStride;
     const int code = cn[5];
 
-    // quadrilateral faces: nodes of edge e on this lane's level j
+    // quadrilateral faces (normals horizontal, so they reach p, u_x, u_y only).
+    // Boundary faces read the own element (a valid address) and blend in the
+    // mirror state arithmetically, without branches.
 #pragma unroll
     for (int ed = 0; ed < 3; ++ed) {
       const int nbr = cn[2 + ed];
+      const T w_in = nbr >= 0 ? T(1) : T(0);
       const int ned = (code >> (8 + 2 * ed)) & 3;
       const T Ja = g[20 + 4 * ed], Jb = g[21 + 4 * ed];
       const T nx = g[22 + 4 * ed], ny = g[23 + 4 * ed];
-      const T Zp = nbr >= 0 ? geo[int64_t(nbr) * kGeoStride + 11] : Zm;
-      const T taup = central ? T(0) : T(2) / (Zm + Zp);
-      const T tauu = central ? T(0) : (Zm + Zp) * T(0.5);
-      const V4<T>* nb_el = Uin + int64_t(nbr >= 0 ? nbr : 0) * NP + j * NT;
-      T fap[Nq], fbp[Nq], fau[Nq], fbu[Nq];
+      const int64_t src_el = nbr >= 0 ? int64_t(nbr) : e;
+      const T zs = g[34 + ed];  // Z- + Z+ (= 2 Z- on the boundary)
+      const T taup = tau_on * T(2) / zs;
+      const T tauu = tau_on * zs * T(0.5);
+      const V4<T>* nb_el = Uin + src_el * NP + j * NT;
+      T fa[Nq], fb[Nq];
 #pragma unroll
       for (int q = 0; q < Nq; ++q) {
-        const int i = edge_node(N, ed, q);
-        const T pm = p[i];
-        const T unm = nx * ux[i] + ny * uy[i];
-        T pp, unp;
-        if (nbr >= 0) {
-          const int ni = ned == 0 ? edge_node(N, 0, N - q) : (ned == 1 ? edge_node(N, 1, N - q) : edge_node(N, 2, N - q));
-          const V4<T> v = nb_el[ni];
-          pp = v.x;
-          unp = nx * v.y + ny * v.z;
-        } else if (dirichlet) {
-          pp = -pm;
-          unp = unm;
-        } else {
-          pp = pm;
-          unp = -unm;
-        }
+        const V4<T> own = el[j * NT + edge_node(N, ed, q)];
+        const int ni = ned == 0 ? edge_node(N, 0, N - q) : (ned == 1 ? edge_node(N, 1, N - q) : edge_node(N, 2, N - q));
+        const V4<T> v = nb_el[ni];
+        const T pm = own.p;
+        const T unm = nx * own.ux + ny * own.uy;
+        // mirror state: p+ = s p-, u_n+ = -s u_n- (s = -1 Dirichlet, +1 rigid)
+        const T pb = bsign * pm, ub = -bsign * unm;
+        const T pp = pb + w_in * (v.p - pb);
+        const T unp = ub + w_in * ((nx * v.ux + ny * v.uy) - ub);
         const T jp = pp - pm, jun = unp - unm;
-        const T Fp = T(0.5) * (taup * jp - jun);
-        const T Fu = T(0.5) * (tauu * jun - jp);
-        fap[q] = Ja * Fp;
-        fbp[q] = Jb * Fp;
-        fau[q] = Ja * Fu;
-        fbu[q] = Jb * Fu;
+        const T F = role == 0 ? T(0.5) * (taup * jp - jun) : T(0.5) * (tauu * jun - jp);
+        fa[q] = Ja * F;
+        fb[q] = Jb * F;
       }
+      if (role == 0) {
 #pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        T sp = 0, su = 0;
+        for (int i = 0; i < NT; ++i) {
+          T sp = 0;
 #pragma unroll
-        for (int q = 0; q < Nq; ++q) {
-          const T ea = op->Ea[ed][i * Nq + q], eb = op->Eb[ed][i * Nq + q];
-          sp += ea * fap[q] + eb * fbp[q];
-          su += ea * fau[q] + eb * fbu[q];
+          for (int q = 0; q < Nq; ++q) {
+            constexpr_or_skip(RT::Ea[(ed * NT + i) * Nq + q], sp, fa[q]);
+            constexpr_or_skip(RT::Eb[(ed * NT + i) * Nq + q], sp, fb[q]);
+          }
+          B0[i] += sp;
         }
-        Bp[i] += sp;
-        Bx[i] += nx * su;
-        By[i] += ny * su;
+      } else {
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+          T su = 0;
+#pragma unroll
+          for (int q = 0; q < Nq; ++q) {
+            constexpr_or_skip(RT::Ea[(ed * NT + i) * Nq + q], su, fa[q]);
+            constexpr_or_skip(RT::Eb[(ed * NT + i) * Nq + q], su, fb[q]);
+          }
+          B0[i] += nx * su;
+          B1[i] += ny * su;
+        }
       }
     }
 
-    // triangular faces: the bottom level computes the bottom face, the top level the top face
-    if (j == 0 || j == N) {
-      const int face = j == 0 ? 0 : 1;
+    // triangular faces: their 2 NT nodes are shared out over the 2 Nq lanes of
+    // the element; fluxes (premultiplied by J_f) go to LDS for every level
+    constexpr int per = (NT + Nq - 1) / Nq;
+    const int slot = role * Nq + j;
+#pragma unroll
+    for (int t = 0; t < per; ++t) {
+      const int fraw = slot * per + t;
+      const int fnode = fraw < 2 * NT ? fraw : 2 * NT - 1;  // surplus slots redo the last node
+      const int face = fnode >= NT ? 1 : 0;
+      const int i = fnode - face * NT;
       const int nbr = cn[face];
+      const T w_in = nbr >= 0 ? T(1) : T(0);
       const int pc = (code >> (3 * face)) & 7;
       const int nlev = ((code >> (6 + face)) & 1) ? N : 0;
-      const T Jf = g[12 + 4 * face];
-      const T nx = g[13 + 4 * face], ny = g[14 + 4 * face], nz = g[15 + 4 * face];
-      const T Zp = nbr >= 0 ? geo[int64_t(nbr) * kGeoStride + 11] : Zm;
-      const T taup = central ? T(0) : T(2) / (Zm + Zp);
-      const T tauu = central ? T(0) : (Zm + Zp) * T(0.5);
-      const V4<T>* nb_el = Uin + int64_t(nbr >= 0 ? nbr : 0) * NP + nlev * NT;
-      T* f = sF + (le * 2 + face) * NT * 2;
-#pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        const T pm = p[i];
-        const T unm = nx * ux[i] + ny * uy[i] + nz * uz[i];
-        T pp, unp;
-        if (nbr >= 0) {
-          const V4<T> v = nb_el[op->perm[pc * NT + i]];
-          pp = v.x;
-          unp = nx * v.y + ny * v.z + nz * v.w;
-        } else if (dirichlet) {
-          pp = -pm;
-          unp = unm;
-        } else {
-          pp = pm;
-          unp = -unm;
-        }
-        const T jp = pp - pm, jun = unp - unm;
-        f[2 * i] = Jf * T(0.5) * (taup * jp - jun);
-        f[2 * i + 1] = Jf * T(0.5) * (tauu * jun - jp);
+      const T* gf = g + 12 + 4 * face;
+      const T Jf = gf[0], nx = gf[1], ny = gf[2], nz = gf[3];
+      const int64_t src_el = nbr >= 0 ? int64_t(nbr) : e;
+      const T zs = g[32 + face];
+      const T taup = tau_on * T(2) / zs;
+      const T tauu = tau_on * zs * T(0.5);
+      const V4<T> own = el[face * N * NT + i];
+      const V4<T> v = Uin[src_el * NP + nlev * NT + fp->perm[pc * NT + i]];
+      const T pm = own.p;
+      const T unm = nx * own.ux + ny * own.uy + nz * own.uz;
+      const T pb = bsign * pm, ub = -bsign * unm;
+      const T pp = pb + w_in * (v.p - pb);
+      const T unp = ub + w_in * ((nx * v.ux + ny * v.uy + nz * v.uz) - ub);
+      const T jp = pp - pm, jun = unp - unm;
+      if (fraw < 2 * NT) {
+        T* f = sF + ((le * 2 + face) * NT + i) * 2;
+        f[0] = Jf * T(0.5) * (taup * jp - jun);
+        f[1] = Jf * T(0.5) * (tauu * jun - jp);
       }
     }
   }
   __syncthreads();
   if (!active) return;
 
-  const T* g = geo + e * kGeoStride;
-  const V4<T>* el = sU + le * NP;
+  const bool rd = (A.flags & kReadRes) != 0, wu = (A.flags & kWriteU) != 0;
+  // residual of the previous stage (this role's two fields): load now, use at the end
+  V2<T>* rr = reinterpret_cast<V2<T>*>(static_cast<V4<T>*>(A.res) + e * NP + j * NT) + role;
+  V2<T> rprev[NT];
+  if (rd) {
+#pragma unroll
+    for (int i = 0; i < NT; ++i) rprev[i] = rr[2 * i];
+  }
+
   // triangular-face lifts: flux spread over all levels by (M^1D)^-1 e_{0,N}
   {
-    const T g0j = op->g0[j], gNj = op->gN[j];
-    const T bx = g[13], by = g[14], bz = g[15], tx = g[17], ty = g[18], tz = g[19];
-    const T* fb = sF + (le * 2 + 0) * NT * 2;
-    const T* ft = sF + (le * 2 + 1) * NT * 2;
+    const T g0j = pick<Nq, T>(RT::g0, j, 1, 0), gNj = pick<Nq, T>(RT::gN, j, 1, 0);
+    const T* fbt = sF + (le * 2 + 0) * NT * 2;
+    const T* ftp = sF + (le * 2 + 1) * NT * 2;
+    if (role == 0) {
+      const T bz = g[15], tz = g[19];
 #pragma unroll
-    for (int i = 0; i < NT; ++i) {
-      Bp[i] += g0j * fb[2 * i] + gNj * ft[2 * i];
-      const T wb = g0j * fb[2 * i + 1], wt = gNj * ft[2 * i + 1];
-      Bx[i] += wb * bx + wt * tx;
-      By[i] += wb * by + wt * ty;
-      Bz[i] += wb * bz + wt * tz;
-    }
-  }
-
-  // horizontal part: (r_x D_r + s_x D_s) etc. on the own slice
-  T Rp[NT], Rx[NT], Ry[NT], Rz[NT];
-  {
-    const T rx = g[0], ry = g[1], sx = g[2], sy = g[3];
-    T P[NT], Ar[NT], As[NT];
-#pragma unroll
-    for (int m = 0; m < NT; ++m) {
-      const V4<T> v = el[j * NT + m];
-      P[m] = v.x;
-      Ar[m] = rx * v.y + ry * v.z;
-      As[m] = sx * v.y + sy * v.z;
-    }
-#pragma unroll
-    for (int i = 0; i < NT; ++i) {
-      T dA = 0, dPr = 0, dPs = 0;
-#pragma unroll
-      for (int m = 0; m < NT; ++m) {
-        const T dr = op->Dr[i * NT + m], ds = op->Ds[i * NT + m];
-        dA += dr * Ar[m] + ds * As[m];
-        dPr += dr * P[m];
-        dPs += ds * P[m];
+      for (int i = 0; i < NT; ++i) {
+        B0[i] += g0j * fbt[2 * i];
+        B0[i] += gNj * ftp[2 * i];
+        B1[i] += (g0j * fbt[2 * i + 1]) * bz;
+        B1[i] += (gNj * ftp[2 * i + 1]) * tz;
       }
-      Rp[i] = -dA;
-      Rx[i] = -(rx * dPr + sx * dPs);
-      Ry[i] = -(ry * dPr + sy * dPs);
-      Rz[i] = 0;
+    } else {
+      const T bx = g[13], by = g[14], tx = g[17], ty = g[18];
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        const T wb = g0j * fbt[2 * i + 1], wt = gNj * ftp[2 * i + 1];
+        B0[i] += wb * bx;
+        B0[i] += wt * tx;
+        B1[i] += wb * by;
+        B1[i] += wt * ty;
+      }
     }
   }
 
-  // triangular lift L^{tri,k} applied to every field on this level
+  // triangular lift L^{tri,k} on this level: R = L B
+  T R0[NT], R1[NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) R0[i] = R1[i] = T(0);
   {
-    const V4<T>* Lv = reinterpret_cast<const V4<T>*>(Lm + e * LS);
+    const V4<T>* Lv = sL + le * (LS / 4);
 #pragma unroll
     for (int c = 0; c < LS / 4; ++c) {
       const V4<T> l4 = Lv[c];
-      const T lv[4] = {l4.x, l4.y, l4.z, l4.w};
+      const T lv[4] = {l4.p, l4.uz, l4.ux, l4.uy};
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int f = 4 * c + k;
         if (f < NT * NT) {
           const int i = f / NT, m = f % NT;
-          Rp[i] += lv[k] * Bp[m];
-          Rx[i] += lv[k] * Bx[m];
-          Ry[i] += lv[k] * By[m];
-          Rz[i] += lv[k] * Bz[m];
+          R0[i] += lv[k] * B0[m];
+          R1[i] += lv[k] * B1[m];
         }
       }
     }
   }
 
-  const T kap = g[9], irho = g[10];
+  // horizontal part on the own slice
+  {
+    const T rx = g[0], ry = g[1], sx = g[2], sy = g[3];
+    if (role == 0) {
+      // R_p -= (D_r (r_x u_x + r_y u_y) + D_s (s_x u_x + s_y u_y))
+      T Ar[NT], As[NT];
 #pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    Rp[i] *= kap;
-    Rx[i] *= irho;
-    Ry[i] *= irho;
-    Rz[i] *= irho;
-  }
-  for (int s = 0; s < A.nsrc; ++s) {
-    if (A.src_elem[s] == e) {
-      const T* sv = static_cast<const T*>(A.srcvec) + s * NP + j * NT;
-      const T amp = T(A.src_amp[s]);
+      for (int m = 0; m < NT; ++m) {
+        const V4<T> v = el[j * NT + m];
+        Ar[m] = rx * v.ux + ry * v.uy;
+        As[m] = sx * v.ux + sy * v.uy;
+      }
 #pragma unroll
-      for (int i = 0; i < NT; ++i) Rp[i] += amp * sv[i];
+      for (int i = 0; i < NT; ++i) {
+        T dA = 0, dB = 0;
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
+          constexpr_or_skip(RT::Dr[i * NT + m], dA, Ar[m]);
+          constexpr_or_skip(RT::Ds[i * NT + m], dB, As[m]);
+        }
+        R0[i] -= dA;
+        R0[i] -= dB;
+      }
+    } else {
+      // R_x -= r_x D_r p + s_x D_s p ; R_y -= r_y D_r p + s_y D_s p
+      T P[NT];
+#pragma unroll
+      for (int m = 0; m < NT; ++m) P[m] = el[j * NT + m].p;
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        T dPr = 0, dPs = 0;
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
+          constexpr_or_skip(RT::Dr[i * NT + m], dPr, P[m]);
+          constexpr_or_skip(RT::Ds[i * NT + m], dPs, P[m]);
+        }
+        R0[i] -= rx * dPr;
+        R0[i] -= sx * dPs;
+        R1[i] -= ry * dPr;
+        R1[i] -= sy * dPs;
+      }
     }
   }
 
-  // low-storage Runge-Kutta update
-  const T ca = T(A.a), cb = T(A.b), dt = T(A.dt);
-  const bool rd = (A.flags & kReadRes) != 0, wu = (A.flags & kWriteU) != 0;
-  V4<T>* rr = res + e * NP + j * NT;
-  V4<T>* uo = Uout + e * NP + j * NT;
+  const T kap = g[9], irho = g[10];
+  const T s0 = role == 0 ? kap : irho;
 #pragma unroll
   for (int i = 0; i < NT; ++i) {
-    V4<T> r;
-    if (rd) {
-      r = rr[i];
-      r.x = ca * r.x + dt * Rp[i];
-      r.y = ca * r.y + dt * Rx[i];
-      r.z = ca * r.z + dt * Ry[i];
-      r.w = ca * r.w + dt * Rz[i];
-    } else {
-      r.x = dt * Rp[i];
-      r.y = dt * Rx[i];
-      r.z = dt * Ry[i];
-      r.w = dt * Rz[i];
+    R0[i] *= s0;
+    R1[i] *= irho;
+  }
+  if (role == 0) {
+    for (int s = 0; s < A.nsrc; ++s) {
+      if (A.src_elem[s] == e) {
+        const T* sv = static_cast<const T*>(A.srcvec) + s * NP + j * NT;
+        const T amp = T(A.src_amp[s]);
+#pragma unroll
+        for (int i = 0; i < NT; ++i) R0[i] += amp * sv[i];
+      }
     }
-    rr[i] = r;
-    if (wu) {
-      V4<T> u = el[j * NT + i];
-      u.x += cb * r.x;
-      u.y += cb * r.y;
-      u.z += cb * r.z;
-      u.w += cb * r.w;
-      uo[i] = u;
+  }
+
+  // low-storage Runge-Kutta update of this role's two fields
+  const T ca = T(A.a), cb = T(A.b), dt = T(A.dt);
+  V2<T> r[NT];
+  if (rd) {
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      r[i].a = ca * rprev[i].a + dt * R0[i];
+      r[i].b = ca * rprev[i].b + dt * R1[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      r[i].a = dt * R0[i];
+      r[i].b = dt * R1[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NT; ++i) rr[2 * i] = r[i];
+  if (wu) {
+    V2<T>* uo = reinterpret_cast<V2<T>*>(static_cast<V4<T>*>(A.Uout) + e * NP + j * NT) + role;
+    const V2<T>* ui = reinterpret_cast<const V2<T>*>(el + j * NT) + role;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      V2<T> u = ui[2 * i];
+      u.a += cb * r[i].a;
+      u.b += cb * r[i].b;
+      uo[2 * i] = u;
     }
   }
 }
@@ -406,6 +502,7 @@ __global__ void __launch_bounds__(64) setup_kernel(int NT, int LS, int64_t K, co
       gf[9] = 1.0;
       gf[10] = 1.0;
       gf[11] = 1.0;
+      for (int f = 0; f < 5; ++f) gf[32 + f] = 2.0;  // rho = c = 1 until the material is set
       for (int face = 0; face < 2; ++face) {
         const double* zz = face == 0 ? zb : zt;
         const double ax = xb[1] - xb[0], ay = yb[1] - yb[0], az = zz[1] - zz[0];
@@ -478,13 +575,18 @@ __global__ void __launch_bounds__(64) setup_kernel(int NT, int LS, int64_t K, co
 
 template <typename T>
 __global__ void material_kernel(int64_t K, const double* __restrict__ c, const double* __restrict__ rho,
-                                T* __restrict__ geo, double* __restrict__ aux) {
+                                const int* __restrict__ conn, T* __restrict__ geo, double* __restrict__ aux) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= K) return;
   const double kap = rho[k] * c[k] * c[k];
+  const double Z = rho[k] * c[k];
   geo[k * kGeoStride + 9] = T(kap);
   geo[k * kGeoStride + 10] = T(1.0 / rho[k]);
-  geo[k * kGeoStride + 11] = T(rho[k] * c[k]);
+  geo[k * kGeoStride + 11] = T(Z);
+  for (int f = 0; f < 5; ++f) {
+    const int nb = conn[k * kConnStride + f];
+    geo[k * kGeoStride + 32 + f] = T(Z + (nb >= 0 ? rho[nb] * c[nb] : Z));
+  }
   aux[k * kAuxStride + 4] = kap;
   aux[k * kAuxStride + 5] = rho[k];
 }
@@ -541,30 +643,10 @@ __global__ void __launch_bounds__(256) energy_kernel(int64_t K, const T* __restr
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-template <int N, typename T>
-void fill_ops_t(void* dst, const double* Dr, const double* Ds, const double* const* Ea, const double* const* Eb,
-                const double* Dt, const double* g0, const double* gN, const double* t, const int* perm) {
-  using O = Ops<N, T>;
-  constexpr int NT = O::NT, Nq = O::Nq;
-  O* o = static_cast<O*>(dst);
-  std::memset(o, 0, sizeof(O));
-  for (int i = 0; i < NT * NT; ++i) {
-    o->Dr[i] = T(Dr[i]);
-    o->Ds[i] = T(Ds[i]);
-  }
-  for (int e = 0; e < 3; ++e)
-    for (int i = 0; i < NT * Nq; ++i) {
-      o->Ea[e][i] = T(Ea[e][i]);
-      o->Eb[e][i] = T(Eb[e][i]);
-    }
-  for (int i = 0; i < Nq * Nq; ++i) o->Dt[i] = T(Dt[i]);
-  for (int j = 0; j < Nq; ++j) {
-    o->g0[j] = T(g0[j]);
-    o->gN[j] = T(gN[j]);
-    o->tlo[j] = T(0.5 * (1.0 - t[j]));
-    o->thi[j] = T(0.5 * (1.0 + t[j]));
-  }
-  for (int i = 0; i < 6 * NT; ++i) o->perm[i] = perm[i];
+template <int N>
+void fill_perm_t(void* dst, const int* perm) {
+  FacePerm<N>* o = static_cast<FacePerm<N>*>(dst);
+  for (int i = 0; i < 6 * Dim<N>::NT; ++i) o->perm[i] = perm[i];
 }
 
 template <int N, typename T>
@@ -603,20 +685,26 @@ hipError_t launch_energy_t(int64_t K, const void* U, const double* aux, const do
     default: break;                                        \
   }
 
-size_t ops_bytes(int N, int bits) {
-  size_t out = 0;
-#define WDG_SZ(n, T) out = sizeof(Ops<n, T>)
-  WDG_DISPATCH_N(N, bits, WDG_SZ)
-#undef WDG_SZ
-  return out;
+size_t ops_bytes(int N) {
+  switch (N) {
+    case 1: return sizeof(FacePerm<1>);
+    case 2: return sizeof(FacePerm<2>);
+    case 3: return sizeof(FacePerm<3>);
+    case 4: return sizeof(FacePerm<4>);
+    case 5: return sizeof(FacePerm<5>);
+    default: return 0;
+  }
 }
 
-void fill_ops(int N, int bits, void* dst, const double* Dr, const double* Ds, const double* const* Ea,
-              const double* const* Eb, const double* Dt, const double* g0, const double* gN, const double* t,
-              const int* perm) {
-#define WDG_FILL(n, T) fill_ops_t<n, T>(dst, Dr, Ds, Ea, Eb, Dt, g0, gN, t, perm)
-  WDG_DISPATCH_N(N, bits, WDG_FILL)
-#undef WDG_FILL
+void fill_ops(int N, void* dst, const int* perm) {
+  switch (N) {
+    case 1: fill_perm_t<1>(dst, perm); break;
+    case 2: fill_perm_t<2>(dst, perm); break;
+    case 3: fill_perm_t<3>(dst, perm); break;
+    case 4: fill_perm_t<4>(dst, perm); break;
+    case 5: fill_perm_t<5>(dst, perm); break;
+    default: break;
+  }
 }
 
 int lift_stride(int N) {
@@ -639,15 +727,16 @@ hipError_t launch_setup(int N, int bits, int64_t K, const double* dX, const doub
   return hipGetLastError();
 }
 
-hipError_t launch_material(int bits, int64_t K, const double* dc, const double* drho, void* dGeo, double* dAux,
-                           hipStream_t st) {
+hipError_t launch_material(int bits, int64_t K, const double* dc, const double* drho, const int* dConn, void* dGeo,
+                           double* dAux, hipStream_t st) {
   const unsigned nb = unsigned((K + 255) / 256);
   if (nb == 0) return hipSuccess;
   if (bits == 32)
-    hipLaunchKernelGGL(material_kernel<float>, dim3(nb), dim3(256), 0, st, K, dc, drho, static_cast<float*>(dGeo), dAux);
+    hipLaunchKernelGGL(material_kernel<float>, dim3(nb), dim3(256), 0, st, K, dc, drho, dConn,
+                       static_cast<float*>(dGeo), dAux);
   else
-    hipLaunchKernelGGL(material_kernel<double>, dim3(nb), dim3(256), 0, st, K, dc, drho, static_cast<double*>(dGeo),
-                       dAux);
+    hipLaunchKernelGGL(material_kernel<double>, dim3(nb), dim3(256), 0, st, K, dc, drho, dConn,
+                       static_cast<double*>(dGeo), dAux);
   return hipGetLastError();
 }
 

@@ -10,8 +10,10 @@ namespace wdg {
 // Per-element record of geometric factors and material (values of type T):
 //   0 r_x, 1 r_y, 2 s_x, 3 s_y, 4 t_zJ, 5/6 t_xJ at t=-1/+1, 7/8 t_yJ at t=-1/+1,
 //   9 kappa, 10 1/rho, 11 rho c, 12..15 bottom (J_f, n), 16..19 top (J_f, n),
-//   20+4e.. quad face e: J_f at first/second edge vertex, n_x, n_y.
-constexpr int kGeoStride = 32;
+//   20+4e.. quad face e: J_f at first/second edge vertex, n_x, n_y,
+//   32..36 rho c + (rho c of the neighbour, or own on the boundary) per face
+//   (bottom, top, quad 0..2), 37..39 unused.
+constexpr int kGeoStride = 40;
 // Per-element FP64 auxiliary record: 0..2 J_tri h_v / 2 (M^{tri,k} weights), 3 J_tri, 4 kappa, 5 rho.
 constexpr int kAuxStride = 8;
 // Per-element connectivity (int32): 0..4 neighbour of bottom, top, quad 0..2 (-1: boundary);
@@ -47,17 +49,17 @@ struct StageLaunch {
 
 // Per-element stride (values) of the stored triangular lift: Np_tri^2 padded to a multiple of 4.
 int lift_stride(int N);
-// Size in bytes of the device operator block for (N, precision).
-size_t ops_bytes(int N, int bits);
-// Fill the operator block (host memory of ops_bytes) from FP64 reference data.
-void fill_ops(int N, int bits, void* dst, const double* Dr, const double* Ds, const double* const* Ea,
-              const double* const* Eb, const double* Dt, const double* g0, const double* gN, const double* t,
-              const int* perm);
+// Size in bytes of the device face-permutation table of order N (the only
+// operator data the stage kernel reads from memory; the reference triangle
+// and 1D operators are compiled into the kernel).
+size_t ops_bytes(int N);
+// Fill that table (host memory of ops_bytes(N)) from the 6 x Np_tri permutation list.
+void fill_ops(int N, void* dst, const int* perm);
 
 hipError_t launch_setup(int N, int bits, int64_t K, const double* dX, const double* dMv, const double* dMtri,
                         void* dGeo, void* dL, double* dAux, hipStream_t st);
-hipError_t launch_material(int bits, int64_t K, const double* dc, const double* drho, void* dGeo, double* dAux,
-                           hipStream_t st);
+hipError_t launch_material(int bits, int64_t K, const double* dc, const double* drho, const int* dConn, void* dGeo,
+                           double* dAux, hipStream_t st);
 hipError_t launch_stage(int N, int bits, const StageLaunch& a, hipStream_t st);
 hipError_t launch_receivers(int bits, int NP, int nrec, const void* U, const int* elem, const double* rows,
                             double* out, hipStream_t st);

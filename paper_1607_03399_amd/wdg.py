@@ -269,8 +269,8 @@ class Solver:
         return ms.value, n.value
 
     def element_data(self):
-        """(geo (K,32), lift (K,Np_tri,Np_tri)) built by the device setup kernel."""
-        geo = np.zeros((self.K, 32))
+        """(geo (K,40), lift (K,Np_tri,Np_tri)) built by the device setup kernel."""
+        geo = np.zeros((self.K, 40))
         lift = np.zeros((self.K, self.NT, self.NT))
         self._check(self._lib.wdg_get_element_data(self._h, _ptr(geo), _ptr(lift)), "get_element_data")
         return geo, lift
