@@ -38,47 +38,40 @@ struct FacePerm {
   int perm[6 * Dim<N>::NT];
 };
 
-// Node-interleaved state: one 4-vector per node in the order (p, u_z, u_x, u_y),
-// so that each of the two lane roles below owns one contiguous half.
+// Node-interleaved state: one 4-vector per node in the order (p, u_z, u_x, u_y).
 template <typename T>
 struct alignas(4 * sizeof(T)) V4 {
   T p, uz, ux, uy;
 };
-template <typename T>
-struct alignas(2 * sizeof(T)) V2 {
-  T a, b;
-};
 
-// Launch shape.  A wavefront holds EPW elements x Nq levels; a block has 4
-// wavefronts (2 if the staged state would not fit in 48 KiB of LDS): the first
-// half computes the (p, u_z) equations of its elements, the second half the
-// (u_x, u_y) equations of the same elements.
-#ifndef WDG_STAGE_WAVES
-#define WDG_STAGE_WAVES 4
-#endif
+// Launch shape: one wavefront per block, lane = (element, level j), so a block
+// holds EPB = 64 / Nq elements (fewer where the LDS would exceed 64 KiB).  LDS
+// holds the staged state (per-element stride NPP, odd in 4-vectors, so that the
+// elements of a wavefront fall on different banks) and a second region that
+// first holds the triangular lifts, geometry records and triangular-face
+// fluxes, and afterwards the right-hand side on its way to the coalesced
+// update.
 template <int N, typename T>
 struct Cfg {
   static constexpr int NT = Dim<N>::NT, Nq = Dim<N>::Nq, NP = Dim<N>::NP;
-  // LDS bytes of one element: staged state, fluxes, lift, geometry, connectivity
-  static constexpr int per_elem =
-      (NP * 4 + 2 * NT * 2 + Dim<N>::LS + kGeoStride) * int(sizeof(T)) + kConnStride * 4;
-  static constexpr int EPW_FULL = 64 / Nq;
-  static constexpr int WAVES = (WDG_STAGE_WAVES == 4 && EPW_FULL * 2 * per_elem <= 49152) ? 4 : 2;
-  // with two wavefronts, shrink the wavefront's element count until LDS fits 60 KiB
-  static constexpr int EPW = (WAVES == 4 || EPW_FULL * per_elem <= 61440) ? EPW_FULL : 61440 / per_elem;
-  static constexpr int BS = 64 * WAVES;
-  static constexpr int EPB = EPW * (WAVES / 2);
+  static constexpr int NPP = NP | 1;
+  static constexpr int VL = Dim<N>::LS / 4, VG = kGeoStride / 4, VF = NT;  // 4-vectors per element
+  static constexpr int XPE = (VL + VG + VF) > NPP ? (VL + VG + VF) : NPP;
+  static constexpr int per_elem = (NPP + XPE) * 4 * int(sizeof(T)) + kConnStride * 4;
+  static constexpr int EPB_FULL = 64 / Nq;
+  static constexpr int EPB = EPB_FULL * per_elem <= 65536 ? EPB_FULL : 65536 / per_elem;
+  static constexpr int BS = 64;
+  // 4-vectors of the chunk each lane carries through the coalesced update
+  static constexpr int UPD = (EPB * NP + BS - 1) / BS;
+  // prefetch the previous residual into registers when that costs at most 40 of them
+#ifndef WDG_PREFETCH_REGS
+#define WDG_PREFETCH_REGS 40
+#endif
+  static constexpr bool PREFETCH = UPD * 4 * int(sizeof(T)) / 4 <= WDG_PREFETCH_REGS;
 };
 
 // acc1 += c x1; acc2 += c x2 for a reference-operator entry c known at
 // compile time; exact zeros of the operator cost nothing
-template <typename T>
-__device__ __forceinline__ void constexpr_or_skip(double c, T& acc1, T x1, T& acc2, T x2) {
-  if (c != 0.0) {
-    acc1 += T(c) * x1;
-    acc2 += T(c) * x2;
-  }
-}
 template <typename T>
 __device__ __forceinline__ void constexpr_or_skip(double c, T& acc, T x) {
   if (c != 0.0) acc += T(c) * x;
@@ -93,37 +86,56 @@ __device__ __forceinline__ T pick(const double* tab, int j, int stride, int col)
   return v;
 }
 
+// Node of the neighbour's triangular face that coincides with node i of this
+// element's face, for vertex permutation code p: node i has lattice indices
+// (N-a-b, a, b); the permutation reorders them.  Selector of the neighbour's
+// second / third index for each p, two bits per code (see the host's table of
+// the six vertex permutations).
+template <int N>
+__device__ __forceinline__ int face_perm(int p, int i) {
+  int b = 0;
+#pragma unroll
+  for (int bb = 1; bb <= N; ++bb) b += i >= tri_idx(N, 0, bb) ? 1 : 0;
+  const int a = i - (b * (N + 1) - b * (b - 1) / 2);
+  const int c = N - a - b;
+  const int s1 = (417 >> (2 * p)) & 3, s2 = (2118 >> (2 * p)) & 3;
+  const int j1 = s1 == 0 ? c : (s1 == 1 ? a : b);
+  const int j2 = s2 == 0 ? c : (s2 == 1 ? a : b);
+  return j2 * (N + 1) - j2 * (j2 - 1) / 2 + j1;
+}
+
 // ---------------------------------------------------------------------------
 // Fused stage kernel
 //
-// Lane (element, level j, role) owns the triangular slice j of its element for
-// two of the four equations: role 0 the pressure and u_z equations, role 1
-// the u_x and u_y equations (role is uniform per wavefront).  The reference
-// triangle and 1D operators are compile-time constants (instruction
-// literals).  The element's state is staged in LDS: the vertical derivative
+// Lane (element, level j) owns the triangular slice j of its element for all
+// four equations.  The reference triangle and 1D operators are compile-time
+// constants (instruction literals).  The chunk's state, lifts, geometry and
+// connectivity are staged in LDS with coalesced loads; the vertical derivative
 // and the triangle-face lifts couple the levels of one element through it.
 //   phase 1: B = -W (vertical part of D_x, D_y, D_z, before L^{tri,k}) plus the
 //            quadrilateral-face lifts of this level; triangular-face fluxes
 //   phase 2: B += triangular-face lifts; R = L^{tri,k} B + H (horizontal part);
-//            scale by kappa, 1/rho; sources; low-storage Runge-Kutta update
+//            scale by kappa, 1/rho; sources
+//   update:  R goes through LDS so that the low-storage Runge-Kutta update
+//            reads and writes res and U with fully coalesced accesses
 // ---------------------------------------------------------------------------
 #ifndef WDG_STAGE_WAVES_PER_EU
-#define WDG_STAGE_WAVES_PER_EU 1
+#define WDG_STAGE_WAVES_PER_EU 2
 #endif
 template <int N, typename T>
-__global__ void __launch_bounds__((Cfg<N, T>::BS), WDG_STAGE_WAVES_PER_EU) wedge_stage(StageLaunch A) {
+__global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageLaunch A) {
   using C = Cfg<N, T>;
   using RT = gen::RefTables<N>;
-  constexpr int NT = C::NT, Nq = C::Nq, NP = C::NP, EPW = C::EPW, EPB = C::EPB, BS = C::BS;
-  constexpr int HALF = C::WAVES / 2;
-  constexpr int LS = Dim<N>::LS;
-  __shared__ V4<T> sU[EPB * NP];
-  __shared__ V4<T> sL[EPB * LS / 4];
-  __shared__ V4<T> sG[EPB * kGeoStride / 4];
+  constexpr int NT = C::NT, Nq = C::Nq, NP = C::NP, NPP = C::NPP, EPB = C::EPB;
+  constexpr int VL = C::VL, VG = C::VG;
+  __shared__ V4<T> sU[EPB * NPP];
+  __shared__ V4<T> sX[EPB * C::XPE];
   __shared__ int4 sC[EPB * kConnStride / 4];
-  __shared__ T sF[EPB * 2 * NT * 2];
+  V4<T>* const sL = sX;
+  V4<T>* const sG = sX + EPB * VL;
+  T* const sF = reinterpret_cast<T*>(sG + EPB * VG);
+  V4<T>* const sR = sX;
 
-  const FacePerm<N>* __restrict__ fp = static_cast<const FacePerm<N>*>(A.ops);
   const V4<T>* __restrict__ Uin = static_cast<const V4<T>*>(A.Uin);
   const T* __restrict__ geo = static_cast<const T*>(A.geo);
   const T* __restrict__ Lm = static_cast<const T*>(A.L);
@@ -139,34 +151,31 @@ __global__ void __launch_bounds__((Cfg<N, T>::BS), WDG_STAGE_WAVES_PER_EU) wedge
   const int nE = left < EPB ? int(left) : EPB;
   const int tid = threadIdx.x;
 
-  // stage the chunk's state, triangular lifts, geometry and connectivity in
-  // LDS with coalesced 16-byte loads; lanes then read them by broadcast
+  // stage the chunk with coalesced 16-byte loads
   {
     const V4<T>* src = Uin + e0 * NP;
-    for (int idx = tid; idx < nE * NP; idx += BS) sU[idx] = src[idx];
-    const V4<T>* Ls = reinterpret_cast<const V4<T>*>(Lm + e0 * LS);
-    for (int idx = tid; idx < nE * (LS / 4); idx += BS) sL[idx] = Ls[idx];
+    for (int idx = tid; idx < nE * NP; idx += 64) sU[idx + (idx / NP) * (NPP - NP)] = src[idx];
+    const V4<T>* Ls = reinterpret_cast<const V4<T>*>(Lm + e0 * Dim<N>::LS);
+    for (int idx = tid; idx < nE * VL; idx += 64) sL[idx] = Ls[idx];
     const V4<T>* Gs = reinterpret_cast<const V4<T>*>(geo + e0 * kGeoStride);
-    for (int idx = tid; idx < nE * (kGeoStride / 4); idx += BS) sG[idx] = Gs[idx];
+    for (int idx = tid; idx < nE * VG; idx += 64) sG[idx] = Gs[idx];
     const int4* Cs = reinterpret_cast<const int4*>(conn + e0 * kConnStride);
-    for (int idx = tid; idx < nE * (kConnStride / 4); idx += BS) sC[idx] = Cs[idx];
+    for (int idx = tid; idx < nE * (kConnStride / 4); idx += 64) sC[idx] = Cs[idx];
   }
   __syncthreads();
 
-  const int wv = tid >> 6, ln = tid & 63;
-  const int role = wv / HALF;  // uniform per wavefront
-  const int le = (wv % HALF) * EPW + ln / Nq;
-  const int j = ln % Nq;
-  const bool active = ln < EPW * Nq && le < nE;
+  const int le = tid / Nq;
+  const int j = tid - le * Nq;
+  const bool active = tid < EPB * Nq && le < nE;
   const int64_t e = e0 + le;
   const T bsign = (A.flags & kDirichlet) ? T(-1) : T(1);
   const T tau_on = (A.flags & kCentral) ? T(0) : T(1);
-  const V4<T>* el = sU + le * NP;
-
-  // role 0: (B0, B1) = (p, u_z) equations; role 1: (u_x, u_y)
-  T B0[NT], B1[NT];
-
+  const V4<T>* el = sU + le * NPP;
   const T* g = reinterpret_cast<const T*>(sG) + le * kGeoStride;
+
+  // pre-lift accumulators of the four equations on this level
+  T Bp[NT], Bz[NT], Bx[NT], By[NT];
+
   if (active) {
     const T tzJ = g[4];
     const T tl = T(0.5) * (T(1) - pick<Nq, T>(RT::t, j, 1, 0));
@@ -178,33 +187,24 @@ __global__ void __launch_bounds__((Cfg<N, T>::BS), WDG_STAGE_WAVES_PER_EU) wedge
     for (int m = 0; m < Nq; ++m) dtr[m] = pick<Nq, T>(RT::Dt, j, Nq, m);
 
     // vertical part: W = t_dJ(t_j) (D_t U)(level j)
-    if (role == 0) {
 #pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        T dP = 0, dX = 0, dY = 0, dZ = 0;
+    for (int i = 0; i < NT; ++i) {
+      T dP = 0, dX = 0, dY = 0, dZ = 0;
 #pragma unroll
-        for (int m = 0; m < Nq; ++m) {
-          const V4<T> v = el[m * NT + i];
-          dP += dtr[m] * v.p;
-          dX += dtr[m] * v.ux;
-          dY += dtr[m] * v.uy;
-          dZ += dtr[m] * v.uz;
-        }
-        T w = txJ * dX;
-        w += tyJ * dY;
-        w += tzJ * dZ;
-        B0[i] = -w;
-        B1[i] = -(tzJ * dP);
+      for (int m = 0; m < Nq; ++m) {
+        const V4<T> v = el[m * NT + i];
+        dP += dtr[m] * v.p;
+        dX += dtr[m] * v.ux;
+        dY += dtr[m] * v.uy;
+        dZ += dtr[m] * v.uz;
       }
-    } else {
-#pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        T dP = 0;
-#pragma unroll
-        for (int m = 0; m < Nq; ++m) dP += dtr[m] * el[m * NT + i].p;
-        B0[i] = -(txJ * dP);
-        B1[i] = -(tyJ * dP);
-      }
+      T w = txJ * dX;
+      w += tyJ * dY;
+      w += tzJ * dZ;
+      Bp[i] = -w;
+      Bx[i] = -(txJ * dP);
+      By[i] = -(tyJ * dP);
+      Bz[i] = -(tzJ * dP);
     }
 
     const int* cn = reinterpret_cast<const int*>(sC) + le * kConnStride;
@@ -225,7 +225,7 @@ __global__ void __launch_bounds__((Cfg<N, T>::BS), WDG_STAGE_WAVES_PER_EU) wedge
       const T taup = tau_on * T(2) / zs;
       const T tauu = tau_on * zs * T(0.5);
       const V4<T>* nb_el = Uin + src_el * NP + j * NT;
-      T fa[Nq], fb[Nq];
+      T fpa[Nq], fpb[Nq], fua[Nq], fub[Nq];
 #pragma unroll
       for (int q = 0; q < Nq; ++q) {
         const V4<T> own = el[j * NT + edge_node(N, ed, q)];
@@ -236,45 +236,38 @@ __global__ void __launch_bounds__((Cfg<N, T>::BS), WDG_STAGE_WAVES_PER_EU) wedge
         // mirror state: p+ = s p-, u_n+ = -s u_n- (s = -1 Dirichlet, +1 rigid)
         const T pb = bsign * pm, ub = -bsign * unm;
         const T pp = pb + w_in * (v.p - pb);
-        const T unp = ub + w_in * ((nx * v.ux + ny * v.uy) - ub);
+        // (u_z enters with weight zero, which keeps the gather one 16-byte load)
+        const T unp = ub + w_in * ((nx * v.ux + ny * v.uy + T(0) * v.uz) - ub);
         const T jp = pp - pm, jun = unp - unm;
-        const T F = role == 0 ? T(0.5) * (taup * jp - jun) : T(0.5) * (tauu * jun - jp);
-        fa[q] = Ja * F;
-        fb[q] = Jb * F;
+        const T Fp = T(0.5) * (taup * jp - jun);
+        const T Fu = T(0.5) * (tauu * jun - jp);
+        fpa[q] = Ja * Fp;
+        fpb[q] = Jb * Fp;
+        fua[q] = Ja * Fu;
+        fub[q] = Jb * Fu;
       }
-      if (role == 0) {
 #pragma unroll
-        for (int i = 0; i < NT; ++i) {
-          T sp = 0;
+      for (int i = 0; i < NT; ++i) {
+        T sp = 0, su = 0;
 #pragma unroll
-          for (int q = 0; q < Nq; ++q) {
-            constexpr_or_skip(RT::Ea[(ed * NT + i) * Nq + q], sp, fa[q]);
-            constexpr_or_skip(RT::Eb[(ed * NT + i) * Nq + q], sp, fb[q]);
-          }
-          B0[i] += sp;
+        for (int q = 0; q < Nq; ++q) {
+          constexpr_or_skip(RT::Ea[(ed * NT + i) * Nq + q], sp, fpa[q]);
+          constexpr_or_skip(RT::Eb[(ed * NT + i) * Nq + q], sp, fpb[q]);
+          constexpr_or_skip(RT::Ea[(ed * NT + i) * Nq + q], su, fua[q]);
+          constexpr_or_skip(RT::Eb[(ed * NT + i) * Nq + q], su, fub[q]);
         }
-      } else {
-#pragma unroll
-        for (int i = 0; i < NT; ++i) {
-          T su = 0;
-#pragma unroll
-          for (int q = 0; q < Nq; ++q) {
-            constexpr_or_skip(RT::Ea[(ed * NT + i) * Nq + q], su, fa[q]);
-            constexpr_or_skip(RT::Eb[(ed * NT + i) * Nq + q], su, fb[q]);
-          }
-          B0[i] += nx * su;
-          B1[i] += ny * su;
-        }
+        Bp[i] += sp;
+        Bx[i] += nx * su;
+        By[i] += ny * su;
       }
     }
 
-    // triangular faces: their 2 NT nodes are shared out over the 2 Nq lanes of
+    // triangular faces: their 2 NT nodes are shared out over the Nq lanes of
     // the element; fluxes (premultiplied by J_f) go to LDS for every level
-    constexpr int per = (NT + Nq - 1) / Nq;
-    const int slot = role * Nq + j;
+    constexpr int per = (2 * NT + Nq - 1) / Nq;
 #pragma unroll
     for (int t = 0; t < per; ++t) {
-      const int fraw = slot * per + t;
+      const int fraw = j * per + t;
       const int fnode = fraw < 2 * NT ? fraw : 2 * NT - 1;  // surplus slots redo the last node
       const int face = fnode >= NT ? 1 : 0;
       const int i = fnode - face * NT;
@@ -289,7 +282,7 @@ __global__ void __launch_bounds__((Cfg<N, T>::BS), WDG_STAGE_WAVES_PER_EU) wedge
       const T taup = tau_on * T(2) / zs;
       const T tauu = tau_on * zs * T(0.5);
       const V4<T> own = el[face * N * NT + i];
-      const V4<T> v = Uin[src_el * NP + nlev * NT + fp->perm[pc * NT + i]];
+      const V4<T> v = Uin[src_el * NP + nlev * NT + face_perm<N>(pc, i)];
       const T pm = own.p;
       const T unm = nx * own.ux + ny * own.uy + nz * own.uz;
       const T pb = bsign * pm, ub = -bsign * unm;
@@ -304,155 +297,142 @@ __global__ void __launch_bounds__((Cfg<N, T>::BS), WDG_STAGE_WAVES_PER_EU) wedge
     }
   }
   __syncthreads();
-  if (!active) return;
 
   const bool rd = (A.flags & kReadRes) != 0, wu = (A.flags & kWriteU) != 0;
-  // residual of the previous stage (this role's two fields): load now, use at the end
-  V2<T>* rr = reinterpret_cast<V2<T>*>(static_cast<V4<T>*>(A.res) + e * NP + j * NT) + role;
-  V2<T> rprev[NT];
-  if (rd) {
+  V4<T>* __restrict__ res = static_cast<V4<T>*>(A.res) + e0 * NP;
+  // residual of the previous stage, in the coalesced layout of the update
+  V4<T> rprev[C::PREFETCH ? C::UPD : 1];
+  if (C::PREFETCH && rd) {
 #pragma unroll
-    for (int i = 0; i < NT; ++i) rprev[i] = rr[2 * i];
-  }
-
-  // triangular-face lifts: flux spread over all levels by (M^1D)^-1 e_{0,N}
-  {
-    const T g0j = pick<Nq, T>(RT::g0, j, 1, 0), gNj = pick<Nq, T>(RT::gN, j, 1, 0);
-    const T* fbt = sF + (le * 2 + 0) * NT * 2;
-    const T* ftp = sF + (le * 2 + 1) * NT * 2;
-    if (role == 0) {
-      const T bz = g[15], tz = g[19];
-#pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        B0[i] += g0j * fbt[2 * i];
-        B0[i] += gNj * ftp[2 * i];
-        B1[i] += (g0j * fbt[2 * i + 1]) * bz;
-        B1[i] += (gNj * ftp[2 * i + 1]) * tz;
-      }
-    } else {
-      const T bx = g[13], by = g[14], tx = g[17], ty = g[18];
-#pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        const T wb = g0j * fbt[2 * i + 1], wt = gNj * ftp[2 * i + 1];
-        B0[i] += wb * bx;
-        B0[i] += wt * tx;
-        B1[i] += wb * by;
-        B1[i] += wt * ty;
-      }
+    for (int k = 0; k < C::UPD; ++k) {
+      const int idx = tid + 64 * k;
+      if (idx < nE * NP) rprev[k] = res[idx];
     }
   }
 
-  // triangular lift L^{tri,k} on this level: R = L B
-  T R0[NT], R1[NT];
+  T Rp[NT], Rz[NT], Rx[NT], Ry[NT];
+  if (active) {
+    // triangular-face lifts: flux spread over all levels by (M^1D)^-1 e_{0,N}
+    {
+      const T g0j = pick<Nq, T>(RT::g0, j, 1, 0), gNj = pick<Nq, T>(RT::gN, j, 1, 0);
+      const T* fbt = sF + (le * 2 + 0) * NT * 2;
+      const T* ftp = sF + (le * 2 + 1) * NT * 2;
+      const T bx = g[13], by = g[14], bz = g[15], tx = g[17], ty = g[18], tz = g[19];
 #pragma unroll
-  for (int i = 0; i < NT; ++i) R0[i] = R1[i] = T(0);
-  {
-    const V4<T>* Lv = sL + le * (LS / 4);
+      for (int i = 0; i < NT; ++i) {
+        Bp[i] += g0j * fbt[2 * i];
+        Bp[i] += gNj * ftp[2 * i];
+        const T wb = g0j * fbt[2 * i + 1], wt = gNj * ftp[2 * i + 1];
+        Bx[i] += wb * bx;
+        Bx[i] += wt * tx;
+        By[i] += wb * by;
+        By[i] += wt * ty;
+        Bz[i] += wb * bz;
+        Bz[i] += wt * tz;
+      }
+    }
+
+    // triangular lift L^{tri,k} on this level: R = L B
 #pragma unroll
-    for (int c = 0; c < LS / 4; ++c) {
-      const V4<T> l4 = Lv[c];
-      const T lv[4] = {l4.p, l4.uz, l4.ux, l4.uy};
+    for (int i = 0; i < NT; ++i) Rp[i] = Rz[i] = Rx[i] = Ry[i] = T(0);
+    {
+      const V4<T>* Lv = sL + le * VL;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int f = 4 * c + k;
-        if (f < NT * NT) {
-          const int i = f / NT, m = f % NT;
-          R0[i] += lv[k] * B0[m];
-          R1[i] += lv[k] * B1[m];
+      for (int c = 0; c < VL; ++c) {
+        const V4<T> l4 = Lv[c];
+        const T lv[4] = {l4.p, l4.uz, l4.ux, l4.uy};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int f = 4 * c + k;
+          if (f < NT * NT) {
+            const int i = f / NT, m = f % NT;
+            Rp[i] += lv[k] * Bp[m];
+            Rz[i] += lv[k] * Bz[m];
+            Rx[i] += lv[k] * Bx[m];
+            Ry[i] += lv[k] * By[m];
+          }
         }
       }
     }
-  }
 
-  // horizontal part on the own slice
-  {
-    const T rx = g[0], ry = g[1], sx = g[2], sy = g[3];
-    if (role == 0) {
-      // R_p -= (D_r (r_x u_x + r_y u_y) + D_s (s_x u_x + s_y u_y))
-      T Ar[NT], As[NT];
+    // horizontal part on the own slice:
+    //   R_p -= D_r (r_x u_x + r_y u_y) + D_s (s_x u_x + s_y u_y)
+    //   R_x -= r_x D_r p + s_x D_s p ;  R_y -= r_y D_r p + s_y D_s p
+    {
+      const T rx = g[0], ry = g[1], sx = g[2], sy = g[3];
+      T Ar[NT], As[NT], P[NT];
 #pragma unroll
       for (int m = 0; m < NT; ++m) {
         const V4<T> v = el[j * NT + m];
         Ar[m] = rx * v.ux + ry * v.uy;
         As[m] = sx * v.ux + sy * v.uy;
+        P[m] = v.p;
       }
 #pragma unroll
       for (int i = 0; i < NT; ++i) {
-        T dA = 0, dB = 0;
+        T dA = 0, dB = 0, dPr = 0, dPs = 0;
 #pragma unroll
         for (int m = 0; m < NT; ++m) {
           constexpr_or_skip(RT::Dr[i * NT + m], dA, Ar[m]);
           constexpr_or_skip(RT::Ds[i * NT + m], dB, As[m]);
-        }
-        R0[i] -= dA;
-        R0[i] -= dB;
-      }
-    } else {
-      // R_x -= r_x D_r p + s_x D_s p ; R_y -= r_y D_r p + s_y D_s p
-      T P[NT];
-#pragma unroll
-      for (int m = 0; m < NT; ++m) P[m] = el[j * NT + m].p;
-#pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        T dPr = 0, dPs = 0;
-#pragma unroll
-        for (int m = 0; m < NT; ++m) {
           constexpr_or_skip(RT::Dr[i * NT + m], dPr, P[m]);
           constexpr_or_skip(RT::Ds[i * NT + m], dPs, P[m]);
         }
-        R0[i] -= rx * dPr;
-        R0[i] -= sx * dPs;
-        R1[i] -= ry * dPr;
-        R1[i] -= sy * dPs;
+        Rp[i] -= dA;
+        Rp[i] -= dB;
+        Rx[i] -= rx * dPr;
+        Rx[i] -= sx * dPs;
+        Ry[i] -= ry * dPr;
+        Ry[i] -= sy * dPs;
       }
     }
-  }
 
-  const T kap = g[9], irho = g[10];
-  const T s0 = role == 0 ? kap : irho;
+    const T kap = g[9], irho = g[10];
 #pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    R0[i] *= s0;
-    R1[i] *= irho;
-  }
-  if (role == 0) {
+    for (int i = 0; i < NT; ++i) {
+      Rp[i] *= kap;
+      Rz[i] *= irho;
+      Rx[i] *= irho;
+      Ry[i] *= irho;
+    }
     for (int s = 0; s < A.nsrc; ++s) {
       if (A.src_elem[s] == e) {
         const T* sv = static_cast<const T*>(A.srcvec) + s * NP + j * NT;
         const T amp = T(A.src_amp[s]);
 #pragma unroll
-        for (int i = 0; i < NT; ++i) R0[i] += amp * sv[i];
+        for (int i = 0; i < NT; ++i) Rp[i] += amp * sv[i];
       }
     }
   }
-
-  // low-storage Runge-Kutta update of this role's two fields
-  const T ca = T(A.a), cb = T(A.b), dt = T(A.dt);
-  V2<T> r[NT];
-  if (rd) {
+  // the right-hand side replaces lifts, geometry and fluxes in LDS
+  __syncthreads();
+  if (active) {
 #pragma unroll
-    for (int i = 0; i < NT; ++i) {
-      r[i].a = ca * rprev[i].a + dt * R0[i];
-      r[i].b = ca * rprev[i].b + dt * R1[i];
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < NT; ++i) {
-      r[i].a = dt * R0[i];
-      r[i].b = dt * R1[i];
-    }
+    for (int i = 0; i < NT; ++i) sR[le * NPP + j * NT + i] = V4<T>{Rp[i], Rz[i], Rx[i], Ry[i]};
   }
+  __syncthreads();
+
+  // low-storage Runge-Kutta update, coalesced over the chunk
+  const T ca = T(A.a), cb = T(A.b), dt = T(A.dt);
+  V4<T>* __restrict__ uo = static_cast<V4<T>*>(A.Uout) + e0 * NP;
 #pragma unroll
-  for (int i = 0; i < NT; ++i) rr[2 * i] = r[i];
-  if (wu) {
-    V2<T>* uo = reinterpret_cast<V2<T>*>(static_cast<V4<T>*>(A.Uout) + e * NP + j * NT) + role;
-    const V2<T>* ui = reinterpret_cast<const V2<T>*>(el + j * NT) + role;
-#pragma unroll
-    for (int i = 0; i < NT; ++i) {
-      V2<T> u = ui[2 * i];
-      u.a += cb * r[i].a;
-      u.b += cb * r[i].b;
-      uo[2 * i] = u;
+  for (int k = 0; k < C::UPD; ++k) {
+    const int idx = tid + 64 * k;
+    if (idx < nE * NP) {
+      const int l = idx + (idx / NP) * (NPP - NP);
+      const V4<T> R = sR[l];
+      V4<T> r;
+      if (rd) {
+        const V4<T> q = C::PREFETCH ? rprev[k] : res[idx];
+        r = V4<T>{ca * q.p + dt * R.p, ca * q.uz + dt * R.uz, ca * q.ux + dt * R.ux, ca * q.uy + dt * R.uy};
+      } else {
+        r = V4<T>{dt * R.p, dt * R.uz, dt * R.ux, dt * R.uy};
+      }
+      res[idx] = r;
+      if (wu) {
+        const V4<T> u = sU[l];
+        uo[idx] = V4<T>{u.p + cb * r.p, u.uz + cb * r.uz, u.ux + cb * r.ux, u.uy + cb * r.uy};
+      }
     }
   }
 }
