@@ -57,7 +57,7 @@ struct Cfg {
   static constexpr int NPP = NP | 1;
   static constexpr int VL = Dim<N>::LS / 4, VG = kGeoStride / 4, VF = NT;  // 4-vectors per element
   static constexpr int XPE = (VL + VG + VF) > NPP ? (VL + VG + VF) : NPP;
-  static constexpr int per_elem = (NPP + XPE) * 4 * int(sizeof(T)) + kConnStride * 4;
+  static constexpr int per_elem = (NPP + XPE) * 4 * int(sizeof(T));
   static constexpr int EPB_FULL = 64 / Nq;
   static constexpr int EPB = EPB_FULL * per_elem <= 65536 ? EPB_FULL : 65536 / per_elem;
   static constexpr int BS = 64;
@@ -104,6 +104,40 @@ __device__ __forceinline__ int face_perm(int p, int i) {
   return j2 * (N + 1) - j2 * (j2 - 1) / 2 + j1;
 }
 
+// Raw buffer access to one chunk of a stream.  Loads past the resource's
+// byte count return zeros and stores there are dropped by the hardware, so
+// the ragged last chunk needs no branches around memory operations (a branch
+// lets the compiler sink a load next to its use and serialise the latencies).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kRsrcWord3 = 0x00020000;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), kRsrcWord3);
+}
+template <typename T>
+__device__ __forceinline__ V4<T> bload(__amdgpu_buffer_rsrc_t r, int idx) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(V4<T>, __builtin_amdgcn_raw_buffer_load_b128(r, idx * 16, 0, 0));
+  } else {
+    struct H2 {
+      u32x4 lo, hi;
+    } h{__builtin_amdgcn_raw_buffer_load_b128(r, idx * 32, 0, 0), __builtin_amdgcn_raw_buffer_load_b128(r, idx * 32 + 16, 0, 0)};
+    return __builtin_bit_cast(V4<T>, h);
+  }
+}
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int idx, const V4<T>& v) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, idx * 16, 0, 0);
+  } else {
+    struct H2 {
+      u32x4 lo, hi;
+    };
+    const H2 h = __builtin_bit_cast(H2, v);
+    __builtin_amdgcn_raw_buffer_store_b128(h.lo, r, idx * 32, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(h.hi, r, idx * 32 + 16, 0, 0);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Fused stage kernel
 //
@@ -128,9 +162,10 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
   using RT = gen::RefTables<N>;
   constexpr int NT = C::NT, Nq = C::Nq, NP = C::NP, NPP = C::NPP, EPB = C::EPB;
   constexpr int VL = C::VL, VG = C::VG;
-  __shared__ V4<T> sU[EPB * NPP];
-  __shared__ V4<T> sX[EPB * C::XPE];
-  __shared__ int4 sC[EPB * kConnStride / 4];
+  // one spare 4-vector at the end of each array takes the stores of lanes
+  // past the end of a staged stream
+  __shared__ V4<T> sU[EPB * NPP + 1];
+  __shared__ V4<T> sX[EPB * C::XPE + 1];
   V4<T>* const sL = sX;
   V4<T>* const sG = sX + EPB * VL;
   T* const sF = reinterpret_cast<T*>(sG + EPB * VG);
@@ -151,25 +186,88 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
   const int nE = left < EPB ? int(left) : EPB;
   const int tid = threadIdx.x;
 
-  // stage the chunk with coalesced 16-byte loads
-  {
-    const V4<T>* src = Uin + e0 * NP;
-    for (int idx = tid; idx < nE * NP; idx += 64) sU[idx + (idx / NP) * (NPP - NP)] = src[idx];
-    const V4<T>* Ls = reinterpret_cast<const V4<T>*>(Lm + e0 * Dim<N>::LS);
-    for (int idx = tid; idx < nE * VL; idx += 64) sL[idx] = Ls[idx];
-    const V4<T>* Gs = reinterpret_cast<const V4<T>*>(geo + e0 * kGeoStride);
-    for (int idx = tid; idx < nE * VG; idx += 64) sG[idx] = Gs[idx];
-    const int4* Cs = reinterpret_cast<const int4*>(conn + e0 * kConnStride);
-    for (int idx = tid; idx < nE * (kConnStride / 4); idx += 64) sC[idx] = Cs[idx];
-  }
-  __syncthreads();
-
   const int le = tid / Nq;
   const int j = tid - le * Nq;
   const bool active = tid < EPB * Nq && le < nE;
-  const int64_t e = e0 + le;
+  const int64_t e = e0 + (active ? le : 0);  // idle lanes shadow a valid element
   const T bsign = (A.flags & kDirichlet) ? T(-1) : T(1);
   const T tau_on = (A.flags & kCentral) ? T(0) : T(1);
+  constexpr int per = (2 * NT + Nq - 1) / Nq;  // triangular-face nodes per lane
+
+  // The lane's own connectivity is read first and the neighbour gathers are
+  // issued as soon as it arrives, while the chunk's coalesced staging loads
+  // are still in flight: both memory latencies overlap.
+  int cn[6];
+  {
+    const int4* cp = reinterpret_cast<const int4*>(conn + e * kConnStride);
+    const int4 c0 = cp[0], c1 = cp[1];
+    cn[0] = c0.x;
+    cn[1] = c0.y;
+    cn[2] = c0.z;
+    cn[3] = c0.w;
+    cn[4] = c1.x;
+    cn[5] = c1.y;
+  }
+  constexpr int SU = (EPB * NP + 63) / 64, SL = (EPB * VL + 63) / 64, SG = (EPB * VG + 63) / 64;
+  constexpr int V4B = 4 * int(sizeof(T));
+  V4<T> rU[SU], rL[SL], rG[SG];
+  {
+    const auto bu = chunk_rsrc(Uin + e0 * NP, int64_t(nE) * NP * V4B);
+    const auto bl = chunk_rsrc(Lm + e0 * Dim<N>::LS, int64_t(nE) * VL * V4B);
+    const auto bg = chunk_rsrc(geo + e0 * kGeoStride, int64_t(nE) * VG * V4B);
+#pragma unroll
+    for (int k = 0; k < SU; ++k) rU[k] = bload<T>(bu, tid + 64 * k);
+#pragma unroll
+    for (int k = 0; k < SL; ++k) rL[k] = bload<T>(bl, tid + 64 * k);
+#pragma unroll
+    for (int k = 0; k < SG; ++k) rG[k] = bload<T>(bg, tid + 64 * k);
+  }
+  const int code = cn[5];
+  // quadrilateral-face neighbour nodes on this level (boundary faces read the
+  // own element, a valid address; the mirror state is blended in later)
+  V4<T> gq[3][Nq];
+#pragma unroll
+  for (int ed = 0; ed < 3; ++ed) {
+    const int nbr = cn[2 + ed];
+    const int ned = (code >> (8 + 2 * ed)) & 3;
+    const V4<T>* nb_el = Uin + (nbr >= 0 ? int64_t(nbr) : e) * NP + j * NT;
+#pragma unroll
+    for (int q = 0; q < Nq; ++q) {
+      const int ni = ned == 0 ? edge_node(N, 0, N - q) : (ned == 1 ? edge_node(N, 1, N - q) : edge_node(N, 2, N - q));
+      gq[ed][q] = nb_el[ni];
+    }
+  }
+  // triangular-face neighbour nodes: the 2 NT face nodes of the element are
+  // shared out over its Nq lanes (surplus slots redo the last node)
+  V4<T> gt[per];
+#pragma unroll
+  for (int t = 0; t < per; ++t) {
+    const int fraw = j * per + t;
+    const int fnode = fraw < 2 * NT ? fraw : 2 * NT - 1;
+    const int face = fnode >= NT ? 1 : 0;
+    const int i = fnode - face * NT;
+    const int nbr = face ? cn[1] : cn[0];
+    const int pc = (code >> (3 * face)) & 7;
+    const int nlev = ((code >> (6 + face)) & 1) ? N : 0;
+    gt[t] = Uin[(nbr >= 0 ? int64_t(nbr) : e) * NP + nlev * NT + face_perm<N>(pc, i)];
+  }
+#pragma unroll
+  for (int k = 0; k < SU; ++k) {
+    const int idx = tid + 64 * k;
+    sU[idx < EPB * NP ? idx + (idx / NP) * (NPP - NP) : EPB * NPP] = rU[k];
+  }
+#pragma unroll
+  for (int k = 0; k < SL; ++k) {
+    const int idx = tid + 64 * k;
+    sX[idx < EPB * VL ? idx : EPB * C::XPE] = rL[k];
+  }
+#pragma unroll
+  for (int k = 0; k < SG; ++k) {
+    const int idx = tid + 64 * k;
+    sX[idx < EPB * VG ? EPB * VL + idx : EPB * C::XPE] = rG[k];
+  }
+  __syncthreads();
+
   const V4<T>* el = sU + le * NPP;
   const T* g = reinterpret_cast<const T*>(sG) + le * kGeoStride;
 
@@ -207,30 +305,21 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
       Bz[i] = -(tzJ * dP);
     }
 
-    const int* cn = reinterpret_cast<const int*>(sC) + le * kConnStride;
-    const int code = cn[5];
-
-    // quadrilateral faces (normals horizontal, so they reach p, u_x, u_y only).
-    // Boundary faces read the own element (a valid address) and blend in the
-    // mirror state arithmetically, without branches.
+    // quadrilateral faces (normals horizontal, so they reach p, u_x, u_y only);
+    // the mirror state of a boundary face is blended in without branches
 #pragma unroll
     for (int ed = 0; ed < 3; ++ed) {
-      const int nbr = cn[2 + ed];
-      const T w_in = nbr >= 0 ? T(1) : T(0);
-      const int ned = (code >> (8 + 2 * ed)) & 3;
+      const T w_in = cn[2 + ed] >= 0 ? T(1) : T(0);
       const T Ja = g[20 + 4 * ed], Jb = g[21 + 4 * ed];
       const T nx = g[22 + 4 * ed], ny = g[23 + 4 * ed];
-      const int64_t src_el = nbr >= 0 ? int64_t(nbr) : e;
       const T zs = g[34 + ed];  // Z- + Z+ (= 2 Z- on the boundary)
       const T taup = tau_on * T(2) / zs;
       const T tauu = tau_on * zs * T(0.5);
-      const V4<T>* nb_el = Uin + src_el * NP + j * NT;
       T fpa[Nq], fpb[Nq], fua[Nq], fub[Nq];
 #pragma unroll
       for (int q = 0; q < Nq; ++q) {
         const V4<T> own = el[j * NT + edge_node(N, ed, q)];
-        const int ni = ned == 0 ? edge_node(N, 0, N - q) : (ned == 1 ? edge_node(N, 1, N - q) : edge_node(N, 2, N - q));
-        const V4<T> v = nb_el[ni];
+        const V4<T> v = gq[ed][q];
         const T pm = own.p;
         const T unm = nx * own.ux + ny * own.uy;
         // mirror state: p+ = s p-, u_n+ = -s u_n- (s = -1 Dirichlet, +1 rigid)
@@ -262,27 +351,21 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
       }
     }
 
-    // triangular faces: their 2 NT nodes are shared out over the Nq lanes of
-    // the element; fluxes (premultiplied by J_f) go to LDS for every level
-    constexpr int per = (2 * NT + Nq - 1) / Nq;
+    // triangular-face fluxes (premultiplied by J_f) go to LDS for every level
 #pragma unroll
     for (int t = 0; t < per; ++t) {
       const int fraw = j * per + t;
-      const int fnode = fraw < 2 * NT ? fraw : 2 * NT - 1;  // surplus slots redo the last node
+      const int fnode = fraw < 2 * NT ? fraw : 2 * NT - 1;
       const int face = fnode >= NT ? 1 : 0;
       const int i = fnode - face * NT;
-      const int nbr = cn[face];
-      const T w_in = nbr >= 0 ? T(1) : T(0);
-      const int pc = (code >> (3 * face)) & 7;
-      const int nlev = ((code >> (6 + face)) & 1) ? N : 0;
+      const T w_in = (face ? cn[1] : cn[0]) >= 0 ? T(1) : T(0);
       const T* gf = g + 12 + 4 * face;
       const T Jf = gf[0], nx = gf[1], ny = gf[2], nz = gf[3];
-      const int64_t src_el = nbr >= 0 ? int64_t(nbr) : e;
       const T zs = g[32 + face];
       const T taup = tau_on * T(2) / zs;
       const T tauu = tau_on * zs * T(0.5);
       const V4<T> own = el[face * N * NT + i];
-      const V4<T> v = Uin[src_el * NP + nlev * NT + face_perm<N>(pc, i)];
+      const V4<T> v = gt[t];
       const T pm = own.p;
       const T unm = nx * own.ux + ny * own.uy + nz * own.uz;
       const T pb = bsign * pm, ub = -bsign * unm;
@@ -299,15 +382,13 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
   __syncthreads();
 
   const bool rd = (A.flags & kReadRes) != 0, wu = (A.flags & kWriteU) != 0;
-  V4<T>* __restrict__ res = static_cast<V4<T>*>(A.res) + e0 * NP;
+  const auto bres = chunk_rsrc(static_cast<V4<T>*>(A.res) + e0 * NP, int64_t(nE) * NP * V4B);
   // residual of the previous stage, in the coalesced layout of the update
+  // (read even when unused, so that no branch sits in front of the loads)
   V4<T> rprev[C::PREFETCH ? C::UPD : 1];
-  if (C::PREFETCH && rd) {
+  if constexpr (C::PREFETCH) {
 #pragma unroll
-    for (int k = 0; k < C::UPD; ++k) {
-      const int idx = tid + 64 * k;
-      if (idx < nE * NP) rprev[k] = res[idx];
-    }
+    for (int k = 0; k < C::UPD; ++k) rprev[k] = bload<T>(bres, tid + 64 * k);
   }
 
   T Rp[NT], Rz[NT], Rx[NT], Ry[NT];
@@ -413,26 +494,25 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
   __syncthreads();
 
   // low-storage Runge-Kutta update, coalesced over the chunk
-  const T ca = T(A.a), cb = T(A.b), dt = T(A.dt);
-  V4<T>* __restrict__ uo = static_cast<V4<T>*>(A.Uout) + e0 * NP;
+  const T ca = rd ? T(A.a) : T(0), cb = T(A.b), dt = T(A.dt);
+  const auto bout = chunk_rsrc(static_cast<V4<T>*>(A.Uout) + e0 * NP, int64_t(nE) * NP * V4B);
 #pragma unroll
   for (int k = 0; k < C::UPD; ++k) {
     const int idx = tid + 64 * k;
-    if (idx < nE * NP) {
-      const int l = idx + (idx / NP) * (NPP - NP);
-      const V4<T> R = sR[l];
-      V4<T> r;
-      if (rd) {
-        const V4<T> q = C::PREFETCH ? rprev[k] : res[idx];
-        r = V4<T>{ca * q.p + dt * R.p, ca * q.uz + dt * R.uz, ca * q.ux + dt * R.ux, ca * q.uy + dt * R.uy};
-      } else {
-        r = V4<T>{dt * R.p, dt * R.uz, dt * R.ux, dt * R.uy};
-      }
-      res[idx] = r;
-      if (wu) {
-        const V4<T> u = sU[l];
-        uo[idx] = V4<T>{u.p + cb * r.p, u.uz + cb * r.uz, u.ux + cb * r.ux, u.uy + cb * r.uy};
-      }
+    const int l = idx < nE * NP ? idx + (idx / NP) * (NPP - NP) : 0;
+    const V4<T> R = sR[l];
+    V4<T> q;
+    if constexpr (C::PREFETCH)
+      q = rprev[k];
+    else
+      q = bload<T>(bres, idx);
+    // the first stage ignores res entirely (it may hold anything)
+    if (!rd) q = V4<T>{T(0), T(0), T(0), T(0)};
+    const V4<T> r{ca * q.p + dt * R.p, ca * q.uz + dt * R.uz, ca * q.ux + dt * R.ux, ca * q.uy + dt * R.uy};
+    bstore<T>(bres, idx, r);
+    if (wu) {
+      const V4<T> u = sU[l];
+      bstore<T>(bout, idx, V4<T>{u.p + cb * r.p, u.uz + cb * r.uz, u.ux + cb * r.ux, u.uy + cb * r.uy});
     }
   }
 }
