@@ -29,16 +29,37 @@ def stage_bytes(N: int, bits: int, reads_res: bool) -> int:
     """Algorithmic HBM bytes of one stage for one wedge.
 
     State U read and U' written, residual written (and read after the first
-    stage): 4 fields x Np values each; per-element geometry record (32
-    values), triangular lift (Np_tri^2 padded to a multiple of 4) and
-    connectivity (8 int32).  Neighbour traces are counted as cache hits.
+    stage): 4 fields x Np values each; per-element geometry and material
+    record (40 values), triangular lift (Np_tri^2 padded to a multiple of 4)
+    and connectivity (8 int32).  Neighbour traces are counted as cache hits.
+    At N = 3 in FP32 this is 3152 B (2512 B in the first stage).
     """
     NT = (N + 1) * (N + 2) // 2
     NP = NT * (N + 1)
     ts = bits // 8
     LS = (NT * NT + 3) // 4 * 4
     state = 4 * NP * ts
-    return state * (3 + int(reads_res)) + 32 * ts + LS * ts + 8 * 4
+    return state * (3 + int(reads_res)) + 40 * ts + LS * ts + 8 * 4
+
+
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "wedge_stage_cfg2_traffic.json")
+KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1607_03399_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic(config: str):
+    """HBM bytes per stage launch from the committed FETCH_SIZE / WRITE_SIZE
+    counter runs, or None when the kernel source has changed since."""
+    import hashlib
+
+    if config != "cfg2" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        rec = json.load(f)
+    with open(KERNEL_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("kernel_sha256") != sha:
+        return None
+    return float(rec["bytes_per_launch"])
 
 
 def cpu_baseline(mesh, N: int, dt: float, seconds: float, sample: int):
@@ -192,7 +213,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(args.config),
             "measured_copy_GBs": copy_gbs,
         },
     }

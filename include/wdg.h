@@ -163,8 +163,11 @@ int wdg_get_element_data(const wdg_ctx* ctx, double* geo, double* lift);
  * inspection.  name: "r","s" (triangle nodes), "t" (GLL nodes), "Dr","Ds"
  * (Np_tri x Np_tri), "Dt","M1" (Nq x Nq), "Mtri", "Mv0","Mv1","Mv2"
  * (Np_tri x Np_tri, int l_a l_b lambda_v), "g0","gN" (Nq), "Ea0".."Ea2",
- * "Eb0".."Eb2" (Np_tri x Nq), "edge0".."edge2" (N+1 node ids).  Writes at
- * most cap values; *count receives the full size. */
+ * "Eb0".."Eb2" (Np_tri x Nq), "edge0".."edge2" (N+1 node ids); tetrahedron:
+ * "tet_r","tet_s","tet_t" (Np_tet nodes), "tet_Dr","tet_Ds","tet_Dt","tet_M"
+ * (Np_tet x Np_tet), "tet_LIFT" (Np_tet x 4 Np_tri), "tet_face0".."tet_face3"
+ * (Np_tri node ids).  Writes at most cap values; *count receives the full
+ * size. */
 int wdg_reference_operator(int order_N, const char* name, double* out, int64_t cap, int64_t* count);
 
 #ifdef __cplusplus

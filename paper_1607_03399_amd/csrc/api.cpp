@@ -20,6 +20,7 @@
 #include "wdg.h"
 
 using wdg::RefOps;
+using wdg::TetOps;
 
 namespace {
 
@@ -51,11 +52,15 @@ struct wdg_ctx {
   int N = 0, bits = 64, device = -1;
   bool host_only = true;
   std::unique_ptr<RefOps> ref;
+  std::unique_ptr<TetOps> tref;  // built on first use (meshes with tetrahedra)
   mutable std::string err;
   int state = kCreated;
-  int64_t K = 0;
-  std::vector<double> X;      // K x 6 x 3 vertex coordinates
-  std::vector<int32_t> conn;  // K x kConnStride
+  int64_t K = 0, Kw = 0, Kt = 0;  // elements: wedges first, then tetrahedra
+  std::vector<double> X;      // Kw x 6 x 3 wedge vertex coordinates
+  std::vector<double> Xt;     // Kt x 4 x 3 tetrahedron vertex coordinates
+  std::vector<int32_t> conn;  // Kw x kConnStride
+  std::vector<int32_t> connT;  // Kt x kTetConnStride
+  std::vector<double> geoT;   // Kt x kTetGeoStride (FP64 master copy)
   std::vector<double> c, rho;
   int bc = WDG_BC_RIGID, flux = WDG_FLUX_UPWIND;
   double time = 0.0;
@@ -67,16 +72,21 @@ struct wdg_ctx {
   int cur = 0;
   void* dGeo = nullptr;
   void* dL = nullptr;
-  void* dOps = nullptr;
   void* dSrcVec = nullptr;
   double* dAux = nullptr;
   double* dMv = nullptr;
   double* dM1 = nullptr;
   double* dPartial = nullptr;
   int32_t* dConn = nullptr;
+  void* dGeoT = nullptr;
+  void* dOpsT = nullptr;
+  double* dAuxT = nullptr;
+  double* dMt = nullptr;
+  int32_t* dConnT = nullptr;
   std::vector<Source> src;
   int64_t nrec = 0;
-  int* dRecElem = nullptr;
+  int64_t* dRecBase = nullptr;
+  int* dRecNN = nullptr;
   double* dRecRows = nullptr;
   double* dRecBuf = nullptr;
   int64_t rec_cap = 0, rec_steps = 0;
@@ -86,7 +96,12 @@ struct wdg_ctx {
 
   size_t tsize() const { return bits == 32 ? 4 : 8; }
   int NT() const { return ref->NT; }
-  int NP() const { return ref->NP; }
+  int NP() const { return ref->NP; }  // nodes of a wedge
+  int NPt() const { return (N + 1) * (N + 2) * (N + 3) / 6; }
+  int NPof(int64_t k) const { return k < Kw ? NP() : NPt(); }
+  // first node of element k in the node-major state layout
+  int64_t node_base(int64_t k) const { return k < Kw ? k * NP() : Kw * NP() + (k - Kw) * NPt(); }
+  int64_t nodes() const { return Kw * NP() + Kt * NPt(); }
 };
 
 namespace {
@@ -125,14 +140,19 @@ void release_device(wdg_ctx* ctx) {
   ctx->own_state = true;
   dfree(ctx->dGeo);
   dfree(ctx->dL);
-  dfree(ctx->dOps);
   dfree(ctx->dSrcVec);
   dfree(ctx->dAux);
   dfree(ctx->dMv);
   dfree(ctx->dM1);
   dfree(ctx->dPartial);
   dfree(ctx->dConn);
-  dfree(ctx->dRecElem);
+  dfree(ctx->dGeoT);
+  dfree(ctx->dOpsT);
+  dfree(ctx->dAuxT);
+  dfree(ctx->dMt);
+  dfree(ctx->dConnT);
+  dfree(ctx->dRecBase);
+  dfree(ctx->dRecNN);
   dfree(ctx->dRecRows);
   dfree(ctx->dRecBuf);
   ctx->rec_cap = 0;
@@ -162,9 +182,27 @@ void wedge_ref_coords(const double* Xk, const double* x, double& r, double& s, d
   t = 2.0 * (x[2] - zb) / (zt - zb) - 1.0;
 }
 
+// barycentric reference coordinates of x in affine tetrahedron k (r = 2 lambda_1 - 1, ...)
+void tet_ref_coords(const double* Xk, const double* x, double& r, double& s, double& t) {
+  double A[9], b[3];
+  for (int d = 0; d < 3; ++d) {
+    for (int v = 0; v < 3; ++v) A[d * 3 + v] = Xk[3 * (v + 1) + d] - Xk[d];
+    b[d] = x[d] - Xk[d];
+  }
+  std::vector<double> Am(A, A + 9), bv(b, b + 3);
+  if (!wdg::solve_dense(3, 1, Am, bv)) {
+    r = s = t = 1e300;
+    return;
+  }
+  r = 2.0 * bv[0] - 1.0;
+  s = 2.0 * bv[1] - 1.0;
+  t = 2.0 * bv[2] - 1.0;
+}
+
+// element containing x (lowest global id), with reference coordinates
 int64_t locate(const wdg_ctx* ctx, const double* x, double& r, double& s, double& t) {
   const double tol = 1e-12;
-  for (int64_t k = 0; k < ctx->K; ++k) {
+  for (int64_t k = 0; k < ctx->Kw; ++k) {
     double rr, ss, tt;
     wedge_ref_coords(&ctx->X[k * 18], x, rr, ss, tt);
     if (rr >= -1 - tol && ss >= -1 - tol && rr + ss <= tol && std::fabs(tt) <= 1 + tol) {
@@ -172,6 +210,16 @@ int64_t locate(const wdg_ctx* ctx, const double* x, double& r, double& s, double
       s = ss;
       t = tt;
       return k;
+    }
+  }
+  for (int64_t k = 0; k < ctx->Kt; ++k) {
+    double rr, ss, tt;
+    tet_ref_coords(&ctx->Xt[k * 12], x, rr, ss, tt);
+    if (rr >= -1 - tol && ss >= -1 - tol && tt >= -1 - tol && rr + ss + tt <= -1 + tol) {
+      r = rr;
+      s = ss;
+      t = tt;
+      return ctx->Kw + k;
     }
   }
   return -1;
@@ -187,8 +235,27 @@ void wedge_basis(const RefOps& R, double r, double s, double t, std::vector<doub
     for (int i = 0; i < R.NT; ++i) out[j * R.NT + i] = lt[i] * l1[j];
 }
 
-// kappa (M^k)^-1 l with M^k = M^{tri,k} (x) M^1D (Sec. 4.2)
+double tet_jacobian(const double* Xk) {
+  double a[3], b[3], c[3];
+  for (int d = 0; d < 3; ++d) {
+    a[d] = 0.5 * (Xk[3 + d] - Xk[d]);
+    b[d] = 0.5 * (Xk[6 + d] - Xk[d]);
+    c[d] = 0.5 * (Xk[9 + d] - Xk[d]);
+  }
+  return a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) + a[2] * (b[0] * c[1] - b[1] * c[0]);
+}
+
+// kappa (M^k)^-1 l(x_s): wedges M^k = M^{tri,k} (x) M^1D (Sec. 4.2); tetrahedra M^k = J M
 std::vector<double> mass_inverse_times(const wdg_ctx* ctx, int64_t k, double kappa, double r, double s, double t) {
+  if (k >= ctx->Kw) {
+    const TetOps& Tt = *ctx->tref;
+    std::vector<double> l(Tt.NP);
+    Tt.basis(r, s, t, l.data());
+    wdg::solve_dense(Tt.NP, 1, Tt.M, l);
+    const double J = tet_jacobian(&ctx->Xt[(k - ctx->Kw) * 12]);
+    for (auto& v : l) v *= kappa / J;
+    return l;
+  }
   const RefOps& R = *ctx->ref;
   const double* Xk = &ctx->X[k * 18];
   const double xr = 0.5 * (Xk[3] - Xk[0]), xs = 0.5 * (Xk[6] - Xk[0]);
@@ -213,7 +280,7 @@ std::vector<double> mass_inverse_times(const wdg_ctx* ctx, int64_t k, double kap
 template <typename T>
 void to_interleaved(const wdg_ctx* ctx, const double* p, const double* ux, const double* uy, const double* uz,
                     std::vector<unsigned char>& buf) {
-  const int64_t n = ctx->K * ctx->NP();
+  const int64_t n = ctx->nodes();
   buf.resize(size_t(n) * 4 * sizeof(T));
   T* o = reinterpret_cast<T*>(buf.data());
   for (int64_t m = 0; m < n; ++m) {  // device node layout: (p, u_z, u_x, u_y)
@@ -227,7 +294,7 @@ void to_interleaved(const wdg_ctx* ctx, const double* p, const double* ux, const
 template <typename T>
 void from_interleaved(const wdg_ctx* ctx, const std::vector<unsigned char>& buf, double* p, double* ux, double* uy,
                       double* uz) {
-  const int64_t n = ctx->K * ctx->NP();
+  const int64_t n = ctx->nodes();
   const T* o = reinterpret_cast<const T*>(buf.data());
   for (int64_t m = 0; m < n; ++m) {
     if (p) p[m] = double(o[4 * m]);
@@ -247,7 +314,7 @@ int upload_state(wdg_ctx* ctx, void* dst, const double* p, const double* ux, con
 }
 
 int download_state(const wdg_ctx* ctx, const void* src, double* p, double* ux, double* uy, double* uz) {
-  std::vector<unsigned char> buf(size_t(ctx->K * ctx->NP()) * 4 * ctx->tsize());
+  std::vector<unsigned char> buf(size_t(ctx->nodes()) * 4 * ctx->tsize());
   HIPCHK(hipMemcpyAsync(buf.data(), src, buf.size(), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (ctx->bits == 32) from_interleaved<float>(ctx, buf, p, ux, uy, uz);
@@ -260,7 +327,7 @@ int upload_sources(wdg_ctx* ctx) {
   const int NP = ctx->NP();
   std::vector<unsigned char> buf(size_t(wdg::kMaxSources) * NP * ctx->tsize(), 0);
   for (size_t s = 0; s < ctx->src.size(); ++s)
-    for (int n = 0; n < NP; ++n) {
+    for (int n = 0; n < int(ctx->src[s].vec.size()); ++n) {
       if (ctx->bits == 32) reinterpret_cast<float*>(buf.data())[s * NP + n] = float(ctx->src[s].vec[n]);
       else reinterpret_cast<double*>(buf.data())[s * NP + n] = ctx->src[s].vec[n];
     }
@@ -279,7 +346,9 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.geo = ctx->dGeo;
   L.L = ctx->dL;
   L.conn = ctx->dConn;
-  L.ops = ctx->dOps;
+  L.geoT = ctx->dGeoT;
+  L.connT = ctx->dConnT;
+  L.opsT = ctx->dOpsT;
   L.srcvec = ctx->dSrcVec;
   L.nsrc = int(ctx->src.size());
   for (int s = 0; s < L.nsrc; ++s) {
@@ -289,7 +358,8 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.a = a;
   L.b = b;
   L.dt = dt;
-  L.K = ctx->K;
+  L.Kw = ctx->Kw;
+  L.Kt = ctx->Kt;
   L.flags = flags | (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
             (ctx->flux == WDG_FLUX_CENTRAL ? wdg::kCentral : 0);
   if (ctx->timing) {
@@ -322,6 +392,28 @@ int ensure_receiver_capacity(wdg_ctx* ctx, int64_t steps_needed) {
   dfree(ctx->dRecBuf);
   ctx->dRecBuf = nb;
   ctx->rec_cap = cap;
+  return WDG_OK;
+}
+
+// tetrahedron geometry and material records (FP64 master copy -> device precision)
+int upload_tet_geometry(wdg_ctx* ctx) {
+  if (ctx->host_only || ctx->Kt == 0) return WDG_OK;
+  const size_t n = ctx->geoT.size();
+  std::vector<unsigned char> buf(n * ctx->tsize());
+  for (size_t i = 0; i < n; ++i) {
+    if (ctx->bits == 32) reinterpret_cast<float*>(buf.data())[i] = float(ctx->geoT[i]);
+    else reinterpret_cast<double*>(buf.data())[i] = ctx->geoT[i];
+  }
+  std::vector<double> aux(size_t(ctx->Kt) * wdg::kTetAuxStride, 0.0);
+  for (int64_t k = 0; k < ctx->Kt; ++k) {
+    const int64_t g = ctx->Kw + k;
+    aux[k * wdg::kTetAuxStride] = tet_jacobian(&ctx->Xt[k * 12]);
+    aux[k * wdg::kTetAuxStride + 1] = ctx->rho[g] * ctx->c[g] * ctx->c[g];
+    aux[k * wdg::kTetAuxStride + 2] = ctx->rho[g];
+  }
+  HIPCHK(hipMemcpyAsync(ctx->dGeoT, buf.data(), buf.size(), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->dAuxT, aux.data(), aux.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
   return WDG_OK;
 }
 
@@ -375,15 +467,14 @@ const char* wdg_last_error(const wdg_ctx* ctx) {
 int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const int64_t* wedge_v, int64_t nt,
                  const int64_t* tet_v) {
   if (!ctx) return WDG_ERR_ARG;
-  (void)tet_v;
-  if (nv <= 0 || !vxyz || nw <= 0 || !wedge_v || nt < 0) return fail(ctx, WDG_ERR_ARG, "bad mesh arguments");
-  if (nt > 0) return fail(ctx, WDG_ERR_ARG, "tetrahedra are not supported in this version");
-  if (nw > (int64_t(1) << 31) / 8) return fail(ctx, WDG_ERR_ARG, "too many elements");
+  if (nv <= 0 || !vxyz || nw < 0 || nt < 0 || nw + nt <= 0 || (nw > 0 && !wedge_v) || (nt > 0 && !tet_v))
+    return fail(ctx, WDG_ERR_ARG, "bad mesh arguments");
+  if (nw + nt > (int64_t(1) << 31) / 8) return fail(ctx, WDG_ERR_ARG, "too many elements");
   for (int64_t i = 0; i < nv * 3; ++i)
     if (!std::isfinite(vxyz[i])) return fail(ctx, WDG_ERR_ARG, "non-finite vertex coordinate");
-  const int64_t K = nw;
-  std::vector<double> X(size_t(K) * 18);
-  for (int64_t k = 0; k < K; ++k) {
+  const int64_t Kw = nw, Kt = nt, K = nw + nt;
+  std::vector<double> X(size_t(Kw) * 18), Xt(size_t(Kt) * 12);
+  for (int64_t k = 0; k < Kw; ++k) {
     for (int v = 0; v < 6; ++v) {
       const int64_t id = wedge_v[k * 6 + v];
       if (id < 0 || id >= nv) return fail(ctx, WDG_ERR_ARG, "vertex id out of range in wedge " + std::to_string(k));
@@ -409,53 +500,96 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
       if (x[3 * (v + 3) + 2] - x[3 * v + 2] <= 1e-14 * h)
         return fail(ctx, WDG_ERR_JACOBIAN, "wedge " + std::to_string(k) + " has a non-positive vertical edge");
   }
+  for (int64_t k = 0; k < Kt; ++k) {
+    for (int v = 0; v < 4; ++v) {
+      const int64_t id = tet_v[k * 4 + v];
+      if (id < 0 || id >= nv) return fail(ctx, WDG_ERR_ARG, "vertex id out of range in tetrahedron " + std::to_string(k));
+      for (int d = 0; d < 3; ++d) Xt[k * 12 + 3 * v + d] = vxyz[id * 3 + d];
+    }
+    const double* x = &Xt[k * 12];
+    double h = 0.0;
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b) {
+        double d2 = 0;
+        for (int d = 0; d < 3; ++d) d2 += (x[3 * a + d] - x[3 * b + d]) * (x[3 * a + d] - x[3 * b + d]);
+        h = std::max(h, std::sqrt(d2));
+      }
+    const double J = tet_jacobian(x);
+    if (std::fabs(J) <= 1e-14 * h * h * h)
+      return fail(ctx, WDG_ERR_JACOBIAN, "tetrahedron " + std::to_string(k) + " is degenerate");
+    if (J < 0) return fail(ctx, WDG_ERR_ORIENTATION, "tetrahedron " + std::to_string(k) + " is negatively oriented");
+  }
 
-  // face matching by sorted vertex ids
+  // face matching by sorted vertex ids; face id = element * 5 + local face
   static const int kFaceVerts[5][4] = {{0, 1, 2, -1}, {3, 4, 5, -1}, {0, 1, 4, 3}, {1, 2, 5, 4}, {2, 0, 3, 5}};
+  auto face_vertex = [&](int64_t k, int f, int m) -> int64_t {
+    return k < Kw ? wedge_v[k * 6 + kFaceVerts[f][m]] : tet_v[(k - Kw) * 4 + wdg::kTetFaceVerts[f][m]];
+  };
   struct FaceKey {
     std::array<int64_t, 4> key;
-    int64_t id;  // k * 5 + f
+    int64_t id;
   };
-  std::vector<FaceKey> faces(size_t(K) * 5);
-  for (int64_t k = 0; k < K; ++k)
-    for (int f = 0; f < 5; ++f) {
+  std::vector<FaceKey> faces;
+  faces.reserve(size_t(Kw) * 5 + size_t(Kt) * 4);
+  for (int64_t k = 0; k < K; ++k) {
+    const int nf = k < Kw ? 5 : 4;
+    for (int f = 0; f < nf; ++f) {
       std::array<int64_t, 4> kk{-1, -1, -1, -1};
-      const int nvf = f < 2 ? 3 : 4;
-      for (int m = 0; m < nvf; ++m) kk[m] = wedge_v[k * 6 + kFaceVerts[f][m]];
+      const int nvf = (k < Kw && f >= 2) ? 4 : 3;
+      for (int m = 0; m < nvf; ++m) kk[m] = face_vertex(k, f, m);
       std::sort(kk.begin(), kk.begin() + nvf);
       if (nvf == 3) kk = {-1, kk[0], kk[1], kk[2]};
-      faces[k * 5 + f] = {kk, k * 5 + f};
+      faces.push_back({kk, k * 5 + f});
     }
+  }
   std::sort(faces.begin(), faces.end(), [](const FaceKey& a, const FaceKey& b) { return a.key < b.key; });
-  std::vector<int32_t> conn(size_t(K) * wdg::kConnStride, 0);
-  for (int64_t k = 0; k < K; ++k)
+  std::vector<int32_t> conn(size_t(Kw) * wdg::kConnStride, 0), connT(size_t(Kt) * wdg::kTetConnStride, 0);
+  for (int64_t k = 0; k < Kw; ++k)
     for (int f = 0; f < 5; ++f) conn[k * wdg::kConnStride + f] = -1;
+  for (int64_t k = 0; k < Kt; ++k)
+    for (int f = 0; f < 4; ++f) connT[k * wdg::kTetConnStride + f] = -1;
+  std::vector<std::array<int64_t, 4>> open_tri;  // unmatched triangular faces
   for (size_t a = 0; a < faces.size();) {
     size_t b = a + 1;
     while (b < faces.size() && faces[b].key == faces[a].key) ++b;
     if (b - a > 2) return fail(ctx, WDG_ERR_NONCONFORMING, "a face is shared by more than two elements");
+    if (b - a == 1 && faces[a].key[0] < 0) open_tri.push_back(faces[a].key);
     if (b - a == 2) {
       for (int side = 0; side < 2; ++side) {
         const int64_t me = faces[a + side].id, other = faces[a + 1 - side].id;
         const int64_t k1 = me / 5, k2 = other / 5;
         const int f1 = int(me % 5), f2 = int(other % 5);
-        int32_t* cn = &conn[k1 * wdg::kConnStride];
-        cn[f1] = int32_t(k2);
-        if (f1 < 2) {
+        const bool tri = k1 >= Kw || f1 < 2;
+        if (tri) {
+          // vertex permutation between the two numberings of the shared triangle
           int pi[3];
           for (int v = 0; v < 3; ++v) {
-            const int64_t gid = wedge_v[k1 * 6 + kFaceVerts[f1][v]];
+            const int64_t gid = face_vertex(k1, f1, v);
             pi[v] = -1;
             for (int m = 0; m < 3; ++m)
-              if (wedge_v[k2 * 6 + kFaceVerts[f2][m]] == gid) pi[v] = m;
+              if (face_vertex(k2, f2, m) == gid) pi[v] = m;
           }
           int code = -1;
           for (int p = 0; p < 6; ++p)
             if (wdg::kPerm[p][0] == pi[0] && wdg::kPerm[p][1] == pi[1] && wdg::kPerm[p][2] == pi[2]) code = p;
           if (code < 0) return fail(ctx, WDG_ERR_NONCONFORMING, "triangular face vertex mismatch");
-          cn[5] |= code << (3 * f1);
-          if (f2 == 1) cn[5] |= 1 << (6 + f1);
+          if (k1 < Kw) {
+            int32_t* cn = &conn[k1 * wdg::kConnStride];
+            cn[f1] = int32_t(k2);
+            cn[5] |= code << (3 * f1);
+            if (k2 < Kw) {
+              if (f2 == 1) cn[5] |= 1 << (6 + f1);
+            } else {
+              cn[5] |= f2 << (14 + 2 * f1);
+            }
+          } else {
+            int32_t* cn = &connT[(k1 - Kw) * wdg::kTetConnStride];
+            cn[f1] = int32_t(k2);
+            cn[4] |= (code | (f2 << 3)) << (5 * f1);
+          }
         } else {
+          int32_t* cn = &conn[k1 * wdg::kConnStride];
+          cn[f1] = int32_t(k2);
           const int e1 = f1 - 2, e2 = f2 - 2;
           const int64_t A = wedge_v[k1 * 6 + e1], B = wedge_v[k1 * 6 + (e1 + 1) % 3];
           const int64_t A2 = wedge_v[k2 * 6 + e2], B2 = wedge_v[k2 * 6 + (e2 + 1) % 3];
@@ -467,15 +601,79 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
     }
     a = b;
   }
+  // a wedge's quadrilateral face left open while triangles on its vertices are
+  // open too would be a quadrilateral against split triangles: not conforming
+  if (Kt > 0 && !open_tri.empty()) {
+    std::sort(open_tri.begin(), open_tri.end());
+    for (int64_t k = 0; k < Kw; ++k)
+      for (int f = 2; f < 5; ++f) {
+        if (conn[k * wdg::kConnStride + f] >= 0) continue;
+        int64_t v4[4];
+        for (int m = 0; m < 4; ++m) v4[m] = face_vertex(k, f, m);
+        for (int skip = 0; skip < 4; ++skip) {
+          std::array<int64_t, 4> t{-1, 0, 0, 0};
+          int n = 1;
+          for (int m = 0; m < 4; ++m)
+            if (m != skip) t[n++] = v4[m];
+          std::sort(t.begin() + 1, t.end());
+          if (std::binary_search(open_tri.begin(), open_tri.end(), t))
+            return fail(ctx, WDG_ERR_NONCONFORMING,
+                        "wedge " + std::to_string(k) + " has a quadrilateral face against triangular faces");
+        }
+      }
+  }
+
+  // tetrahedron geometry (affine: constant metric, planar faces)
+  std::vector<double> geoT(size_t(Kt) * wdg::kTetGeoStride, 0.0);
+  for (int64_t k = 0; k < Kt; ++k) {
+    const double* x = &Xt[k * 12];
+    double Jm[3][3];  // d x_d / d (r, s, t)
+    for (int d = 0; d < 3; ++d)
+      for (int c = 0; c < 3; ++c) Jm[d][c] = 0.5 * (x[3 * (c + 1) + d] - x[d]);
+    const double J = tet_jacobian(x);
+    double* g = &geoT[k * wdg::kTetGeoStride];
+    // inverse metric: row c of the inverse is grad of reference coordinate c
+    for (int c = 0; c < 3; ++c)
+      for (int d = 0; d < 3; ++d) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3, d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+        g[3 * c + d] = (Jm[d1][c1] * Jm[d2][c2] - Jm[d1][c2] * Jm[d2][c1]) / J;
+      }
+    g[9] = g[10] = g[11] = 1.0;
+    for (int f = 0; f < 4; ++f) {
+      const int* fv = wdg::kTetFaceVerts[f];
+      int opp = 0 + 1 + 2 + 3 - fv[0] - fv[1] - fv[2];
+      double u[3], w[3], n[3];
+      for (int d = 0; d < 3; ++d) {
+        u[d] = x[3 * fv[1] + d] - x[3 * fv[0] + d];
+        w[d] = x[3 * fv[2] + d] - x[3 * fv[0] + d];
+      }
+      n[0] = u[1] * w[2] - u[2] * w[1];
+      n[1] = u[2] * w[0] - u[0] * w[2];
+      n[2] = u[0] * w[1] - u[1] * w[0];
+      const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      double side = 0;
+      for (int d = 0; d < 3; ++d) side += n[d] * (x[3 * opp + d] - x[3 * fv[0] + d]);
+      const double sg = side > 0 ? -1.0 : 1.0;  // outward
+      g[12 + 4 * f] = (0.25 * nn) / J;          // J_f / J, J_f = area / 2
+      for (int d = 0; d < 3; ++d) g[13 + 4 * f + d] = sg * n[d] / nn;
+      g[28 + f] = 2.0;
+    }
+  }
 
   // accept: replace any previous mesh
-  if (!ctx->host_only && ctx->dGeo) {
+  if (!ctx->host_only && (ctx->dGeo || ctx->dGeoT)) {
     (void)hipSetDevice(ctx->device);
     release_device(ctx);
   }
+  if (Kt > 0 && !ctx->tref) ctx->tref = std::make_unique<TetOps>(ctx->N);
   ctx->K = K;
+  ctx->Kw = Kw;
+  ctx->Kt = Kt;
   ctx->X.swap(X);
+  ctx->Xt.swap(Xt);
   ctx->conn.swap(conn);
+  ctx->connT.swap(connT);
+  ctx->geoT.swap(geoT);
   ctx->c.assign(size_t(K), 1.0);
   ctx->rho.assign(size_t(K), 1.0);
   ctx->src.clear();
@@ -493,43 +691,70 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
   HIPCHK(hipSetDevice(ctx->device));
   const RefOps& R = *ctx->ref;
   const size_t ts = ctx->tsize();
-  const size_t nstate = size_t(K) * R.NP * 4 * ts;
+  const size_t nstate = size_t(ctx->nodes()) * 4 * ts;
   const int LS = wdg::lift_stride(ctx->N);
+  const size_t kw1 = size_t(std::max<int64_t>(Kw, 1));
   HIPCHK(hipMalloc(&ctx->dU[0], nstate));
   HIPCHK(hipMalloc(&ctx->dU[1], nstate));
   HIPCHK(hipMalloc(&ctx->dRes, nstate));
-  HIPCHK(hipMalloc(&ctx->dGeo, size_t(K) * wdg::kGeoStride * ts));
-  HIPCHK(hipMalloc(&ctx->dL, size_t(K) * LS * ts));
-  HIPCHK(hipMalloc(&ctx->dAux, size_t(K) * wdg::kAuxStride * sizeof(double)));
-  HIPCHK(hipMalloc(&ctx->dConn, size_t(K) * wdg::kConnStride * sizeof(int32_t)));
-  HIPCHK(hipMalloc(&ctx->dOps, wdg::ops_bytes(ctx->N)));
+  HIPCHK(hipMalloc(&ctx->dGeo, kw1 * wdg::kGeoStride * ts));
+  HIPCHK(hipMalloc(&ctx->dL, kw1 * LS * ts));
+  HIPCHK(hipMalloc(&ctx->dAux, kw1 * wdg::kAuxStride * sizeof(double)));
+  HIPCHK(hipMalloc(&ctx->dConn, kw1 * wdg::kConnStride * sizeof(int32_t)));
   HIPCHK(hipMalloc(&ctx->dMv, 3 * size_t(R.NT) * R.NT * sizeof(double)));
   HIPCHK(hipMalloc(&ctx->dM1, size_t(R.Nq) * R.Nq * sizeof(double)));
-  HIPCHK(hipMalloc(&ctx->dPartial, 1024 * sizeof(double)));
+  HIPCHK(hipMalloc(&ctx->dPartial, 2048 * sizeof(double)));
   HIPCHK(hipMalloc(&ctx->dSrcVec, size_t(wdg::kMaxSources) * R.NP * ts));
   HIPCHK(hipMemsetAsync(ctx->dU[0], 0, nstate, ctx->stream));
   HIPCHK(hipMemsetAsync(ctx->dU[1], 0, nstate, ctx->stream));
   HIPCHK(hipMemsetAsync(ctx->dRes, 0, nstate, ctx->stream));
   HIPCHK(hipMemsetAsync(ctx->dSrcVec, 0, size_t(wdg::kMaxSources) * R.NP * ts, ctx->stream));
 
-  std::vector<unsigned char> ops(wdg::ops_bytes(ctx->N));
-  wdg::fill_ops(ctx->N, ops.data(), R.perm.data());
   std::vector<double> Mv(3 * size_t(R.NT) * R.NT);
   for (int v = 0; v < 3; ++v) std::copy(R.Mv[v].begin(), R.Mv[v].end(), Mv.begin() + v * R.NT * R.NT);
-  double *dX = nullptr, *dMtri = nullptr;
-  HIPCHK(hipMalloc(&dX, ctx->X.size() * sizeof(double)));
-  HIPCHK(hipMalloc(&dMtri, R.Mtri.size() * sizeof(double)));
-  HIPCHK(hipMemcpyAsync(ctx->dOps, ops.data(), ops.size(), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->dMv, Mv.data(), Mv.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->dM1, R.M1.data(), R.M1.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipMemcpyAsync(dX, ctx->X.data(), ctx->X.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipMemcpyAsync(dMtri, R.Mtri.data(), R.Mtri.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipMemcpyAsync(ctx->dConn, ctx->conn.data(), ctx->conn.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                        ctx->stream));
-  HIPCHK(wdg::launch_setup(ctx->N, ctx->bits, K, dX, ctx->dMv, dMtri, ctx->dGeo, ctx->dL, ctx->dAux, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
-  HIPCHK(hipFree(dX));
-  HIPCHK(hipFree(dMtri));
+  if (Kw > 0) {
+    double *dX = nullptr, *dMtri = nullptr;
+    HIPCHK(hipMalloc(&dX, ctx->X.size() * sizeof(double)));
+    HIPCHK(hipMalloc(&dMtri, R.Mtri.size() * sizeof(double)));
+    HIPCHK(hipMemcpyAsync(dX, ctx->X.data(), ctx->X.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(dMtri, R.Mtri.data(), R.Mtri.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->dConn, ctx->conn.data(), ctx->conn.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(wdg::launch_setup(ctx->N, ctx->bits, Kw, dX, ctx->dMv, dMtri, ctx->dGeo, ctx->dL, ctx->dAux, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipFree(dX));
+    HIPCHK(hipFree(dMtri));
+  }
+  if (Kt > 0) {
+    const TetOps& Tt = *ctx->tref;
+    const int NPt = Tt.NP, NT = R.NT;
+    HIPCHK(hipMalloc(&ctx->dGeoT, size_t(Kt) * wdg::kTetGeoStride * ts));
+    HIPCHK(hipMalloc(&ctx->dConnT, size_t(Kt) * wdg::kTetConnStride * sizeof(int32_t)));
+    HIPCHK(hipMalloc(&ctx->dAuxT, size_t(Kt) * wdg::kTetAuxStride * sizeof(double)));
+    const size_t nops = 3 * size_t(NPt) * NPt + size_t(NPt) * 4 * NT;
+    HIPCHK(hipMalloc(&ctx->dOpsT, nops * ts));
+    HIPCHK(hipMalloc(&ctx->dMt, size_t(NPt) * NPt * sizeof(double)));
+    std::vector<double> ops;
+    ops.reserve(nops);
+    ops.insert(ops.end(), Tt.Dr.begin(), Tt.Dr.end());
+    ops.insert(ops.end(), Tt.Ds.begin(), Tt.Ds.end());
+    ops.insert(ops.end(), Tt.Dt.begin(), Tt.Dt.end());
+    ops.insert(ops.end(), Tt.LIFT.begin(), Tt.LIFT.end());
+    std::vector<unsigned char> buf(nops * ts);
+    for (size_t i = 0; i < nops; ++i) {
+      if (ctx->bits == 32) reinterpret_cast<float*>(buf.data())[i] = float(ops[i]);
+      else reinterpret_cast<double*>(buf.data())[i] = ops[i];
+    }
+    HIPCHK(hipMemcpyAsync(ctx->dOpsT, buf.data(), buf.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->dMt, Tt.M.data(), Tt.M.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->dConnT, ctx->connT.data(), ctx->connT.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    int rc = upload_tet_geometry(ctx);
+    if (rc) return rc;
+  }
   ctx->state = kMesh;
   return WDG_OK;
 }
@@ -545,21 +770,39 @@ int wdg_set_material(wdg_ctx* ctx, const double* c, const double* rho) {
   ctx->rho.assign(rho, rho + ctx->K);
   for (auto& s : ctx->src) {
     double r, ss, t;
-    wedge_ref_coords(&ctx->X[s.elem * 18], s.xyz, r, ss, t);
+    if (s.elem < ctx->Kw) wedge_ref_coords(&ctx->X[s.elem * 18], s.xyz, r, ss, t);
+    else tet_ref_coords(&ctx->Xt[(s.elem - ctx->Kw) * 12], s.xyz, r, ss, t);
     s.vec = mass_inverse_times(ctx, s.elem, ctx->rho[s.elem] * ctx->c[s.elem] * ctx->c[s.elem], r, ss, t);
+  }
+  // tetrahedron material slots: kappa, 1/rho, rho c and the impedance sums per face
+  for (int64_t k = 0; k < ctx->Kt; ++k) {
+    const int64_t gk = ctx->Kw + k;
+    double* g = &ctx->geoT[k * wdg::kTetGeoStride];
+    const double Z = ctx->rho[gk] * ctx->c[gk];
+    g[9] = ctx->rho[gk] * ctx->c[gk] * ctx->c[gk];
+    g[10] = 1.0 / ctx->rho[gk];
+    g[11] = Z;
+    for (int f = 0; f < 4; ++f) {
+      const int nb = ctx->connT[k * wdg::kTetConnStride + f];
+      g[28 + f] = Z + (nb >= 0 ? ctx->rho[nb] * ctx->c[nb] : Z);
+    }
   }
   if (!ctx->host_only) {
     HIPCHK(hipSetDevice(ctx->device));
-    double *dc = nullptr, *dr = nullptr;
-    HIPCHK(hipMalloc(&dc, ctx->K * sizeof(double)));
-    HIPCHK(hipMalloc(&dr, ctx->K * sizeof(double)));
-    HIPCHK(hipMemcpyAsync(dc, c, ctx->K * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(hipMemcpyAsync(dr, rho, ctx->K * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(wdg::launch_material(ctx->bits, ctx->K, dc, dr, ctx->dConn, ctx->dGeo, ctx->dAux, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    HIPCHK(hipFree(dc));
-    HIPCHK(hipFree(dr));
-    int rc = upload_sources(ctx);
+    if (ctx->Kw > 0) {
+      double *dc = nullptr, *dr = nullptr;
+      HIPCHK(hipMalloc(&dc, ctx->K * sizeof(double)));
+      HIPCHK(hipMalloc(&dr, ctx->K * sizeof(double)));
+      HIPCHK(hipMemcpyAsync(dc, c, ctx->K * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+      HIPCHK(hipMemcpyAsync(dr, rho, ctx->K * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+      HIPCHK(wdg::launch_material(ctx->bits, ctx->Kw, dc, dr, ctx->dConn, ctx->dGeo, ctx->dAux, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      HIPCHK(hipFree(dc));
+      HIPCHK(hipFree(dr));
+    }
+    int rc = upload_tet_geometry(ctx);
+    if (rc) return rc;
+    rc = upload_sources(ctx);
     if (rc) return rc;
   }
   ctx->state = std::max(ctx->state, int(kMaterial));
@@ -583,7 +826,7 @@ int wdg_set_flux(wdg_ctx* ctx, int flux) {
 int wdg_num_nodes(const wdg_ctx* ctx, int64_t* n) {
   if (!ctx || !n) return WDG_ERR_ARG;
   if (ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "no mesh");
-  *n = ctx->K * ctx->NP();
+  *n = ctx->nodes();
   return WDG_OK;
 }
 
@@ -591,7 +834,21 @@ int wdg_get_node_coords(const wdg_ctx* ctx, double* xyz) {
   if (!ctx || !xyz) return WDG_ERR_ARG;
   if (ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "no mesh");
   const RefOps& R = *ctx->ref;
-  for (int64_t k = 0; k < ctx->K; ++k) {
+  for (int64_t k = 0; k < ctx->Kt; ++k) {
+    const TetOps& Tt = *ctx->tref;
+    const double* x = &ctx->Xt[k * 12];
+    for (int i = 0; i < Tt.NP; ++i) {
+      const double lam[4] = {-(1.0 + Tt.r[i] + Tt.s[i] + Tt.t[i]) / 2.0, (1.0 + Tt.r[i]) / 2.0, (1.0 + Tt.s[i]) / 2.0,
+                             (1.0 + Tt.t[i]) / 2.0};
+      double* o = xyz + 3 * (ctx->node_base(ctx->Kw + k) + i);
+      for (int d = 0; d < 3; ++d) {
+        double acc = 0;
+        for (int v = 0; v < 4; ++v) acc += lam[v] * x[3 * v + d];
+        o[d] = acc;
+      }
+    }
+  }
+  for (int64_t k = 0; k < ctx->Kw; ++k) {
     const double* x = &ctx->X[k * 18];
     for (int j = 0; j < R.Nq; ++j)
       for (int i = 0; i < R.NT; ++i) {
@@ -613,7 +870,7 @@ int wdg_set_fields(wdg_ctx* ctx, const double* p, const double* ux, const double
   if (ctx->state < kMaterial) return fail(ctx, WDG_ERR_STATE, "set_fields before set_material");
   if (!p || !ux || !uy || !uz) return fail(ctx, WDG_ERR_ARG, "null field array");
   if (ctx->host_only) return fail(ctx, WDG_ERR_STATE, "host-only context cannot hold fields");
-  const int64_t n = ctx->K * ctx->NP();
+  const int64_t n = ctx->nodes();
   if (!finite_all(p, n) || !finite_all(ux, n) || !finite_all(uy, n) || !finite_all(uz, n))
     return fail(ctx, WDG_ERR_UNSTABLE, "non-finite field values");
   HIPCHK(hipSetDevice(ctx->device));
@@ -641,7 +898,7 @@ int wdg_bind_device_state(wdg_ctx* ctx, void* d_U, void* d_res, void* hip_stream
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   if (!d_U) return WDG_OK;
-  const size_t nstate = size_t(ctx->K) * ctx->NP() * 4 * ctx->tsize();
+  const size_t nstate = size_t(ctx->nodes()) * 4 * ctx->tsize();
   HIPCHK(hipMemcpyAsync(d_U, ctx->dU[ctx->cur], nstate, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(d_res, ctx->dRes, nstate, hipMemcpyDeviceToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -687,15 +944,22 @@ int wdg_set_receivers(wdg_ctx* ctx, int64_t n, const double* xyz) {
   if (ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "receivers before set_mesh");
   if (n < 0 || (n > 0 && !xyz)) return fail(ctx, WDG_ERR_ARG, "bad receivers");
   const RefOps& R = *ctx->ref;
-  std::vector<int> el(static_cast<size_t>(n));
-  std::vector<double> rows(static_cast<size_t>(n) * R.NP);
+  std::vector<int64_t> base(static_cast<size_t>(n));
+  std::vector<int> nn(static_cast<size_t>(n));
+  std::vector<double> rows(static_cast<size_t>(n) * R.NP, 0.0);
   for (int64_t q = 0; q < n; ++q) {
     double r, s, t;
     const int64_t k = locate(ctx, xyz + 3 * q, r, s, t);
     if (k < 0) return fail(ctx, WDG_ERR_OUTSIDE, "receiver " + std::to_string(q) + " outside the mesh");
-    el[q] = int(k);
+    base[q] = ctx->node_base(k);
+    nn[q] = ctx->NPof(k);
     std::vector<double> b;
-    wedge_basis(R, r, s, t, b);
+    if (k < ctx->Kw) {
+      wedge_basis(R, r, s, t, b);
+    } else {
+      b.resize(ctx->tref->NP);
+      ctx->tref->basis(r, s, t, b.data());
+    }
     std::copy(b.begin(), b.end(), rows.begin() + q * R.NP);
   }
   ctx->rec_steps = 0;
@@ -705,15 +969,18 @@ int wdg_set_receivers(wdg_ctx* ctx, int64_t n, const double* xyz) {
   }
   HIPCHK(hipSetDevice(ctx->device));
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  dfree(ctx->dRecElem);
+  dfree(ctx->dRecBase);
+  dfree(ctx->dRecNN);
   dfree(ctx->dRecRows);
   dfree(ctx->dRecBuf);
   ctx->rec_cap = 0;
   ctx->nrec = n;
   if (n == 0) return WDG_OK;
-  HIPCHK(hipMalloc(&ctx->dRecElem, el.size() * sizeof(int)));
+  HIPCHK(hipMalloc(&ctx->dRecBase, base.size() * sizeof(int64_t)));
+  HIPCHK(hipMalloc(&ctx->dRecNN, nn.size() * sizeof(int)));
   HIPCHK(hipMalloc(&ctx->dRecRows, rows.size() * sizeof(double)));
-  HIPCHK(hipMemcpyAsync(ctx->dRecElem, el.data(), el.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->dRecBase, base.data(), base.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->dRecNN, nn.data(), nn.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->dRecRows, rows.data(), rows.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return WDG_OK;
@@ -736,7 +1003,13 @@ int wdg_stable_dt(const wdg_ctx* ctx, double cfl, double* dt) {
   if (!(cfl > 0)) return fail(ctx, WDG_ERR_ARG, "cfl must be positive");
   const int N = ctx->N;
   double worst = 0.0;
-  for (int64_t k = 0; k < ctx->K; ++k) {
+  for (int64_t k = 0; k < ctx->Kt; ++k) {
+    // affine tetrahedron: J and J_f constant; J_f / J is stored per face
+    double ratio = 0.0;
+    for (int f = 0; f < 4; ++f) ratio = std::max(ratio, ctx->geoT[k * wdg::kTetGeoStride + 12 + 4 * f]);
+    worst = std::max(worst, ctx->c[ctx->Kw + k] * (N + 1.0) * (N + 3.0) / 3.0 * ratio);
+  }
+  for (int64_t k = 0; k < ctx->Kw; ++k) {
     const double* x = &ctx->X[k * 18];
     const double xr = 0.5 * (x[3] - x[0]), xs = 0.5 * (x[6] - x[0]);
     const double yr = 0.5 * (x[4] - x[1]), ys = 0.5 * (x[7] - x[1]);
@@ -782,8 +1055,8 @@ int wdg_step(wdg_ctx* ctx, int64_t nsteps, double dt) {
       ctx->cur = 1 - ctx->cur;
     }
     if (ctx->nrec > 0) {
-      HIPCHK(wdg::launch_receivers(ctx->bits, ctx->NP(), int(ctx->nrec), ctx->dU[ctx->cur], ctx->dRecElem,
-                                   ctx->dRecRows, ctx->dRecBuf + ctx->rec_steps * ctx->nrec, ctx->stream));
+      HIPCHK(wdg::launch_receivers(ctx->bits, ctx->NP(), int(ctx->nrec), ctx->dU[ctx->cur], ctx->dRecBase,
+                                   ctx->dRecNN, ctx->dRecRows, ctx->dRecBuf + ctx->rec_steps * ctx->nrec, ctx->stream));
       ctx->rec_steps += 1;
     }
   }
@@ -816,7 +1089,7 @@ int wdg_eval_rhs(wdg_ctx* ctx, double t, const double* in4, double* out4) {
   if (ctx->state < kMaterial || ctx->host_only) return fail(ctx, WDG_ERR_STATE, "eval_rhs before set_material");
   if (!in4 || !out4) return fail(ctx, WDG_ERR_ARG, "null array");
   HIPCHK(hipSetDevice(ctx->device));
-  const int64_t n = ctx->K * ctx->NP();
+  const int64_t n = ctx->nodes();
   const size_t nstate = size_t(n) * 4 * ctx->tsize();
   void *dIn = nullptr, *dOut = nullptr;
   HIPCHK(hipMalloc(&dIn, nstate));
@@ -833,14 +1106,26 @@ int wdg_energy(wdg_ctx* ctx, double* E) {
   if (!ctx || !E) return WDG_ERR_ARG;
   if (ctx->state < kFields) return fail(ctx, WDG_ERR_STATE, "energy before set_fields");
   HIPCHK(hipSetDevice(ctx->device));
-  int nb = 0;
-  HIPCHK(wdg::launch_energy(ctx->N, ctx->bits, ctx->K, ctx->dU[ctx->cur], ctx->dAux, ctx->dMv, ctx->dM1,
-                            ctx->dPartial, &nb, ctx->stream));
-  std::vector<double> part(nb);
-  HIPCHK(hipMemcpyAsync(part.data(), ctx->dPartial, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
   double acc = 0.0;
-  for (double v : part) acc += v;
+  if (ctx->Kw > 0) {
+    int nb = 0;
+    HIPCHK(wdg::launch_energy(ctx->N, ctx->bits, ctx->Kw, ctx->dU[ctx->cur], ctx->dAux, ctx->dMv, ctx->dM1,
+                              ctx->dPartial, &nb, ctx->stream));
+    std::vector<double> part(nb);
+    HIPCHK(hipMemcpyAsync(part.data(), ctx->dPartial, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (double v : part) acc += v;
+  }
+  if (ctx->Kt > 0) {
+    int nb = 0;
+    const void* Ut = static_cast<const unsigned char*>(ctx->dU[ctx->cur]) + size_t(ctx->Kw) * ctx->NP() * 4 * ctx->tsize();
+    HIPCHK(wdg::launch_energy_tet(ctx->N, ctx->bits, ctx->Kt, Ut, ctx->dAuxT, ctx->dMt, ctx->dPartial + 1024, &nb,
+                                  ctx->stream));
+    std::vector<double> part(nb);
+    HIPCHK(hipMemcpyAsync(part.data(), ctx->dPartial + 1024, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (double v : part) acc += v;
+  }
   *E = acc;
   return WDG_OK;
 }
@@ -880,7 +1165,7 @@ int wdg_get_element_data(const wdg_ctx* ctx, double* geo, double* lift) {
     std::vector<unsigned char> buf(count * ctx->tsize());
     HIPCHK(hipMemcpyAsync(buf.data(), src, buf.size(), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    for (int64_t k = 0; k < ctx->K; ++k)
+    for (int64_t k = 0; k < ctx->Kw; ++k)
       for (int i = 0; i < used; ++i) {
         const size_t m = size_t(k) * stride + i;
         dst[k * used + i] = ctx->bits == 32 ? double(reinterpret_cast<float*>(buf.data())[m])
@@ -889,11 +1174,11 @@ int wdg_get_element_data(const wdg_ctx* ctx, double* geo, double* lift) {
     return WDG_OK;
   };
   if (geo) {
-    int rc = fetch(ctx->dGeo, size_t(ctx->K) * wdg::kGeoStride, geo, wdg::kGeoStride, wdg::kGeoStride);
+    int rc = fetch(ctx->dGeo, size_t(ctx->Kw) * wdg::kGeoStride, geo, wdg::kGeoStride, wdg::kGeoStride);
     if (rc) return rc;
   }
   if (lift) {
-    int rc = fetch(ctx->dL, size_t(ctx->K) * LS, lift, LS, NT * NT);
+    int rc = fetch(ctx->dL, size_t(ctx->Kw) * LS, lift, LS, NT * NT);
     if (rc) return rc;
   }
   return WDG_OK;
@@ -901,9 +1186,29 @@ int wdg_get_element_data(const wdg_ctx* ctx, double* geo, double* lift) {
 
 int wdg_reference_operator(int order_N, const char* name, double* out, int64_t cap, int64_t* count) {
   if (!name || !count || order_N < 1 || order_N > 5 || cap < 0) return WDG_ERR_ARG;
-  RefOps R(order_N);
   std::vector<double> v;
   const std::string n(name);
+  if (n.rfind("tet_", 0) == 0) {
+    const wdg::TetOps Tt(order_N);
+    const std::string m = n.substr(4);
+    if (m == "r") v = Tt.r;
+    else if (m == "s") v = Tt.s;
+    else if (m == "t") v = Tt.t;
+    else if (m == "Dr") v = Tt.Dr;
+    else if (m == "Ds") v = Tt.Ds;
+    else if (m == "Dt") v = Tt.Dt;
+    else if (m == "M") v = Tt.M;
+    else if (m == "LIFT") v = Tt.LIFT;
+    else if (m.size() == 5 && m.substr(0, 4) == "face" && m[4] >= '0' && m[4] <= '3') {
+      for (int id : Tt.face_nodes[m[4] - '0']) v.push_back(id);
+    } else {
+      return WDG_ERR_ARG;
+    }
+    *count = int64_t(v.size());
+    if (out) std::copy(v.begin(), v.begin() + std::min<int64_t>(cap, int64_t(v.size())), out);
+    return WDG_OK;
+  }
+  RefOps R(order_N);
   if (n == "r") v = R.r;
   else if (n == "s") v = R.s;
   else if (n == "t") v = R.t;

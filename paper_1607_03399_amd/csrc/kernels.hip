@@ -2,8 +2,11 @@
 //
 //   setup_kernel     FP64 geometric factors (Lemma 1), face Jacobians and normals,
 //                    triangular lift L^{tri,k} = (M^{tri,k})^-1 M^tri (Sec. 4.2)
-//   wedge_stage      one Runge-Kutta stage: volume term, surface fluxes, lifts,
-//                    L^{tri,k} application and the low-storage update, fused
+//   wedge_stage      one Runge-Kutta stage on the wedges: volume term, surface
+//                    fluxes, lifts, L^{tri,k} application and the low-storage
+//                    update, fused
+//   tet_stage        the same stage on the affine tetrahedra of hybrid meshes
+//                    (standard nodal DG; they meet wedges at triangular faces)
 //   sample_receivers pressure at receiver points
 //   energy_kernel    discrete energy with M^k = M^{tri,k} (x) M^1D
 #include <hip/hip_runtime.h>
@@ -30,13 +33,6 @@ __host__ __device__ constexpr int tri_idx(int N, int a, int b) { return b * (N +
 __host__ __device__ constexpr int edge_node(int N, int e, int q) {
   return e == 0 ? tri_idx(N, q, 0) : (e == 1 ? tri_idx(N, N - q, q) : tri_idx(N, 0, N - q));
 }
-
-// Vertex permutations of the triangle nodes across a shared triangular face
-// (6 permutations x NT nodes), the only operator data the stage kernel loads.
-template <int N>
-struct FacePerm {
-  int perm[6 * Dim<N>::NT];
-};
 
 // Node-interleaved state: one 4-vector per node in the order (p, u_z, u_x, u_y).
 template <typename T>
@@ -104,6 +100,31 @@ __device__ __forceinline__ int face_perm(int p, int i) {
   return j2 * (N + 1) - j2 * (j2 - 1) / 2 + j1;
 }
 
+template <int N>
+struct TDim {
+  static constexpr int NT = (N + 1) * (N + 2) / 2;
+  static constexpr int NP = (N + 1) * (N + 2) * (N + 3) / 6;
+};
+__host__ __device__ constexpr int tet_np(int n) { return (n + 1) * (n + 2) * (n + 3) / 6; }
+
+// Tetrahedron node of face f's triangle node m.  The face node has integer
+// barycentrics (N-a-b, a, b) relative to the face's vertices (faces
+// (V0,V1,V2), (V0,V1,V3), (V1,V2,V3), (V0,V2,V3)); the tetrahedron orders its
+// lattice (l1, l2, l3) by l3, then l2, then l1.
+template <int N>
+__device__ __forceinline__ int tet_face_node(int f, int m) {
+  int b = 0;
+#pragma unroll
+  for (int bb = 1; bb <= N; ++bb) b += m >= tri_idx(N, 0, bb) ? 1 : 0;
+  const int a = m - (b * (N + 1) - b * (b - 1) / 2);
+  const int c = N - a - b;
+  const int l1 = f == 0 ? a : (f == 1 ? a : (f == 2 ? c : 0));
+  const int l2 = f == 0 ? b : (f == 1 ? 0 : a);
+  const int l3 = f == 0 ? 0 : b;
+  const int n = N - l3;  // the slice l3 is a triangle lattice of order n
+  return tet_np(N) - tet_np(n) + l2 * (n + 1) - l2 * (l2 - 1) / 2 + l1;
+}
+
 // Raw buffer access to one chunk of a stream.  Loads past the resource's
 // byte count return zeros and stores there are dropped by the hardware, so
 // the ragged last chunk needs no branches around memory operations (a branch
@@ -156,7 +177,7 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int idx, const 
 #ifndef WDG_STAGE_WAVES_PER_EU
 #define WDG_STAGE_WAVES_PER_EU 2
 #endif
-template <int N, typename T>
+template <int N, typename T, bool HYB>
 __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageLaunch A) {
   using C = Cfg<N, T>;
   using RT = gen::RefTables<N>;
@@ -182,7 +203,7 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
   const int qd = nb / 8, rm = nb % 8, xcd = bid % 8, kk = bid / 8;
   const int chunk = xcd < rm ? xcd * (qd + 1) + kk : rm * (qd + 1) + (xcd - rm) * qd + kk;
   const int64_t e0 = int64_t(chunk) * EPB;
-  const int64_t left = A.K - e0;
+  const int64_t left = A.Kw - e0;
   const int nE = left < EPB ? int(left) : EPB;
   const int tid = threadIdx.x;
 
@@ -249,7 +270,16 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
     const int nbr = face ? cn[1] : cn[0];
     const int pc = (code >> (3 * face)) & 7;
     const int nlev = ((code >> (6 + face)) & 1) ? N : 0;
-    gt[t] = Uin[(nbr >= 0 ? int64_t(nbr) : e) * NP + nlev * NT + face_perm<N>(pc, i)];
+    const int64_t src = nbr >= 0 ? int64_t(nbr) : e;
+    const int fn = face_perm<N>(pc, i);
+    if constexpr (HYB) {
+      // a tetrahedron neighbour: its nodes follow all wedge nodes
+      const int tf = (code >> (14 + 2 * face)) & 3;
+      const bool tet = src >= A.Kw;
+      gt[t] = Uin[tet ? A.Kw * NP + (src - A.Kw) * TDim<N>::NP + tet_face_node<N>(tf, fn) : src * NP + nlev * NT + fn];
+    } else {
+      gt[t] = Uin[src * NP + nlev * NT + fn];
+    }
   }
 #pragma unroll
   for (int k = 0; k < SU; ++k) {
@@ -382,13 +412,16 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
   __syncthreads();
 
   const bool rd = (A.flags & kReadRes) != 0, wu = (A.flags & kWriteU) != 0;
-  const auto bres = chunk_rsrc(static_cast<V4<T>*>(A.res) + e0 * NP, int64_t(nE) * NP * V4B);
-  // residual of the previous stage, in the coalesced layout of the update
-  // (read even when unused, so that no branch sits in front of the loads)
+  // residual of the previous stage, in the coalesced layout of the update.
+  // The first stage reads none: its resource has an empty range, so the
+  // loads return zeros without touching memory and need no branch.
+  V4<T>* const res_chunk = static_cast<V4<T>*>(A.res) + e0 * NP;
+  const auto bres_in = chunk_rsrc(res_chunk, rd ? int64_t(nE) * NP * V4B : 0);
+  const auto bres = chunk_rsrc(res_chunk, int64_t(nE) * NP * V4B);
   V4<T> rprev[C::PREFETCH ? C::UPD : 1];
   if constexpr (C::PREFETCH) {
 #pragma unroll
-    for (int k = 0; k < C::UPD; ++k) rprev[k] = bload<T>(bres, tid + 64 * k);
+    for (int k = 0; k < C::UPD; ++k) rprev[k] = bload<T>(bres_in, tid + 64 * k);
   }
 
   T Rp[NT], Rz[NT], Rx[NT], Ry[NT];
@@ -494,7 +527,7 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
   __syncthreads();
 
   // low-storage Runge-Kutta update, coalesced over the chunk
-  const T ca = rd ? T(A.a) : T(0), cb = T(A.b), dt = T(A.dt);
+  const T ca = T(A.a), cb = T(A.b), dt = T(A.dt);
   const auto bout = chunk_rsrc(static_cast<V4<T>*>(A.Uout) + e0 * NP, int64_t(nE) * NP * V4B);
 #pragma unroll
   for (int k = 0; k < C::UPD; ++k) {
@@ -505,14 +538,178 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
     if constexpr (C::PREFETCH)
       q = rprev[k];
     else
-      q = bload<T>(bres, idx);
-    // the first stage ignores res entirely (it may hold anything)
-    if (!rd) q = V4<T>{T(0), T(0), T(0), T(0)};
+      q = bload<T>(bres_in, idx);
     const V4<T> r{ca * q.p + dt * R.p, ca * q.uz + dt * R.uz, ca * q.ux + dt * R.ux, ca * q.uy + dt * R.uy};
     bstore<T>(bres, idx, r);
     if (wu) {
       const V4<T> u = sU[l];
       bstore<T>(bout, idx, V4<T>{u.p + cb * r.p, u.uz + cb * r.uz, u.ux + cb * r.ux, u.uy + cb * r.uy});
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tetrahedron stage kernel (affine tetrahedra, standard nodal DG)
+//
+// Lane (element, node i); a block of 256 lanes holds EPB = 256 / Np
+// tetrahedra per chunk and loops over chunks (persistent), so the reference
+// operators Dr, Ds, Dt and LIFT are staged in LDS once per block where they
+// fit (read from memory otherwise).  Per chunk:
+//   1. node i stores (p, r.u, s.u, t.u) with r.u = r_x u_x + r_y u_y + r_z u_z
+//      (and likewise s, t), so that div u = D_r(r.u) + D_s(s.u) + D_t(t.u);
+//      the 4 Np_tri face nodes are shared out over the lanes, whose fluxes
+//      (scaled by J_f / J) go to LDS
+//   2. node i: volume terms, LIFT of the fluxes, material scaling, sources and
+//      the low-storage update (node-contiguous, coalesced)
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+struct TCfg {
+  static constexpr int NT = TDim<N>::NT, NP = TDim<N>::NP;
+  static constexpr int BS = 256;
+  static constexpr int EPB = BS / NP;
+  static constexpr int NOPS = 3 * NP * NP + NP * 4 * NT;
+  static constexpr bool OPS_LDS = NOPS * int(sizeof(T)) <= 40960;
+  static constexpr int SLOTS = (4 * NT + NP - 1) / NP;  // face nodes per lane
+};
+
+template <typename T>
+struct alignas(4 * sizeof(T)) Q4 {
+  T p, ar, as, at;
+};
+
+template <int N, typename T>
+__global__ void __launch_bounds__(256) tet_stage(StageLaunch A) {
+  using C = TCfg<N, T>;
+  constexpr int NT = C::NT, NP = C::NP, EPB = C::EPB;
+  constexpr int NPW = Dim<N>::NP;
+  __shared__ T sOps[C::OPS_LDS ? C::NOPS : 1];
+  __shared__ V4<T> sU[EPB * NP];
+  __shared__ Q4<T> sW[EPB * NP];
+  __shared__ T sF[EPB * 4 * NT * 2];
+  __shared__ T sG[EPB * kTetGeoStride];
+  __shared__ int sC[EPB * kTetConnStride];
+
+  const T* gops = static_cast<const T*>(A.opsT);
+  if constexpr (C::OPS_LDS) {
+    for (int idx = threadIdx.x; idx < C::NOPS; idx += C::BS) sOps[idx] = gops[idx];
+  }
+  const T* ops = C::OPS_LDS ? static_cast<const T*>(sOps) : gops;
+  const T* Dr = ops;
+  const T* Ds = ops + NP * NP;
+  const T* Dt = ops + 2 * NP * NP;
+  const T* LIFT = ops + 3 * NP * NP;
+
+  const V4<T>* __restrict__ Uin = static_cast<const V4<T>*>(A.Uin);
+  V4<T>* __restrict__ res = static_cast<V4<T>*>(A.res);
+  V4<T>* __restrict__ Uout = static_cast<V4<T>*>(A.Uout);
+  const T* __restrict__ geo = static_cast<const T*>(A.geoT);
+  const int* __restrict__ conn = A.connT;
+  const int64_t tb = A.Kw * NPW;  // first tetrahedron node
+  const int tid = threadIdx.x;
+  const int le = tid / NP, i = tid - le * NP;
+  const T bsign = (A.flags & kDirichlet) ? T(-1) : T(1);
+  const T tau_on = (A.flags & kCentral) ? T(0) : T(1);
+  const bool rd = (A.flags & kReadRes) != 0, wu = (A.flags & kWriteU) != 0;
+  const int64_t nchunks = (A.Kt + EPB - 1) / EPB;
+
+  for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+    const int64_t e0 = chunk * EPB;
+    const int nE = int(A.Kt - e0 < EPB ? A.Kt - e0 : EPB);
+    __syncthreads();  // the previous chunk is done with LDS
+    for (int idx = tid; idx < nE * NP; idx += C::BS) sU[idx] = Uin[tb + e0 * NP + idx];
+    for (int idx = tid; idx < nE * kTetGeoStride; idx += C::BS) sG[idx] = geo[e0 * kTetGeoStride + idx];
+    for (int idx = tid; idx < nE * kTetConnStride; idx += C::BS) sC[idx] = conn[e0 * kTetConnStride + idx];
+    __syncthreads();
+
+    const bool active = tid < EPB * NP && le < nE;
+    const T* g = sG + le * kTetGeoStride;
+    const int* cn = sC + le * kTetConnStride;
+    const int64_t e = e0 + le;
+    if (active) {
+      const V4<T> v = sU[le * NP + i];
+      sW[le * NP + i] = Q4<T>{v.p, g[0] * v.ux + g[1] * v.uy + g[2] * v.uz, g[3] * v.ux + g[4] * v.uy + g[5] * v.uz,
+                              g[6] * v.ux + g[7] * v.uy + g[8] * v.uz};
+      const int code = cn[4];
+#pragma unroll
+      for (int sl = 0; sl < C::SLOTS; ++sl) {
+        const int q = i + NP * sl;
+        if (q < 4 * NT) {
+          const int f = q / NT, m = q - f * NT;
+          const int nbr = cn[f];
+          const T w_in = nbr >= 0 ? T(1) : T(0);
+          const int pc = (code >> (5 * f)) & 7, nf = (code >> (5 * f + 3)) & 3;
+          const int fn = face_perm<N>(pc, m);
+          const int64_t src = nbr >= 0 ? int64_t(nbr) : A.Kw + e;
+          const int64_t gi = src >= A.Kw ? tb + (src - A.Kw) * NP + tet_face_node<N>(nf, fn)
+                                         : src * NPW + (nf == 1 ? N * NT : 0) + fn;
+          const V4<T> own = sU[le * NP + tet_face_node<N>(f, m)];
+          const V4<T> nb = Uin[gi];
+          const T Fs = g[12 + 4 * f], nx = g[13 + 4 * f], ny = g[14 + 4 * f], nz = g[15 + 4 * f];
+          const T zs = g[28 + f];
+          const T taup = tau_on * T(2) / zs;
+          const T tauu = tau_on * zs * T(0.5);
+          const T pm = own.p;
+          const T unm = nx * own.ux + ny * own.uy + nz * own.uz;
+          const T pb = bsign * pm, ub = -bsign * unm;
+          const T pp = pb + w_in * (nb.p - pb);
+          const T unp = ub + w_in * ((nx * nb.ux + ny * nb.uy + nz * nb.uz) - ub);
+          const T jp = pp - pm, jun = unp - unm;
+          sF[(le * 4 * NT + q) * 2] = Fs * T(0.5) * (taup * jp - jun);
+          sF[(le * 4 * NT + q) * 2 + 1] = Fs * T(0.5) * (tauu * jun - jp);
+        }
+      }
+    }
+    __syncthreads();
+    if (!active) continue;
+
+    T dpr = 0, dps = 0, dpt = 0, div = 0;
+#pragma unroll 5
+    for (int m = 0; m < NP; ++m) {
+      const Q4<T> w = sW[le * NP + m];
+      const T dr = Dr[i * NP + m], ds = Ds[i * NP + m], dt = Dt[i * NP + m];
+      dpr += dr * w.p;
+      dps += ds * w.p;
+      dpt += dt * w.p;
+      div += dr * w.ar;
+      div += ds * w.as;
+      div += dt * w.at;
+    }
+    T lp = 0, lx = 0, ly = 0, lz = 0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      T su = 0;
+#pragma unroll 3
+      for (int m = 0; m < NT; ++m) {
+        const T l = LIFT[i * 4 * NT + f * NT + m];
+        lp += l * sF[(le * 4 * NT + f * NT + m) * 2];
+        su += l * sF[(le * 4 * NT + f * NT + m) * 2 + 1];
+      }
+      lx += g[13 + 4 * f] * su;
+      ly += g[14 + 4 * f] * su;
+      lz += g[15 + 4 * f] * su;
+    }
+    const T kap = g[9], irho = g[10];
+    T Rp = kap * (lp - div);
+    const T Rx = irho * (lx - (g[0] * dpr + g[3] * dps + g[6] * dpt));
+    const T Ry = irho * (ly - (g[1] * dpr + g[4] * dps + g[7] * dpt));
+    const T Rz = irho * (lz - (g[2] * dpr + g[5] * dps + g[8] * dpt));
+    for (int s = 0; s < A.nsrc; ++s)
+      if (A.src_elem[s] == A.Kw + e) Rp += T(A.src_amp[s]) * static_cast<const T*>(A.srcvec)[s * NPW + i];
+
+    const int64_t gi = tb + e * NP + i;
+    const T ca = T(A.a), cb = T(A.b), dtt = T(A.dt);
+    V4<T> r{dtt * Rp, dtt * Rz, dtt * Rx, dtt * Ry};
+    if (rd) {
+      const V4<T> q = res[gi];
+      r.p += ca * q.p;
+      r.uz += ca * q.uz;
+      r.ux += ca * q.ux;
+      r.uy += ca * q.uy;
+    }
+    res[gi] = r;
+    if (wu) {
+      const V4<T> u = sU[le * NP + i];
+      Uout[gi] = V4<T>{u.p + cb * r.p, u.uz + cb * r.uz, u.ux + cb * r.ux, u.uy + cb * r.uy};
     }
   }
 }
@@ -652,13 +849,13 @@ __global__ void material_kernel(int64_t K, const double* __restrict__ c, const d
 }
 
 template <typename T>
-__global__ void sample_receivers(int NP, int nrec, const T* __restrict__ U, const int* __restrict__ elem,
-                                 const double* __restrict__ rows, double* __restrict__ out) {
+__global__ void sample_receivers(int ld, int nrec, const T* __restrict__ U, const int64_t* __restrict__ base,
+                                 const int* __restrict__ nn, const double* __restrict__ rows, double* __restrict__ out) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrec) return;
-  const T* Ue = U + int64_t(elem[r]) * NP * 4;
+  const T* Ue = U + base[r] * 4;
   double acc = 0.0;
-  for (int n = 0; n < NP; ++n) acc += rows[int64_t(r) * NP + n] * double(Ue[4 * n]);
+  for (int n = 0; n < nn[r]; ++n) acc += rows[int64_t(r) * ld + n] * double(Ue[4 * n]);
   out[r] = acc;
 }
 
@@ -703,19 +900,56 @@ __global__ void __launch_bounds__(256) energy_kernel(int64_t K, const T* __restr
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-template <int N>
-void fill_perm_t(void* dst, const int* perm) {
-  FacePerm<N>* o = static_cast<FacePerm<N>*>(dst);
-  for (int i = 0; i < 6 * Dim<N>::NT; ++i) o->perm[i] = perm[i];
+// E_k = 1/2 J (p^T M p / kappa + rho sum_d u_d^T M u_d) for affine tetrahedra
+template <int N, typename T>
+__global__ void __launch_bounds__(256) energy_tet_kernel(int64_t Kt, const T* __restrict__ U,
+                                                         const double* __restrict__ aux, const double* __restrict__ Mt,
+                                                         double* __restrict__ partial) {
+  constexpr int NP = TDim<N>::NP;
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < Kt; k += int64_t(gridDim.x) * 256) {
+    const double J = aux[k * kTetAuxStride], kap = aux[k * kTetAuxStride + 1], rho = aux[k * kTetAuxStride + 2];
+    const T* Ue = U + k * NP * 4;
+    for (int f = 0; f < 4; ++f) {
+      double ef = 0.0;
+      for (int i = 0; i < NP; ++i) {
+        double y = 0.0;
+        for (int m = 0; m < NP; ++m) y += Mt[i * NP + m] * double(Ue[4 * m + f]);
+        ef += double(Ue[4 * i + f]) * y;
+      }
+      acc += 0.5 * J * (f == 0 ? 1.0 / kap : rho) * ef;
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
 template <int N, typename T>
 hipError_t launch_stage_t(const StageLaunch& a, hipStream_t st) {
   using C = Cfg<N, T>;
-  const int64_t nchunks = (a.K + C::EPB - 1) / C::EPB;
-  if (nchunks <= 0) return hipSuccess;
-  hipLaunchKernelGGL((wedge_stage<N, T>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
-  return hipGetLastError();
+  const int64_t nchunks = (a.Kw + C::EPB - 1) / C::EPB;
+  if (nchunks > 0) {
+    if (a.Kt > 0)
+      hipLaunchKernelGGL((wedge_stage<N, T, true>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
+    else
+      hipLaunchKernelGGL((wedge_stage<N, T, false>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  if (a.Kt > 0) {
+    using TC = TCfg<N, T>;
+    const int64_t tchunks = (a.Kt + TC::EPB - 1) / TC::EPB;
+    const unsigned grid = unsigned(tchunks < 2048 ? tchunks : 2048);
+    hipLaunchKernelGGL((tet_stage<N, T>), dim3(grid), dim3(TC::BS), 0, st, a);
+    return hipGetLastError();
+  }
+  return hipSuccess;
 }
 
 template <int N, typename T>
@@ -726,6 +960,18 @@ hipError_t launch_energy_t(int64_t K, const void* U, const double* aux, const do
   if (nb < 1) nb = 1;
   *nblocks = nb;
   hipLaunchKernelGGL((energy_kernel<N, T>), dim3(nb), dim3(256), 0, st, K, static_cast<const T*>(U), aux, Mv, M1,
+                     partial);
+  return hipGetLastError();
+}
+
+template <int N, typename T>
+hipError_t launch_energy_tet_t(int64_t Kt, const void* U, const double* aux, const double* Mt, double* partial,
+                               int* nblocks, hipStream_t st) {
+  int nb = int((Kt + 255) / 256);
+  if (nb > 1024) nb = 1024;
+  if (nb < 1) nb = 1;
+  *nblocks = nb;
+  hipLaunchKernelGGL((energy_tet_kernel<N, T>), dim3(nb), dim3(256), 0, st, Kt, static_cast<const T*>(U), aux, Mt,
                      partial);
   return hipGetLastError();
 }
@@ -744,28 +990,6 @@ hipError_t launch_energy_t(int64_t K, const void* U, const double* aux, const do
     case 5: if (BITS_ == 32) { CALL(5, float); } else { CALL(5, double); } break; \
     default: break;                                        \
   }
-
-size_t ops_bytes(int N) {
-  switch (N) {
-    case 1: return sizeof(FacePerm<1>);
-    case 2: return sizeof(FacePerm<2>);
-    case 3: return sizeof(FacePerm<3>);
-    case 4: return sizeof(FacePerm<4>);
-    case 5: return sizeof(FacePerm<5>);
-    default: return 0;
-  }
-}
-
-void fill_ops(int N, void* dst, const int* perm) {
-  switch (N) {
-    case 1: fill_perm_t<1>(dst, perm); break;
-    case 2: fill_perm_t<2>(dst, perm); break;
-    case 3: fill_perm_t<3>(dst, perm); break;
-    case 4: fill_perm_t<4>(dst, perm); break;
-    case 5: fill_perm_t<5>(dst, perm); break;
-    default: break;
-  }
-}
 
 int lift_stride(int N) {
   const int NT = (N + 1) * (N + 2) / 2;
@@ -808,16 +1032,16 @@ hipError_t launch_stage(int N, int bits, const StageLaunch& a, hipStream_t st) {
   return err;
 }
 
-hipError_t launch_receivers(int bits, int NP, int nrec, const void* U, const int* elem, const double* rows,
-                            double* out, hipStream_t st) {
+hipError_t launch_receivers(int bits, int ld, int nrec, const void* U, const int64_t* base, const int* nn,
+                            const double* rows, double* out, hipStream_t st) {
   if (nrec <= 0) return hipSuccess;
   const unsigned nb = unsigned((nrec + 63) / 64);
   if (bits == 32)
-    hipLaunchKernelGGL(sample_receivers<float>, dim3(nb), dim3(64), 0, st, NP, nrec, static_cast<const float*>(U), elem,
-                       rows, out);
+    hipLaunchKernelGGL(sample_receivers<float>, dim3(nb), dim3(64), 0, st, ld, nrec, static_cast<const float*>(U), base,
+                       nn, rows, out);
   else
-    hipLaunchKernelGGL(sample_receivers<double>, dim3(nb), dim3(64), 0, st, NP, nrec, static_cast<const double*>(U),
-                       elem, rows, out);
+    hipLaunchKernelGGL(sample_receivers<double>, dim3(nb), dim3(64), 0, st, ld, nrec, static_cast<const double*>(U),
+                       base, nn, rows, out);
   return hipGetLastError();
 }
 
@@ -827,6 +1051,15 @@ hipError_t launch_energy(int N, int bits, int64_t K, const void* U, const double
 #define WDG_EN(n, T) err = launch_energy_t<n, T>(K, U, aux, Mv, M1, partial, nblocks, st)
   WDG_DISPATCH_N(N, bits, WDG_EN)
 #undef WDG_EN
+  return err;
+}
+
+hipError_t launch_energy_tet(int N, int bits, int64_t Kt, const void* U, const double* auxT, const double* Mt,
+                             double* partial, int* nblocks, hipStream_t st) {
+  hipError_t err = hipErrorInvalidValue;
+#define WDG_ENT(n, T) err = launch_energy_tet_t<n, T>(Kt, U, auxT, Mt, partial, nblocks, st)
+  WDG_DISPATCH_N(N, bits, WDG_ENT)
+#undef WDG_ENT
   return err;
 }
 

@@ -19,9 +19,20 @@ constexpr int kAuxStride = 8;
 // Per-element connectivity (int32): 0..4 neighbour of bottom, top, quad 0..2 (-1: boundary);
 // 5 packed codes: bits 0-2 / 3-5 vertex permutation of the bottom / top neighbour face,
 // bit 6 / 7 set when that neighbour face is the neighbour's top triangle, bits 8+2e..9+2e
-// neighbour edge of quad face e.
+// neighbour edge of quad face e, bits 14-15 / 16-17 the neighbour's face when the bottom /
+// top neighbour is a tetrahedron (global id >= number of wedges).
 constexpr int kConnStride = 8;
 constexpr int kMaxSources = 8;
+// Per-tetrahedron record (values of type T): 0..8 r_x r_y r_z s_x s_y s_z t_x t_y t_z,
+// 9 kappa, 10 1/rho, 11 rho c, 12+4f.. face f: J_f / J, n_x, n_y, n_z,
+// 28+f rho c + (rho c of the neighbour, or own on the boundary) across face f.
+constexpr int kTetGeoStride = 32;
+// Per-tetrahedron connectivity (int32): 0..3 neighbour across face f (global element id,
+// wedges first; -1 boundary); 4 packed codes, 5 bits per face: bits 5f..5f+2 vertex
+// permutation, 5f+3..5f+4 the neighbour's face (wedge: 0 bottom, 1 top; tetrahedron: 0..3).
+constexpr int kTetConnStride = 8;
+// Per-tetrahedron FP64 auxiliary record: 0 J, 1 kappa, 2 rho.
+constexpr int kTetAuxStride = 4;
 
 enum StageFlags : int {
   kReadRes = 1,    // res = a res + dt rhs (else res = dt rhs)
@@ -30,41 +41,43 @@ enum StageFlags : int {
   kCentral = 8,    // else upwind flux
 };
 
+// One stage over the whole mesh.  State buffers hold wedges first (Kw x Np_wedge
+// nodes), then tetrahedra (Kt x Np_tet nodes), one 4-vector per node.
 struct StageLaunch {
   const void* Uin;
   void* Uout;
   void* res;
-  const void* geo;
+  const void* geo;   // wedges
   const void* L;
   const int* conn;
-  const void* ops;
-  const void* srcvec;
+  const void* geoT;  // tetrahedra
+  const int* connT;
+  const void* opsT;  // tetrahedron operators: Dr, Ds, Dt (Np x Np each), LIFT (Np x 4 Np_tri)
+  const void* srcvec;  // kMaxSources x Np_wedge (a tetrahedron source uses the first Np_tet)
   int src_elem[kMaxSources];
   double src_amp[kMaxSources];
   int nsrc;
   double a, b, dt;
-  int64_t K;
+  int64_t Kw, Kt;
   int flags;
 };
 
 // Per-element stride (values) of the stored triangular lift: Np_tri^2 padded to a multiple of 4.
 int lift_stride(int N);
-// Size in bytes of the device face-permutation table of order N (the only
-// operator data the stage kernel reads from memory; the reference triangle
-// and 1D operators are compiled into the kernel).
-size_t ops_bytes(int N);
-// Fill that table (host memory of ops_bytes(N)) from the 6 x Np_tri permutation list.
-void fill_ops(int N, void* dst, const int* perm);
 
 hipError_t launch_setup(int N, int bits, int64_t K, const double* dX, const double* dMv, const double* dMtri,
                         void* dGeo, void* dL, double* dAux, hipStream_t st);
 hipError_t launch_material(int bits, int64_t K, const double* dc, const double* drho, const int* dConn, void* dGeo,
                            double* dAux, hipStream_t st);
 hipError_t launch_stage(int N, int bits, const StageLaunch& a, hipStream_t st);
-hipError_t launch_receivers(int bits, int NP, int nrec, const void* U, const int* elem, const double* rows,
-                            double* out, hipStream_t st);
+// Pressure at receivers: receiver r reads nn[r] nodes from 4-vector index base[r] with row stride ld.
+hipError_t launch_receivers(int bits, int ld, int nrec, const void* U, const int64_t* base, const int* nn,
+                            const double* rows, double* out, hipStream_t st);
 // Per-block partial energies; returns the number of partials written.
 hipError_t launch_energy(int N, int bits, int64_t K, const void* U, const double* aux, const double* Mv,
                          const double* M1, double* partial, int* nblocks, hipStream_t st);
+// Tetrahedron energies (U points at the first tetrahedron node), added to the same partial sums layout.
+hipError_t launch_energy_tet(int N, int bits, int64_t Kt, const void* U, const double* auxT, const double* Mt,
+                             double* partial, int* nblocks, hipStream_t st);
 
 }  // namespace wdg

@@ -15,6 +15,14 @@ const int kPerm[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 2, 1}, {2, 1, 0}, 
 
 int tri_index(int N, int a, int b) { return b * (N + 1) - b * (b - 1) / 2 + a; }
 
+int tet_index(int N, int a, int b, int c) {
+  int off = 0;
+  for (int cc = 0; cc < c; ++cc) off += (N - cc + 1) * (N - cc + 2) / 2;
+  return off + tri_index(N - c, a, b);
+}
+
+const int kTetFaceVerts[4][3] = {{0, 1, 2}, {0, 1, 3}, {1, 2, 3}, {0, 2, 3}};
+
 namespace {
 
 // Orthonormal Jacobi polynomial P_n^{(al,be)}(x) w.r.t. (1-x)^al (1+x)^be on [-1,1].
@@ -106,6 +114,44 @@ void dubiner(int N, double r, double s, double* psi, double* pr, double* ps) {
       }
     }
   }
+}
+
+// Orthonormal Proriol-Koornwinder-Dubiner basis on the bi-unit tetrahedron
+// and its gradient.  Collapsed coordinates a = 2(1+r)/(-s-t) - 1,
+// b = 2(1+s)/(1-t) - 1, c = t, and
+//   psi_ijk = 2 sqrt(2) P_i(a) P_j^(2i+1,0)(b) (1-b)^i P_k^(2i+2j+2,0)(c) (1-c)^(i+j).
+// The gradient follows from the chain rule with -s-t = (1-b)(1-c)/2 and
+// 1-t = 1-c; the powers (1-b)^(i-1), (1-c)^(i+j-1) stay finite where the
+// collapse is singular, because the factor in front vanishes when the power
+// would be negative.
+void pkd3(int N, double r, double s, double t, double* psi, double* pr, double* ps, double* pt) {
+  const double mst = -s - t, omt = 1.0 - t;
+  const double a = std::fabs(mst) > 1e-14 ? 2.0 * (1.0 + r) / mst - 1.0 : -1.0;
+  const double b = std::fabs(omt) > 1e-14 ? 2.0 * (1.0 + s) / omt - 1.0 : -1.0;
+  const double c = t;
+  const double k0 = 2.0 * std::sqrt(2.0);
+  auto pw = [](double x, int e) { return e <= 0 ? (e == 0 ? 1.0 : 0.0) : std::pow(x, e); };
+  int m = 0;
+  for (int i = 0; i <= N; ++i)
+    for (int j = 0; j <= N - i; ++j)
+      for (int k = 0; k <= N - i - j; ++k, ++m) {
+        const double F = jacobi(i, 0, 0, a), dF = djacobi(i, 0, 0, a);
+        const double G = jacobi(j, 2.0 * i + 1.0, 0, b), dG = djacobi(j, 2.0 * i + 1.0, 0, b);
+        const double H = jacobi(k, 2.0 * (i + j) + 2.0, 0, c), dH = djacobi(k, 2.0 * (i + j) + 2.0, 0, c);
+        const double bi = pw(1.0 - b, i), bi1 = pw(1.0 - b, i - 1);
+        const double cij = pw(1.0 - c, i + j), cij1 = pw(1.0 - c, i + j - 1);
+        psi[m] = k0 * F * G * bi * H * cij;
+        if (!pr) continue;
+        // d/da, d/db, d/dc of psi with one power of (1-b) resp. (1-c) taken out
+        const double da_red = (i > 0) ? k0 * dF * G * bi1 * H * cij1 : 0.0;     // psi_a / ((1-b)(1-c))
+        const double gb = dG * bi - (i > 0 ? i * G * bi1 : 0.0);                 // d/db [G (1-b)^i]
+        const double db_red = (i + j > 0) ? k0 * F * gb * H * cij1 : 0.0;       // psi_b / (1-c)
+        const double hc = dH * cij - (i + j > 0 ? (i + j) * H * cij1 : 0.0);    // d/dc [H (1-c)^(i+j)]
+        const double dc = k0 * F * G * bi * hc;                                  // psi_c
+        pr[m] = 4.0 * da_red;
+        ps[m] = 2.0 * (1.0 + a) * da_red + 2.0 * db_red;
+        pt[m] = 2.0 * (1.0 + a) * da_red + (1.0 + b) * db_red + dc;
+      }
 }
 
 void invert(int n, const std::vector<double>& A, std::vector<double>& Ainv) {
@@ -333,6 +379,138 @@ void RefOps::line_basis(double tt, double* out) const {
     for (int m = 0; m < Nq; ++m)
       if (m != j) l *= (tt - t[m]) / (t[j] - t[m]);
     out[j] = l;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tetrahedron
+// ---------------------------------------------------------------------------
+TetOps::TetOps(int N_) : N(N_) {
+  if (N < 1 || N > 5) throw std::invalid_argument("order out of range");
+  NT = (N + 1) * (N + 2) / 2;
+  NP = (N + 1) * (N + 2) * (N + 3) / 6;
+
+  // Warp & Blend nodes (alpha = 0) built on the equilateral tetrahedron:
+  // every face adds its triangle warp (edge warps of the face, as for the
+  // triangle nodes) times the face blend b c d / ((b + a/2)(c + a/2)(d + a/2))
+  // (a: barycentric of the opposite vertex, b c d those of the face); a node
+  // on an edge gets exactly that edge's warp.
+  const double s3 = std::sqrt(3.0), s6 = std::sqrt(6.0);
+  const double E[4][3] = {{-1.0, -1.0 / s3, -1.0 / s6}, {1.0, -1.0 / s3, -1.0 / s6}, {0.0, 2.0 / s3, -1.0 / s6},
+                          {0.0, 0.0, 3.0 / s6}};
+  const int faces[4][4] = {{3, 0, 1, 2}, {2, 0, 1, 3}, {0, 1, 2, 3}, {1, 0, 2, 3}};  // opposite, face vertices
+  std::vector<double> xgll, wgll_;
+  gll(N, xgll, wgll_);
+  std::vector<double> xeq(N + 1);
+  for (int k = 0; k <= N; ++k) xeq[k] = -1.0 + 2.0 * k / N;
+  auto warp = [&](double x) {
+    if (std::fabs(x) >= 1.0 - 1e-10) return 0.0;
+    double acc = 0.0;
+    for (int i = 0; i <= N; ++i) {
+      double li = 1.0;
+      for (int m = 0; m <= N; ++m)
+        if (m != i) li *= (x - xeq[m]) / (xeq[i] - xeq[m]);
+      acc += li * (xgll[i] - xeq[i]);
+    }
+    return acc / (1.0 - x * x);
+  };
+  r.assign(NP, 0.0);
+  s.assign(NP, 0.0);
+  t.assign(NP, 0.0);
+  const double tol = 1e-10;
+  for (int c = 0; c <= N; ++c)
+    for (int b = 0; b + c <= N; ++b)
+      for (int a = 0; a + b + c <= N; ++a) {
+        const double lam[4] = {double(N - a - b - c) / N, double(a) / N, double(b) / N, double(c) / N};
+        double X[3] = {0, 0, 0};
+        for (int v = 0; v < 4; ++v)
+          for (int d = 0; d < 3; ++d) X[d] += lam[v] * E[v][d];
+        int nonzero = 0;
+        for (int v = 0; v < 4; ++v) nonzero += lam[v] > tol;
+        double shift[3] = {0, 0, 0};
+        for (const auto& f : faces) {
+          const int va = f[0];
+          const int fv[3] = {f[1], f[2], f[3]};
+          double w[3] = {0, 0, 0};
+          for (int e = 0; e < 3; ++e) {
+            const int u = fv[e], v = fv[(e + 1) % 3];
+            double dir[3], len = 0;
+            for (int d = 0; d < 3; ++d) {
+              dir[d] = E[v][d] - E[u][d];
+              len += dir[d] * dir[d];
+            }
+            len = std::sqrt(len);
+            const double amt = 4.0 * lam[u] * lam[v] * warp(lam[v] - lam[u]);
+            for (int d = 0; d < 3; ++d) w[d] += amt * dir[d] / len;
+          }
+          const double la = lam[va], lb = lam[fv[0]], lc = lam[fv[1]], ld = lam[fv[2]];
+          const double den = (lb + 0.5 * la) * (lc + 0.5 * la) * (ld + 0.5 * la);
+          const double beta = den > tol ? lb * lc * ld / den : 0.0;
+          for (int d = 0; d < 3; ++d) shift[d] += beta * w[d];
+          if (la < tol && nonzero == 2)
+            for (int d = 0; d < 3; ++d) shift[d] = w[d];
+        }
+        for (int d = 0; d < 3; ++d) X[d] += shift[d];
+        // back to barycentrics of the equilateral tetrahedron, then bi-unit
+        double A4[16], rhs[4] = {X[0], X[1], X[2], 1.0};
+        for (int d = 0; d < 3; ++d)
+          for (int v = 0; v < 4; ++v) A4[d * 4 + v] = E[v][d];
+        for (int v = 0; v < 4; ++v) A4[12 + v] = 1.0;
+        std::vector<double> Am(A4, A4 + 16), bv(rhs, rhs + 4);
+        if (!solve_dense(4, 1, Am, bv)) throw std::runtime_error("tet node map");
+        const int idx = tet_index(N, a, b, c);
+        r[idx] = -1.0 + 2.0 * bv[1];
+        s[idx] = -1.0 + 2.0 * bv[2];
+        t[idx] = -1.0 + 2.0 * bv[3];
+      }
+
+  // operators
+  std::vector<double> V(NP * NP), Vr(NP * NP), Vs(NP * NP), Vt(NP * NP);
+  for (int i = 0; i < NP; ++i) pkd3(N, r[i], s[i], t[i], &V[i * NP], &Vr[i * NP], &Vs[i * NP], &Vt[i * NP]);
+  invert(NP, V, Vinv_);
+  Dr = matmul(NP, NP, NP, Vr, Vinv_);
+  Ds = matmul(NP, NP, NP, Vs, Vinv_);
+  Dt = matmul(NP, NP, NP, Vt, Vinv_);
+  {
+    std::vector<double> VVt(NP * NP, 0.0);
+    for (int i = 0; i < NP; ++i)
+      for (int j = 0; j < NP; ++j)
+        for (int m = 0; m < NP; ++m) VVt[i * NP + j] += V[i * NP + m] * V[j * NP + m];
+    invert(NP, VVt, M);
+  }
+
+  // face node lists: face-local triangle node (a', b') has barycentrics
+  // (N-a'-b', a', b') relative to the face's vertices
+  for (int f = 0; f < 4; ++f) {
+    face_nodes[f].assign(NT, 0);
+    for (int bb = 0; bb <= N; ++bb)
+      for (int aa = 0; aa + bb <= N; ++aa) {
+        int L[4] = {0, 0, 0, 0};
+        L[kTetFaceVerts[f][0]] = N - aa - bb;
+        L[kTetFaceVerts[f][1]] = aa;
+        L[kTetFaceVerts[f][2]] = bb;
+        face_nodes[f][tri_index(N, aa, bb)] = tet_index(N, L[1], L[2], L[3]);
+      }
+  }
+  // LIFT = M^-1 [E_0 .. E_3]: on its face a tetrahedron basis function is the
+  // triangle basis function of the face node (or zero), so E_f holds the
+  // reference triangle mass in the rows of the face's nodes
+  RefOps tri(N);
+  std::vector<double> Ef(NP * 4 * NT, 0.0);
+  for (int f = 0; f < 4; ++f)
+    for (int m = 0; m < NT; ++m)
+      for (int q = 0; q < NT; ++q) Ef[face_nodes[f][m] * 4 * NT + f * NT + q] = tri.Mtri[m * NT + q];
+  LIFT = Ef;
+  if (!solve_dense(NP, 4 * NT, M, LIFT)) throw std::runtime_error("tet lift");
+}
+
+void TetOps::basis(double rr, double ss, double tt, double* out) const {
+  std::vector<double> psi(NP);
+  pkd3(N, rr, ss, tt, psi.data(), nullptr, nullptr, nullptr);
+  for (int j = 0; j < NP; ++j) {
+    double acc = 0.0;
+    for (int m = 0; m < NP; ++m) acc += Vinv_[m * NP + j] * psi[m];
+    out[j] = acc;
   }
 }
 

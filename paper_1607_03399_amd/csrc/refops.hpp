@@ -44,6 +44,35 @@ struct RefOps {
 
 int tri_index(int N, int a, int b);
 
+// Tetrahedron reference operators for the affine tetrahedra of hybrid meshes
+// (standard nodal DG on simplices).  Bi-unit tetrahedron with vertices
+// V0=(-1,-1,-1), V1=(1,-1,-1), V2=(-1,1,-1), V3=(-1,-1,1).  Nodes: Warp &
+// Blend (alpha = 0); lattice (a,b,c), a+b+c <= N, integer barycentrics
+// (N-a-b-c, a, b, c) relative to (V0..V3), index tet_index(N,a,b,c).  The
+// nodes of each face coincide with the triangle nodes, so tetrahedra and the
+// wedges' triangular faces share face nodes (Sec. 3.1).
+// Faces: 0 = (V0,V1,V2), 1 = (V0,V1,V3), 2 = (V1,V2,V3), 3 = (V0,V2,V3); the
+// nodes of a face are numbered as the triangle's, with barycentrics relative
+// to the face's vertices in that order.
+struct TetOps {
+  int N = 0, NT = 0, NP = 0;
+  std::vector<double> r, s, t;          // NP nodes
+  std::vector<double> Dr, Ds, Dt;       // NP x NP, row = output node
+  std::vector<double> M;                // NP x NP exact reference mass
+  std::vector<double> LIFT;             // NP x 4 NT: M^-1 [E_0 .. E_3], E_f = reference face mass
+  std::array<std::vector<int>, 4> face_nodes;  // NT tetrahedron node ids per face
+
+  explicit TetOps(int N);
+  // Lagrange basis of the tetrahedron at (r,s,t): NP values.
+  void basis(double rr, double ss, double tt, double* out) const;
+
+ private:
+  std::vector<double> Vinv_;
+};
+
+int tet_index(int N, int a, int b, int c);
+extern const int kTetFaceVerts[4][3];
+
 // The six permutations of three face vertices; permutation p maps own face
 // vertex k to neighbour face vertex kPerm[p][k].
 extern const int kPerm[6][3];

@@ -150,7 +150,15 @@ class Solver:
         t = np.ascontiguousarray(np.zeros((0, 4)) if tets is None else tets, dtype=np.int64)
         self._check(self._lib.wdg_set_mesh(self._h, len(v), _ptr(v), len(w), _ptr(w, C.c_int64), len(t),
                                            _ptr(t, C.c_int64)), "set_mesh")
-        self.K = len(w) + len(t)
+        self.Kw, self.Kt = len(w), len(t)
+        self.K = self.Kw + self.Kt
+        self.Npt = (self.N + 1) * (self.N + 2) * (self.N + 3) // 6
+        # element-major arrays are padded to the largest element: (K, ..., NPmax);
+        # mask[k, i] marks the nodes element k has (wedges first, then tetrahedra)
+        self.NPmax = self.Np if self.Kw else self.Npt
+        self.mask = np.zeros((self.K, self.NPmax), dtype=bool)
+        self.mask[:self.Kw, :self.Np] = True
+        self.mask[self.Kw:, :self.Npt] = True
 
     def set_material(self, c, rho):
         c = np.ascontiguousarray(np.broadcast_to(c, (self.K,)), dtype=np.float64)
@@ -169,20 +177,34 @@ class Solver:
         return n.value
 
     def node_coords(self) -> np.ndarray:
+        """(K, NPmax, 3) node coordinates, zero on padding."""
         out = np.zeros((self.num_nodes(), 3))
         self._check(self._lib.wdg_get_node_coords(self._h, _ptr(out)), "get_node_coords")
-        return out.reshape(self.K, self.Np, 3)
+        X = np.zeros((self.K, self.NPmax, 3))
+        X[self.mask] = out
+        return X
+
+    def _flatten(self, U) -> np.ndarray:
+        """(K, 4, NPmax) -> (4, nodes) in the library's node order."""
+        U = np.asarray(U, dtype=np.float64).reshape(self.K, 4, self.NPmax)
+        return np.ascontiguousarray(np.stack([U[:, f, :][self.mask] for f in range(4)]))
+
+    def _unflatten(self, F) -> np.ndarray:
+        U = np.zeros((self.K, 4, self.NPmax))
+        for f in range(4):
+            U[:, f, :][self.mask] = F[f]
+        return U
 
     # -- state -------------------------------------------------------------
     def set_fields(self, U):
-        U = np.asarray(U, dtype=np.float64).reshape(self.K, 4, self.Np)
-        f = [np.ascontiguousarray(U[:, i, :]) for i in range(4)]
-        self._check(self._lib.wdg_set_fields(self._h, *[_ptr(a) for a in f]), "set_fields")
+        """U: (K, 4, NPmax) nodal values of (p, u_x, u_y, u_z); padding ignored."""
+        F = self._flatten(U)
+        self._check(self._lib.wdg_set_fields(self._h, *[_ptr(F[i]) for i in range(4)]), "set_fields")
 
     def get_fields(self) -> np.ndarray:
-        f = [np.zeros((self.K, self.Np)) for _ in range(4)]
-        self._check(self._lib.wdg_get_fields(self._h, *[_ptr(a) for a in f]), "get_fields")
-        return np.stack(f, axis=1)
+        F = np.zeros((4, self.num_nodes()))
+        self._check(self._lib.wdg_get_fields(self._h, *[_ptr(F[i]) for i in range(4)]), "get_fields")
+        return self._unflatten(F)
 
     def bind_torch(self, device=None, stream=None):
         """Allocate the state as torch tensors on the current HIP device and run
@@ -247,11 +269,10 @@ class Solver:
         self._check(self._lib.wdg_synchronize(self._h), "synchronize")
 
     def eval_rhs(self, U, t: float = 0.0) -> np.ndarray:
-        U = np.asarray(U, dtype=np.float64).reshape(self.K, 4, self.Np)
-        inp = np.ascontiguousarray(np.transpose(U, (1, 0, 2)))  # field blocks
+        inp = self._flatten(U)  # field blocks
         out = np.zeros_like(inp)
         self._check(self._lib.wdg_eval_rhs(self._h, float(t), _ptr(inp), _ptr(out)), "eval_rhs")
-        return np.ascontiguousarray(np.transpose(out, (1, 0, 2)))
+        return self._unflatten(out)
 
     def energy(self) -> float:
         E = C.c_double()
@@ -269,8 +290,8 @@ class Solver:
         return ms.value, n.value
 
     def element_data(self):
-        """(geo (K,40), lift (K,Np_tri,Np_tri)) built by the device setup kernel."""
-        geo = np.zeros((self.K, 40))
-        lift = np.zeros((self.K, self.NT, self.NT))
+        """(geo (Kw,40), lift (Kw,Np_tri,Np_tri)) of the wedges, built by the device setup kernel."""
+        geo = np.zeros((self.Kw, 40))
+        lift = np.zeros((self.Kw, self.NT, self.NT))
         self._check(self._lib.wdg_get_element_data(self._h, _ptr(geo), _ptr(lift)), "get_element_data")
         return geo, lift

@@ -134,7 +134,15 @@ def test_validation_error_codes():
     degenerate[2, :2] = degenerate[5, :2] = [2.0, 0.0]
     _expect("WDG_ERR_JACOBIAN", s.set_mesh, degenerate, w)
     _expect("WDG_ERR_ARG", s.set_mesh, v, np.array([[0, 1, 2, 3, 4, 9]]))
-    _expect("WDG_ERR_ARG", s.set_mesh, v, w, np.array([[0, 1, 2, 3]]))
+    # a tetrahedron on the bottom triangle and one vertex of the top: its
+    # triangles cut across the wedge's quadrilateral faces
+    _expect("WDG_ERR_NONCONFORMING", s.set_mesh, v, w, np.array([[0, 1, 2, 3]]))
+    vt = np.vstack([v, [[0.3, 0.3, -1.0]]])
+    s.set_mesh(vt, w, np.array([[0, 2, 1, 6]]))  # tetrahedron below the wedge (valid)
+    _expect("WDG_ERR_ORIENTATION", s.set_mesh, vt, w, np.array([[0, 1, 2, 6]]))
+    _expect("WDG_ERR_ARG", s.set_mesh, vt, w, np.array([[0, 1, 2, 7]]))
+    flat_t = np.vstack([v, [[0.3, 0.3, 0.0]]])
+    _expect("WDG_ERR_JACOBIAN", s.set_mesh, flat_t, w, np.array([[0, 2, 1, 6]]))
     # three wedges on one triangle face
     v2 = np.vstack([v, v[3:] + [0, 0, 1], v[:3] - [0, 0, 1]])
     w3 = np.array([[0, 1, 2, 3, 4, 5], [3, 4, 5, 6, 7, 8], [9, 10, 11, 3, 4, 5]])
@@ -192,4 +200,69 @@ def test_no_device_is_an_error_not_a_fallback():
     v, w = _one_wedge()
     s = wdg.Solver(2, 64, 0)
     _expect("WDG_ERR_HIP", s.set_mesh, v, w)
+    s.close()
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5])
+def test_tet_reference_operators_match_oracle(N):
+    """Tetrahedron nodes, derivative, mass and lift matrices of the library's
+    own construction against the oracle's (nodes: same Warp & Blend reading;
+    operators: the oracle's Vandermonde derivatives and quadrature)."""
+    T = OB.Tet(N)
+    Np, NT = T.Np, (N + 1) * (N + 2) // 2
+    for name, ref in (("tet_r", T.r), ("tet_s", T.s), ("tet_t", T.t)):
+        np.testing.assert_allclose(wdg.reference_operator(N, name), ref, atol=1e-13)
+    _, G = T.eval(T.r, T.s, T.t)
+    for d, name in enumerate(("tet_Dr", "tet_Ds", "tet_Dt")):
+        np.testing.assert_allclose(wdg.reference_operator(N, name).reshape(Np, Np), G[..., d], atol=1e-10)
+    r, s, t, w = OB.tet_quadrature(N + 2)
+    Bq, _ = T.eval(r, s, t)
+    M = np.einsum("q,qi,qj->ij", w, Bq, Bq)
+    np.testing.assert_allclose(wdg.reference_operator(N, "tet_M").reshape(Np, Np), M, atol=1e-12)
+    tri = OB.Triangle(N)
+    E = np.zeros((Np, 4 * NT))
+    for f, (xi, wf, _, _) in enumerate(T.face_rules()):
+        Bf, _ = T.eval(xi[:, 0], xi[:, 1], xi[:, 2])
+        ra, sa, _ = OB.tri_quadrature(N + 2)
+        Lt, _, _ = tri.eval(ra, sa)
+        E[:, f * NT:(f + 1) * NT] = np.einsum("q,qi,qm->im", wf, Bf, Lt)
+    LIFT = np.linalg.solve(M, E)
+    np.testing.assert_allclose(wdg.reference_operator(N, "tet_LIFT").reshape(Np, 4 * NT), LIFT, atol=1e-10)
+    # face node lists: the triangle nodes mapped through the face's vertices, in order
+    tr, ts = OB.tri_nodes(N)
+    lam = np.stack([-(tr + ts) / 2, (1 + tr) / 2, (1 + ts) / 2], 1)
+    X = np.stack([T.r, T.s, T.t], 1)
+    for f, fv in enumerate(T.face_verts):
+        ids = wdg.reference_operator(N, f"tet_face{f}").astype(int)
+        P = lam @ T.ref_verts[list(fv)]
+        np.testing.assert_allclose(X[ids], P, atol=1e-13)
+
+
+def _hybrid_mesh(nx=3, layers=4, tet_layers=2, seed=1):
+    m = inputs.layered_config(nx, layers, 0.3, seed=seed)
+    return inputs.split_layers(m, tet_layers)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+def test_hybrid_node_coordinates_and_dt_match_oracle(N):
+    v, w, t, c, rho = _hybrid_mesh()
+    s = _host_solver(N)
+    s.set_mesh(v, w, t)
+    assert s.num_nodes() == len(w) * s.Np + len(t) * s.Npt
+    om = dg.Mesh(v, w, c, rho, tets=t)
+    np.testing.assert_allclose(s.node_coords(), dg.node_coords(om, N), atol=1e-14)
+    s.set_material(c, rho)
+    dt = s.stable_dt(0.5)
+    ref = dg.stable_dt(om, N, 0.5)
+    assert abs(dt - ref) < 1e-12 * ref
+    s.close()
+
+
+def test_tetrahedra_only_mesh_is_accepted():
+    v, w, t, c, rho = _hybrid_mesh(nx=2, layers=2, tet_layers=2)
+    assert len(w) == 0
+    s = _host_solver(2)
+    s.set_mesh(v, w, t)
+    om = dg.Mesh(v, w, c, rho, tets=t)
+    np.testing.assert_allclose(s.node_coords(), dg.node_coords(om, 2)[:, :s.Npt], atol=1e-14)
     s.close()
