@@ -25,6 +25,16 @@ import numpy as np
 HBM_PEAK_GBS = 8000.0
 
 
+def tet_stage_bytes(N: int, bits: int, reads_res: bool) -> int:
+    """Algorithmic HBM bytes of one stage for one tetrahedron: state, residual
+    as for wedges (4 fields x Np_tet), geometry and material record (32
+    values), connectivity (8 int32); reference operators are read once per
+    block and counted as cache hits."""
+    NP = (N + 1) * (N + 2) * (N + 3) // 6
+    ts = bits // 8
+    return 4 * NP * ts * (3 + int(reads_res)) + 32 * ts + 8 * 4
+
+
 def stage_bytes(N: int, bits: int, reads_res: bool) -> int:
     """Algorithmic HBM bytes of one stage for one wedge.
 
@@ -124,7 +134,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="cfg2", choices=["cfg2", "cfg5"])
+    ap.add_argument("--config", default="cfg2", choices=["cfg2", "cfg5", "cfg3"],
+                    help="cfg2 (default): 262144 wedges, N=3; cfg5: 524288 wedges, N=3; cfg3: hybrid "
+                         "38912 wedges + 30720 tetrahedra (lowest 5 of 24 layers split), N=4")
+    ap.add_argument("--precision", type=int, default=32, choices=[32, 64])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -149,16 +162,29 @@ def main():
     if args.copy_calibration:
         copy_gbs = copy_bandwidth()
 
-    N, bits = 3, 32
-    mesh = inputs.cfg2_mesh() if args.config == "cfg2" else inputs.cfg5_mesh()
-    K = mesh.K
+    bits = args.precision
+    if args.config == "cfg3":
+        N = 4
+        verts, wedges, tets, c, rho = inputs.cfg3_hybrid_mesh()
+        mesh = None
+        desc = ("cfg3 (layer-split reading): 32x32 base x 24 layers, lowest 5 layers split into 3 tetrahedra per "
+                f"prism: {len(wedges)} wedges + {len(tets)} tetrahedra, N=4 (75/35 nodes), banded c and rho, "
+                "rigid walls, upwind flux, Ricker source f0=10, LSRK(5,4), CFL 0.5")
+    else:
+        N = 3
+        mesh = inputs.cfg2_mesh() if args.config == "cfg2" else inputs.cfg5_mesh()
+        verts, wedges, tets, c, rho = mesh.verts, mesh.wedges, np.zeros((0, 4), np.int64), mesh.c, mesh.rho
+        desc = (f"{args.config}: layered vertically mapped wedges, {len(wedges)} elements "
+                f"({'64x64x32' if args.config == 'cfg2' else '128x128x16'}), N=3 (40 nodes/wedge), "
+                "banded c and rho, rigid walls, upwind flux, Ricker source f0=10, LSRK(5,4), CFL 0.5")
+    Kw, Kt = len(wedges), len(tets)
     s = wdg.Solver(N, bits, device=0)
-    s.set_mesh(mesh.verts, mesh.wedges)
-    s.set_material(mesh.c, mesh.rho)
+    s.set_mesh(verts, wedges, tets)
+    s.set_material(c, rho)
     s.set_boundary("rigid")
     s.set_flux("upwind")
     s.add_ricker_source([0.5, 0.5, 0.5], 10.0, 0.1, 1.0)
-    s.set_fields(np.zeros((K, 4, s.Np)))
+    s.set_fields(np.zeros((s.K, 4, s.NPmax)))
     s.bind_torch()
     dt = s.stable_dt(0.5)
 
@@ -171,7 +197,7 @@ def main():
     s.synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kms, nlaunch = s.read_kernel_timing()
+    w_ms, t_ms, nlaunch = s.read_kernel_timing_split()
     s.kernel_timing(False)
     U = s.get_fields()
     if not np.all(np.isfinite(U)):
@@ -179,13 +205,21 @@ def main():
 
     launches_expected = 5 * args.steps
     assert nlaunch == launches_expected, (nlaunch, launches_expected)
-    bytes_total = K * args.steps * (stage_bytes(N, bits, False) + 4 * stage_bytes(N, bits, True))
-    avg_launch_s = kms / 1e3 / nlaunch
-    achieved = bytes_total / nlaunch / avg_launch_s / 1e9
-    value = K * s.Np * 5 * args.steps / wall
+    nodes = Kw * s.Np + Kt * s.Npt
+    value = nodes * 5 * args.steps / wall
+    wbytes = Kw * args.steps * (stage_bytes(N, bits, False) + 4 * stage_bytes(N, bits, True))
+    tbytes = Kt * args.steps * (tet_stage_bytes(N, bits, False) + 4 * tet_stage_bytes(N, bits, True))
+    kernels = {}
+    if Kw:
+        kernels["wedge_stage"] = {"avg_us": w_ms * 1e3 / nlaunch, "GBs": wbytes / (w_ms / 1e3) / 1e9}
+    if Kt:
+        kernels["tet_stage"] = {"avg_us": t_ms * 1e3 / nlaunch, "GBs": tbytes / (t_ms / 1e3) / 1e9}
+    dominant = max(kernels, key=lambda k: kernels[k]["avg_us"])
+    achieved = kernels[dominant]["GBs"]
+    dtype = "f32" if bits == 32 else "f64"
 
     out = {
-        "metric": "DG node-updates/s per RK stage (wedge N=3, FP32)",
+        "metric": f"DG node-updates/s per RK stage ({'wedge' if not Kt else 'wedge+tet'} N={N}, FP{bits})",
         "value": value,
         "unit": "node-updates/s",
         "n_gpus": 1,
@@ -195,30 +229,31 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {
-            "workload": f"{args.config}: layered vertically mapped wedges, {K} elements "
-                        f"({'64x64x32' if args.config == 'cfg2' else '128x128x16'}), N=3 (40 nodes/wedge), FP32, "
-                        "banded c and rho, rigid walls, upwind flux, Ricker source f0=10, LSRK(5,4), CFL 0.5",
-            "elements": K,
+            "workload": desc,
+            "elements": Kw + Kt,
+            "wedges": Kw,
+            "tetrahedra": Kt,
             "order": N,
-            "nodes_per_element": s.Np,
+            "nodes": nodes,
             "dt": dt,
-            "stage_kernel_avg_us": avg_launch_s * 1e6,
+            "kernels": kernels,
         },
         "roofline": {
             "bound": "hbm",
+            "kernel": dominant,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.config),
+            "traffic": measured_traffic(args.config) if bits == 32 else None,
             "measured_copy_GBs": copy_gbs,
         },
     }
     s.close()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and mesh is not None:
         out["cpu_baseline"] = cpu_baseline(mesh, N, dt, args.cpu_seconds, args.cpu_sample)
     print(json.dumps(out), flush=True)
 

@@ -139,12 +139,15 @@ int wdg_eval_rhs(wdg_ctx* ctx, double t, const double* in4, double* out4);
  * M^k = M^{tri,k} (x) M^1D (Sec. 4.2), evaluated on the device. */
 int wdg_energy(wdg_ctx* ctx, double* E);
 
-/* Per-launch timing of the stage kernel with HIP events on the context stream:
+/* Per-launch timing of the stage kernels with HIP events on the context stream:
  * enable = 1 starts collecting (and clears), 0 stops.  read returns the summed
- * kernel time in milliseconds and the number of timed launches since the last
- * read or enable, waiting for the stream first. */
+ * kernel time in milliseconds and the number of timed stages since the last
+ * read or enable, waiting for the stream first; the split variant returns the
+ * wedge kernel's and the tetrahedron kernel's time separately (a stage runs
+ * the wedge kernel, then the tetrahedron kernel of hybrid meshes). */
 int wdg_kernel_timing(wdg_ctx* ctx, int enable);
 int wdg_read_kernel_timing(wdg_ctx* ctx, double* total_ms, int64_t* launches);
+int wdg_read_kernel_timing_split(wdg_ctx* ctx, double* wedge_ms, double* tet_ms, int64_t* launches);
 
 /* Test hook: per-element data built on the device by the FP64 setup kernel,
  * converted to double.  geo: nw x 40 values, slots

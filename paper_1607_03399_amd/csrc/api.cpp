@@ -91,7 +91,7 @@ struct wdg_ctx {
   double* dRecBuf = nullptr;
   int64_t rec_cap = 0, rec_steps = 0;
   bool timing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  std::vector<std::array<hipEvent_t, 3>> events;  // stage start, after the wedge kernel, after the tet kernel
   size_t events_used = 0;
 
   size_t tsize() const { return bits == 32 ? 4 : 8; }
@@ -156,10 +156,8 @@ void release_device(wdg_ctx* ctx) {
   dfree(ctx->dRecRows);
   dfree(ctx->dRecBuf);
   ctx->rec_cap = 0;
-  for (auto& ev : ctx->events) {
-    (void)hipEventDestroy(ev.first);
-    (void)hipEventDestroy(ev.second);
-  }
+  for (auto& ev : ctx->events)
+    for (auto& e : ev) (void)hipEventDestroy(e);
   ctx->events.clear();
   ctx->events_used = 0;
 }
@@ -364,18 +362,20 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
             (ctx->flux == WDG_FLUX_CENTRAL ? wdg::kCentral : 0);
   if (ctx->timing) {
     if (ctx->events_used == ctx->events.size()) {
-      hipEvent_t a, b;
-      HIPCHK(hipEventCreate(&a));
-      HIPCHK(hipEventCreate(&b));
-      ctx->events.emplace_back(a, b);
+      std::array<hipEvent_t, 3> ev;
+      for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+      ctx->events.push_back(ev);
     }
     auto& ev = ctx->events[ctx->events_used++];
-    HIPCHK(hipEventRecord(ev.first, ctx->stream));
-    HIPCHK(wdg::launch_stage(ctx->N, ctx->bits, L, ctx->stream));
-    HIPCHK(hipEventRecord(ev.second, ctx->stream));
+    HIPCHK(hipEventRecord(ev[0], ctx->stream));
+    HIPCHK(wdg::launch_wedge_stage(ctx->N, ctx->bits, L, ctx->stream));
+    HIPCHK(hipEventRecord(ev[1], ctx->stream));
+    HIPCHK(wdg::launch_tet_stage(ctx->N, ctx->bits, L, ctx->stream));
+    HIPCHK(hipEventRecord(ev[2], ctx->stream));
     return WDG_OK;
   }
-  HIPCHK(wdg::launch_stage(ctx->N, ctx->bits, L, ctx->stream));
+  HIPCHK(wdg::launch_wedge_stage(ctx->N, ctx->bits, L, ctx->stream));
+  HIPCHK(wdg::launch_tet_stage(ctx->N, ctx->bits, L, ctx->stream));
   return WDG_OK;
 }
 
@@ -1138,21 +1138,32 @@ int wdg_kernel_timing(wdg_ctx* ctx, int enable) {
   return WDG_OK;
 }
 
-int wdg_read_kernel_timing(wdg_ctx* ctx, double* total_ms, int64_t* launches) {
-  if (!ctx || !total_ms || !launches) return WDG_ERR_ARG;
+int wdg_read_kernel_timing_split(wdg_ctx* ctx, double* wedge_ms, double* tet_ms, int64_t* launches) {
+  if (!ctx || !wedge_ms || !tet_ms || !launches) return WDG_ERR_ARG;
   if (ctx->host_only || ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "timing needs a device mesh");
   HIPCHK(hipSetDevice(ctx->device));
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  double acc = 0.0;
+  double aw = 0.0, at = 0.0;
   for (size_t i = 0; i < ctx->events_used; ++i) {
     float ms = 0.0f;
-    HIPCHK(hipEventElapsedTime(&ms, ctx->events[i].first, ctx->events[i].second));
-    acc += ms;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->events[i][0], ctx->events[i][1]));
+    aw += ms;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->events[i][1], ctx->events[i][2]));
+    at += ms;
   }
-  *total_ms = acc;
+  *wedge_ms = aw;
+  *tet_ms = at;
   *launches = int64_t(ctx->events_used);
   ctx->events_used = 0;
   return WDG_OK;
+}
+
+int wdg_read_kernel_timing(wdg_ctx* ctx, double* total_ms, int64_t* launches) {
+  if (!total_ms) return WDG_ERR_ARG;
+  double w = 0.0, t = 0.0;
+  const int rc = wdg_read_kernel_timing_split(ctx, &w, &t, launches);
+  if (rc == WDG_OK) *total_ms = w + t;
+  return rc;
 }
 
 int wdg_get_element_data(const wdg_ctx* ctx, double* geo, double* lift) {

@@ -931,25 +931,25 @@ __global__ void __launch_bounds__(256) energy_tet_kernel(int64_t Kt, const T* __
 }
 
 template <int N, typename T>
-hipError_t launch_stage_t(const StageLaunch& a, hipStream_t st) {
+hipError_t launch_wedge_stage_t(const StageLaunch& a, hipStream_t st) {
   using C = Cfg<N, T>;
   const int64_t nchunks = (a.Kw + C::EPB - 1) / C::EPB;
-  if (nchunks > 0) {
-    if (a.Kt > 0)
-      hipLaunchKernelGGL((wedge_stage<N, T, true>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
-    else
-      hipLaunchKernelGGL((wedge_stage<N, T, false>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-  }
-  if (a.Kt > 0) {
-    using TC = TCfg<N, T>;
-    const int64_t tchunks = (a.Kt + TC::EPB - 1) / TC::EPB;
-    const unsigned grid = unsigned(tchunks < 2048 ? tchunks : 2048);
-    hipLaunchKernelGGL((tet_stage<N, T>), dim3(grid), dim3(TC::BS), 0, st, a);
-    return hipGetLastError();
-  }
-  return hipSuccess;
+  if (nchunks <= 0) return hipSuccess;
+  if (a.Kt > 0)
+    hipLaunchKernelGGL((wedge_stage<N, T, true>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
+  else
+    hipLaunchKernelGGL((wedge_stage<N, T, false>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int N, typename T>
+hipError_t launch_tet_stage_t(const StageLaunch& a, hipStream_t st) {
+  if (a.Kt <= 0) return hipSuccess;
+  using TC = TCfg<N, T>;
+  const int64_t tchunks = (a.Kt + TC::EPB - 1) / TC::EPB;
+  const unsigned grid = unsigned(tchunks < 2048 ? tchunks : 2048);
+  hipLaunchKernelGGL((tet_stage<N, T>), dim3(grid), dim3(TC::BS), 0, st, a);
+  return hipGetLastError();
 }
 
 template <int N, typename T>
@@ -1024,9 +1024,17 @@ hipError_t launch_material(int bits, int64_t K, const double* dc, const double* 
   return hipGetLastError();
 }
 
-hipError_t launch_stage(int N, int bits, const StageLaunch& a, hipStream_t st) {
+hipError_t launch_wedge_stage(int N, int bits, const StageLaunch& a, hipStream_t st) {
   hipError_t err = hipErrorInvalidValue;
-#define WDG_STAGE(n, T) err = launch_stage_t<n, T>(a, st)
+#define WDG_STAGE(n, T) err = launch_wedge_stage_t<n, T>(a, st)
+  WDG_DISPATCH_N(N, bits, WDG_STAGE)
+#undef WDG_STAGE
+  return err;
+}
+
+hipError_t launch_tet_stage(int N, int bits, const StageLaunch& a, hipStream_t st) {
+  hipError_t err = hipErrorInvalidValue;
+#define WDG_STAGE(n, T) err = launch_tet_stage_t<n, T>(a, st)
   WDG_DISPATCH_N(N, bits, WDG_STAGE)
 #undef WDG_STAGE
   return err;

@@ -69,7 +69,9 @@ hipError_t launch_setup(int N, int bits, int64_t K, const double* dX, const doub
                         void* dGeo, void* dL, double* dAux, hipStream_t st);
 hipError_t launch_material(int bits, int64_t K, const double* dc, const double* drho, const int* dConn, void* dGeo,
                            double* dAux, hipStream_t st);
-hipError_t launch_stage(int N, int bits, const StageLaunch& a, hipStream_t st);
+// One stage: the wedge kernel, then (hybrid meshes) the tetrahedron kernel, on the same stream.
+hipError_t launch_wedge_stage(int N, int bits, const StageLaunch& a, hipStream_t st);
+hipError_t launch_tet_stage(int N, int bits, const StageLaunch& a, hipStream_t st);
 // Pressure at receivers: receiver r reads nn[r] nodes from 4-vector index base[r] with row stride ld.
 hipError_t launch_receivers(int bits, int ld, int nrec, const void* U, const int64_t* base, const int* nn,
                             const double* rows, double* out, hipStream_t st);

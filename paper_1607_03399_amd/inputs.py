@@ -186,6 +186,14 @@ def cfg5_mesh() -> WedgeMesh:
     return layered_config(128, 16, 0.3, 0, "cfg5")
 
 
+def cfg3_hybrid_mesh(tet_layers: int = 5):
+    """32x32 base (2048 triangles) x 24 layers with random smooth interfaces;
+    the lowest ``tet_layers`` layers split into tetrahedra (3 per prism):
+    38912 wedges + 30720 tetrahedra at the default, N = 4.  Returns
+    (verts, wedges, tets, c, rho) as ``split_layers``."""
+    return split_layers(layered_config(32, 24, 0.3, 0, "cfg3"), tet_layers)
+
+
 def cube_mesh(n: int, lo: float = -1.0, hi: float = 1.0, z_jitter: float = 0.0, xy_jitter: float = 0.0,
               seed: int = 0) -> WedgeMesh:
     """[lo,hi]^3 with n x n base squares and n layers (mesh size h = (hi-lo)/n).
