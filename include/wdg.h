@@ -54,6 +54,7 @@ enum {
 
 enum { WDG_BC_DIRICHLET_P0 = 0, WDG_BC_RIGID = 1 };
 enum { WDG_FLUX_UPWIND = 0, WDG_FLUX_CENTRAL = 1 };
+enum { WDG_MASS_EXACT = 0, WDG_MASS_LUMPED = 1 };
 
 /* Create a context for polynomial order 1 <= order_N <= 5 computing in
  * precision_bits = 32 (FP32 fields and operators; FP64 setup) or 64.
@@ -70,12 +71,17 @@ const char* wdg_last_error(const wdg_ctx* ctx);
  * counter-clockwise seen from +z, and v4,v5,v6 lie directly above v1,v2,v3
  * (vertex pairs (1,4),(2,5),(3,6) share x and y to 1e-12 relative to the
  * element size, else WDG_ERR_NOT_VERTICAL).  Every vertical edge must have
- * positive length (WDG_ERR_JACOBIAN).  tet_v: nt x 4 (tetrahedra; nt must be
- * 0 in this version, else WDG_ERR_ARG).  Faces are matched through their
- * vertex ids; unmatched faces are domain boundary.  On success the geometric
- * factors and triangular lifts are built on the device in FP64 (host-only
- * contexts build host data only).  Material defaults to c = rho = 1,
- * boundary to rigid, flux to upwind, fields to zero. */
+ * positive length (WDG_ERR_JACOBIAN).  tet_v: nt x 4 vertex ids of affine
+ * tetrahedra with positive orientation (det[v1-v0, v2-v0, v3-v0] > 0, else
+ * WDG_ERR_ORIENTATION; degenerate: WDG_ERR_JACOBIAN); nw or nt may be 0.
+ * Elements are numbered wedges first, then tetrahedra.  Faces are matched
+ * through their vertex ids; unmatched faces are domain boundary.  Tetrahedra
+ * meet wedges only at triangular faces (Sec. 3.1): a wedge's quadrilateral
+ * face left against triangles of tetrahedra is WDG_ERR_NONCONFORMING.  On
+ * success the geometric factors and triangular lifts are built in FP64 (on
+ * the device for wedges, on the host for tetrahedra; host-only contexts build
+ * host data only).  Material defaults to c = rho = 1, boundary to rigid, flux
+ * to upwind, mass to exact, fields to zero. */
 int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const int64_t* wedge_v,
                  int64_t nt, const int64_t* tet_v);
 
@@ -88,6 +94,12 @@ int wdg_set_boundary(wdg_ctx* ctx, int bc);
 /* Numerical flux: WDG_FLUX_UPWIND (tau_p = 1/{rho c}, tau_u = {rho c}; Sec. 2)
  * or WDG_FLUX_CENTRAL (tau = 0; Sec. 4.1). */
 int wdg_set_flux(wdg_ctx* ctx, int flux);
+/* Wedge mass treatment: WDG_MASS_EXACT (default: exact quadrature with the
+ * stored L^{tri,k}, Sec. 4.2-4.3; energy stable) or WDG_MASS_LUMPED
+ * (Gauss-Lobatto quadrature in t, Sec. 4.1: block-diagonal mass, not energy
+ * stable on vertically varying wedges; kept for comparison).  Applies to
+ * the right-hand side and to wdg_energy; tetrahedra are unaffected. */
+int wdg_set_mass(wdg_ctx* ctx, int mass);
 
 /* Total number of nodes (sum over elements of Np). */
 int wdg_num_nodes(const wdg_ctx* ctx, int64_t* n);

@@ -62,7 +62,7 @@ struct wdg_ctx {
   std::vector<int32_t> connT;  // Kt x kTetConnStride
   std::vector<double> geoT;   // Kt x kTetGeoStride (FP64 master copy)
   std::vector<double> c, rho;
-  int bc = WDG_BC_RIGID, flux = WDG_FLUX_UPWIND;
+  int bc = WDG_BC_RIGID, flux = WDG_FLUX_UPWIND, mass = WDG_MASS_EXACT;
   double time = 0.0;
 
   hipStream_t stream = nullptr;
@@ -268,7 +268,11 @@ std::vector<double> mass_inverse_times(const wdg_ctx* ctx, int64_t k, double kap
   R.tri_basis(r, s, lt.data());
   R.line_basis(t, l1.data());
   wdg::solve_dense(R.NT, 1, Mt, lt);
-  wdg::solve_dense(R.Nq, 1, R.M1, l1);
+  if (ctx->mass == WDG_MASS_LUMPED) {
+    for (int j = 0; j < R.Nq; ++j) l1[j] /= R.wgll[j];
+  } else {
+    wdg::solve_dense(R.Nq, 1, R.M1, l1);
+  }
   std::vector<double> out(R.NP);
   for (int j = 0; j < R.Nq; ++j)
     for (int i = 0; i < R.NT; ++i) out[j * R.NT + i] = kappa * lt[i] * l1[j];
@@ -359,7 +363,7 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.Kw = ctx->Kw;
   L.Kt = ctx->Kt;
   L.flags = flags | (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
-            (ctx->flux == WDG_FLUX_CENTRAL ? wdg::kCentral : 0);
+            (ctx->flux == WDG_FLUX_CENTRAL ? wdg::kCentral : 0) | (ctx->mass == WDG_MASS_LUMPED ? wdg::kLumped : 0);
   if (ctx->timing) {
     if (ctx->events_used == ctx->events.size()) {
       std::array<hipEvent_t, 3> ev;
@@ -392,6 +396,20 @@ int ensure_receiver_capacity(wdg_ctx* ctx, int64_t steps_needed) {
   dfree(ctx->dRecBuf);
   ctx->dRecBuf = nb;
   ctx->rec_cap = cap;
+  return WDG_OK;
+}
+
+// vertical mass used by the energy: exact M^1D, or the Gauss-Lobatto weights when lumped
+int upload_vertical_mass(wdg_ctx* ctx) {
+  if (ctx->host_only || !ctx->dM1) return WDG_OK;
+  const RefOps& R = *ctx->ref;
+  std::vector<double> M1 = R.M1;
+  if (ctx->mass == WDG_MASS_LUMPED) {
+    std::fill(M1.begin(), M1.end(), 0.0);
+    for (int j = 0; j < R.Nq; ++j) M1[j * R.Nq + j] = R.wgll[j];
+  }
+  HIPCHK(hipMemcpyAsync(ctx->dM1, M1.data(), M1.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
   return WDG_OK;
 }
 
@@ -713,7 +731,10 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
   std::vector<double> Mv(3 * size_t(R.NT) * R.NT);
   for (int v = 0; v < 3; ++v) std::copy(R.Mv[v].begin(), R.Mv[v].end(), Mv.begin() + v * R.NT * R.NT);
   HIPCHK(hipMemcpyAsync(ctx->dMv, Mv.data(), Mv.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipMemcpyAsync(ctx->dM1, R.M1.data(), R.M1.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  {
+    int rc = upload_vertical_mass(ctx);
+    if (rc) return rc;
+  }
   if (Kw > 0) {
     double *dX = nullptr, *dMtri = nullptr;
     HIPCHK(hipMalloc(&dX, ctx->X.size() * sizeof(double)));
@@ -820,6 +841,26 @@ int wdg_set_flux(wdg_ctx* ctx, int flux) {
   if (!ctx) return WDG_ERR_ARG;
   if (flux != WDG_FLUX_UPWIND && flux != WDG_FLUX_CENTRAL) return fail(ctx, WDG_ERR_ARG, "unknown flux");
   ctx->flux = flux;
+  return WDG_OK;
+}
+
+int wdg_set_mass(wdg_ctx* ctx, int mass) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (mass != WDG_MASS_EXACT && mass != WDG_MASS_LUMPED) return fail(ctx, WDG_ERR_ARG, "unknown mass treatment");
+  ctx->mass = mass;
+  // source vectors kappa (M^k)^-1 l(x_s) follow the mass treatment
+  for (auto& s : ctx->src) {
+    double r, ss, t;
+    if (s.elem < ctx->Kw) wedge_ref_coords(&ctx->X[s.elem * 18], s.xyz, r, ss, t);
+    else tet_ref_coords(&ctx->Xt[(s.elem - ctx->Kw) * 12], s.xyz, r, ss, t);
+    s.vec = mass_inverse_times(ctx, s.elem, ctx->rho[s.elem] * ctx->c[s.elem] * ctx->c[s.elem], r, ss, t);
+  }
+  if (!ctx->host_only && ctx->state >= kMesh) {
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc = upload_vertical_mass(ctx);
+    if (rc) return rc;
+    return upload_sources(ctx);
+  }
   return WDG_OK;
 }
 

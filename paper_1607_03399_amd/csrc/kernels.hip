@@ -428,7 +428,11 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
   if (active) {
     // triangular-face lifts: flux spread over all levels by (M^1D)^-1 e_{0,N}
     {
-      const T g0j = pick<Nq, T>(RT::g0, j, 1, 0), gNj = pick<Nq, T>(RT::gN, j, 1, 0);
+      // exact mass: (M^1D)^-1 e_{0,N}; lumped mass (Gauss-Lobatto weights w): e_{0,N} / w_{0,N}
+      const T wend = T(0.5 * N * (N + 1));  // 1 / w_0 = 1 / w_N
+      const bool lumped = (A.flags & kLumped) != 0;
+      const T g0j = lumped ? (j == 0 ? wend : T(0)) : pick<Nq, T>(RT::g0, j, 1, 0);
+      const T gNj = lumped ? (j == N ? wend : T(0)) : pick<Nq, T>(RT::gN, j, 1, 0);
       const T* fbt = sF + (le * 2 + 0) * NT * 2;
       const T* ftp = sF + (le * 2 + 1) * NT * 2;
       const T bx = g[13], by = g[14], bz = g[15], tx = g[17], ty = g[18], tz = g[19];

@@ -39,6 +39,7 @@ enum StageFlags : int {
   kWriteU = 2,     // U_out = U_in + b res
   kDirichlet = 4,  // else rigid wall
   kCentral = 8,    // else upwind flux
+  kLumped = 16,    // Gauss-Lobatto mass in t: (M^1D)^-1 e_{0,N} becomes e_{0,N} / w_{0,N}
 };
 
 // One stage over the whole mesh.  State buffers hold wedges first (Kw x Np_wedge

@@ -22,6 +22,7 @@ ERRORS = {
 }
 BC = {"dirichlet": 0, "rigid": 1}
 FLUX = {"upwind": 0, "central": 1}
+MASS = {"exact": 0, "lumped": 1}
 
 _lib = None
 _dp = C.POINTER(C.c_double)
@@ -58,6 +59,7 @@ def load_library() -> C.CDLL:
         "wdg_set_material": (C.c_int, [vp, _dp, _dp]),
         "wdg_set_boundary": (C.c_int, [vp, C.c_int]),
         "wdg_set_flux": (C.c_int, [vp, C.c_int]),
+        "wdg_set_mass": (C.c_int, [vp, C.c_int]),
         "wdg_num_nodes": (C.c_int, [vp, _i64p]),
         "wdg_get_node_coords": (C.c_int, [vp, _dp]),
         "wdg_set_fields": (C.c_int, [vp, _dp, _dp, _dp, _dp]),
@@ -171,6 +173,10 @@ class Solver:
 
     def set_flux(self, flux: str):
         self._check(self._lib.wdg_set_flux(self._h, FLUX[flux]), "set_flux")
+
+    def set_mass(self, mass: str):
+        """'exact' (default, energy stable) or 'lumped' (Gauss-Lobatto in t, for comparison)."""
+        self._check(self._lib.wdg_set_mass(self._h, MASS[mass]), "set_mass")
 
     def num_nodes(self) -> int:
         n = C.c_int64()
