@@ -24,7 +24,11 @@ quadrature point through the neighbour's inverse map.  No node maps,
 orientation codes or Kronecker factorisations are used.
 
 Meshes mix wedges (elements 0..nw-1) and tetrahedra (nw..nw+nt-1), joined
-through triangular faces (Sec. 3.1).  Nodal arrays are (K, 4, Np) with Np
+through triangular faces (Sec. 3.1).  Where a wedge's quadrilateral face is
+covered by two triangular tetrahedron faces instead (columns of prisms split
+into tetrahedra next to unsplit columns), the flux is integrated on the
+common refinement, the two triangles, with quadrature exact in the vertical
+coordinate and converged along the edge (``mortar_faces``).  Nodal arrays are (K, 4, Np) with Np
 the largest element size; a tetrahedron uses its first Np_tet entries and
 the rest stay zero (see ``node_mask``).
 """
@@ -133,6 +137,158 @@ def face_connectivity(mesh: Mesh):
     return nbr.reshape(K, NFACE), nbr_face.reshape(K, NFACE)
 
 
+def mortar_faces(mesh: Mesh, nbr: np.ndarray):
+    """Wedge quadrilateral faces covered by two triangular tetrahedron faces.
+
+    The quadrilateral of wedge face f (corners A0, A1 on the bottom edge from
+    its first to its second vertex, A2, A3 above them) is split along A0-A2
+    (diagonal 0) or A1-A3 (diagonal 1).  Returns a list of
+    (wedge, face, diagonal, ((tet, tet_face) below the diagonal,
+    (tet, tet_face) above it)); ``nbr`` is marked -3 on every face involved.
+    """
+    if not mesh.nt:
+        return []
+    open_tri = {}
+    kinds = mesh.kinds()
+    for k in np.nonzero((kinds == 1) & np.any(nbr[:, :4] == -1, axis=1))[0]:
+        for f, fv in enumerate(B.Tet.face_verts):
+            if nbr[k, f] == -1:
+                open_tri[tuple(sorted(mesh.tets[k - mesh.nw][list(fv)]))] = (k, f)
+    out = []
+    for k in range(mesh.nw):
+        for f in range(2, 5):
+            if nbr[k, f] != -1:
+                continue
+            A = mesh.wedges[k][list(B.Wedge.face_verts[f])]  # A0 A1 A2 A3
+            for diag, (lo, hi) in enumerate((((0, 1, 2), (0, 2, 3)), ((0, 1, 3), (1, 2, 3)))):
+                kl = tuple(sorted(A[list(lo)]))
+                kh = tuple(sorted(A[list(hi)]))
+                if kl in open_tri and kh in open_tri:
+                    tl, th = open_tri.pop(kl), open_tri.pop(kh)
+                    out.append((k, f, diag, (tl, th)))
+                    nbr[k, f] = -3
+                    nbr[tl[0], tl[1]] = -3
+                    nbr[th[0], th[1]] = -3
+                    break
+    return out
+
+
+def _mortar_rule(N: int):
+    """Rule on the quadrilateral face in (edge parameter xi, vertical t):
+    Gauss in xi (24 points: the integrand is rational along the edge, with
+    poles far outside [-1,1] while the wedge has positive height) times
+    Gauss in t on each side of the diagonal (N+3 points: exact, the
+    integrands are polynomials of degree <= 2N in t at fixed xi)."""
+    xg, wg = B.gauss_nodes_weights(24)
+    tg, wt = B.gauss_nodes_weights(N + 3)
+    return xg, wg, tg, wt
+
+
+def build_mortars(mesh: Mesh, N: int, refs, elems: np.ndarray):
+    """Quadrature data of every mortar region touching ``elems``: own wedge and
+    tetrahedron basis values at the points of the common refinement."""
+    nbr, _ = face_connectivity(mesh)
+    mortars = mortar_faces(mesh, nbr)
+    if not mortars:
+        return None
+    xg, wg, tg, wt = _mortar_rule(N)
+    W, T = refs[0], refs[1]
+    pos = -np.ones(mesh.K, dtype=np.int64)
+    pos[elems] = np.arange(len(elems))
+    Z = mesh.rho * mesh.c
+    regions = []
+    for (k, f, diag, tets) in mortars:
+        X = mesh.verts[mesh.wedges[k]]
+        e = f - 2
+        a, b = e, (e + 1) % 3
+        zb = X[a, 2] * (1 - xg) / 2 + X[b, 2] * (1 + xg) / 2
+        zt = X[a + 3, 2] * (1 - xg) / 2 + X[b + 3, 2] * (1 + xg) / 2
+        if diag == 0:
+            zd = X[a, 2] * (1 - xg) / 2 + X[b + 3, 2] * (1 + xg) / 2
+        else:
+            zd = X[b, 2] * (1 + xg) / 2 + X[a + 3, 2] * (1 - xg) / 2
+        td = (2 * zd - zb - zt) / (zt - zb)
+        centroid = X.mean(axis=0)
+        for side, (t_el, t_face) in enumerate(tets):
+            if pos[k] < 0 and pos[t_el] < 0:
+                continue
+            lo = -1.0 if side == 0 else td
+            hi = td if side == 0 else 1.0
+            T_ = (lo + hi)[:, None] / 2 + ((hi - lo)[:, None] / 2) * tg[None, :]   # (nxi, nt)
+            w = wg[:, None] * wt[None, :] * (hi - lo)[:, None] / 2
+            xi_e = np.repeat(xg, len(tg))
+            tt = T_.ravel()
+            if e == 0:
+                rs = np.stack([xi_e, -np.ones_like(xi_e)], 1)
+                da = np.array([1.0, 0, 0])
+            elif e == 1:
+                rs = np.stack([-xi_e, xi_e], 1)
+                da = np.array([-1.0, 1.0, 0])
+            else:
+                rs = np.stack([-np.ones_like(xi_e), -xi_e], 1)
+                da = np.array([0, -1.0, 0])
+            xi = np.concatenate([rs, tt[:, None]], 1)
+            xq, Jq = G.map_points("wedge", X[None], xi)
+            xq, Jq = xq[0], Jq[0]
+            t1 = Jq @ da
+            t2 = Jq @ np.array([0, 0, 1.0])
+            cr = np.cross(t1, t2)
+            area = np.linalg.norm(cr, axis=-1)
+            n = cr[0] / area[0]
+            if np.dot(xq[0] - centroid, n) < 0:
+                n = -n
+            wJ = w.ravel() * area
+            Pw, _ = W.eval(xi[:, 0], xi[:, 1], xi[:, 2])
+            Xt = mesh.verts[mesh.tets[t_el - mesh.nw]]
+            xt = G.inverse_map("tet", np.repeat(Xt[None], len(xq), axis=0), xq)
+            Pt, _ = T.eval(xt[:, 0], xt[:, 1], xt[:, 2])
+            Zs = Z[k] + Z[t_el]
+            if mesh.flux == "upwind":
+                tp, tu = 2.0 / Zs, Zs / 2.0
+            else:
+                tp = tu = 0.0
+            regions.append(dict(k=k, f=f, t=t_el, pk=pos[k], pt=pos[t_el], Pw=Pw, Pt=Pt, wJ=wJ, n=n,
+                                tau_p=tp, tau_u=tu))
+    return regions
+
+
+def _mortar_fluxes(reg, U):
+    """Traces and fluxes of one mortar region seen from the wedge."""
+    Uw = U[..., reg["k"], :, :]
+    Ut = U[..., reg["t"], :, :]
+    Pw, Pt, n = reg["Pw"], reg["Pt"], reg["n"]
+    pm = np.einsum("qj,...j->...q", Pw, Uw[..., 0, :Pw.shape[1]])
+    um = np.einsum("qj,...dj->...dq", Pw, Uw[..., 1:4, :Pw.shape[1]])
+    pp = np.einsum("qj,...j->...q", Pt, Ut[..., 0, :Pt.shape[1]])
+    up = np.einsum("qj,...dj->...dq", Pt, Ut[..., 1:4, :Pt.shape[1]])
+    jp = pp - pm
+    jun = np.einsum("...dq,d->...q", up - um, n)
+    return jp, jun
+
+
+def _add_mortars(ops, U, surf):
+    for reg in ops.extra.get("mortars") or []:
+        jp, jun = _mortar_fluxes(reg, U)
+        tp, tu, n, wJ = reg["tau_p"], reg["tau_u"], reg["n"], reg["wJ"]
+        if reg["pk"] >= 0:
+            Fp = 0.5 * (tp * jp - jun)
+            Fu = 0.5 * (tu * jun - jp)
+            Pw = reg["Pw"]
+            nw_ = Pw.shape[1]
+            surf[..., reg["pk"], 0, :nw_] += np.einsum("qj,...q->...j", Pw, wJ * Fp)
+            for d in range(3):
+                surf[..., reg["pk"], d + 1, :nw_] += np.einsum("qj,...q->...j", Pw, wJ * n[d] * Fu)
+        if reg["pt"] >= 0:
+            # seen from the tetrahedron: normal -n, jumps [p]' = -[p], [u.n]' = [u.n]
+            Fp = 0.5 * (-tp * jp - jun)
+            Fu = 0.5 * (tu * jun + jp)
+            Pt = reg["Pt"]
+            nt_ = Pt.shape[1]
+            surf[..., reg["pt"], 0, :nt_] += np.einsum("qj,...q->...j", Pt, wJ * Fp)
+            for d in range(3):
+                surf[..., reg["pt"], d + 1, :nt_] -= np.einsum("qj,...q->...j", Pt, wJ * n[d] * Fu)
+
+
 # ---------------------------------------------------------------------------
 # Dense element operators
 # ---------------------------------------------------------------------------
@@ -172,6 +328,7 @@ def build_operators(mesh: Mesh, N: int, elems=None, lumped: bool = False, chunk:
     nq = max(len(rule[1]) for rr in rules for rule in rr)
 
     nbr_all, _ = face_connectivity(mesh)
+    mortar_faces(mesh, nbr_all)  # marks the faces integrated on the common refinement (-3)
     kappa_all = mesh.rho * mesh.c ** 2
     Z_all = mesh.rho * mesh.c
 
@@ -221,7 +378,7 @@ def build_operators(mesh: Mesh, N: int, elems=None, lumped: bool = False, chunk:
                 nvec = cr / area[..., None]
                 sign = np.sign(np.einsum("kqd,kqd->k", xq - centroid[:, None, :], nvec))
                 nn[f][loc, :m_f] = nvec * sign[:, None, None]
-                wJ[f][loc, :m_f] = w_f[None, :] * area
+                wJ[f][loc, :m_f] = w_f[None, :] * area * (nbr_all[ids, f] != -3)[:, None]
                 nb = nbr_all[ids, f]
                 for nkind, nref in enumerate(refs):
                     inner = np.nonzero((nb >= 0) & (kinds_all[np.maximum(nb, 0)] == nkind))[0]
@@ -243,9 +400,11 @@ def build_operators(mesh: Mesh, N: int, elems=None, lumped: bool = False, chunk:
         tau_u = np.zeros_like(Zm)
     else:
         raise ValueError(mesh.flux)
-    return Operators(N=N, elems=elems, M=M, Minv=Minv, S=Sd, Pown=Pown, wJ=wJ, n=nn, nbr=nbr,
-                     Pnbr=Pnbr, tau_p=tau_p, tau_u=tau_u, kappa=kappa_all[elems], rho=mesh.rho[elems],
-                     bc=mesh.bc)
+    ops = Operators(N=N, elems=elems, M=M, Minv=Minv, S=Sd, Pown=Pown, wJ=wJ, n=nn, nbr=nbr,
+                    Pnbr=Pnbr, tau_p=tau_p, tau_u=tau_u, kappa=kappa_all[elems], rho=mesh.rho[elems],
+                    bc=mesh.bc)
+    ops.extra["mortars"] = build_mortars(mesh, N, refs, elems)
+    return ops
 
 
 # ---------------------------------------------------------------------------
@@ -301,6 +460,7 @@ def rhs(ops: Operators, U: np.ndarray) -> np.ndarray:
         surf[..., 0, :] += np.einsum("kqj,...kq->...kj", P, ops.wJ[f] * Fp)
         for d in range(3):
             surf[..., d + 1, :] += np.einsum("kqj,...kq->...kj", P, ops.wJ[f] * n[..., d] * Fu)
+    _add_mortars(ops, U, surf)
     out = np.einsum("kij,...kfj->...kfi", ops.Minv, vol + surf)
     out[..., 0, :] *= ops.kappa[:, None]
     out[..., 1:, :] *= (1.0 / ops.rho)[:, None, None]
@@ -334,6 +494,10 @@ def energy_rate_from_jumps(ops: Operators, U: np.ndarray) -> float:
         # boundary faces: the mirror states give [p] = -2 p- (Dirichlet) or
         # [u_n] = -2 u_n- (rigid), so -tau (.)^2 is again -1/4 of the jump form
         total += float(np.sum(-0.25 * ops.wJ[f] * integrand))
+    # faces on a common refinement are visited once: -1/2 of the jump form
+    for reg in ops.extra.get("mortars") or []:
+        jp, jun = _mortar_fluxes(reg, U)
+        total += float(np.sum(-0.5 * reg["wJ"] * (reg["tau_p"] * jp ** 2 + reg["tau_u"] * jun ** 2)))
     return total
 
 

@@ -315,3 +315,34 @@ def split_layers(mesh: WedgeMesh, tet_layers: int):
     c = np.concatenate([mesh.c[keep], np.array(tc)])
     rho = np.concatenate([mesh.rho[keep], np.array(tr)])
     return mesh.verts, wedges, np.array(tets, dtype=np.int64).reshape(-1, 4), c, rho
+
+
+def split_columns(mesh: WedgeMesh, columns):
+    """Hybrid mesh: every wedge of the given base columns (element =
+    column x layers + layer) becomes 3 tetrahedra.  The quadrilateral faces
+    between a split and an unsplit column are then covered by two triangular
+    tetrahedron faces each (nonconforming: a wedge quadrilateral against two
+    triangles).  Returns (verts, wedges, tets, c, rho) as ``split_layers``."""
+    col = np.arange(mesh.K) // mesh.layers
+    split = np.isin(col, np.asarray(columns))
+    tets, tc, tr = [], [], []
+    for k in np.nonzero(split)[0]:
+        for t in prism_to_tets(mesh.wedges[k], mesh.verts):
+            tets.append(t)
+            tc.append(mesh.c[k])
+            tr.append(mesh.rho[k])
+    keep = ~split
+    wedges = mesh.wedges[keep]
+    c = np.concatenate([mesh.c[keep], np.array(tc)])
+    rho = np.concatenate([mesh.rho[keep], np.array(tr)])
+    return mesh.verts, wedges, np.array(tets, dtype=np.int64).reshape(-1, 4), c, rho
+
+
+def cfg3_columns_mesh(fraction: float = 0.2, seed: int = 0):
+    """32x32 base (2048 triangles) x 24 layers with random smooth interfaces and
+    banded material; a seeded random ``fraction`` of the columns split into
+    tetrahedra (410 columns at 20 %: 39312 wedges + 29520 tetrahedra), N = 4."""
+    m = layered_config(32, 24, 0.3, seed, "cfg3")
+    ncol = m.K // m.layers
+    cols = np.random.default_rng(seed).choice(ncol, int(round(fraction * ncol)), replace=False)
+    return split_columns(m, cols)
