@@ -76,8 +76,10 @@ const char* wdg_last_error(const wdg_ctx* ctx);
  * WDG_ERR_ORIENTATION; degenerate: WDG_ERR_JACOBIAN); nw or nt may be 0.
  * Elements are numbered wedges first, then tetrahedra.  Faces are matched
  * through their vertex ids; unmatched faces are domain boundary.  Tetrahedra
- * meet wedges only at triangular faces (Sec. 3.1): a wedge's quadrilateral
- * face left against triangles of tetrahedra is WDG_ERR_NONCONFORMING.  On
+ * meet wedges at triangular faces (Sec. 3.1); a wedge quadrilateral face
+ * covered by two tetrahedron triangles (split along one of its diagonals, as
+ * when columns of prisms are split into tetrahedra) is coupled on that common
+ * refinement; any other partial cover is WDG_ERR_NONCONFORMING.  On
  * success the geometric factors and triangular lifts are built in FP64 (on
  * the device for wedges, on the host for tetrahedra; host-only contexts build
  * host data only).  Material defaults to c = rho = 1, boundary to rigid, flux
@@ -154,12 +156,13 @@ int wdg_energy(wdg_ctx* ctx, double* E);
 /* Per-launch timing of the stage kernels with HIP events on the context stream:
  * enable = 1 starts collecting (and clears), 0 stops.  read returns the summed
  * kernel time in milliseconds and the number of timed stages since the last
- * read or enable, waiting for the stream first; the split variant returns the
- * wedge kernel's and the tetrahedron kernel's time separately (a stage runs
- * the wedge kernel, then the tetrahedron kernel of hybrid meshes). */
+ * read or enable, waiting for the stream first; the split variant writes
+ * ms3[0] wedge kernel, ms3[1] tetrahedron kernel, ms3[2] mortar kernel (a
+ * stage runs the mortar kernel of meshes with nonconforming faces, the wedge
+ * kernel, then the tetrahedron kernel of hybrid meshes). */
 int wdg_kernel_timing(wdg_ctx* ctx, int enable);
 int wdg_read_kernel_timing(wdg_ctx* ctx, double* total_ms, int64_t* launches);
-int wdg_read_kernel_timing_split(wdg_ctx* ctx, double* wedge_ms, double* tet_ms, int64_t* launches);
+int wdg_read_kernel_timing_split(wdg_ctx* ctx, double* ms3, int64_t* launches);
 
 /* Test hook: per-element data built on the device by the FP64 setup kernel,
  * converted to double.  geo: nw x 40 values, slots

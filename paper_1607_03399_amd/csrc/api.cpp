@@ -44,6 +44,18 @@ struct Source {
   }
 };
 
+// A wedge quadrilateral face covered by two tetrahedron triangles (the
+// common refinement of a column-split hybrid mesh).
+struct MortarHost {
+  int64_t k = 0;          // wedge
+  int e = 0, diag = 0;    // quadrilateral face (edge e) and its diagonal (0: A0-A2, 1: A1-A3)
+  int64_t t[2] = {0, 0};  // tetrahedra below / above the diagonal (global ids)
+  int tf[2] = {0, 0};     // their faces
+  double zba = 0, zbb = 0, zta = 0, ztb = 0, ell = 0, nx = 0, ny = 0;
+  double lam[2][9] = {};  // tetrahedron face barycentrics as affine functions of (xi, z)
+  double Jft[2] = {0, 0};  // tetrahedron face area / 2
+};
+
 enum State { kCreated = 0, kMesh = 1, kMaterial = 2, kFields = 3 };
 
 }  // namespace
@@ -83,6 +95,12 @@ struct wdg_ctx {
   double* dAuxT = nullptr;
   double* dMt = nullptr;
   int32_t* dConnT = nullptr;
+  std::vector<MortarHost> mort;
+  int32_t* dMortI = nullptr;
+  void* dMortG = nullptr;
+  void* dMortTab = nullptr;
+  void* dMortB = nullptr;
+  void* dMortF = nullptr;
   std::vector<Source> src;
   int64_t nrec = 0;
   int64_t* dRecBase = nullptr;
@@ -91,7 +109,8 @@ struct wdg_ctx {
   double* dRecBuf = nullptr;
   int64_t rec_cap = 0, rec_steps = 0;
   bool timing = false;
-  std::vector<std::array<hipEvent_t, 3>> events;  // stage start, after the wedge kernel, after the tet kernel
+  // per stage: start, after the mortar kernel, after the wedge kernel, after the tet kernel
+  std::vector<std::array<hipEvent_t, 4>> events;
   size_t events_used = 0;
 
   size_t tsize() const { return bits == 32 ? 4 : 8; }
@@ -151,6 +170,11 @@ void release_device(wdg_ctx* ctx) {
   dfree(ctx->dAuxT);
   dfree(ctx->dMt);
   dfree(ctx->dConnT);
+  dfree(ctx->dMortI);
+  dfree(ctx->dMortG);
+  dfree(ctx->dMortTab);
+  dfree(ctx->dMortB);
+  dfree(ctx->dMortF);
   dfree(ctx->dRecBase);
   dfree(ctx->dRecNN);
   dfree(ctx->dRecRows);
@@ -352,6 +376,12 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.connT = ctx->dConnT;
   L.opsT = ctx->dOpsT;
   L.srcvec = ctx->dSrcVec;
+  L.mortI = ctx->dMortI;
+  L.mortG = ctx->dMortG;
+  L.mortTab = ctx->dMortTab;
+  L.mortB = ctx->dMortB;
+  L.mortF = ctx->dMortF;
+  L.nmort = int64_t(ctx->mort.size());
   L.nsrc = int(ctx->src.size());
   for (int s = 0; s < L.nsrc; ++s) {
     L.src_elem[s] = int(ctx->src[s].elem);
@@ -366,18 +396,21 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
             (ctx->flux == WDG_FLUX_CENTRAL ? wdg::kCentral : 0) | (ctx->mass == WDG_MASS_LUMPED ? wdg::kLumped : 0);
   if (ctx->timing) {
     if (ctx->events_used == ctx->events.size()) {
-      std::array<hipEvent_t, 3> ev;
+      std::array<hipEvent_t, 4> ev;
       for (auto& e : ev) HIPCHK(hipEventCreate(&e));
       ctx->events.push_back(ev);
     }
     auto& ev = ctx->events[ctx->events_used++];
     HIPCHK(hipEventRecord(ev[0], ctx->stream));
-    HIPCHK(wdg::launch_wedge_stage(ctx->N, ctx->bits, L, ctx->stream));
+    HIPCHK(wdg::launch_mortar_stage(ctx->N, ctx->bits, L, ctx->stream));
     HIPCHK(hipEventRecord(ev[1], ctx->stream));
-    HIPCHK(wdg::launch_tet_stage(ctx->N, ctx->bits, L, ctx->stream));
+    HIPCHK(wdg::launch_wedge_stage(ctx->N, ctx->bits, L, ctx->stream));
     HIPCHK(hipEventRecord(ev[2], ctx->stream));
+    HIPCHK(wdg::launch_tet_stage(ctx->N, ctx->bits, L, ctx->stream));
+    HIPCHK(hipEventRecord(ev[3], ctx->stream));
     return WDG_OK;
   }
+  HIPCHK(wdg::launch_mortar_stage(ctx->N, ctx->bits, L, ctx->stream));
   HIPCHK(wdg::launch_wedge_stage(ctx->N, ctx->bits, L, ctx->stream));
   HIPCHK(wdg::launch_tet_stage(ctx->N, ctx->bits, L, ctx->stream));
   return WDG_OK;
@@ -411,6 +444,93 @@ int upload_vertical_mass(wdg_ctx* ctx) {
   HIPCHK(hipMemcpyAsync(ctx->dM1, M1.data(), M1.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return WDG_OK;
+}
+
+// classical Legendre polynomials P_0..P_N at x
+void legendre_all(int N, double x, double* P) {
+  P[0] = 1.0;
+  if (N >= 1) P[1] = x;
+  for (int n = 1; n < N; ++n) P[n + 1] = ((2.0 * n + 1.0) * x * P[n] - n * P[n - 1]) / (n + 1.0);
+}
+
+// Reference tables of the mortar quadrature, in the layout of wdg::mortar_table_size
+std::vector<double> mortar_tables(const RefOps& R) {
+  const int N = R.N, NT = R.NT, Nq = R.Nq, NX = wdg::mort_nx(R.N);
+  std::vector<double> out;
+  std::vector<double> xg, wg, tg, wt;
+  wdg::gauss_legendre(NX, xg, wg);
+  wdg::gauss_legendre(Nq, tg, wt);
+  out.insert(out.end(), xg.begin(), xg.end());
+  out.insert(out.end(), wg.begin(), wg.end());
+  out.insert(out.end(), tg.begin(), tg.end());
+  out.insert(out.end(), wt.begin(), wt.end());
+  out.insert(out.end(), R.t.begin(), R.t.end());
+  std::vector<double> Minv1(Nq * Nq, 0.0);
+  for (int i = 0; i < Nq; ++i) Minv1[i * Nq + i] = 1.0;
+  wdg::solve_dense(Nq, Nq, R.M1, Minv1);
+  out.insert(out.end(), Minv1.begin(), Minv1.end());
+  std::vector<double> E(NX * Nq);
+  for (int a = 0; a < NX; ++a) R.line_basis(xg[a], &E[a * Nq]);
+  out.insert(out.end(), E.begin(), E.end());
+  std::vector<double> MtriInv(NT * NT, 0.0);
+  for (int i = 0; i < NT; ++i) MtriInv[i * NT + i] = 1.0;
+  wdg::solve_dense(NT, NT, R.Mtri, MtriInv);
+  for (int e = 0; e < 3; ++e)
+    for (int i = 0; i < NT; ++i)
+      for (int a = 0; a < NX; ++a) {
+        double acc = 0.0;
+        for (int q = 0; q < Nq; ++q) acc += MtriInv[i * NT + R.edge_nodes[e][q]] * E[a * Nq + q];
+        out.push_back(acc);
+      }
+  out.insert(out.end(), MtriInv.begin(), MtriInv.end());
+  // Legendre-product modes P_a(r) P_b(s), a + b <= N (a outer), at the triangle nodes
+  std::vector<double> V(NT * NT), Vinv(NT * NT, 0.0), Pr(N + 1), Ps(N + 1);
+  for (int i = 0; i < NT; ++i) {
+    legendre_all(N, R.r[i], Pr.data());
+    legendre_all(N, R.s[i], Ps.data());
+    int md = 0;
+    for (int a = 0; a <= N; ++a)
+      for (int b = 0; a + b <= N; ++b) V[i * NT + md++] = Pr[a] * Ps[b];
+  }
+  for (int i = 0; i < NT; ++i) Vinv[i * NT + i] = 1.0;
+  wdg::solve_dense(NT, NT, V, Vinv);  // Vinv[md][i]
+  out.insert(out.end(), Vinv.begin(), Vinv.end());
+  return out;
+}
+
+template <typename V>
+int upload_values(wdg_ctx* ctx, void* dst, const V& vals) {
+  std::vector<unsigned char> buf(vals.size() * ctx->tsize());
+  for (size_t i = 0; i < vals.size(); ++i) {
+    if (ctx->bits == 32) reinterpret_cast<float*>(buf.data())[i] = float(vals[i]);
+    else reinterpret_cast<double*>(buf.data())[i] = double(vals[i]);
+  }
+  HIPCHK(hipMemcpyAsync(dst, buf.data(), buf.size(), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return WDG_OK;
+}
+
+// mortar value records (geometry, and the impedance sums of the current material)
+int upload_mortar_geometry(wdg_ctx* ctx) {
+  if (ctx->host_only || ctx->mort.empty()) return WDG_OK;
+  std::vector<double> g(ctx->mort.size() * wdg::kMortGeoStride, 0.0);
+  for (size_t m = 0; m < ctx->mort.size(); ++m) {
+    const MortarHost& M = ctx->mort[m];
+    double* o = &g[m * wdg::kMortGeoStride];
+    o[0] = M.zba;
+    o[1] = M.zbb;
+    o[2] = M.zta;
+    o[3] = M.ztb;
+    o[4] = M.ell;
+    o[5] = M.nx;
+    o[6] = M.ny;
+    for (int side = 0; side < 2; ++side) {
+      for (int i = 0; i < 9; ++i) o[7 + 9 * side + i] = M.lam[side][i];
+      o[25 + side] = 1.0 / M.Jft[side];
+      o[27 + side] = ctx->rho[M.k] * ctx->c[M.k] + ctx->rho[M.t[side]] * ctx->c[M.t[side]];
+    }
+  }
+  return upload_values(ctx, ctx->dMortG, g);
 }
 
 // tetrahedron geometry and material records (FP64 master copy -> device precision)
@@ -566,12 +686,12 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
     for (int f = 0; f < 5; ++f) conn[k * wdg::kConnStride + f] = -1;
   for (int64_t k = 0; k < Kt; ++k)
     for (int f = 0; f < 4; ++f) connT[k * wdg::kTetConnStride + f] = -1;
-  std::vector<std::array<int64_t, 4>> open_tri;  // unmatched triangular faces
+  std::vector<std::pair<std::array<int64_t, 4>, int64_t>> open_tri;  // unmatched triangular faces (key, face id)
   for (size_t a = 0; a < faces.size();) {
     size_t b = a + 1;
     while (b < faces.size() && faces[b].key == faces[a].key) ++b;
     if (b - a > 2) return fail(ctx, WDG_ERR_NONCONFORMING, "a face is shared by more than two elements");
-    if (b - a == 1 && faces[a].key[0] < 0) open_tri.push_back(faces[a].key);
+    if (b - a == 1 && faces[a].key[0] < 0) open_tri.push_back({faces[a].key, faces[a].id});
     if (b - a == 2) {
       for (int side = 0; side < 2; ++side) {
         const int64_t me = faces[a + side].id, other = faces[a + 1 - side].id;
@@ -619,26 +739,108 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
     }
     a = b;
   }
-  // a wedge's quadrilateral face left open while triangles on its vertices are
-  // open too would be a quadrilateral against split triangles: not conforming
+  // A wedge's quadrilateral face left open next to open tetrahedron triangles:
+  // when two of them cover it (split along a diagonal) the face is integrated
+  // on that common refinement (a mortar); anything else is not conforming.
+  // Corners of the quadrilateral: A0, A1 the bottom edge from its first to
+  // its second vertex, A2, A3 above A1, A0; diagonal 0 joins A0-A2, 1 A1-A3.
+  std::vector<MortarHost> mortars;
   if (Kt > 0 && !open_tri.empty()) {
     std::sort(open_tri.begin(), open_tri.end());
+    std::vector<char> used(open_tri.size(), 0);
+    auto find_tri = [&](int64_t p, int64_t q, int64_t r) -> int64_t {
+      std::array<int64_t, 4> t{-1, p, q, r};
+      std::sort(t.begin() + 1, t.end());
+      auto it = std::lower_bound(open_tri.begin(), open_tri.end(), std::make_pair(t, int64_t(-1)));
+      if (it == open_tri.end() || it->first != t) return -1;
+      return int64_t(it - open_tri.begin());
+    };
+    static const int kDiagTris[2][2][3] = {{{0, 1, 2}, {0, 2, 3}}, {{0, 1, 3}, {1, 2, 3}}};
     for (int64_t k = 0; k < Kw; ++k)
       for (int f = 2; f < 5; ++f) {
         if (conn[k * wdg::kConnStride + f] >= 0) continue;
-        int64_t v4[4];
-        for (int m = 0; m < 4; ++m) v4[m] = face_vertex(k, f, m);
-        for (int skip = 0; skip < 4; ++skip) {
-          std::array<int64_t, 4> t{-1, 0, 0, 0};
-          int n = 1;
-          for (int m = 0; m < 4; ++m)
-            if (m != skip) t[n++] = v4[m];
-          std::sort(t.begin() + 1, t.end());
-          if (std::binary_search(open_tri.begin(), open_tri.end(), t))
+        int64_t A[4];
+        for (int m = 0; m < 4; ++m) A[m] = face_vertex(k, f, m);
+        int found = -1;
+        int64_t hit[2] = {-1, -1};
+        int partial = 0;
+        for (int d = 0; d < 2; ++d) {
+          const int64_t i0 = find_tri(A[kDiagTris[d][0][0]], A[kDiagTris[d][0][1]], A[kDiagTris[d][0][2]]);
+          const int64_t i1 = find_tri(A[kDiagTris[d][1][0]], A[kDiagTris[d][1][1]], A[kDiagTris[d][1][2]]);
+          partial += (i0 >= 0) + (i1 >= 0);
+          if (i0 >= 0 && i1 >= 0 && !used[i0] && !used[i1]) {
+            found = d;
+            hit[0] = i0;
+            hit[1] = i1;
+          }
+        }
+        if (found < 0) {
+          if (partial > 0)
             return fail(ctx, WDG_ERR_NONCONFORMING,
                         "wedge " + std::to_string(k) + " has a quadrilateral face against triangular faces");
+          continue;
         }
+        used[hit[0]] = used[hit[1]] = 1;
+        MortarHost M;
+        M.k = k;
+        M.e = f - 2;
+        M.diag = found;
+        for (int side = 0; side < 2; ++side) {
+          const int64_t id = open_tri[hit[side]].second;
+          M.t[side] = id / 5;
+          M.tf[side] = int(id % 5);
+        }
+        mortars.push_back(M);
       }
+  }
+  const int64_t nmort = int64_t(mortars.size());
+  for (int64_t m = 0; m < nmort; ++m) {
+    MortarHost& M = mortars[m];
+    conn[M.k * wdg::kConnStride + 2 + M.e] = int32_t(-2 - m);
+    for (int side = 0; side < 2; ++side)
+      connT[(M.t[side] - Kw) * wdg::kTetConnStride + M.tf[side]] = int32_t(-2 - (2 * m + side));
+    // geometry of the quadrilateral in its (edge parameter xi, height z) plane
+    const double* x = &X[M.k * 18];
+    const int a = M.e, b = (M.e + 1) % 3;
+    M.zba = x[3 * a + 2];
+    M.zbb = x[3 * b + 2];
+    M.zta = x[3 * (a + 3) + 2];
+    M.ztb = x[3 * (b + 3) + 2];
+    const double dx = x[3 * b] - x[3 * a], dy = x[3 * b + 1] - x[3 * a + 1];
+    M.ell = std::sqrt(dx * dx + dy * dy);
+    M.nx = dy / M.ell;
+    M.ny = -dx / M.ell;
+    const int64_t corner_id[4] = {wedge_v[M.k * 6 + a], wedge_v[M.k * 6 + b], wedge_v[M.k * 6 + b + 3],
+                                  wedge_v[M.k * 6 + a + 3]};
+    const double cxi[4] = {-1.0, 1.0, 1.0, -1.0};
+    const double cz[4] = {M.zba, M.zbb, M.ztb, M.zta};
+    for (int side = 0; side < 2; ++side) {
+      const int64_t tl = M.t[side] - Kw;
+      // barycentrics of the tetrahedron face (its own vertex order) as affine functions of (xi, z)
+      std::vector<double> Am(9), Binv(9, 0.0);
+      double P[3][3];
+      for (int v = 0; v < 3; ++v) {
+        const int64_t gid = tet_v[tl * 4 + wdg::kTetFaceVerts[M.tf[side]][v]];
+        int c = -1;
+        for (int q = 0; q < 4; ++q)
+          if (corner_id[q] == gid) c = q;
+        if (c < 0) return fail(ctx, WDG_ERR_NONCONFORMING, "mortar face corner mismatch");
+        Am[0 * 3 + v] = cxi[c];
+        Am[1 * 3 + v] = cz[c];
+        Am[2 * 3 + v] = 1.0;
+        for (int d = 0; d < 3; ++d) P[v][d] = vxyz[gid * 3 + d];
+      }
+      for (int i = 0; i < 3; ++i) Binv[i * 3 + i] = 1.0;
+      if (!wdg::solve_dense(3, 3, Am, Binv)) return fail(ctx, WDG_ERR_NONCONFORMING, "degenerate mortar triangle");
+      for (int i = 0; i < 9; ++i) M.lam[side][i] = Binv[i];  // lambda_v = B[v][0] xi + B[v][1] z + B[v][2]
+      double u[3], w[3];
+      for (int d = 0; d < 3; ++d) {
+        u[d] = P[1][d] - P[0][d];
+        w[d] = P[2][d] - P[0][d];
+      }
+      const double cx = u[1] * w[2] - u[2] * w[1], cy = u[2] * w[0] - u[0] * w[2], cz2 = u[0] * w[1] - u[1] * w[0];
+      M.Jft[side] = 0.25 * std::sqrt(cx * cx + cy * cy + cz2 * cz2);  // area / 2
+    }
   }
 
   // tetrahedron geometry (affine: constant metric, planar faces)
@@ -691,6 +893,7 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
   ctx->Xt.swap(Xt);
   ctx->conn.swap(conn);
   ctx->connT.swap(connT);
+  ctx->mort.swap(mortars);
   ctx->geoT.swap(geoT);
   ctx->c.assign(size_t(K), 1.0);
   ctx->rho.assign(size_t(K), 1.0);
@@ -776,6 +979,33 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
     int rc = upload_tet_geometry(ctx);
     if (rc) return rc;
   }
+  if (!ctx->mort.empty()) {
+    const size_t nm = ctx->mort.size();
+    const int NT = R.NT, Nq = R.Nq, NTP = (NT + 3) / 4 * 4;
+    std::vector<int32_t> mi(nm * wdg::kMortIntStride, 0);
+    for (size_t m = 0; m < nm; ++m) {
+      const MortarHost& M = ctx->mort[m];
+      int32_t* o = &mi[m * wdg::kMortIntStride];
+      o[0] = int32_t(M.k);
+      o[1] = M.e;
+      o[2] = M.diag;
+      o[3] = int32_t(M.t[0]);
+      o[4] = M.tf[0];
+      o[5] = int32_t(M.t[1]);
+      o[6] = M.tf[1];
+    }
+    const std::vector<double> tabs = mortar_tables(R);
+    if (int(tabs.size()) != wdg::mortar_table_size(ctx->N)) return fail(ctx, WDG_ERR_HIP, "mortar table layout");
+    HIPCHK(hipMalloc(&ctx->dMortI, mi.size() * sizeof(int32_t)));
+    HIPCHK(hipMalloc(&ctx->dMortG, nm * wdg::kMortGeoStride * ts));
+    HIPCHK(hipMalloc(&ctx->dMortTab, tabs.size() * ts));
+    HIPCHK(hipMalloc(&ctx->dMortB, nm * 2 * Nq * NTP * ts));
+    HIPCHK(hipMalloc(&ctx->dMortF, nm * 2 * 2 * NT * ts));
+    HIPCHK(hipMemcpyAsync(ctx->dMortI, mi.data(), mi.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    int rc = upload_values(ctx, ctx->dMortTab, tabs);
+    if (!rc) rc = upload_mortar_geometry(ctx);
+    if (rc) return rc;
+  }
   ctx->state = kMesh;
   return WDG_OK;
 }
@@ -822,8 +1052,8 @@ int wdg_set_material(wdg_ctx* ctx, const double* c, const double* rho) {
       HIPCHK(hipFree(dr));
     }
     int rc = upload_tet_geometry(ctx);
-    if (rc) return rc;
-    rc = upload_sources(ctx);
+    if (!rc) rc = upload_mortar_geometry(ctx);
+    if (!rc) rc = upload_sources(ctx);
     if (rc) return rc;
   }
   ctx->state = std::max(ctx->state, int(kMaterial));
@@ -1179,21 +1409,22 @@ int wdg_kernel_timing(wdg_ctx* ctx, int enable) {
   return WDG_OK;
 }
 
-int wdg_read_kernel_timing_split(wdg_ctx* ctx, double* wedge_ms, double* tet_ms, int64_t* launches) {
-  if (!ctx || !wedge_ms || !tet_ms || !launches) return WDG_ERR_ARG;
+int wdg_read_kernel_timing_split(wdg_ctx* ctx, double* ms3, int64_t* launches) {
+  if (!ctx || !ms3 || !launches) return WDG_ERR_ARG;
   if (ctx->host_only || ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "timing needs a device mesh");
   HIPCHK(hipSetDevice(ctx->device));
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  double aw = 0.0, at = 0.0;
+  double acc[3] = {0.0, 0.0, 0.0};
   for (size_t i = 0; i < ctx->events_used; ++i) {
     float ms = 0.0f;
-    HIPCHK(hipEventElapsedTime(&ms, ctx->events[i][0], ctx->events[i][1]));
-    aw += ms;
     HIPCHK(hipEventElapsedTime(&ms, ctx->events[i][1], ctx->events[i][2]));
-    at += ms;
+    acc[0] += ms;  // wedge kernel
+    HIPCHK(hipEventElapsedTime(&ms, ctx->events[i][2], ctx->events[i][3]));
+    acc[1] += ms;  // tetrahedron kernel
+    HIPCHK(hipEventElapsedTime(&ms, ctx->events[i][0], ctx->events[i][1]));
+    acc[2] += ms;  // mortar kernel
   }
-  *wedge_ms = aw;
-  *tet_ms = at;
+  for (int i = 0; i < 3; ++i) ms3[i] = acc[i];
   *launches = int64_t(ctx->events_used);
   ctx->events_used = 0;
   return WDG_OK;
@@ -1201,9 +1432,9 @@ int wdg_read_kernel_timing_split(wdg_ctx* ctx, double* wedge_ms, double* tet_ms,
 
 int wdg_read_kernel_timing(wdg_ctx* ctx, double* total_ms, int64_t* launches) {
   if (!total_ms) return WDG_ERR_ARG;
-  double w = 0.0, t = 0.0;
-  const int rc = wdg_read_kernel_timing_split(ctx, &w, &t, launches);
-  if (rc == WDG_OK) *total_ms = w + t;
+  double ms3[3] = {0.0, 0.0, 0.0};
+  const int rc = wdg_read_kernel_timing_split(ctx, ms3, launches);
+  if (rc == WDG_OK) *total_ms = ms3[0] + ms3[1] + ms3[2];
   return rc;
 }
 

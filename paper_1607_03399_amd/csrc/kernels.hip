@@ -177,8 +177,10 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int idx, const 
 #ifndef WDG_STAGE_WAVES_PER_EU
 #define WDG_STAGE_WAVES_PER_EU 2
 #endif
-template <int N, typename T, bool HYB>
+// MODE 0: wedges only; 1: tetrahedra across triangular faces; 2: also mortars
+template <int N, typename T, int MODE>
 __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageLaunch A) {
+  constexpr bool HYB = MODE >= 1;
   using C = Cfg<N, T>;
   using RT = gen::RefTables<N>;
   constexpr int NT = C::NT, Nq = C::Nq, NP = C::NP, NPP = C::NPP, EPB = C::EPB;
@@ -340,7 +342,9 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
 #pragma unroll
     for (int ed = 0; ed < 3; ++ed) {
       const T w_in = cn[2 + ed] >= 0 ? T(1) : T(0);
-      const T Ja = g[20 + 4 * ed], Jb = g[21 + 4 * ed];
+      // a mortar face (-2 - m) takes its flux from the mortar kernel instead
+      const T Ja = MODE == 2 && cn[2 + ed] <= -2 ? T(0) : g[20 + 4 * ed];
+      const T Jb = MODE == 2 && cn[2 + ed] <= -2 ? T(0) : g[21 + 4 * ed];
       const T nx = g[22 + 4 * ed], ny = g[23 + 4 * ed];
       const T zs = g[34 + ed];  // Z- + Z+ (= 2 Z- on the boundary)
       const T taup = tau_on * T(2) / zs;
@@ -450,6 +454,34 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
       }
     }
 
+    if constexpr (MODE == 2) {
+      // mortar faces: pre-lift contributions of the common refinement; the
+      // buffer's range check returns zeros for the other faces
+      constexpr int NTP = (NT + 3) / 4 * 4;
+      const auto rb = chunk_rsrc(A.mortB, A.nmort * 2 * Nq * NTP * int64_t(sizeof(T)));
+#pragma unroll
+      for (int ed = 0; ed < 3; ++ed) {
+        const int nbr = cn[2 + ed];
+        const T nxe = g[22 + 4 * ed], nye = g[23 + 4 * ed];
+        const int64_t mo = nbr <= -2 ? int64_t(-2 - nbr) : int64_t(A.nmort);
+        const int idx0 = int((mo * 2 * Nq + j) * NTP / 4);
+#pragma unroll
+        for (int c = 0; c < NTP / 4; ++c) {
+          const V4<T> sp = bload<T>(rb, idx0 + c);
+          const V4<T> su = bload<T>(rb, idx0 + Nq * NTP / 4 + c);
+          const T vp[4] = {sp.p, sp.uz, sp.ux, sp.uy}, vu[4] = {su.p, su.uz, su.ux, su.uy};
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            if (4 * c + kk < NT) {
+              Bp[4 * c + kk] += vp[kk];
+              Bx[4 * c + kk] += nxe * vu[kk];
+              By[4 * c + kk] += nye * vu[kk];
+            }
+          }
+        }
+      }
+    }
+
     // triangular lift L^{tri,k} on this level: R = L B
 #pragma unroll
     for (int i = 0; i < NT; ++i) Rp[i] = Rz[i] = Rx[i] = Ry[i] = T(0);
@@ -548,6 +580,200 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
     if (wu) {
       const V4<T> u = sU[l];
       bstore<T>(bout, idx, V4<T>{u.p + cb * r.p, u.uz + cb * r.uz, u.ux + cb * r.ux, u.uy + cb * r.uy});
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mortar kernel: wedge quadrilateral faces covered by two tetrahedron triangles
+//
+// The flux is integrated on the common refinement in the wedge face's
+// coordinates (edge parameter xi, vertical t): mort_nx(N) Gauss points in xi
+// times Nq Gauss points in t on each side of the diagonal (exact in t).  One
+// wavefront per mortar (persistent over mortars):
+//   A. per point: wedge trace (GLL tensor interpolation of the face nodes),
+//      tetrahedron trace (Lagrange basis of the tetrahedron face at the
+//      point's barycentrics), upwind / central flux seen from both sides
+//   B. wedge: pre-lift contributions (M^tri)^-1 int l_i l_j F, resolved into
+//      the GLL levels by (M^1D)^-1, added by the wedge kernel before L^{tri,k};
+//      tetrahedra: face moments int l_i F', returned as the equivalent nodal
+//      face flux (M^tri)^-1 moments / (area/2) that the tetrahedron kernel lifts
+// ---------------------------------------------------------------------------
+template <int N>
+struct MortTab {
+  static constexpr int NT = (N + 1) * (N + 2) / 2, Nq = N + 1, NX = mort_nx(N);
+  static constexpr int XG = 0, WG = NX, TG = 2 * NX, WT = TG + Nq, TGLL = WT + Nq, MI1 = TGLL + Nq;
+  static constexpr int E = MI1 + Nq * Nq, A = E + NX * Nq, MTI = A + 3 * NT * NX, VI = MTI + NT * NT;
+  static constexpr int SIZE = VI + NT * NT;
+};
+
+template <int N, typename T>
+__global__ void __launch_bounds__(64) mortar_kernel(StageLaunch A) {
+  using TB = MortTab<N>;
+  constexpr int NT = TB::NT, Nq = TB::Nq, NX = TB::NX;
+  constexpr int NPW = Dim<N>::NP, NPT = TDim<N>::NP;
+  constexpr int NQ1 = NX * Nq;  // points on one side of the diagonal
+  constexpr int NTP = (NT + 3) / 4 * 4;
+  constexpr int NB = 2 * Nq * NTP;       // wedge outputs per mortar
+  constexpr int NBL = (NB + 63) / 64;    // ... per lane
+  __shared__ V4<T> sW[Nq * Nq];  // wedge face nodes [level][edge node]
+  __shared__ V4<T> sT[2 * NT];   // tetrahedron face nodes [side][face node]
+  __shared__ T sC[NQ1 * 4];      // per point: w Fp, w Fu (wedge), w Fp', w Fu' (tetrahedron)
+  __shared__ T sG[NQ1 * Nq];     // per point: ((M^1D)^-1 l(t))_j
+  __shared__ T sL[NQ1 * NT];     // per point: tetrahedron face Lagrange basis
+  __shared__ T sM[2 * NT];       // moments of one side [field][i]
+
+  const T* __restrict__ tab = static_cast<const T*>(A.mortTab);
+  const V4<T>* __restrict__ Uin = static_cast<const V4<T>*>(A.Uin);
+  const T tau_on = (A.flags & kCentral) ? T(0) : T(1);
+  const int tid = threadIdx.x;
+  const int64_t tb = A.Kw * NPW;
+
+  for (int64_t mo = blockIdx.x; mo < A.nmort; mo += gridDim.x) {
+    const int* mi = A.mortI + mo * kMortIntStride;
+    const T* mg = static_cast<const T*>(A.mortG) + mo * kMortGeoStride;
+    const int64_t k = mi[0];
+    const int e = mi[1], diag = mi[2];
+    const int64_t tet[2] = {mi[3], mi[5]};
+    const int tf[2] = {mi[4], mi[6]};
+    __syncthreads();  // the previous mortar is done with LDS
+    for (int idx = tid; idx < Nq * Nq; idx += 64) {
+      const int lev = idx / Nq, q = idx - lev * Nq;
+      sW[idx] = Uin[k * NPW + lev * NT + edge_node(N, e, q)];
+    }
+    for (int idx = tid; idx < 2 * NT; idx += 64) {
+      const int side = idx / NT, i = idx - side * NT;
+      sT[idx] = Uin[tb + (tet[side] - A.Kw) * NPT + tet_face_node<N>(tf[side], i)];
+    }
+    const T zba = mg[0], zbb = mg[1], zta = mg[2], ztb = mg[3], ell = mg[4], nx = mg[5], ny = mg[6];
+    T accB[NBL];
+#pragma unroll
+    for (int r = 0; r < NBL; ++r) accB[r] = T(0);
+
+    for (int side = 0; side < 2; ++side) {
+      __syncthreads();  // staged nodes ready; previous side's point data consumed
+      // A. fluxes at the points of this side
+      for (int q = tid; q < NQ1; q += 64) {
+        const int a = q / Nq, g = q - a * Nq;
+        const T xi = tab[TB::XG + a];
+        const T zb = zba * T(0.5) * (T(1) - xi) + zbb * T(0.5) * (T(1) + xi);
+        const T zt = zta * T(0.5) * (T(1) - xi) + ztb * T(0.5) * (T(1) + xi);
+        const T h = zt - zb;
+        const T zd = diag == 0 ? zba * T(0.5) * (T(1) - xi) + ztb * T(0.5) * (T(1) + xi)
+                               : zbb * T(0.5) * (T(1) + xi) + zta * T(0.5) * (T(1) - xi);
+        const T td = (T(2) * zd - zb - zt) / h;
+        const T lo = side == 0 ? T(-1) : td, hi = side == 0 ? td : T(1);
+        const T t = T(0.5) * (lo + hi) + T(0.5) * (hi - lo) * tab[TB::TG + g];
+        const T w = tab[TB::WG + a] * tab[TB::WT + g] * T(0.5) * (hi - lo) * T(0.25) * ell * h;
+        const T z = zb * T(0.5) * (T(1) - t) + zt * T(0.5) * (T(1) + t);
+        // GLL Lagrange basis in t, then the wedge trace
+        T lt[Nq];
+#pragma unroll
+        for (int m = 0; m < Nq; ++m) {
+          T v = T(1);
+#pragma unroll
+          for (int mm = 0; mm < Nq; ++mm)
+            if (mm != m) v *= (t - tab[TB::TGLL + mm]) / (tab[TB::TGLL + m] - tab[TB::TGLL + mm]);
+          lt[m] = v;
+        }
+        T wp = 0, wx = 0, wy = 0;
+#pragma unroll
+        for (int qq = 0; qq < Nq; ++qq) {
+          const T eq = tab[TB::E + a * Nq + qq];
+#pragma unroll
+          for (int m = 0; m < Nq; ++m) {
+            const V4<T> v = sW[m * Nq + qq];
+            const T c = eq * lt[m];
+            wp += c * v.p;
+            wx += c * v.ux;
+            wy += c * v.uy;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < Nq; ++j) {
+          T gj = 0;
+#pragma unroll
+          for (int m = 0; m < Nq; ++m) gj += tab[TB::MI1 + j * Nq + m] * lt[m];
+          sG[q * Nq + j] = gj;
+        }
+        // tetrahedron face barycentrics -> Legendre-product modes -> Lagrange basis
+        const T* lm = mg + 7 + 9 * side;
+        const T l1 = lm[3] * xi + lm[4] * z + lm[5];
+        const T l2 = lm[6] * xi + lm[7] * z + lm[8];
+        const T rr = T(2) * l1 - T(1), ss = T(2) * l2 - T(1);
+        T Pr[Nq], Ps[Nq];
+        Pr[0] = Ps[0] = T(1);
+        Pr[1] = rr;
+        Ps[1] = ss;
+#pragma unroll
+        for (int n = 1; n < N; ++n) {
+          Pr[n + 1] = (T(2 * n + 1) * rr * Pr[n] - T(n) * Pr[n - 1]) / T(n + 1);
+          Ps[n + 1] = (T(2 * n + 1) * ss * Ps[n] - T(n) * Ps[n - 1]) / T(n + 1);
+        }
+        T phi[NT];
+        {
+          int md = 0;
+#pragma unroll
+          for (int aa = 0; aa <= N; ++aa)
+#pragma unroll
+            for (int bb = 0; bb + aa <= N; ++bb) phi[md++] = Pr[aa] * Ps[bb];
+        }
+        T tp = 0, tx = 0, ty = 0;
+#pragma unroll 1
+        for (int i = 0; i < NT; ++i) {
+          T li = 0;
+#pragma unroll
+          for (int md = 0; md < NT; ++md) li += tab[TB::VI + md * NT + i] * phi[md];
+          sL[q * NT + i] = li;
+          const V4<T> v = sT[side * NT + i];
+          tp += li * v.p;
+          tx += li * v.ux;
+          ty += li * v.uy;
+        }
+        const T zs = mg[27 + side];
+        const T taup = tau_on * T(2) / zs, tauu = tau_on * zs * T(0.5);
+        const T jp = tp - wp;
+        const T jun = nx * (tx - wx) + ny * (ty - wy);
+        sC[q * 4 + 0] = w * T(0.5) * (taup * jp - jun);
+        sC[q * 4 + 1] = w * T(0.5) * (tauu * jun - jp);
+        sC[q * 4 + 2] = w * T(0.5) * (-taup * jp - jun);  // seen from the tetrahedron: [p]' = -[p]
+        sC[q * 4 + 3] = w * T(0.5) * (tauu * jun + jp);
+      }
+      __syncthreads();
+
+      // B1. wedge pre-lift contributions [field][level j][node i], summed over both sides
+#pragma unroll
+      for (int r = 0; r < NBL; ++r) {
+        const int o = tid + 64 * r;
+        const int f = o / (Nq * NTP), rem = o - f * Nq * NTP, j = rem / NTP, i = rem - j * NTP;
+        if (o < NB && i < NT) {
+          const T* Ai = tab + TB::A + (e * NT + i) * NX;
+          T acc = 0;
+          for (int q = 0; q < NQ1; ++q) acc += sC[q * 4 + f] * Ai[q / Nq] * sG[q * Nq + j];
+          accB[r] += acc;
+        }
+      }
+      // B2. tetrahedron face moments of this side [field][i]
+      for (int o = tid; o < 2 * NT; o += 64) {
+        const int f = o / NT, i = o - f * NT;
+        T acc = 0;
+        for (int q = 0; q < NQ1; ++q) acc += sC[q * 4 + 2 + f] * sL[q * NT + i];
+        sM[o] = acc;
+      }
+      __syncthreads();
+      // B3. equivalent nodal flux of this side's tetrahedron face
+      for (int o = tid; o < 2 * NT; o += 64) {
+        const int f = o / NT, i = o - f * NT;
+        T acc = 0;
+        for (int m = 0; m < NT; ++m) acc += tab[TB::MTI + i * NT + m] * sM[f * NT + m];
+        static_cast<T*>(A.mortF)[(mo * 2 + side) * 2 * NT + o] = acc * mg[25 + side];
+      }
+    }
+    T* outB = static_cast<T*>(A.mortB) + mo * NB;
+#pragma unroll
+    for (int r = 0; r < NBL; ++r) {
+      const int o = tid + 64 * r;
+      if (o < NB) outB[o] = accB[r];
     }
   }
 }
@@ -658,8 +884,15 @@ __global__ void __launch_bounds__(256) tet_stage(StageLaunch A) {
           const T pp = pb + w_in * (nb.p - pb);
           const T unp = ub + w_in * ((nx * nb.ux + ny * nb.uy + nz * nb.uz) - ub);
           const T jp = pp - pm, jun = unp - unm;
-          sF[(le * 4 * NT + q) * 2] = Fs * T(0.5) * (taup * jp - jun);
-          sF[(le * 4 * NT + q) * 2 + 1] = Fs * T(0.5) * (tauu * jun - jp);
+          T Fp = T(0.5) * (taup * jp - jun), Fu = T(0.5) * (tauu * jun - jp);
+          if (nbr <= -2) {
+            // mortar side: the equivalent nodal flux of the common refinement
+            const T* mf = static_cast<const T*>(A.mortF) + int64_t(-2 - nbr) * 2 * NT;
+            Fp = mf[m];
+            Fu = mf[NT + m];
+          }
+          sF[(le * 4 * NT + q) * 2] = Fs * Fp;
+          sF[(le * 4 * NT + q) * 2 + 1] = Fs * Fu;
         }
       }
     }
@@ -939,10 +1172,20 @@ hipError_t launch_wedge_stage_t(const StageLaunch& a, hipStream_t st) {
   using C = Cfg<N, T>;
   const int64_t nchunks = (a.Kw + C::EPB - 1) / C::EPB;
   if (nchunks <= 0) return hipSuccess;
-  if (a.Kt > 0)
-    hipLaunchKernelGGL((wedge_stage<N, T, true>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
+  if (a.nmort > 0)
+    hipLaunchKernelGGL((wedge_stage<N, T, 2>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
+  else if (a.Kt > 0)
+    hipLaunchKernelGGL((wedge_stage<N, T, 1>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
   else
-    hipLaunchKernelGGL((wedge_stage<N, T, false>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
+    hipLaunchKernelGGL((wedge_stage<N, T, 0>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int N, typename T>
+hipError_t launch_mortar_stage_t(const StageLaunch& a, hipStream_t st) {
+  if (a.nmort <= 0) return hipSuccess;
+  const unsigned grid = unsigned(a.nmort < 8192 ? a.nmort : 8192);
+  hipLaunchKernelGGL((mortar_kernel<N, T>), dim3(grid), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1034,6 +1277,25 @@ hipError_t launch_wedge_stage(int N, int bits, const StageLaunch& a, hipStream_t
   WDG_DISPATCH_N(N, bits, WDG_STAGE)
 #undef WDG_STAGE
   return err;
+}
+
+hipError_t launch_mortar_stage(int N, int bits, const StageLaunch& a, hipStream_t st) {
+  hipError_t err = hipErrorInvalidValue;
+#define WDG_STAGE(n, T) err = launch_mortar_stage_t<n, T>(a, st)
+  WDG_DISPATCH_N(N, bits, WDG_STAGE)
+#undef WDG_STAGE
+  return err;
+}
+
+int mortar_table_size(int N) {
+  switch (N) {
+    case 1: return MortTab<1>::SIZE;
+    case 2: return MortTab<2>::SIZE;
+    case 3: return MortTab<3>::SIZE;
+    case 4: return MortTab<4>::SIZE;
+    case 5: return MortTab<5>::SIZE;
+    default: return 0;
+  }
 }
 
 hipError_t launch_tet_stage(int N, int bits, const StageLaunch& a, hipStream_t st) {

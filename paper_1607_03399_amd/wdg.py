@@ -78,7 +78,7 @@ def load_library() -> C.CDLL:
         "wdg_get_element_data": (C.c_int, [vp, _dp, _dp]),
         "wdg_kernel_timing": (C.c_int, [vp, C.c_int]),
         "wdg_read_kernel_timing": (C.c_int, [vp, _dp, _i64p]),
-        "wdg_read_kernel_timing_split": (C.c_int, [vp, _dp, _dp, _i64p]),
+        "wdg_read_kernel_timing_split": (C.c_int, [vp, _dp, _i64p]),
         "wdg_reference_operator": (C.c_int, [C.c_int, C.c_char_p, _dp, C.c_int64, _i64p]),
     }
     for name, (res, args) in sig.items():
@@ -297,12 +297,11 @@ class Solver:
         return ms.value, n.value
 
     def read_kernel_timing_split(self):
-        """(wedge-kernel milliseconds, tetrahedron-kernel milliseconds, number of timed stages)."""
-        w, t = C.c_double(), C.c_double()
+        """(wedge, tetrahedron, mortar kernel milliseconds, number of timed stages)."""
+        ms = np.zeros(3)
         n = C.c_int64()
-        self._check(self._lib.wdg_read_kernel_timing_split(self._h, C.byref(w), C.byref(t), C.byref(n)),
-                    "read_kernel_timing_split")
-        return w.value, t.value, n.value
+        self._check(self._lib.wdg_read_kernel_timing_split(self._h, _ptr(ms), C.byref(n)), "read_kernel_timing_split")
+        return float(ms[0]), float(ms[1]), float(ms[2]), n.value
 
     def element_data(self):
         """(geo (Kw,40), lift (Kw,Np_tri,Np_tri)) of the wedges, built by the device setup kernel."""

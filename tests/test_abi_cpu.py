@@ -266,3 +266,20 @@ def test_tetrahedra_only_mesh_is_accepted():
     om = dg.Mesh(v, w, c, rho, tets=t)
     np.testing.assert_allclose(s.node_coords(), dg.node_coords(om, 2)[:, :s.Npt], atol=1e-14)
     s.close()
+
+
+def test_column_split_mesh_host_side():
+    """Columns split into tetrahedra: wedge quadrilaterals against two
+    tetrahedron triangles are accepted (coupled on the common refinement);
+    node coordinates and time step as the oracle's."""
+    m = inputs.layered_config(3, 3, 0.3, seed=1)
+    v, w, t, c, rho = inputs.split_columns(m, [4, 9])
+    s = _host_solver(2)
+    s.set_mesh(v, w, t)
+    om = dg.Mesh(v, w, c, rho, tets=t)
+    np.testing.assert_allclose(s.node_coords(), dg.node_coords(om, 2), atol=1e-14)
+    s.set_material(c, rho)
+    assert abs(s.stable_dt(0.5) - dg.stable_dt(om, 2, 0.5)) < 1e-12 * s.stable_dt(0.5)
+    # one triangle of a split quadrilateral missing: not conforming
+    _expect("WDG_ERR_NONCONFORMING", s.set_mesh, v, w, t[1:])
+    s.close()
