@@ -395,18 +395,24 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.flags = flags | (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
             (ctx->flux == WDG_FLUX_CENTRAL ? wdg::kCentral : 0) | (ctx->mass == WDG_MASS_LUMPED ? wdg::kLumped : 0);
   if (ctx->timing) {
+    // events only between kernels that actually run (an event adds a gap to the stream)
     if (ctx->events_used == ctx->events.size()) {
       std::array<hipEvent_t, 4> ev;
       for (auto& e : ev) HIPCHK(hipEventCreate(&e));
       ctx->events.push_back(ev);
     }
     auto& ev = ctx->events[ctx->events_used++];
+    const bool has_m = !ctx->mort.empty(), has_t = ctx->Kt > 0;
     HIPCHK(hipEventRecord(ev[0], ctx->stream));
-    HIPCHK(wdg::launch_mortar_stage(ctx->N, ctx->bits, L, ctx->stream));
-    HIPCHK(hipEventRecord(ev[1], ctx->stream));
+    if (has_m) {
+      HIPCHK(wdg::launch_mortar_stage(ctx->N, ctx->bits, L, ctx->stream));
+      HIPCHK(hipEventRecord(ev[1], ctx->stream));
+    }
     HIPCHK(wdg::launch_wedge_stage(ctx->N, ctx->bits, L, ctx->stream));
-    HIPCHK(hipEventRecord(ev[2], ctx->stream));
-    HIPCHK(wdg::launch_tet_stage(ctx->N, ctx->bits, L, ctx->stream));
+    if (has_t) {
+      HIPCHK(hipEventRecord(ev[2], ctx->stream));
+      HIPCHK(wdg::launch_tet_stage(ctx->N, ctx->bits, L, ctx->stream));
+    }
     HIPCHK(hipEventRecord(ev[3], ctx->stream));
     return WDG_OK;
   }
@@ -454,8 +460,8 @@ void legendre_all(int N, double x, double* P) {
 }
 
 // Reference tables of the mortar quadrature, in the layout of wdg::mortar_table_size
-std::vector<double> mortar_tables(const RefOps& R) {
-  const int N = R.N, NT = R.NT, Nq = R.Nq, NX = wdg::mort_nx(R.N);
+std::vector<double> mortar_tables(const RefOps& R, int bits) {
+  const int N = R.N, NT = R.NT, Nq = R.Nq, NX = wdg::mort_nx(R.N, bits);
   std::vector<double> out;
   std::vector<double> xg, wg, tg, wt;
   wdg::gauss_legendre(NX, xg, wg);
@@ -465,6 +471,8 @@ std::vector<double> mortar_tables(const RefOps& R) {
   out.insert(out.end(), tg.begin(), tg.end());
   out.insert(out.end(), wt.begin(), wt.end());
   out.insert(out.end(), R.t.begin(), R.t.end());
+  for (int m = 0; m < Nq; ++m)
+    for (int mm = 0; mm < Nq; ++mm) out.push_back(m == mm ? 0.0 : 1.0 / (R.t[m] - R.t[mm]));
   std::vector<double> Minv1(Nq * Nq, 0.0);
   for (int i = 0; i < Nq; ++i) Minv1[i * Nq + i] = 1.0;
   wdg::solve_dense(Nq, Nq, R.M1, Minv1);
@@ -482,7 +490,6 @@ std::vector<double> mortar_tables(const RefOps& R) {
         for (int q = 0; q < Nq; ++q) acc += MtriInv[i * NT + R.edge_nodes[e][q]] * E[a * Nq + q];
         out.push_back(acc);
       }
-  out.insert(out.end(), MtriInv.begin(), MtriInv.end());
   // Legendre-product modes P_a(r) P_b(s), a + b <= N (a outer), at the triangle nodes
   std::vector<double> V(NT * NT), Vinv(NT * NT, 0.0), Pr(N + 1), Ps(N + 1);
   for (int i = 0; i < NT; ++i) {
@@ -493,21 +500,16 @@ std::vector<double> mortar_tables(const RefOps& R) {
       for (int b = 0; a + b <= N; ++b) V[i * NT + md++] = Pr[a] * Ps[b];
   }
   for (int i = 0; i < NT; ++i) Vinv[i * NT + i] = 1.0;
-  wdg::solve_dense(NT, NT, V, Vinv);  // Vinv[md][i]
+  wdg::solve_dense(NT, NT, V, Vinv);  // Vinv[md][i]: nodal values -> modal coefficients
   out.insert(out.end(), Vinv.begin(), Vinv.end());
+  // P = (M^tri)^-1 Vinv^T maps modal moments to the equivalent nodal face flux
+  for (int i = 0; i < NT; ++i)
+    for (int md = 0; md < NT; ++md) {
+      double acc = 0.0;
+      for (int m = 0; m < NT; ++m) acc += MtriInv[i * NT + m] * Vinv[md * NT + m];
+      out.push_back(acc);
+    }
   return out;
-}
-
-template <typename V>
-int upload_values(wdg_ctx* ctx, void* dst, const V& vals) {
-  std::vector<unsigned char> buf(vals.size() * ctx->tsize());
-  for (size_t i = 0; i < vals.size(); ++i) {
-    if (ctx->bits == 32) reinterpret_cast<float*>(buf.data())[i] = float(vals[i]);
-    else reinterpret_cast<double*>(buf.data())[i] = double(vals[i]);
-  }
-  HIPCHK(hipMemcpyAsync(dst, buf.data(), buf.size(), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
-  return WDG_OK;
 }
 
 // mortar value records (geometry, and the impedance sums of the current material)
@@ -530,7 +532,9 @@ int upload_mortar_geometry(wdg_ctx* ctx) {
       o[27 + side] = ctx->rho[M.k] * ctx->c[M.k] + ctx->rho[M.t[side]] * ctx->c[M.t[side]];
     }
   }
-  return upload_values(ctx, ctx->dMortG, g);
+  HIPCHK(hipMemcpyAsync(ctx->dMortG, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return WDG_OK;
 }
 
 // tetrahedron geometry and material records (FP64 master copy -> device precision)
@@ -994,16 +998,18 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
       o[5] = int32_t(M.t[1]);
       o[6] = M.tf[1];
     }
-    const std::vector<double> tabs = mortar_tables(R);
-    if (int(tabs.size()) != wdg::mortar_table_size(ctx->N)) return fail(ctx, WDG_ERR_HIP, "mortar table layout");
+    const std::vector<double> tabs = mortar_tables(R, ctx->bits);
+    if (int(tabs.size()) != wdg::mortar_table_size(ctx->N, ctx->bits))
+      return fail(ctx, WDG_ERR_HIP, "mortar table layout");
     HIPCHK(hipMalloc(&ctx->dMortI, mi.size() * sizeof(int32_t)));
-    HIPCHK(hipMalloc(&ctx->dMortG, nm * wdg::kMortGeoStride * ts));
-    HIPCHK(hipMalloc(&ctx->dMortTab, tabs.size() * ts));
+    HIPCHK(hipMalloc(&ctx->dMortG, nm * wdg::kMortGeoStride * sizeof(double)));
+    HIPCHK(hipMalloc(&ctx->dMortTab, tabs.size() * sizeof(double)));
     HIPCHK(hipMalloc(&ctx->dMortB, nm * 2 * Nq * NTP * ts));
     HIPCHK(hipMalloc(&ctx->dMortF, nm * 2 * 2 * NT * ts));
     HIPCHK(hipMemcpyAsync(ctx->dMortI, mi.data(), mi.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
-    int rc = upload_values(ctx, ctx->dMortTab, tabs);
-    if (!rc) rc = upload_mortar_geometry(ctx);
+    HIPCHK(hipMemcpyAsync(ctx->dMortTab, tabs.data(), tabs.size() * sizeof(double), hipMemcpyHostToDevice,
+                          ctx->stream));
+    int rc = upload_mortar_geometry(ctx);
     if (rc) return rc;
   }
   ctx->state = kMesh;
@@ -1415,14 +1421,22 @@ int wdg_read_kernel_timing_split(wdg_ctx* ctx, double* ms3, int64_t* launches) {
   HIPCHK(hipSetDevice(ctx->device));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   double acc[3] = {0.0, 0.0, 0.0};
+  const bool has_m = !ctx->mort.empty(), has_t = ctx->Kt > 0;
   for (size_t i = 0; i < ctx->events_used; ++i) {
+    const auto& ev = ctx->events[i];
+    const hipEvent_t wedge_start = has_m ? ev[1] : ev[0];
+    const hipEvent_t wedge_end = has_t ? ev[2] : ev[3];
     float ms = 0.0f;
-    HIPCHK(hipEventElapsedTime(&ms, ctx->events[i][1], ctx->events[i][2]));
+    HIPCHK(hipEventElapsedTime(&ms, wedge_start, wedge_end));
     acc[0] += ms;  // wedge kernel
-    HIPCHK(hipEventElapsedTime(&ms, ctx->events[i][2], ctx->events[i][3]));
-    acc[1] += ms;  // tetrahedron kernel
-    HIPCHK(hipEventElapsedTime(&ms, ctx->events[i][0], ctx->events[i][1]));
-    acc[2] += ms;  // mortar kernel
+    if (has_t) {
+      HIPCHK(hipEventElapsedTime(&ms, ev[2], ev[3]));
+      acc[1] += ms;  // tetrahedron kernel
+    }
+    if (has_m) {
+      HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+      acc[2] += ms;  // mortar kernel
+    }
   }
   for (int i = 0; i < 3; ++i) ms3[i] = acc[i];
   *launches = int64_t(ctx->events_used);

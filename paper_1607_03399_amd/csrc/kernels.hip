@@ -145,17 +145,20 @@ __device__ __forceinline__ V4<T> bload(__amdgpu_buffer_rsrc_t r, int idx) {
     return __builtin_bit_cast(V4<T>, h);
   }
 }
+// Stores of the stage outputs are streaming (cache policy: non-temporal):
+// the next stage reads them back from HBM anyway.
+constexpr int kStreamStore = 2;
 template <typename T>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int idx, const V4<T>& v) {
   if constexpr (sizeof(T) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, idx * 16, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, idx * 16, 0, kStreamStore);
   } else {
     struct H2 {
       u32x4 lo, hi;
     };
     const H2 h = __builtin_bit_cast(H2, v);
-    __builtin_amdgcn_raw_buffer_store_b128(h.lo, r, idx * 32, 0, 0);
-    __builtin_amdgcn_raw_buffer_store_b128(h.hi, r, idx * 32 + 16, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(h.lo, r, idx * 32, 0, kStreamStore);
+    __builtin_amdgcn_raw_buffer_store_b128(h.hi, r, idx * 32 + 16, 0, kStreamStore);
   }
 }
 
@@ -599,181 +602,218 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
 //      tetrahedra: face moments int l_i F', returned as the equivalent nodal
 //      face flux (M^tri)^-1 moments / (area/2) that the tetrahedron kernel lifts
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, int BITS>
 struct MortTab {
-  static constexpr int NT = (N + 1) * (N + 2) / 2, Nq = N + 1, NX = mort_nx(N);
-  static constexpr int XG = 0, WG = NX, TG = 2 * NX, WT = TG + Nq, TGLL = WT + Nq, MI1 = TGLL + Nq;
-  static constexpr int E = MI1 + Nq * Nq, A = E + NX * Nq, MTI = A + 3 * NT * NX, VI = MTI + NT * NT;
-  static constexpr int SIZE = VI + NT * NT;
+  static constexpr int NT = (N + 1) * (N + 2) / 2, Nq = N + 1, NX = mort_nx(N, BITS);
+  static constexpr int XG = 0, WG = NX, TG = 2 * NX, WT = TG + Nq, TGLL = WT + Nq, DEN = TGLL + Nq;
+  static constexpr int MI1 = DEN + Nq * Nq, E = MI1 + Nq * Nq, A = E + NX * Nq, VI = A + 3 * NT * NX;
+  static constexpr int P = VI + NT * NT;
+  static constexpr int SIZE = P + NT * NT;
 };
 
+// The mortar arithmetic runs in FP64 for either state precision: the
+// tetrahedron trace goes through a Legendre-product Vandermonde whose
+// conditioning would cost FP32 digits at high order; tables and records are
+// FP64 as well.
 template <int N, typename T>
 __global__ void __launch_bounds__(64) mortar_kernel(StageLaunch A) {
-  using TB = MortTab<N>;
+  using TB = MortTab<N, int(sizeof(T)) * 8>;
+  using D = double;
   constexpr int NT = TB::NT, Nq = TB::Nq, NX = TB::NX;
   constexpr int NPW = Dim<N>::NP, NPT = TDim<N>::NP;
   constexpr int NQ1 = NX * Nq;  // points on one side of the diagonal
+  constexpr int PPL = (NQ1 + 63) / 64;  // points per lane
   constexpr int NTP = (NT + 3) / 4 * 4;
   constexpr int NB = 2 * Nq * NTP;       // wedge outputs per mortar
   constexpr int NBL = (NB + 63) / 64;    // ... per lane
-  __shared__ V4<T> sW[Nq * Nq];  // wedge face nodes [level][edge node]
-  __shared__ V4<T> sT[2 * NT];   // tetrahedron face nodes [side][face node]
-  __shared__ T sC[NQ1 * 4];      // per point: w Fp, w Fu (wedge), w Fp', w Fu' (tetrahedron)
-  __shared__ T sG[NQ1 * Nq];     // per point: ((M^1D)^-1 l(t))_j
-  __shared__ T sL[NQ1 * NT];     // per point: tetrahedron face Lagrange basis
-  __shared__ T sM[2 * NT];       // moments of one side [field][i]
+  __shared__ D tab[TB::SIZE];
+  __shared__ V4<T> sW[Nq * Nq];   // wedge face nodes [level][edge node]
+  __shared__ V4<T> sTF[2 * NT];   // tetrahedron face nodes [side][face node]
+  __shared__ D sCT[3 * NT];       // modal coefficients of one side's tetrahedron trace (p, u_x, u_y)
+  __shared__ D sC[NQ1 * 2];       // per point: w Fp, w Fu (wedge side)
+  __shared__ D sG[NQ1 * Nq];      // per point: ((M^1D)^-1 l(t))_j
+  __shared__ D sH[2 * NX * Nq];   // sums over the t points of one edge point: [field][a][j]
+  __shared__ D sRed[64 * 2 * NT]; // per-lane partial modal moments of the tetrahedron side
+  __shared__ D sMM[2 * NT];       // modal moments [field][mode]
 
-  const T* __restrict__ tab = static_cast<const T*>(A.mortTab);
+  const D* __restrict__ gtab = static_cast<const D*>(A.mortTab);
+  for (int idx = threadIdx.x; idx < TB::SIZE; idx += 64) tab[idx] = gtab[idx];
   const V4<T>* __restrict__ Uin = static_cast<const V4<T>*>(A.Uin);
-  const T tau_on = (A.flags & kCentral) ? T(0) : T(1);
+  const D tau_on = (A.flags & kCentral) ? 0.0 : 1.0;
   const int tid = threadIdx.x;
   const int64_t tb = A.Kw * NPW;
 
   for (int64_t mo = blockIdx.x; mo < A.nmort; mo += gridDim.x) {
     const int* mi = A.mortI + mo * kMortIntStride;
-    const T* mg = static_cast<const T*>(A.mortG) + mo * kMortGeoStride;
+    const D* mg = static_cast<const D*>(A.mortG) + mo * kMortGeoStride;
     const int64_t k = mi[0];
     const int e = mi[1], diag = mi[2];
-    const int64_t tet[2] = {mi[3], mi[5]};
-    const int tf[2] = {mi[4], mi[6]};
-    __syncthreads();  // the previous mortar is done with LDS
-    for (int idx = tid; idx < Nq * Nq; idx += 64) {
-      const int lev = idx / Nq, q = idx - lev * Nq;
-      sW[idx] = Uin[k * NPW + lev * NT + edge_node(N, e, q)];
+    __syncthreads();  // tables loaded; the previous mortar is done with LDS
+    // stage the wedge face nodes and both tetrahedron faces (one load per lane)
+    for (int idx = tid; idx < Nq * Nq + 2 * NT; idx += 64) {
+      if (idx < Nq * Nq) {
+        const int lev = idx / Nq, q = idx - lev * Nq;
+        sW[idx] = Uin[k * NPW + lev * NT + edge_node(N, e, q)];
+      } else {
+        const int r = idx - Nq * Nq, side = r / NT, i = r - side * NT;
+        sTF[r] = Uin[tb + (int64_t(mi[3 + 2 * side]) - A.Kw) * NPT + tet_face_node<N>(mi[4 + 2 * side], i)];
+      }
     }
-    for (int idx = tid; idx < 2 * NT; idx += 64) {
-      const int side = idx / NT, i = idx - side * NT;
-      sT[idx] = Uin[tb + (tet[side] - A.Kw) * NPT + tet_face_node<N>(tf[side], i)];
-    }
-    const T zba = mg[0], zbb = mg[1], zta = mg[2], ztb = mg[3], ell = mg[4], nx = mg[5], ny = mg[6];
-    T accB[NBL];
+    const D zba = mg[0], zbb = mg[1], zta = mg[2], ztb = mg[3], ell = mg[4], nx = mg[5], ny = mg[6];
+    D accB[NBL];
 #pragma unroll
-    for (int r = 0; r < NBL; ++r) accB[r] = T(0);
+    for (int r = 0; r < NBL; ++r) accB[r] = 0.0;
 
     for (int side = 0; side < 2; ++side) {
-      __syncthreads();  // staged nodes ready; previous side's point data consumed
-      // A. fluxes at the points of this side
-      for (int q = tid; q < NQ1; q += 64) {
+      __syncthreads();  // staged nodes ready; the previous side's data consumed
+      if (tid < 3 * NT) {
+        const int f = tid / NT, md = tid - f * NT;
+        D acc = 0;
+        for (int i = 0; i < NT; ++i) {
+          const V4<T> v = sTF[side * NT + i];
+          acc += tab[TB::VI + md * NT + i] * D(f == 0 ? v.p : (f == 1 ? v.ux : v.uy));
+        }
+        sCT[tid] = acc;
+      }
+      __syncthreads();
+      // A. fluxes at the points of this side; partial modal moments per lane
+      D pm[2 * NT];
+#pragma unroll
+      for (int md = 0; md < 2 * NT; ++md) pm[md] = 0.0;
+#pragma unroll
+      for (int pp = 0; pp < PPL; ++pp) {
+        const int q = tid + 64 * pp;
+        if (q >= NQ1) break;
         const int a = q / Nq, g = q - a * Nq;
-        const T xi = tab[TB::XG + a];
-        const T zb = zba * T(0.5) * (T(1) - xi) + zbb * T(0.5) * (T(1) + xi);
-        const T zt = zta * T(0.5) * (T(1) - xi) + ztb * T(0.5) * (T(1) + xi);
-        const T h = zt - zb;
-        const T zd = diag == 0 ? zba * T(0.5) * (T(1) - xi) + ztb * T(0.5) * (T(1) + xi)
-                               : zbb * T(0.5) * (T(1) + xi) + zta * T(0.5) * (T(1) - xi);
-        const T td = (T(2) * zd - zb - zt) / h;
-        const T lo = side == 0 ? T(-1) : td, hi = side == 0 ? td : T(1);
-        const T t = T(0.5) * (lo + hi) + T(0.5) * (hi - lo) * tab[TB::TG + g];
-        const T w = tab[TB::WG + a] * tab[TB::WT + g] * T(0.5) * (hi - lo) * T(0.25) * ell * h;
-        const T z = zb * T(0.5) * (T(1) - t) + zt * T(0.5) * (T(1) + t);
-        // GLL Lagrange basis in t, then the wedge trace
-        T lt[Nq];
+        const D xi = tab[TB::XG + a];
+        const D zb = zba * 0.5 * (1.0 - xi) + zbb * 0.5 * (1.0 + xi);
+        const D zt = zta * 0.5 * (1.0 - xi) + ztb * 0.5 * (1.0 + xi);
+        const D h = zt - zb;
+        const D zd = diag == 0 ? zba * 0.5 * (1.0 - xi) + ztb * 0.5 * (1.0 + xi)
+                               : zbb * 0.5 * (1.0 + xi) + zta * 0.5 * (1.0 - xi);
+        const D td = (2.0 * zd - zb - zt) / h;
+        const D lo = side == 0 ? -1.0 : td, hi = side == 0 ? td : 1.0;
+        const D t = 0.5 * (lo + hi) + 0.5 * (hi - lo) * tab[TB::TG + g];
+        const D w = tab[TB::WG + a] * tab[TB::WT + g] * 0.5 * (hi - lo) * 0.25 * ell * h;
+        const D z = zb * 0.5 * (1.0 - t) + zt * 0.5 * (1.0 + t);
+        // GLL Lagrange basis in t (inverse denominators tabulated), then the wedge trace
+        D lt[Nq];
 #pragma unroll
         for (int m = 0; m < Nq; ++m) {
-          T v = T(1);
+          D v = 1.0;
 #pragma unroll
           for (int mm = 0; mm < Nq; ++mm)
-            if (mm != m) v *= (t - tab[TB::TGLL + mm]) / (tab[TB::TGLL + m] - tab[TB::TGLL + mm]);
+            if (mm != m) v *= (t - tab[TB::TGLL + mm]) * tab[TB::DEN + m * Nq + mm];
           lt[m] = v;
         }
-        T wp = 0, wx = 0, wy = 0;
+        D wp = 0, wx = 0, wy = 0;
 #pragma unroll
         for (int qq = 0; qq < Nq; ++qq) {
-          const T eq = tab[TB::E + a * Nq + qq];
+          const D eq = tab[TB::E + a * Nq + qq];
 #pragma unroll
           for (int m = 0; m < Nq; ++m) {
             const V4<T> v = sW[m * Nq + qq];
-            const T c = eq * lt[m];
-            wp += c * v.p;
-            wx += c * v.ux;
-            wy += c * v.uy;
+            const D c = eq * lt[m];
+            wp += c * D(v.p);
+            wx += c * D(v.ux);
+            wy += c * D(v.uy);
           }
         }
 #pragma unroll
         for (int j = 0; j < Nq; ++j) {
-          T gj = 0;
+          D gj = 0;
 #pragma unroll
           for (int m = 0; m < Nq; ++m) gj += tab[TB::MI1 + j * Nq + m] * lt[m];
           sG[q * Nq + j] = gj;
         }
-        // tetrahedron face barycentrics -> Legendre-product modes -> Lagrange basis
-        const T* lm = mg + 7 + 9 * side;
-        const T l1 = lm[3] * xi + lm[4] * z + lm[5];
-        const T l2 = lm[6] * xi + lm[7] * z + lm[8];
-        const T rr = T(2) * l1 - T(1), ss = T(2) * l2 - T(1);
-        T Pr[Nq], Ps[Nq];
-        Pr[0] = Ps[0] = T(1);
+        // tetrahedron face: barycentrics -> Legendre-product modes -> trace
+        const D* lm = mg + 7 + 9 * side;
+        const D l1 = lm[3] * xi + lm[4] * z + lm[5];
+        const D l2 = lm[6] * xi + lm[7] * z + lm[8];
+        const D rr = 2.0 * l1 - 1.0, ss = 2.0 * l2 - 1.0;
+        D Pr[Nq], Ps[Nq];
+        Pr[0] = Ps[0] = 1.0;
         Pr[1] = rr;
         Ps[1] = ss;
 #pragma unroll
         for (int n = 1; n < N; ++n) {
-          Pr[n + 1] = (T(2 * n + 1) * rr * Pr[n] - T(n) * Pr[n - 1]) / T(n + 1);
-          Ps[n + 1] = (T(2 * n + 1) * ss * Ps[n] - T(n) * Ps[n - 1]) / T(n + 1);
+          Pr[n + 1] = ((2 * n + 1) * rr * Pr[n] - n * Pr[n - 1]) * (1.0 / (n + 1));
+          Ps[n + 1] = ((2 * n + 1) * ss * Ps[n] - n * Ps[n - 1]) * (1.0 / (n + 1));
         }
-        T phi[NT];
+        D phi[NT];
+        D tp = 0, tx = 0, ty = 0;
         {
           int md = 0;
 #pragma unroll
           for (int aa = 0; aa <= N; ++aa)
 #pragma unroll
-            for (int bb = 0; bb + aa <= N; ++bb) phi[md++] = Pr[aa] * Ps[bb];
+            for (int bb = 0; bb + aa <= N; ++bb) {
+              const D ph = Pr[aa] * Ps[bb];
+              phi[md] = ph;
+              tp += ph * sCT[md];
+              tx += ph * sCT[NT + md];
+              ty += ph * sCT[2 * NT + md];
+              ++md;
+            }
         }
-        T tp = 0, tx = 0, ty = 0;
-#pragma unroll 1
-        for (int i = 0; i < NT; ++i) {
-          T li = 0;
+        const D zs = mg[27 + side];
+        const D taup = tau_on * 2.0 / zs, tauu = tau_on * zs * 0.5;
+        const D jp = tp - wp;
+        const D jun = nx * (tx - wx) + ny * (ty - wy);
+        sC[q * 2 + 0] = w * 0.5 * (taup * jp - jun);
+        sC[q * 2 + 1] = w * 0.5 * (tauu * jun - jp);
+        // seen from the tetrahedron: [p]' = -[p], [u.n]' = [u.n]
+        const D fp = w * 0.5 * (-taup * jp - jun), fu = w * 0.5 * (tauu * jun + jp);
 #pragma unroll
-          for (int md = 0; md < NT; ++md) li += tab[TB::VI + md * NT + i] * phi[md];
-          sL[q * NT + i] = li;
-          const V4<T> v = sT[side * NT + i];
-          tp += li * v.p;
-          tx += li * v.ux;
-          ty += li * v.uy;
+        for (int md = 0; md < NT; ++md) {
+          pm[md] += fp * phi[md];
+          pm[NT + md] += fu * phi[md];
         }
-        const T zs = mg[27 + side];
-        const T taup = tau_on * T(2) / zs, tauu = tau_on * zs * T(0.5);
-        const T jp = tp - wp;
-        const T jun = nx * (tx - wx) + ny * (ty - wy);
-        sC[q * 4 + 0] = w * T(0.5) * (taup * jp - jun);
-        sC[q * 4 + 1] = w * T(0.5) * (tauu * jun - jp);
-        sC[q * 4 + 2] = w * T(0.5) * (-taup * jp - jun);  // seen from the tetrahedron: [p]' = -[p]
-        sC[q * 4 + 3] = w * T(0.5) * (tauu * jun + jp);
+      }
+#pragma unroll
+      for (int md = 0; md < 2 * NT; ++md) sRed[md * 64 + tid] = pm[md];
+      __syncthreads();
+      // B. H_f[a][j] = sum over the t points of edge point a; reduce the modal moments
+      for (int o = tid; o < 2 * NX * Nq; o += 64) {
+        const int f = o / (NX * Nq), rem = o - f * NX * Nq, a = rem / Nq, j = rem - a * Nq;
+        D acc = 0;
+#pragma unroll
+        for (int g = 0; g < Nq; ++g) acc += sC[(a * Nq + g) * 2 + f] * sG[(a * Nq + g) * Nq + j];
+        sH[o] = acc;
+      }
+      if (tid < 2 * NT) {
+        D acc = 0;
+        for (int l = 0; l < 64; ++l) acc += sRed[tid * 64 + l];
+        sMM[tid] = acc;
       }
       __syncthreads();
-
-      // B1. wedge pre-lift contributions [field][level j][node i], summed over both sides
+      // wedge pre-lift contributions [field][level j][node i], summed over both sides
 #pragma unroll
       for (int r = 0; r < NBL; ++r) {
         const int o = tid + 64 * r;
         const int f = o / (Nq * NTP), rem = o - f * Nq * NTP, j = rem / NTP, i = rem - j * NTP;
         if (o < NB && i < NT) {
-          const T* Ai = tab + TB::A + (e * NT + i) * NX;
-          T acc = 0;
-          for (int q = 0; q < NQ1; ++q) acc += sC[q * 4 + f] * Ai[q / Nq] * sG[q * Nq + j];
+          const D* Ai = tab + TB::A + (e * NT + i) * NX;
+          const D* Hf = sH + f * NX * Nq + j;
+          D acc = 0;
+#pragma unroll 4
+          for (int a = 0; a < NX; ++a) acc += Ai[a] * Hf[a * Nq];
           accB[r] += acc;
         }
       }
-      // B2. tetrahedron face moments of this side [field][i]
-      for (int o = tid; o < 2 * NT; o += 64) {
-        const int f = o / NT, i = o - f * NT;
-        T acc = 0;
-        for (int q = 0; q < NQ1; ++q) acc += sC[q * 4 + 2 + f] * sL[q * NT + i];
-        sM[o] = acc;
-      }
-      __syncthreads();
-      // B3. equivalent nodal flux of this side's tetrahedron face
-      for (int o = tid; o < 2 * NT; o += 64) {
-        const int f = o / NT, i = o - f * NT;
-        T acc = 0;
-        for (int m = 0; m < NT; ++m) acc += tab[TB::MTI + i * NT + m] * sM[f * NT + m];
-        static_cast<T*>(A.mortF)[(mo * 2 + side) * 2 * NT + o] = acc * mg[25 + side];
+      // equivalent nodal flux of this side's tetrahedron face: (M^tri)^-1 Vinv^T mm / (area/2)
+      if (tid < 2 * NT) {
+        const int f = tid / NT, i = tid - f * NT;
+        D acc = 0;
+        for (int md = 0; md < NT; ++md) acc += tab[TB::P + i * NT + md] * sMM[f * NT + md];
+        static_cast<T*>(A.mortF)[(mo * 2 + side) * 2 * NT + tid] = T(acc * mg[25 + side]);
       }
     }
     T* outB = static_cast<T*>(A.mortB) + mo * NB;
 #pragma unroll
     for (int r = 0; r < NBL; ++r) {
       const int o = tid + 64 * r;
-      if (o < NB) outB[o] = accB[r];
+      if (o < NB) outB[o] = T(accB[r]);
     }
   }
 }
@@ -1287,13 +1327,13 @@ hipError_t launch_mortar_stage(int N, int bits, const StageLaunch& a, hipStream_
   return err;
 }
 
-int mortar_table_size(int N) {
+int mortar_table_size(int N, int bits) {
   switch (N) {
-    case 1: return MortTab<1>::SIZE;
-    case 2: return MortTab<2>::SIZE;
-    case 3: return MortTab<3>::SIZE;
-    case 4: return MortTab<4>::SIZE;
-    case 5: return MortTab<5>::SIZE;
+    case 1: return bits == 32 ? MortTab<1, 32>::SIZE : MortTab<1, 64>::SIZE;
+    case 2: return bits == 32 ? MortTab<2, 32>::SIZE : MortTab<2, 64>::SIZE;
+    case 3: return bits == 32 ? MortTab<3, 32>::SIZE : MortTab<3, 64>::SIZE;
+    case 4: return bits == 32 ? MortTab<4, 32>::SIZE : MortTab<4, 64>::SIZE;
+    case 5: return bits == 32 ? MortTab<5, 32>::SIZE : MortTab<5, 64>::SIZE;
     default: return 0;
   }
 }

@@ -38,14 +38,15 @@ constexpr int kTetAuxStride = 4;
 // Integer record: 0 wedge, 1 edge e, 2 diagonal (0: A0-A2, 1: A1-A3), 3/5 tetrahedron
 // below/above the diagonal (global id), 4/6 its face.
 constexpr int kMortIntStride = 8;
-// Value record (type T): 0..3 heights zb_a zb_b zt_a zt_b of the corners, 4 edge length,
+// Value record (FP64): 0..3 heights zb_a zb_b zt_a zt_b of the corners, 4 edge length,
 // 5/6 outward normal of the wedge, 7..15 / 16..24 barycentrics of the tetrahedron faces
 // below / above the diagonal as affine functions of (xi, z) (3 per vertex: xi, z, 1),
 // 25/26 1/(area/2) of those faces, 27/28 rho c of the wedge plus that of the tetrahedron.
 constexpr int kMortGeoStride = 32;
-// Gauss points along the edge of a mortar face (the integrand is rational in
-// the edge parameter; 4N + 8 points reach rounding level on layered meshes).
-constexpr int mort_nx(int N) { return 4 * N + 8; }
+// Gauss points along the edge of a mortar face: the integrand is rational in
+// the edge parameter; 4N + 8 points reach FP64 rounding on layered meshes,
+// 2N + 8 FP32 rounding.
+constexpr int mort_nx(int N, int bits) { return bits == 64 ? 4 * N + 8 : 2 * N + 8; }
 
 enum StageFlags : int {
   kReadRes = 1,    // res = a res + dt rhs (else res = dt rhs)
@@ -69,8 +70,8 @@ struct StageLaunch {
   const void* opsT;  // tetrahedron operators: Dr, Ds, Dt (Np x Np each), LIFT (Np x 4 Np_tri)
   const void* srcvec;  // kMaxSources x Np_wedge (a tetrahedron source uses the first Np_tet)
   const int* mortI;    // mortars: kMortIntStride ints each
-  const void* mortG;   // kMortGeoStride values each
-  const void* mortTab; // reference tables of the mortar quadrature (see mortar_tables)
+  const void* mortG;   // kMortGeoStride FP64 values each
+  const void* mortTab; // FP64 reference tables of the mortar quadrature (see mortar_table_size)
   void* mortB;         // per mortar: wedge pre-lift contributions [p, u][Nq][Np_tri padded to 4]
   void* mortF;         // per mortar side: equivalent nodal tetrahedron-face flux [p, u][Np_tri]
   int64_t nmort;
@@ -94,12 +95,14 @@ hipError_t launch_material(int bits, int64_t K, const double* dc, const double* 
 hipError_t launch_mortar_stage(int N, int bits, const StageLaunch& a, hipStream_t st);
 hipError_t launch_wedge_stage(int N, int bits, const StageLaunch& a, hipStream_t st);
 hipError_t launch_tet_stage(int N, int bits, const StageLaunch& a, hipStream_t st);
-// Values of the mortar reference tables of order N (FP64, host), in the order the
-// mortar kernel reads them: xg, wg (mort_nx), tg, wt (Nq Gauss), tgll (Nq), Minv1 (Nq x Nq),
-// Eedge (mort_nx x Nq: GLL Lagrange basis at xg), A (3 x Np_tri x mort_nx: (M^tri)^-1 restricted
-// to the edge nodes times Eedge), MtriInv (Np_tri x Np_tri), Vinv (Np_tri x Np_tri: Legendre-product
-// modes to the triangle's Lagrange basis).
-int mortar_table_size(int N);
+// Number of FP64 values of the mortar reference tables of order N for the given
+// state precision; the host fills them in this order: xg, wg (mort_nx Gauss points along
+// the edge), tg, wt (Nq Gauss points in t), tgll (Nq GLL nodes), 1/(tgll_m - tgll_mm)
+// (Nq x Nq, diagonal unused), Minv1 (Nq x Nq), Eedge (mort_nx x Nq: GLL Lagrange basis
+// at xg), A (3 x Np_tri x mort_nx: (M^tri)^-1 restricted to the edge nodes times Eedge),
+// Vinv (Np_tri x Np_tri: triangle Lagrange values -> Legendre-product modes P_a(r) P_b(s),
+// a+b <= N, a outer), P = (M^tri)^-1 Vinv^T (Np_tri x Np_tri).
+int mortar_table_size(int N, int bits);
 // Pressure at receivers: receiver r reads nn[r] nodes from 4-vector index base[r] with row stride ld.
 hipError_t launch_receivers(int bits, int ld, int nrec, const void* U, const int64_t* base, const int* nn,
                             const double* rows, double* out, hipStream_t st);
