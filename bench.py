@@ -53,7 +53,9 @@ def stage_bytes(N: int, bits: int, reads_res: bool) -> int:
 
 
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "wedge_stage_cfg2_traffic.json")
-KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1607_03399_amd", "csrc", "kernels.hip")
+# sources the wedge stage kernel is compiled from (its traffic record is tied to them)
+KERNEL_SOURCES = [os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1607_03399_amd", "csrc", f)
+                  for f in ("wedge_stage.hip", "device_common.hpp", "kernels.hpp")]
 
 
 def measured_traffic(config: str):
@@ -65,8 +67,11 @@ def measured_traffic(config: str):
         return None
     with open(TRAFFIC_FILE) as f:
         rec = json.load(f)
-    with open(KERNEL_SOURCE, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    sha = h.hexdigest()
     if rec.get("kernel_sha256") != sha:
         return None
     return float(rec["bytes_per_launch"])

@@ -3,7 +3,8 @@
 // Mesh validation (Definition of vertically mapped wedges, Sec. 3.2),
 // face matching, node coordinates, point location, sources/receivers and the
 // Runge-Kutta driver loop.  All arithmetic of the right-hand side runs in the
-// HIP kernels (kernels.hip); the host only prepares data and launches.
+// HIP kernels (wedge_stage.hip, tet_stage.hip, mortar.hip, setup.hip); the host
+// only prepares data and launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

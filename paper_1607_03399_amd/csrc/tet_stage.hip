@@ -1,0 +1,203 @@
+// Tetrahedron stage kernel of libwdg: affine tetrahedra of hybrid meshes
+// (standard nodal DG; they meet wedges at triangular faces, Sec. 3.1).
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+
+namespace wdg {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Tetrahedron stage kernel (affine tetrahedra, standard nodal DG)
+//
+// Lane (element, node i); a block of 256 lanes holds EPB = 256 / Np
+// tetrahedra per chunk and loops over chunks (persistent), so the reference
+// operators Dr, Ds, Dt and LIFT are staged in LDS once per block where they
+// fit (read from memory otherwise).  Per chunk:
+//   1. node i stores (p, r.u, s.u, t.u) with r.u = r_x u_x + r_y u_y + r_z u_z
+//      (and likewise s, t), so that div u = D_r(r.u) + D_s(s.u) + D_t(t.u);
+//      the 4 Np_tri face nodes are shared out over the lanes, whose fluxes
+//      (scaled by J_f / J) go to LDS
+//   2. node i: volume terms, LIFT of the fluxes, material scaling, sources and
+//      the low-storage update (node-contiguous, coalesced)
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+struct TCfg {
+  static constexpr int NT = TDim<N>::NT, NP = TDim<N>::NP;
+  static constexpr int BS = 256;
+  static constexpr int EPB = BS / NP;
+  static constexpr int NOPS = 3 * NP * NP + NP * 4 * NT;
+  static constexpr bool OPS_LDS = NOPS * int(sizeof(T)) <= 40960;
+  static constexpr int SLOTS = (4 * NT + NP - 1) / NP;  // face nodes per lane
+};
+
+template <typename T>
+struct alignas(4 * sizeof(T)) Q4 {
+  T p, ar, as, at;
+};
+
+template <int N, typename T>
+__global__ void __launch_bounds__(256) tet_stage(StageLaunch A) {
+  using C = TCfg<N, T>;
+  constexpr int NT = C::NT, NP = C::NP, EPB = C::EPB;
+  constexpr int NPW = Dim<N>::NP;
+  __shared__ T sOps[C::OPS_LDS ? C::NOPS : 1];
+  __shared__ V4<T> sU[EPB * NP];
+  __shared__ Q4<T> sW[EPB * NP];
+  __shared__ T sF[EPB * 4 * NT * 2];
+  __shared__ T sG[EPB * kTetGeoStride];
+  __shared__ int sC[EPB * kTetConnStride];
+
+  const T* gops = static_cast<const T*>(A.opsT);
+  if constexpr (C::OPS_LDS) {
+    for (int idx = threadIdx.x; idx < C::NOPS; idx += C::BS) sOps[idx] = gops[idx];
+  }
+  const T* ops = C::OPS_LDS ? static_cast<const T*>(sOps) : gops;
+  const T* Dr = ops;
+  const T* Ds = ops + NP * NP;
+  const T* Dt = ops + 2 * NP * NP;
+  const T* LIFT = ops + 3 * NP * NP;
+
+  const V4<T>* __restrict__ Uin = static_cast<const V4<T>*>(A.Uin);
+  V4<T>* __restrict__ res = static_cast<V4<T>*>(A.res);
+  V4<T>* __restrict__ Uout = static_cast<V4<T>*>(A.Uout);
+  const T* __restrict__ geo = static_cast<const T*>(A.geoT);
+  const int* __restrict__ conn = A.connT;
+  const int64_t tb = A.Kw * NPW;  // first tetrahedron node
+  const int tid = threadIdx.x;
+  const int le = tid / NP, i = tid - le * NP;
+  const T bsign = (A.flags & kDirichlet) ? T(-1) : T(1);
+  const T tau_on = (A.flags & kCentral) ? T(0) : T(1);
+  const bool rd = (A.flags & kReadRes) != 0, wu = (A.flags & kWriteU) != 0;
+  const int64_t nchunks = (A.Kt + EPB - 1) / EPB;
+
+  for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+    const int64_t e0 = chunk * EPB;
+    const int nE = int(A.Kt - e0 < EPB ? A.Kt - e0 : EPB);
+    __syncthreads();  // the previous chunk is done with LDS
+    for (int idx = tid; idx < nE * NP; idx += C::BS) sU[idx] = Uin[tb + e0 * NP + idx];
+    for (int idx = tid; idx < nE * kTetGeoStride; idx += C::BS) sG[idx] = geo[e0 * kTetGeoStride + idx];
+    for (int idx = tid; idx < nE * kTetConnStride; idx += C::BS) sC[idx] = conn[e0 * kTetConnStride + idx];
+    __syncthreads();
+
+    const bool active = tid < EPB * NP && le < nE;
+    const T* g = sG + le * kTetGeoStride;
+    const int* cn = sC + le * kTetConnStride;
+    const int64_t e = e0 + le;
+    if (active) {
+      const V4<T> v = sU[le * NP + i];
+      sW[le * NP + i] = Q4<T>{v.p, g[0] * v.ux + g[1] * v.uy + g[2] * v.uz, g[3] * v.ux + g[4] * v.uy + g[5] * v.uz,
+                              g[6] * v.ux + g[7] * v.uy + g[8] * v.uz};
+      const int code = cn[4];
+#pragma unroll
+      for (int sl = 0; sl < C::SLOTS; ++sl) {
+        const int q = i + NP * sl;
+        if (q < 4 * NT) {
+          const int f = q / NT, m = q - f * NT;
+          const int nbr = cn[f];
+          const T w_in = nbr >= 0 ? T(1) : T(0);
+          const int pc = (code >> (5 * f)) & 7, nf = (code >> (5 * f + 3)) & 3;
+          const int fn = face_perm<N>(pc, m);
+          const int64_t src = nbr >= 0 ? int64_t(nbr) : A.Kw + e;
+          const int64_t gi = src >= A.Kw ? tb + (src - A.Kw) * NP + tet_face_node<N>(nf, fn)
+                                         : src * NPW + (nf == 1 ? N * NT : 0) + fn;
+          const V4<T> own = sU[le * NP + tet_face_node<N>(f, m)];
+          const V4<T> nb = Uin[gi];
+          const T Fs = g[12 + 4 * f], nx = g[13 + 4 * f], ny = g[14 + 4 * f], nz = g[15 + 4 * f];
+          const T zs = g[28 + f];
+          const T taup = tau_on * T(2) / zs;
+          const T tauu = tau_on * zs * T(0.5);
+          const T pm = own.p;
+          const T unm = nx * own.ux + ny * own.uy + nz * own.uz;
+          const T pb = bsign * pm, ub = -bsign * unm;
+          const T pp = pb + w_in * (nb.p - pb);
+          const T unp = ub + w_in * ((nx * nb.ux + ny * nb.uy + nz * nb.uz) - ub);
+          const T jp = pp - pm, jun = unp - unm;
+          T Fp = T(0.5) * (taup * jp - jun), Fu = T(0.5) * (tauu * jun - jp);
+          if (nbr <= -2) {
+            // mortar side: the equivalent nodal flux of the common refinement
+            const T* mf = static_cast<const T*>(A.mortF) + int64_t(-2 - nbr) * 2 * NT;
+            Fp = mf[m];
+            Fu = mf[NT + m];
+          }
+          sF[(le * 4 * NT + q) * 2] = Fs * Fp;
+          sF[(le * 4 * NT + q) * 2 + 1] = Fs * Fu;
+        }
+      }
+    }
+    __syncthreads();
+    if (!active) continue;
+
+    T dpr = 0, dps = 0, dpt = 0, div = 0;
+#pragma unroll 5
+    for (int m = 0; m < NP; ++m) {
+      const Q4<T> w = sW[le * NP + m];
+      const T dr = Dr[i * NP + m], ds = Ds[i * NP + m], dt = Dt[i * NP + m];
+      dpr += dr * w.p;
+      dps += ds * w.p;
+      dpt += dt * w.p;
+      div += dr * w.ar;
+      div += ds * w.as;
+      div += dt * w.at;
+    }
+    T lp = 0, lx = 0, ly = 0, lz = 0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      T su = 0;
+#pragma unroll 3
+      for (int m = 0; m < NT; ++m) {
+        const T l = LIFT[i * 4 * NT + f * NT + m];
+        lp += l * sF[(le * 4 * NT + f * NT + m) * 2];
+        su += l * sF[(le * 4 * NT + f * NT + m) * 2 + 1];
+      }
+      lx += g[13 + 4 * f] * su;
+      ly += g[14 + 4 * f] * su;
+      lz += g[15 + 4 * f] * su;
+    }
+    const T kap = g[9], irho = g[10];
+    T Rp = kap * (lp - div);
+    const T Rx = irho * (lx - (g[0] * dpr + g[3] * dps + g[6] * dpt));
+    const T Ry = irho * (ly - (g[1] * dpr + g[4] * dps + g[7] * dpt));
+    const T Rz = irho * (lz - (g[2] * dpr + g[5] * dps + g[8] * dpt));
+    for (int s = 0; s < A.nsrc; ++s)
+      if (A.src_elem[s] == A.Kw + e) Rp += T(A.src_amp[s]) * static_cast<const T*>(A.srcvec)[s * NPW + i];
+
+    const int64_t gi = tb + e * NP + i;
+    const T ca = T(A.a), cb = T(A.b), dtt = T(A.dt);
+    V4<T> r{dtt * Rp, dtt * Rz, dtt * Rx, dtt * Ry};
+    if (rd) {
+      const V4<T> q = res[gi];
+      r.p += ca * q.p;
+      r.uz += ca * q.uz;
+      r.ux += ca * q.ux;
+      r.uy += ca * q.uy;
+    }
+    res[gi] = r;
+    if (wu) {
+      const V4<T> u = sU[le * NP + i];
+      Uout[gi] = V4<T>{u.p + cb * r.p, u.uz + cb * r.uz, u.ux + cb * r.ux, u.uy + cb * r.uy};
+    }
+  }
+}
+
+template <int N, typename T>
+hipError_t launch_tet_stage_t(const StageLaunch& a, hipStream_t st) {
+  if (a.Kt <= 0) return hipSuccess;
+  using TC = TCfg<N, T>;
+  const int64_t tchunks = (a.Kt + TC::EPB - 1) / TC::EPB;
+  const unsigned grid = unsigned(tchunks < 2048 ? tchunks : 2048);
+  hipLaunchKernelGGL((tet_stage<N, T>), dim3(grid), dim3(TC::BS), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_tet_stage(int N, int bits, const StageLaunch& a, hipStream_t st) {
+  hipError_t err = hipErrorInvalidValue;
+#define WDG_STAGE(n, T) err = launch_tet_stage_t<n, T>(a, st)
+  WDG_DISPATCH_N(N, bits, WDG_STAGE)
+#undef WDG_STAGE
+  return err;
+}
+
+}  // namespace wdg

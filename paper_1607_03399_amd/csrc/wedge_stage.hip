@@ -1,0 +1,503 @@
+// Fused wedge stage kernel of libwdg for CDNA4 (gfx950): volume term,
+// surface fluxes and lifts, L^{tri,k} application and the low-storage
+// Runge-Kutta update of one stage (Sec. 4.2-4.3).
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "ref_tables.inc"
+
+namespace wdg {
+namespace {
+
+// Launch shape: one wavefront per block, lane = (element, level j), so a block
+// holds EPB = 64 / Nq elements (fewer where the LDS would exceed 64 KiB).  LDS
+// holds the staged state (per-element stride NPP, odd in 4-vectors, so that the
+// elements of a wavefront fall on different banks) and a second region that
+// first holds the triangular lifts, geometry records and triangular-face
+// fluxes, and afterwards the right-hand side on its way to the coalesced
+// update.
+template <int N, typename T>
+struct Cfg {
+  static constexpr int NT = Dim<N>::NT, Nq = Dim<N>::Nq, NP = Dim<N>::NP;
+  static constexpr int NPP = NP | 1;
+  static constexpr int VL = Dim<N>::LS / 4, VG = kGeoStride / 4, VF = NT;  // 4-vectors per element
+  static constexpr int XPE = (VL + VG + VF) > NPP ? (VL + VG + VF) : NPP;
+  static constexpr int per_elem = (NPP + XPE) * 4 * int(sizeof(T));
+  static constexpr int EPB_FULL = 64 / Nq;
+  static constexpr int EPB = EPB_FULL * per_elem <= 65536 ? EPB_FULL : 65536 / per_elem;
+  static constexpr int BS = 64;
+  // 4-vectors of the chunk each lane carries through the coalesced update
+  static constexpr int UPD = (EPB * NP + BS - 1) / BS;
+  // prefetch the previous residual into registers when that costs at most 40 of them
+#ifndef WDG_PREFETCH_REGS
+#define WDG_PREFETCH_REGS 40
+#endif
+  static constexpr bool PREFETCH = UPD * 4 * int(sizeof(T)) / 4 <= WDG_PREFETCH_REGS;
+};
+
+// acc1 += c x1; acc2 += c x2 for a reference-operator entry c known at
+// compile time; exact zeros of the operator cost nothing
+template <typename T>
+__device__ __forceinline__ void constexpr_or_skip(double c, T& acc, T x) {
+  if (c != 0.0) acc += T(c) * x;
+}
+
+// entry of a reference table selected by the lane's level j (j < Nq)
+template <int Nq, typename T>
+__device__ __forceinline__ T pick(const double* tab, int j, int stride, int col) {
+  T v = T(tab[col]);
+#pragma unroll
+  for (int jj = 1; jj < Nq; ++jj) v = (j == jj) ? T(tab[jj * stride + col]) : v;
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Fused stage kernel
+//
+// Lane (element, level j) owns the triangular slice j of its element for all
+// four equations.  The reference triangle and 1D operators are compile-time
+// constants (instruction literals).  The chunk's state, lifts, geometry and
+// connectivity are staged in LDS with coalesced loads; the vertical derivative
+// and the triangle-face lifts couple the levels of one element through it.
+//   phase 1: B = -W (vertical part of D_x, D_y, D_z, before L^{tri,k}) plus the
+//            quadrilateral-face lifts of this level; triangular-face fluxes
+//   phase 2: B += triangular-face lifts; R = L^{tri,k} B + H (horizontal part);
+//            scale by kappa, 1/rho; sources
+//   update:  R goes through LDS so that the low-storage Runge-Kutta update
+//            reads and writes res and U with fully coalesced accesses
+// ---------------------------------------------------------------------------
+#ifndef WDG_STAGE_WAVES_PER_EU
+#define WDG_STAGE_WAVES_PER_EU 2
+#endif
+// MODE 0: wedges only; 1: tetrahedra across triangular faces; 2: also mortars
+template <int N, typename T, int MODE>
+__global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageLaunch A) {
+  constexpr bool HYB = MODE >= 1;
+  using C = Cfg<N, T>;
+  using RT = gen::RefTables<N>;
+  constexpr int NT = C::NT, Nq = C::Nq, NP = C::NP, NPP = C::NPP, EPB = C::EPB;
+  constexpr int VL = C::VL, VG = C::VG;
+  // one spare 4-vector at the end of each array takes the stores of lanes
+  // past the end of a staged stream
+  __shared__ V4<T> sU[EPB * NPP + 1];
+  __shared__ V4<T> sX[EPB * C::XPE + 1];
+  V4<T>* const sL = sX;
+  V4<T>* const sG = sX + EPB * VL;
+  T* const sF = reinterpret_cast<T*>(sG + EPB * VG);
+  V4<T>* const sR = sX;
+
+  const V4<T>* __restrict__ Uin = static_cast<const V4<T>*>(A.Uin);
+  const T* __restrict__ geo = static_cast<const T*>(A.geo);
+  const T* __restrict__ Lm = static_cast<const T*>(A.L);
+  const int* __restrict__ conn = A.conn;
+
+  // XCD-aware mapping: consecutive workgroups go to different XCDs, so give
+  // every XCD one contiguous range of chunks (face neighbours share its L2).
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int qd = nb / 8, rm = nb % 8, xcd = bid % 8, kk = bid / 8;
+  const int chunk = xcd < rm ? xcd * (qd + 1) + kk : rm * (qd + 1) + (xcd - rm) * qd + kk;
+  const int64_t e0 = int64_t(chunk) * EPB;
+  const int64_t left = A.Kw - e0;
+  const int nE = left < EPB ? int(left) : EPB;
+  const int tid = threadIdx.x;
+
+  const int le = tid / Nq;
+  const int j = tid - le * Nq;
+  const bool active = tid < EPB * Nq && le < nE;
+  const int64_t e = e0 + (active ? le : 0);  // idle lanes shadow a valid element
+  const T bsign = (A.flags & kDirichlet) ? T(-1) : T(1);
+  const T tau_on = (A.flags & kCentral) ? T(0) : T(1);
+  constexpr int per = (2 * NT + Nq - 1) / Nq;  // triangular-face nodes per lane
+
+  // The lane's own connectivity is read first and the neighbour gathers are
+  // issued as soon as it arrives, while the chunk's coalesced staging loads
+  // are still in flight: both memory latencies overlap.
+  int cn[6];
+  {
+    const int4* cp = reinterpret_cast<const int4*>(conn + e * kConnStride);
+    const int4 c0 = cp[0], c1 = cp[1];
+    cn[0] = c0.x;
+    cn[1] = c0.y;
+    cn[2] = c0.z;
+    cn[3] = c0.w;
+    cn[4] = c1.x;
+    cn[5] = c1.y;
+  }
+  constexpr int SU = (EPB * NP + 63) / 64, SL = (EPB * VL + 63) / 64, SG = (EPB * VG + 63) / 64;
+  constexpr int V4B = 4 * int(sizeof(T));
+  V4<T> rU[SU], rL[SL], rG[SG];
+  {
+    const auto bu = chunk_rsrc(Uin + e0 * NP, int64_t(nE) * NP * V4B);
+    const auto bl = chunk_rsrc(Lm + e0 * Dim<N>::LS, int64_t(nE) * VL * V4B);
+    const auto bg = chunk_rsrc(geo + e0 * kGeoStride, int64_t(nE) * VG * V4B);
+#pragma unroll
+    for (int k = 0; k < SU; ++k) rU[k] = bload<T>(bu, tid + 64 * k);
+#pragma unroll
+    for (int k = 0; k < SL; ++k) rL[k] = bload<T>(bl, tid + 64 * k);
+#pragma unroll
+    for (int k = 0; k < SG; ++k) rG[k] = bload<T>(bg, tid + 64 * k);
+  }
+  const int code = cn[5];
+  // quadrilateral-face neighbour nodes on this level (boundary faces read the
+  // own element, a valid address; the mirror state is blended in later)
+  V4<T> gq[3][Nq];
+#pragma unroll
+  for (int ed = 0; ed < 3; ++ed) {
+    const int nbr = cn[2 + ed];
+    const int ned = (code >> (8 + 2 * ed)) & 3;
+    const V4<T>* nb_el = Uin + (nbr >= 0 ? int64_t(nbr) : e) * NP + j * NT;
+#pragma unroll
+    for (int q = 0; q < Nq; ++q) {
+      const int ni = ned == 0 ? edge_node(N, 0, N - q) : (ned == 1 ? edge_node(N, 1, N - q) : edge_node(N, 2, N - q));
+      gq[ed][q] = nb_el[ni];
+    }
+  }
+  // triangular-face neighbour nodes: the 2 NT face nodes of the element are
+  // shared out over its Nq lanes (surplus slots redo the last node)
+  V4<T> gt[per];
+#pragma unroll
+  for (int t = 0; t < per; ++t) {
+    const int fraw = j * per + t;
+    const int fnode = fraw < 2 * NT ? fraw : 2 * NT - 1;
+    const int face = fnode >= NT ? 1 : 0;
+    const int i = fnode - face * NT;
+    const int nbr = face ? cn[1] : cn[0];
+    const int pc = (code >> (3 * face)) & 7;
+    const int nlev = ((code >> (6 + face)) & 1) ? N : 0;
+    const int64_t src = nbr >= 0 ? int64_t(nbr) : e;
+    const int fn = face_perm<N>(pc, i);
+    if constexpr (HYB) {
+      // a tetrahedron neighbour: its nodes follow all wedge nodes
+      const int tf = (code >> (14 + 2 * face)) & 3;
+      const bool tet = src >= A.Kw;
+      gt[t] = Uin[tet ? A.Kw * NP + (src - A.Kw) * TDim<N>::NP + tet_face_node<N>(tf, fn) : src * NP + nlev * NT + fn];
+    } else {
+      gt[t] = Uin[src * NP + nlev * NT + fn];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < SU; ++k) {
+    const int idx = tid + 64 * k;
+    sU[idx < EPB * NP ? idx + (idx / NP) * (NPP - NP) : EPB * NPP] = rU[k];
+  }
+#pragma unroll
+  for (int k = 0; k < SL; ++k) {
+    const int idx = tid + 64 * k;
+    sX[idx < EPB * VL ? idx : EPB * C::XPE] = rL[k];
+  }
+#pragma unroll
+  for (int k = 0; k < SG; ++k) {
+    const int idx = tid + 64 * k;
+    sX[idx < EPB * VG ? EPB * VL + idx : EPB * C::XPE] = rG[k];
+  }
+  __syncthreads();
+
+  const V4<T>* el = sU + le * NPP;
+  const T* g = reinterpret_cast<const T*>(sG) + le * kGeoStride;
+
+  // pre-lift accumulators of the four equations on this level
+  T Bp[NT], Bz[NT], Bx[NT], By[NT];
+
+  if (active) {
+    const T tzJ = g[4];
+    const T tl = T(0.5) * (T(1) - pick<Nq, T>(RT::t, j, 1, 0));
+    const T th = T(0.5) * (T(1) + pick<Nq, T>(RT::t, j, 1, 0));
+    const T txJ = g[5] * tl + g[6] * th;
+    const T tyJ = g[7] * tl + g[8] * th;
+    T dtr[Nq];
+#pragma unroll
+    for (int m = 0; m < Nq; ++m) dtr[m] = pick<Nq, T>(RT::Dt, j, Nq, m);
+
+    // vertical part: W = t_dJ(t_j) (D_t U)(level j)
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      T dP = 0, dX = 0, dY = 0, dZ = 0;
+#pragma unroll
+      for (int m = 0; m < Nq; ++m) {
+        const V4<T> v = el[m * NT + i];
+        dP += dtr[m] * v.p;
+        dX += dtr[m] * v.ux;
+        dY += dtr[m] * v.uy;
+        dZ += dtr[m] * v.uz;
+      }
+      T w = txJ * dX;
+      w += tyJ * dY;
+      w += tzJ * dZ;
+      Bp[i] = -w;
+      Bx[i] = -(txJ * dP);
+      By[i] = -(tyJ * dP);
+      Bz[i] = -(tzJ * dP);
+    }
+
+    // quadrilateral faces (normals horizontal, so they reach p, u_x, u_y only);
+    // the mirror state of a boundary face is blended in without branches
+#pragma unroll
+    for (int ed = 0; ed < 3; ++ed) {
+      const T w_in = cn[2 + ed] >= 0 ? T(1) : T(0);
+      // a mortar face (-2 - m) takes its flux from the mortar kernel instead
+      const T Ja = MODE == 2 && cn[2 + ed] <= -2 ? T(0) : g[20 + 4 * ed];
+      const T Jb = MODE == 2 && cn[2 + ed] <= -2 ? T(0) : g[21 + 4 * ed];
+      const T nx = g[22 + 4 * ed], ny = g[23 + 4 * ed];
+      const T zs = g[34 + ed];  // Z- + Z+ (= 2 Z- on the boundary)
+      const T taup = tau_on * T(2) / zs;
+      const T tauu = tau_on * zs * T(0.5);
+      T fpa[Nq], fpb[Nq], fua[Nq], fub[Nq];
+#pragma unroll
+      for (int q = 0; q < Nq; ++q) {
+        const V4<T> own = el[j * NT + edge_node(N, ed, q)];
+        const V4<T> v = gq[ed][q];
+        const T pm = own.p;
+        const T unm = nx * own.ux + ny * own.uy;
+        // mirror state: p+ = s p-, u_n+ = -s u_n- (s = -1 Dirichlet, +1 rigid)
+        const T pb = bsign * pm, ub = -bsign * unm;
+        const T pp = pb + w_in * (v.p - pb);
+        // (u_z enters with weight zero, which keeps the gather one 16-byte load)
+        const T unp = ub + w_in * ((nx * v.ux + ny * v.uy + T(0) * v.uz) - ub);
+        const T jp = pp - pm, jun = unp - unm;
+        const T Fp = T(0.5) * (taup * jp - jun);
+        const T Fu = T(0.5) * (tauu * jun - jp);
+        fpa[q] = Ja * Fp;
+        fpb[q] = Jb * Fp;
+        fua[q] = Ja * Fu;
+        fub[q] = Jb * Fu;
+      }
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        T sp = 0, su = 0;
+#pragma unroll
+        for (int q = 0; q < Nq; ++q) {
+          constexpr_or_skip(RT::Ea[(ed * NT + i) * Nq + q], sp, fpa[q]);
+          constexpr_or_skip(RT::Eb[(ed * NT + i) * Nq + q], sp, fpb[q]);
+          constexpr_or_skip(RT::Ea[(ed * NT + i) * Nq + q], su, fua[q]);
+          constexpr_or_skip(RT::Eb[(ed * NT + i) * Nq + q], su, fub[q]);
+        }
+        Bp[i] += sp;
+        Bx[i] += nx * su;
+        By[i] += ny * su;
+      }
+    }
+
+    // triangular-face fluxes (premultiplied by J_f) go to LDS for every level
+#pragma unroll
+    for (int t = 0; t < per; ++t) {
+      const int fraw = j * per + t;
+      const int fnode = fraw < 2 * NT ? fraw : 2 * NT - 1;
+      const int face = fnode >= NT ? 1 : 0;
+      const int i = fnode - face * NT;
+      const T w_in = (face ? cn[1] : cn[0]) >= 0 ? T(1) : T(0);
+      const T* gf = g + 12 + 4 * face;
+      const T Jf = gf[0], nx = gf[1], ny = gf[2], nz = gf[3];
+      const T zs = g[32 + face];
+      const T taup = tau_on * T(2) / zs;
+      const T tauu = tau_on * zs * T(0.5);
+      const V4<T> own = el[face * N * NT + i];
+      const V4<T> v = gt[t];
+      const T pm = own.p;
+      const T unm = nx * own.ux + ny * own.uy + nz * own.uz;
+      const T pb = bsign * pm, ub = -bsign * unm;
+      const T pp = pb + w_in * (v.p - pb);
+      const T unp = ub + w_in * ((nx * v.ux + ny * v.uy + nz * v.uz) - ub);
+      const T jp = pp - pm, jun = unp - unm;
+      if (fraw < 2 * NT) {
+        T* f = sF + ((le * 2 + face) * NT + i) * 2;
+        f[0] = Jf * T(0.5) * (taup * jp - jun);
+        f[1] = Jf * T(0.5) * (tauu * jun - jp);
+      }
+    }
+  }
+  __syncthreads();
+
+  const bool rd = (A.flags & kReadRes) != 0, wu = (A.flags & kWriteU) != 0;
+  // residual of the previous stage, in the coalesced layout of the update.
+  // The first stage reads none: its resource has an empty range, so the
+  // loads return zeros without touching memory and need no branch.
+  V4<T>* const res_chunk = static_cast<V4<T>*>(A.res) + e0 * NP;
+  const auto bres_in = chunk_rsrc(res_chunk, rd ? int64_t(nE) * NP * V4B : 0);
+  const auto bres = chunk_rsrc(res_chunk, int64_t(nE) * NP * V4B);
+  V4<T> rprev[C::PREFETCH ? C::UPD : 1];
+  if constexpr (C::PREFETCH) {
+#pragma unroll
+    for (int k = 0; k < C::UPD; ++k) rprev[k] = bload<T>(bres_in, tid + 64 * k);
+  }
+
+  T Rp[NT], Rz[NT], Rx[NT], Ry[NT];
+  if (active) {
+    // triangular-face lifts: flux spread over all levels by (M^1D)^-1 e_{0,N}
+    {
+      // exact mass: (M^1D)^-1 e_{0,N}; lumped mass (Gauss-Lobatto weights w): e_{0,N} / w_{0,N}
+      const T wend = T(0.5 * N * (N + 1));  // 1 / w_0 = 1 / w_N
+      const bool lumped = (A.flags & kLumped) != 0;
+      const T g0j = lumped ? (j == 0 ? wend : T(0)) : pick<Nq, T>(RT::g0, j, 1, 0);
+      const T gNj = lumped ? (j == N ? wend : T(0)) : pick<Nq, T>(RT::gN, j, 1, 0);
+      const T* fbt = sF + (le * 2 + 0) * NT * 2;
+      const T* ftp = sF + (le * 2 + 1) * NT * 2;
+      const T bx = g[13], by = g[14], bz = g[15], tx = g[17], ty = g[18], tz = g[19];
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        Bp[i] += g0j * fbt[2 * i];
+        Bp[i] += gNj * ftp[2 * i];
+        const T wb = g0j * fbt[2 * i + 1], wt = gNj * ftp[2 * i + 1];
+        Bx[i] += wb * bx;
+        Bx[i] += wt * tx;
+        By[i] += wb * by;
+        By[i] += wt * ty;
+        Bz[i] += wb * bz;
+        Bz[i] += wt * tz;
+      }
+    }
+
+    if constexpr (MODE == 2) {
+      // mortar faces: pre-lift contributions of the common refinement; the
+      // buffer's range check returns zeros for the other faces
+      constexpr int NTP = (NT + 3) / 4 * 4;
+      const auto rb = chunk_rsrc(A.mortB, A.nmort * 2 * Nq * NTP * int64_t(sizeof(T)));
+#pragma unroll
+      for (int ed = 0; ed < 3; ++ed) {
+        const int nbr = cn[2 + ed];
+        const T nxe = g[22 + 4 * ed], nye = g[23 + 4 * ed];
+        const int64_t mo = nbr <= -2 ? int64_t(-2 - nbr) : int64_t(A.nmort);
+        const int idx0 = int((mo * 2 * Nq + j) * NTP / 4);
+#pragma unroll
+        for (int c = 0; c < NTP / 4; ++c) {
+          const V4<T> sp = bload<T>(rb, idx0 + c);
+          const V4<T> su = bload<T>(rb, idx0 + Nq * NTP / 4 + c);
+          const T vp[4] = {sp.p, sp.uz, sp.ux, sp.uy}, vu[4] = {su.p, su.uz, su.ux, su.uy};
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            if (4 * c + kk < NT) {
+              Bp[4 * c + kk] += vp[kk];
+              Bx[4 * c + kk] += nxe * vu[kk];
+              By[4 * c + kk] += nye * vu[kk];
+            }
+          }
+        }
+      }
+    }
+
+    // triangular lift L^{tri,k} on this level: R = L B
+#pragma unroll
+    for (int i = 0; i < NT; ++i) Rp[i] = Rz[i] = Rx[i] = Ry[i] = T(0);
+    {
+      const V4<T>* Lv = sL + le * VL;
+#pragma unroll
+      for (int c = 0; c < VL; ++c) {
+        const V4<T> l4 = Lv[c];
+        const T lv[4] = {l4.p, l4.uz, l4.ux, l4.uy};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int f = 4 * c + k;
+          if (f < NT * NT) {
+            const int i = f / NT, m = f % NT;
+            Rp[i] += lv[k] * Bp[m];
+            Rz[i] += lv[k] * Bz[m];
+            Rx[i] += lv[k] * Bx[m];
+            Ry[i] += lv[k] * By[m];
+          }
+        }
+      }
+    }
+
+    // horizontal part on the own slice:
+    //   R_p -= D_r (r_x u_x + r_y u_y) + D_s (s_x u_x + s_y u_y)
+    //   R_x -= r_x D_r p + s_x D_s p ;  R_y -= r_y D_r p + s_y D_s p
+    {
+      const T rx = g[0], ry = g[1], sx = g[2], sy = g[3];
+      T Ar[NT], As[NT], P[NT];
+#pragma unroll
+      for (int m = 0; m < NT; ++m) {
+        const V4<T> v = el[j * NT + m];
+        Ar[m] = rx * v.ux + ry * v.uy;
+        As[m] = sx * v.ux + sy * v.uy;
+        P[m] = v.p;
+      }
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        T dA = 0, dB = 0, dPr = 0, dPs = 0;
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
+          constexpr_or_skip(RT::Dr[i * NT + m], dA, Ar[m]);
+          constexpr_or_skip(RT::Ds[i * NT + m], dB, As[m]);
+          constexpr_or_skip(RT::Dr[i * NT + m], dPr, P[m]);
+          constexpr_or_skip(RT::Ds[i * NT + m], dPs, P[m]);
+        }
+        Rp[i] -= dA;
+        Rp[i] -= dB;
+        Rx[i] -= rx * dPr;
+        Rx[i] -= sx * dPs;
+        Ry[i] -= ry * dPr;
+        Ry[i] -= sy * dPs;
+      }
+    }
+
+    const T kap = g[9], irho = g[10];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      Rp[i] *= kap;
+      Rz[i] *= irho;
+      Rx[i] *= irho;
+      Ry[i] *= irho;
+    }
+    for (int s = 0; s < A.nsrc; ++s) {
+      if (A.src_elem[s] == e) {
+        const T* sv = static_cast<const T*>(A.srcvec) + s * NP + j * NT;
+        const T amp = T(A.src_amp[s]);
+#pragma unroll
+        for (int i = 0; i < NT; ++i) Rp[i] += amp * sv[i];
+      }
+    }
+  }
+  // the right-hand side replaces lifts, geometry and fluxes in LDS
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < NT; ++i) sR[le * NPP + j * NT + i] = V4<T>{Rp[i], Rz[i], Rx[i], Ry[i]};
+  }
+  __syncthreads();
+
+  // low-storage Runge-Kutta update, coalesced over the chunk
+  const T ca = T(A.a), cb = T(A.b), dt = T(A.dt);
+  const auto bout = chunk_rsrc(static_cast<V4<T>*>(A.Uout) + e0 * NP, int64_t(nE) * NP * V4B);
+#pragma unroll
+  for (int k = 0; k < C::UPD; ++k) {
+    const int idx = tid + 64 * k;
+    const int l = idx < nE * NP ? idx + (idx / NP) * (NPP - NP) : 0;
+    const V4<T> R = sR[l];
+    V4<T> q;
+    if constexpr (C::PREFETCH)
+      q = rprev[k];
+    else
+      q = bload<T>(bres_in, idx);
+    const V4<T> r{ca * q.p + dt * R.p, ca * q.uz + dt * R.uz, ca * q.ux + dt * R.ux, ca * q.uy + dt * R.uy};
+    bstore<T>(bres, idx, r);
+    if (wu) {
+      const V4<T> u = sU[l];
+      bstore<T>(bout, idx, V4<T>{u.p + cb * r.p, u.uz + cb * r.uz, u.ux + cb * r.ux, u.uy + cb * r.uy});
+    }
+  }
+}
+
+template <int N, typename T>
+hipError_t launch_wedge_stage_t(const StageLaunch& a, hipStream_t st) {
+  using C = Cfg<N, T>;
+  const int64_t nchunks = (a.Kw + C::EPB - 1) / C::EPB;
+  if (nchunks <= 0) return hipSuccess;
+  if (a.nmort > 0)
+    hipLaunchKernelGGL((wedge_stage<N, T, 2>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
+  else if (a.Kt > 0)
+    hipLaunchKernelGGL((wedge_stage<N, T, 1>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
+  else
+    hipLaunchKernelGGL((wedge_stage<N, T, 0>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_wedge_stage(int N, int bits, const StageLaunch& a, hipStream_t st) {
+  hipError_t err = hipErrorInvalidValue;
+#define WDG_STAGE(n, T) err = launch_wedge_stage_t<n, T>(a, st)
+  WDG_DISPATCH_N(N, bits, WDG_STAGE)
+#undef WDG_STAGE
+  return err;
+}
+
+}  // namespace wdg
