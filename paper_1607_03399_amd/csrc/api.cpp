@@ -485,8 +485,8 @@ std::vector<double> mortar_tables(const RefOps& R, int bits) {
   for (int i = 0; i < NT; ++i) MtriInv[i * NT + i] = 1.0;
   wdg::solve_dense(NT, NT, R.Mtri, MtriInv);
   for (int e = 0; e < 3; ++e)
-    for (int i = 0; i < NT; ++i)
-      for (int a = 0; a < NX; ++a) {
+    for (int a = 0; a < NX; ++a)
+      for (int i = 0; i < NT; ++i) {
         double acc = 0.0;
         for (int q = 0; q < Nq; ++q) acc += MtriInv[i * NT + R.edge_nodes[e][q]] * E[a * Nq + q];
         out.push_back(acc);

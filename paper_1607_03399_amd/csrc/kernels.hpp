@@ -99,7 +99,7 @@ hipError_t launch_tet_stage(int N, int bits, const StageLaunch& a, hipStream_t s
 // state precision; the host fills them in this order: xg, wg (mort_nx Gauss points along
 // the edge), tg, wt (Nq Gauss points in t), tgll (Nq GLL nodes), 1/(tgll_m - tgll_mm)
 // (Nq x Nq, diagonal unused), Minv1 (Nq x Nq), Eedge (mort_nx x Nq: GLL Lagrange basis
-// at xg), A (3 x Np_tri x mort_nx: (M^tri)^-1 restricted to the edge nodes times Eedge),
+// at xg), A (3 x mort_nx x Np_tri: (M^tri)^-1 restricted to the edge nodes times Eedge),
 // Vinv (Np_tri x Np_tri: triangle Lagrange values -> Legendre-product modes P_a(r) P_b(s),
 // a+b <= N, a outer), P = (M^tri)^-1 Vinv^T (Np_tri x Np_tri).
 int mortar_table_size(int N, int bits);
