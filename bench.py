@@ -10,7 +10,9 @@ five-stage low-storage Runge-Kutta scheme.  Inputs are synthetic (seeded).
 Prints one JSON line: DG node-updates per second per Runge-Kutta stage
 (elements x nodes x 5 x steps / wall time), the HBM-roofline fraction of the
 stage kernel (algorithmic bytes / average kernel time from HIP events on the
-solver stream) and the FP64 CPU oracle timed on a bounded sample.
+solver stream), the adjoint leg (receiver-misfit gradient on 524288 wedges:
+gradient time over forward time) and the FP64 CPU oracle timed on a bounded
+sample.
 """
 from __future__ import annotations
 
@@ -114,6 +116,70 @@ def cpu_baseline(mesh, N: int, dt: float, seconds: float, sample: int):
     }
 
 
+def adjoint_benchmark(steps: int, every: int):
+    """Receiver-misfit gradient on 128 x 128 x 16 = 524288 wedges, N = 3,
+    FP32: 16 seeded receivers record p for ``steps`` steps; the data come from
+    a wave speed with a seeded 10 % Gaussian anomaly; the gradient with respect
+    to every element's c and rho by the discrete adjoint with checkpoints every
+    ``every`` steps.  Times the forward solve and the gradient call (which
+    recomputes its forward states itself) on the same GPU."""
+    from paper_1607_03399_amd import inputs
+    from paper_1607_03399_amd import wdg
+
+    mesh = inputs.cfg5_mesh()
+    rec, src, c_true = inputs.adjoint_problem(mesh)
+    s = wdg.Solver(3, 32, device=0)
+    s.set_mesh(mesh.verts, mesh.wedges)
+    s.set_boundary("rigid")
+    s.set_flux("upwind")
+    s.add_ricker_source(*src)
+    s.set_receivers(rec)
+    s.set_material(mesh.c, mesh.rho)
+    dt = s.stable_dt(0.5)
+    zeros = np.zeros((mesh.K, 4, s.Np))
+    # data: the solve with the anomaly (setup, untimed)
+    s.set_material(c_true, mesh.rho)
+    s.set_fields(zeros)
+    s.time = 0.0
+    s.step(steps, dt)
+    data = s.read_receivers()
+    s.set_material(mesh.c, mesh.rho)
+    s.set_fields(zeros)
+    s.time = 0.0
+    s.step(2, dt)  # warm up the kernels
+    s.synchronize()
+    s.set_fields(zeros)
+    s.time = 0.0
+    t0 = time.perf_counter()
+    s.step(steps, dt)
+    s.synchronize()
+    fwd = time.perf_counter() - t0
+    traces = s.read_receivers()
+    w = traces - data
+    s.set_fields(zeros)
+    s.time = 0.0
+    t0 = time.perf_counter()
+    gc, gr = s.adjoint_gradient(steps, dt, w, every)
+    adj = time.perf_counter() - t0
+    s.close()
+    if not (np.all(np.isfinite(gc)) and np.all(np.isfinite(gr))):
+        raise RuntimeError("non-finite gradient")
+    return {
+        "workload": "cfg5 adjoint: 128x128x16 = 524288 wedges, N=3, FP32, Ricker source (f0=60) at the centre, "
+                    f"16 seeded receivers 0.01-0.04 from it, {steps} steps, misfit against data from a seeded "
+                    "10% Gaussian anomaly in c, "
+                    f"gradient w.r.t. per-element c and rho, checkpoints every {every} steps",
+        "steps": steps,
+        "checkpoint_every": every,
+        "forward_s": fwd,
+        "adjoint_s": adj,
+        "adjoint_fwd_ratio": adj / fwd,
+        "misfit": 0.5 * float(np.sum(w ** 2)),
+        "grad_c_norm": float(np.linalg.norm(gc)),
+        "grad_rho_norm": float(np.linalg.norm(gr)),
+    }
+
+
 def copy_bandwidth(nbytes: int = 512 << 20, reps: int = 10) -> float:
     """Device-to-device copy of nbytes (read + write) timed with events."""
     import torch
@@ -147,6 +213,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint leg (cfg2 runs the cfg5 receiver-misfit gradient after the forward bench)")
+    ap.add_argument("--adjoint-steps", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain 512 MiB device copy first (HBM reference for counters and roofline)")
     args = ap.parse_args()
@@ -269,6 +338,8 @@ def main():
         },
     }
     s.close()
+    if args.config == "cfg2" and bits == 32 and not args.no_adjoint:
+        out["adjoint"] = adjoint_benchmark(args.adjoint_steps, 50)
     if not args.no_cpu_baseline and mesh is not None:
         out["cpu_baseline"] = cpu_baseline(mesh, N, dt, args.cpu_seconds, args.cpu_sample)
     print(json.dumps(out), flush=True)

@@ -49,7 +49,8 @@ enum {
   WDG_ERR_OUTSIDE = -7,       /* source or receiver point not inside any element */
   WDG_ERR_HIP = -8,           /* HIP runtime error (includes: no device) */
   WDG_ERR_OOM = -9,           /* device allocation failed */
-  WDG_ERR_UNSTABLE = -10      /* non-finite values detected */
+  WDG_ERR_UNSTABLE = -10,     /* non-finite values detected */
+  WDG_ERR_UNSUPPORTED = -11   /* not available for this mesh or option */
 };
 
 enum { WDG_BC_DIRICHLET_P0 = 0, WDG_BC_RIGID = 1 };
@@ -152,6 +153,29 @@ int wdg_eval_rhs(wdg_ctx* ctx, double t, const double* in4, double* out4);
 /* E = 1/2 sum_k (p^T M^k p / kappa + rho u^T M^k u) (integrand of eq. estab),
  * M^k = M^{tri,k} (x) M^1D (Sec. 4.2), evaluated on the device. */
 int wdg_energy(wdg_ctx* ctx, double* E);
+
+/* Gradient of a weighted sum of receiver traces with respect to the
+ * per-element wave speed and density, by the discrete adjoint of the whole
+ * time-stepped solve.  The forward solve is the one wdg_step runs: nsteps
+ * steps of size dt from the current fields and time, with the current sources
+ * and material; trace y[n][r] is the pressure at receiver r after step n.
+ * With weights w (host, nsteps x nrec, row n = step n) the call returns
+ *   grad_c[k] = d/dc_k sum_{n,r} w[n][r] y[n][r],  grad_rho[k] likewise
+ * (host arrays of num_elements values); for the misfit
+ * 1/2 sum (y - d)^2 pass w = y - d.  The derivative is that of the discrete
+ * map (the low-storage Runge-Kutta stages included): the adjoint runs the
+ * stage kernels on T E^-1 of the adjoint state, where E is the energy matrix
+ * of eq. estab (diag(M^k/kappa, rho M^k)) and T flips the velocity, because
+ * the operator is E-skew up to its E-symmetric penalty part (Sec. 2).
+ * Forward states are kept every checkpoint_every steps and recomputed
+ * segment by segment on the device; device memory used: about
+ * (nsteps/checkpoint_every + checkpoint_every + 15) states of
+ * num_nodes x 4 values.  Fields, time and receiver history are unchanged on
+ * return.  Meshes of wedges with the exact mass only (tetrahedra, mortars or
+ * WDG_MASS_LUMPED: WDG_ERR_UNSUPPORTED); needs receivers (else
+ * WDG_ERR_STATE); WDG_ERR_OOM if the buffers do not fit. */
+int wdg_adjoint_gradient(wdg_ctx* ctx, int64_t nsteps, double dt, const double* weights, int64_t checkpoint_every,
+                         double* grad_c, double* grad_rho);
 
 /* Per-launch timing of the stage kernels with HIP events on the context stream:
  * enable = 1 starts collecting (and clears), 0 stops.  read returns the summed

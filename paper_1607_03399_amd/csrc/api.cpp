@@ -104,6 +104,7 @@ struct wdg_ctx {
   void* dMortF = nullptr;
   std::vector<Source> src;
   int64_t nrec = 0;
+  std::vector<double> rec_xyz;  // nrec x 3
   int64_t* dRecBase = nullptr;
   int* dRecNN = nullptr;
   double* dRecRows = nullptr;
@@ -365,7 +366,7 @@ int upload_sources(wdg_ctx* ctx) {
 
 // one Runge-Kutta stage (or, with a = 0, dt = 1, no U write, a plain RHS)
 int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a, double b, double dt, double tstage,
-                 int flags) {
+                 int flags, double g = 1.0, void* rout = nullptr, bool sources = true) {
   wdg::StageLaunch L{};
   L.Uin = Uin;
   L.Uout = Uout;
@@ -383,7 +384,7 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.mortB = ctx->dMortB;
   L.mortF = ctx->dMortF;
   L.nmort = int64_t(ctx->mort.size());
-  L.nsrc = int(ctx->src.size());
+  L.nsrc = sources ? int(ctx->src.size()) : 0;
   for (int s = 0; s < L.nsrc; ++s) {
     L.src_elem[s] = int(ctx->src[s].elem);
     L.src_amp[s] = ctx->src[s].value(tstage);
@@ -391,6 +392,8 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.a = a;
   L.b = b;
   L.dt = dt;
+  L.g = g;
+  L.rout = rout;
   L.Kw = ctx->Kw;
   L.Kt = ctx->Kt;
   L.flags = flags | (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
@@ -1241,6 +1244,7 @@ int wdg_set_receivers(wdg_ctx* ctx, int64_t n, const double* xyz) {
     std::copy(b.begin(), b.end(), rows.begin() + q * R.NP);
   }
   ctx->rec_steps = 0;
+  ctx->rec_xyz.assign(xyz, xyz + 3 * n);
   if (ctx->host_only) {
     ctx->nrec = n;
     return WDG_OK;
@@ -1339,6 +1343,180 @@ int wdg_step(wdg_ctx* ctx, int64_t nsteps, double dt) {
     }
   }
   ctx->time = t0 + double(nsteps) * dt;
+  return WDG_OK;
+}
+
+namespace {
+
+// device buffers of one call, freed on every return path
+struct DeviceScratch {
+  std::vector<void*> p;
+  hipError_t alloc(size_t bytes, void** out) {
+    *out = nullptr;
+    const hipError_t e = hipMalloc(out, bytes ? bytes : 1);
+    if (e == hipSuccess) p.push_back(*out);
+    return e;
+  }
+  ~DeviceScratch() {
+    for (void* q : p) (void)hipFree(q);
+  }
+};
+
+// reference triangle mass, then the edge masses int l_q l_q' (1 -+ xi)/2 of the GLL basis
+std::vector<double> gradient_tables(const RefOps& R) {
+  std::vector<double> out(R.Mtri);
+  std::vector<double> x, w, l(R.Nq);
+  wdg::gauss_legendre(R.Nq + 1, x, w);
+  std::vector<double> Ma(R.Nq * R.Nq, 0.0), Mb(R.Nq * R.Nq, 0.0);
+  for (size_t g = 0; g < x.size(); ++g) {
+    R.line_basis(x[g], l.data());
+    for (int q = 0; q < R.Nq; ++q)
+      for (int qq = 0; qq < R.Nq; ++qq) {
+        Ma[q * R.Nq + qq] += w[g] * l[q] * l[qq] * 0.5 * (1.0 - x[g]);
+        Mb[q * R.Nq + qq] += w[g] * l[q] * l[qq] * 0.5 * (1.0 + x[g]);
+      }
+  }
+  out.insert(out.end(), Ma.begin(), Ma.end());
+  out.insert(out.end(), Mb.begin(), Mb.end());
+  return out;
+}
+
+}  // namespace
+
+int wdg_adjoint_gradient(wdg_ctx* ctx, int64_t nsteps, double dt, const double* weights, int64_t checkpoint_every,
+                         double* grad_c, double* grad_rho) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (ctx->state < kFields) return fail(ctx, WDG_ERR_STATE, "adjoint before set_fields");
+  if (nsteps < 1 || !(dt > 0) || !std::isfinite(dt) || checkpoint_every < 1 || !weights || !grad_c || !grad_rho)
+    return fail(ctx, WDG_ERR_ARG, "bad adjoint arguments");
+  if (ctx->Kt > 0 || !ctx->mort.empty()) return fail(ctx, WDG_ERR_UNSUPPORTED, "adjoint: meshes of wedges only");
+  if (ctx->mass != WDG_MASS_EXACT) return fail(ctx, WDG_ERR_UNSUPPORTED, "adjoint: exact mass only");
+  if (ctx->nrec == 0) return fail(ctx, WDG_ERR_STATE, "adjoint without receivers");
+  if (!finite_all(weights, nsteps * ctx->nrec)) return fail(ctx, WDG_ERR_ARG, "non-finite adjoint weights");
+  HIPCHK(hipSetDevice(ctx->device));
+  const int N = ctx->N, NP = ctx->NP(), nrec = int(ctx->nrec);
+  const int64_t K = ctx->Kw;
+  const size_t SB = size_t(ctx->nodes()) * 4 * ctx->tsize();
+  const int64_t C = std::min(checkpoint_every, nsteps);
+  const int64_t ncp = (nsteps + C - 1) / C;
+  const double t0 = ctx->time;
+  const int mflags = (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
+                     (ctx->flux == WDG_FLUX_CENTRAL ? wdg::kCentral : 0);
+
+  // receivers become point sources of the adjoint: kappa (M^k)^-1 l(x_r)
+  std::vector<int64_t> rbase(nrec);
+  std::vector<double> rvec(size_t(nrec) * NP);
+  for (int r = 0; r < nrec; ++r) {
+    double rr, ss, tt;
+    const int64_t k = locate(ctx, &ctx->rec_xyz[3 * r], rr, ss, tt);
+    if (k < 0 || k >= ctx->Kw) return fail(ctx, WDG_ERR_OUTSIDE, "receiver outside the wedges");
+    rbase[r] = ctx->node_base(k);
+    const std::vector<double> v = mass_inverse_times(ctx, k, ctx->rho[k] * ctx->c[k] * ctx->c[k], rr, ss, tt);
+    std::copy(v.begin(), v.end(), rvec.begin() + size_t(r) * NP);
+  }
+  const std::vector<double> tabs = gradient_tables(*ctx->ref);
+
+  DeviceScratch ds;
+  void *cp, *seg, *stg, *tmp, *adj, *pg, *pw, *pv, *pb, *pt;
+  HIPCHK(ds.alloc(SB * size_t(ncp), &cp));  // checkpoints: the state at the start of every segment
+  HIPCHK(ds.alloc(SB * size_t(C), &seg));   // states at the start of every step of one segment
+  HIPCHK(ds.alloc(SB * 9, &stg));           // stage inputs 1..4, stage right-hand sides 0..4
+  HIPCHK(ds.alloc(SB * 3, &tmp));           // forward ping-pong pair and residual
+  HIPCHK(ds.alloc(SB * 3, &adj));           // adjoint state and the ping-pong pair of stage vectors
+  HIPCHK(ds.alloc(size_t(K) * (wdg::kGradStride + 2) * sizeof(double), &pg));
+  HIPCHK(ds.alloc(size_t(nsteps) * nrec * sizeof(double), &pw));
+  HIPCHK(ds.alloc(rvec.size() * sizeof(double), &pv));
+  HIPCHK(ds.alloc(rbase.size() * sizeof(int64_t), &pb));
+  HIPCHK(ds.alloc(tabs.size() * sizeof(double), &pt));
+  auto at = [SB](void* base, int64_t i) -> void* { return static_cast<unsigned char*>(base) + size_t(i) * SB; };
+  double* gacc = static_cast<double*>(pg);
+  double* gout = gacc + K * wdg::kGradStride;
+  const double* dw = static_cast<const double*>(pw);
+  hipStream_t st = ctx->stream;
+  HIPCHK(hipMemcpyAsync(pw, weights, size_t(nsteps) * nrec * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pv, rvec.data(), rvec.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pb, rbase.data(), rbase.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pt, tabs.data(), tabs.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(gacc, 0, size_t(K) * wdg::kGradStride * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(adj, 0, SB * 3, st));
+  HIPCHK(hipMemcpyAsync(cp, ctx->dU[ctx->cur], SB, hipMemcpyDeviceToDevice, st));
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  struct Restore {
+    wdg_ctx* c;
+    bool t;
+    ~Restore() { c->timing = t; }
+  } restore{ctx, timing};
+
+  void* Si[5] = {nullptr, at(stg, 0), at(stg, 1), at(stg, 2), at(stg, 3)};
+  void* Ri[5] = {at(stg, 4), at(stg, 5), at(stg, 6), at(stg, 7), at(stg, 8)};
+  // one forward step X -> Y (Y may be null: not needed); with keep, the stage
+  // inputs go to Si[1..4] and the stage right-hand sides to Ri[0..4]
+  auto forward_step = [&](const void* X, void* Y, double tn, bool keep) -> int {
+    const void* in = X;
+    for (int s = 0; s < 5; ++s) {
+      void* out = keep ? (s < 4 ? Si[s + 1] : nullptr) : (s == 4 ? Y : at(tmp, s & 1));
+      int flags = (s == 0 ? 0 : wdg::kReadRes) | (out ? wdg::kWriteU : 0) | (keep ? wdg::kWriteR : 0);
+      const int rc = launch_stage(ctx, in, out, at(tmp, 2), kRkA[s], kRkB[s], dt, tn + kRkC[s] * dt, flags, 1.0,
+                                  keep ? Ri[s] : nullptr, true);
+      if (rc) return rc;
+      in = out;
+    }
+    return WDG_OK;
+  };
+  // the step-start states of segment g into seg; the state after it into next (if not null)
+  auto run_segment = [&](int64_t g, void* next) -> int {
+    const int64_t n0 = g * C, n1 = std::min(n0 + C, nsteps);
+    HIPCHK(hipMemcpyAsync(seg, at(cp, g), SB, hipMemcpyDeviceToDevice, st));
+    for (int64_t n = n0; n < n1; ++n) {
+      void* Y = n + 1 < n1 ? at(seg, n + 1 - n0) : next;
+      if (!Y) break;
+      const int rc = forward_step(at(seg, n - n0), Y, t0 + double(n) * dt, false);
+      if (rc) return rc;
+    }
+    return WDG_OK;
+  };
+
+  // forward sweep: checkpoints (the last segment's states stay in seg)
+  for (int64_t g = 0; g < ncp; ++g) {
+    const int rc = run_segment(g, g + 1 < ncp ? at(cp, g + 1) : nullptr);
+    if (rc) return rc;
+  }
+  // reverse sweep
+  void* Ua = at(adj, 0);
+  int sc = 1;
+  HIPCHK(wdg::launch_inject(ctx->bits, NP, nrec, static_cast<const int64_t*>(pb), static_cast<const double*>(pv),
+                            dw + (nsteps - 1) * nrec, kRkB[4], Ua, at(adj, sc), st));
+  for (int64_t g = ncp - 1; g >= 0; --g) {
+    if (g != ncp - 1) {
+      const int rc = run_segment(g, nullptr);
+      if (rc) return rc;
+    }
+    const int64_t n0 = g * C, n1 = std::min(n0 + C, nsteps);
+    for (int64_t n = n1 - 1; n >= n0; --n) {
+      void* Un = at(seg, n - n0);
+      int rc = forward_step(Un, nullptr, t0 + double(n) * dt, true);
+      if (rc) return rc;
+      for (int s = 4; s >= 0; --s) {
+        void* sig = at(adj, sc);
+        HIPCHK(wdg::launch_grad_stage(N, ctx->bits, K, sig, s == 0 ? Un : Si[s], Ri[s], ctx->dGeo, ctx->dConn,
+                                      ctx->dAux, ctx->dMv, ctx->dM1, static_cast<const double*>(pt), dt, mflags,
+                                      gacc, st));
+        // U~ += dt A sig;  sig <- a_s sig + b_{s-1} U~  (b of the previous step's last stage at s = 0)
+        rc = launch_stage(ctx, sig, at(adj, 3 - sc), Ua, 1.0, s > 0 ? kRkB[s - 1] : kRkB[4], dt, 0.0,
+                          wdg::kReadRes | wdg::kWriteU, kRkA[s], nullptr, false);
+        if (rc) return rc;
+        sc = 3 - sc;
+      }
+      if (n > 0)
+        HIPCHK(wdg::launch_inject(ctx->bits, NP, nrec, static_cast<const int64_t*>(pb),
+                                  static_cast<const double*>(pv), dw + (n - 1) * nrec, kRkB[4], Ua, at(adj, sc), st));
+    }
+  }
+  HIPCHK(wdg::launch_grad_combine(ctx->bits, K, gacc, ctx->dGeo, ctx->dConn, ctx->dAux, mflags, gout, gout + K, st));
+  HIPCHK(hipMemcpyAsync(grad_c, gout, size_t(K) * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(grad_rho, gout + K, size_t(K) * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
   return WDG_OK;
 }
 

@@ -54,6 +54,7 @@ enum StageFlags : int {
   kDirichlet = 4,  // else rigid wall
   kCentral = 8,    // else upwind flux
   kLumped = 16,    // Gauss-Lobatto mass in t: (M^1D)^-1 e_{0,N} becomes e_{0,N} / w_{0,N}
+  kWriteR = 32,    // also store the stage right-hand side (sources included) to rout (wedges)
 };
 
 // One stage over the whole mesh.  State buffers hold wedges first (Kw x Np_wedge
@@ -78,7 +79,9 @@ struct StageLaunch {
   int src_elem[kMaxSources];
   double src_amp[kMaxSources];
   int nsrc;
-  double a, b, dt;
+  // res' = a res + dt rhs;  U_out = g U_in + b res'  (the forward stages use g = 1)
+  double a, b, dt, g;
+  void* rout;  // kWriteR: the right-hand side, same layout as res
   int64_t Kw, Kt;
   int flags;
 };
@@ -103,6 +106,22 @@ hipError_t launch_tet_stage(int N, int bits, const StageLaunch& a, hipStream_t s
 // Vinv (Np_tri x Np_tri: triangle Lagrange values -> Legendre-product modes P_a(r) P_b(s),
 // a+b <= N, a outer), P = (M^tri)^-1 Vinv^T (Np_tri x Np_tri).
 int mortar_table_size(int N, int bits);
+// Adjoint gradient (wedge meshes).  Per reverse stage: accumulate into gacc
+// (kGradStride FP64 values per wedge) dt times the mass terms sig^T M R of the
+// pressure and of the velocity and the face integrals 1/2 int sig_p [p],
+// 1/2 int sig_un [u_n] of the forward stage input Us; tab holds the reference
+// triangle mass and the two edge masses (see launch_grad_stage's caller).
+constexpr int kGradStride = 12;
+hipError_t launch_grad_stage(int N, int bits, int64_t K, const void* sig, const void* Us, const void* Rs,
+                             const void* geo, const int* conn, const double* aux, const double* Mv, const double* M1,
+                             const double* tab, double dt, int flags, double* gacc, hipStream_t st);
+// Gradient with respect to c and rho from the accumulated terms and the penalty derivatives.
+hipError_t launch_grad_combine(int bits, int64_t K, const double* gacc, const void* geo, const int* conn,
+                               const double* aux, int flags, double* gc, double* grho, hipStream_t st);
+// Receiver injection: for receiver r (first node base[r], vector vec[r] of NP values),
+// U += w[r] vec[r] and S += sb w[r] vec[r] on the pressure.
+hipError_t launch_inject(int bits, int NP, int nrec, const int64_t* base, const double* vec, const double* w,
+                         double sb, void* U, void* S, hipStream_t st);
 // Pressure at receivers: receiver r reads nn[r] nodes from 4-vector index base[r] with row stride ld.
 hipError_t launch_receivers(int bits, int ld, int nrec, const void* U, const int64_t* base, const int* nn,
                             const double* rows, double* out, hipStream_t st);

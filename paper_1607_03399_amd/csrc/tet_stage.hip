@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(256) tet_stage(StageLaunch A) {
       if (A.src_elem[s] == A.Kw + e) Rp += T(A.src_amp[s]) * static_cast<const T*>(A.srcvec)[s * NPW + i];
 
     const int64_t gi = tb + e * NP + i;
-    const T ca = T(A.a), cb = T(A.b), dtt = T(A.dt);
+    const T ca = T(A.a), cb = T(A.b), dtt = T(A.dt), cg = T(A.g);
     V4<T> r{dtt * Rp, dtt * Rz, dtt * Rx, dtt * Ry};
     if (rd) {
       const V4<T> q = res[gi];
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(256) tet_stage(StageLaunch A) {
     res[gi] = r;
     if (wu) {
       const V4<T> u = sU[le * NP + i];
-      Uout[gi] = V4<T>{u.p + cb * r.p, u.uz + cb * r.uz, u.ux + cb * r.ux, u.uy + cb * r.uy};
+      Uout[gi] = V4<T>{cg * u.p + cb * r.p, cg * u.uz + cb * r.uz, cg * u.ux + cb * r.ux, cg * u.uy + cb * r.uy};
     }
   }
 }

@@ -455,8 +455,10 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
   __syncthreads();
 
   // low-storage Runge-Kutta update, coalesced over the chunk
-  const T ca = T(A.a), cb = T(A.b), dt = T(A.dt);
+  const T ca = T(A.a), cb = T(A.b), dt = T(A.dt), cg = T(A.g);
+  const bool wr = (A.flags & kWriteR) != 0;
   const auto bout = chunk_rsrc(static_cast<V4<T>*>(A.Uout) + e0 * NP, int64_t(nE) * NP * V4B);
+  const auto brout = chunk_rsrc(static_cast<V4<T>*>(A.rout) + e0 * NP, wr ? int64_t(nE) * NP * V4B : 0);
 #pragma unroll
   for (int k = 0; k < C::UPD; ++k) {
     const int idx = tid + 64 * k;
@@ -469,9 +471,11 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
       q = bload<T>(bres_in, idx);
     const V4<T> r{ca * q.p + dt * R.p, ca * q.uz + dt * R.uz, ca * q.ux + dt * R.ux, ca * q.uy + dt * R.uy};
     bstore<T>(bres, idx, r);
+    if (wr) bstore<T>(brout, idx, R);
     if (wu) {
       const V4<T> u = sU[l];
-      bstore<T>(bout, idx, V4<T>{u.p + cb * r.p, u.uz + cb * r.uz, u.ux + cb * r.ux, u.uy + cb * r.uy});
+      bstore<T>(bout, idx,
+                V4<T>{cg * u.p + cb * r.p, cg * u.uz + cb * r.uz, cg * u.ux + cb * r.ux, cg * u.uy + cb * r.uy});
     }
   }
 }

@@ -186,6 +186,26 @@ def cfg5_mesh() -> WedgeMesh:
     return layered_config(128, 16, 0.3, 0, "cfg5")
 
 
+def adjoint_problem(mesh: WedgeMesh, nrec: int = 16, seed: int = 0, amplitude: float = 0.1, width: float = 0.1):
+    """Inputs of the receiver-misfit gradient workload on ``mesh`` (a window of
+    a few hundredths of a second at the time steps of a 128 x 128 x 16 mesh):
+    a Ricker source at the centre (f0 = 60, t0 = 0.02, so that it fires inside
+    the window), ``nrec`` seeded receivers 0.01 to 0.04 from it, and the wave
+    speed c (1 + amplitude exp(-|x_e - x_a|^2 / width^2)) per element (x_e:
+    element centroid, x_a: a seeded centre within 0.03 of the source) that
+    synthesises the data.  Returns (receivers (nrec, 3), source
+    (xyz, f0, t0, amp), c_true)."""
+    rng = np.random.default_rng(seed)
+    xs = np.array([0.5, 0.5, 0.5])
+    d = rng.standard_normal((nrec, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rec = xs + d * rng.uniform(0.01, 0.04, (nrec, 1))
+    xa = xs + rng.uniform(-0.03, 0.03, 3)
+    cent = mesh.verts[mesh.wedges].mean(axis=1)
+    bump = np.exp(-np.sum((cent - xa) ** 2, axis=1) / width ** 2)
+    return rec, (xs, 60.0, 0.02, 1.0), mesh.c * (1.0 + amplitude * bump)
+
+
 def cfg3_hybrid_mesh(tet_layers: int = 5):
     """32x32 base (2048 triangles) x 24 layers with random smooth interfaces;
     the lowest ``tet_layers`` layers split into tetrahedra (3 per prism):

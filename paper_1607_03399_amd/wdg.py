@@ -18,7 +18,7 @@ OK = 0
 ERRORS = {
     -1: "WDG_ERR_ARG", -2: "WDG_ERR_STATE", -3: "WDG_ERR_NOT_VERTICAL", -4: "WDG_ERR_JACOBIAN",
     -5: "WDG_ERR_ORIENTATION", -6: "WDG_ERR_NONCONFORMING", -7: "WDG_ERR_OUTSIDE", -8: "WDG_ERR_HIP",
-    -9: "WDG_ERR_OOM", -10: "WDG_ERR_UNSTABLE",
+    -9: "WDG_ERR_OOM", -10: "WDG_ERR_UNSTABLE", -11: "WDG_ERR_UNSUPPORTED",
 }
 BC = {"dirichlet": 0, "rigid": 1}
 FLUX = {"upwind": 0, "central": 1}
@@ -75,6 +75,7 @@ def load_library() -> C.CDLL:
         "wdg_synchronize": (C.c_int, [vp]),
         "wdg_eval_rhs": (C.c_int, [vp, C.c_double, _dp, _dp]),
         "wdg_energy": (C.c_int, [vp, _dp]),
+        "wdg_adjoint_gradient": (C.c_int, [vp, C.c_int64, C.c_double, _dp, C.c_int64, _dp, _dp]),
         "wdg_get_element_data": (C.c_int, [vp, _dp, _dp]),
         "wdg_kernel_timing": (C.c_int, [vp, C.c_int]),
         "wdg_read_kernel_timing": (C.c_int, [vp, _dp, _i64p]),
@@ -285,6 +286,19 @@ class Solver:
         E = C.c_double()
         self._check(self._lib.wdg_energy(self._h, C.byref(E)), "energy")
         return E.value
+
+    def adjoint_gradient(self, nsteps: int, dt: float, weights, checkpoint_every: int = 50):
+        """(dF/dc, dF/drho) per element of F = sum_{n,r} weights[n, r] p_r(after step n)
+        for the solve that ``step(nsteps, dt)`` would run from the current state
+        (discrete adjoint; see wdg_adjoint_gradient).  The state is unchanged."""
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        if w.shape != (int(nsteps), getattr(self, "_nrec", 0)):
+            raise ValueError(f"weights must be (nsteps, nrec) = ({nsteps}, {getattr(self, '_nrec', 0)})")
+        gc = np.zeros(self.K)
+        gr = np.zeros(self.K)
+        self._check(self._lib.wdg_adjoint_gradient(self._h, int(nsteps), float(dt), _ptr(w), int(checkpoint_every),
+                                                   _ptr(gc), _ptr(gr)), "adjoint_gradient")
+        return gc, gr
 
     def kernel_timing(self, enable: bool):
         self._check(self._lib.wdg_kernel_timing(self._h, int(bool(enable))), "kernel_timing")

@@ -283,3 +283,18 @@ def test_column_split_mesh_host_side():
     # one triangle of a split quadrilateral missing: not conforming
     _expect("WDG_ERR_NONCONFORMING", s.set_mesh, v, w, t[1:])
     s.close()
+
+
+def test_adjoint_gradient_argument_checks():
+    """Order and argument checks of wdg_adjoint_gradient (no device work)."""
+    m = inputs.layered_config(2, 2, 0.3, seed=4)
+    s = wdg.Solver(2, 64, device=-1)
+    s.set_mesh(m.verts, m.wedges)
+    s.set_material(m.c, m.rho)
+    s.set_receivers([[0.5, 0.5, 0.5]])
+    with pytest.raises(wdg.WdgError) as e:  # a host-only context holds no fields
+        s.adjoint_gradient(3, 1e-3, np.zeros((3, 1)))
+    assert e.value.name == "WDG_ERR_STATE"
+    with pytest.raises(ValueError):
+        s.adjoint_gradient(3, 1e-3, np.zeros((2, 1)))
+    s.close()

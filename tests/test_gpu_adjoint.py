@@ -1,0 +1,173 @@
+"""Discrete adjoint of the time-stepped solve (through the C ABI and the
+torch.autograd.Function) against the FP64 oracle's exact discrete derivative
+(complex step of the whole solve) and against central finite differences of
+the device's own forward solve."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import adjoint, dg
+from paper_1607_03399_amd import inputs
+from paper_1607_03399_amd import wdg
+
+pytestmark = pytest.mark.gpu
+
+# FP64: both sides compute the same derivative of the same discrete map, so
+# they differ by rounding of long sums only.  FP32: the forward and adjoint
+# states carry single-precision rounding over every stage.
+TOL = {64: 1e-12, 32: 1e-5}
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def _problem(nx=2, layers=2, seed=4, N=2, width=0.25):
+    m = inputs.layered_config(nx, layers, 0.3, seed=seed)
+    x = dg.node_coords(dg.Mesh(m.verts, m.wedges, m.c, m.rho, "rigid", "upwind"), N)
+    U0 = np.zeros((m.K, 4, x.shape[1]))
+    U0[:, 0] = inputs.gaussian_pulse(x, width=width)
+    src = ([0.3, 0.6, 0.4], 4.0, 0.15, 1.0)
+    rec = np.array([[0.7, 0.3, 0.8], [0.2, 0.2, 0.3], [0.55, 0.45, 0.5]])
+    return m, N, U0, src, rec
+
+
+def _solver(m, N, bits, bc, flux, src, rec, c=None, rho=None):
+    s = wdg.Solver(N, bits, device=0)
+    s.set_mesh(m.verts, m.wedges)
+    s.set_material(m.c if c is None else c, m.rho if rho is None else rho)
+    s.set_boundary(bc)
+    s.set_flux(flux)
+    s.add_ricker_source(*src)
+    s.set_receivers(rec)
+    return s
+
+
+@pytest.mark.parametrize("bits", [64, 32])
+@pytest.mark.parametrize("flux,bc", [("upwind", "rigid"), ("central", "rigid"), ("upwind", "dirichlet")])
+def test_gradient_matches_oracle(flux, bc, bits):
+    m, N, U0, src, rec = _problem()
+    om = dg.Mesh(m.verts, m.wedges, m.c, m.rho, bc, flux)
+    dt = dg.stable_dt(om, N, 0.5)
+    nsteps = 12
+    base = adjoint.solve_traces(om, N, U0, dt, nsteps, src, rec)
+    data = 0.9 * base + 0.01
+    elems = np.random.default_rng(7).choice(m.K, 8, replace=False)
+    _say("adjoint vs oracle", flux, bc, bits, "elements", elems)
+    J, gc_ref, gr_ref = adjoint.gradient_complex_step(om, N, U0, dt, nsteps, src, rec, data, elems=elems)
+    s = _solver(m, N, bits, bc, flux, src, rec)
+    s.set_fields(U0)
+    gc, gr = s.adjoint_gradient(nsteps, dt, base - data, checkpoint_every=5)
+    s.close()
+    ec, er = _rel(gc[elems], gc_ref), _rel(gr[elems], gr_ref)
+    _say("   rel err c", ec, "rho", er)
+    assert ec <= TOL[bits] and er <= TOL[bits]
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    m, N, U0, src, rec = _problem()
+    s = _solver(m, N, 64, "rigid", "upwind", src, rec)
+    s.set_fields(U0)
+    dt = s.stable_dt(0.5)
+    w = np.random.default_rng(3).standard_normal((13, len(rec)))
+    out = [s.adjoint_gradient(13, dt, w, checkpoint_every=ce) for ce in (1, 4, 13, 50)]
+    U_after = s.get_fields()
+    s.close()
+    for gc, gr in out[1:]:
+        assert np.array_equal(gc, out[0][0]) and np.array_equal(gr, out[0][1])
+    assert np.array_equal(U_after[:, :, :U0.shape[2]], U0)  # the state is unchanged
+
+
+def test_gradient_matches_central_differences():
+    """Device-only check on a larger mesh (N=3): the adjoint gradient of the
+    misfit against central differences of the device's own forward solve."""
+    m, N, U0, src, rec = _problem(nx=4, layers=4, seed=11, N=3, width=0.2)
+    nsteps = 30
+
+    def misfit(c, rho, data=None):
+        s = _solver(m, N, 64, "rigid", "upwind", src, rec, c, rho)
+        s.set_fields(U0)
+        dt = s.stable_dt(0.5)
+        s.step(nsteps, dt)
+        tr = s.read_receivers()
+        s.close()
+        return tr, dt
+
+    base, dt = misfit(m.c, m.rho)
+    data = 1.05 * base - 0.002
+    s = _solver(m, N, 64, "rigid", "upwind", src, rec)
+    s.set_fields(U0)
+    gc, gr = s.adjoint_gradient(nsteps, dt, base - data)
+    s.close()
+    J = lambda tr: 0.5 * float(np.sum((tr - data) ** 2))
+    J0 = J(base)
+    elems = np.random.default_rng(5).choice(m.K, 8, replace=False)
+    for k in elems:
+        for which, g in (("c", gc[k]), ("rho", gr[k])):
+            vals = []
+            for sgn in (1, -1):
+                c, rho = m.c.copy(), m.rho.copy()
+                arr = c if which == "c" else rho
+                eps = 1e-4 * arr[k]
+                arr[k] += sgn * eps
+                s = _solver(m, N, 64, "rigid", "upwind", src, rec, c, rho)
+                s.set_fields(U0)
+                s.step(nsteps, dt)
+                vals.append(J(s.read_receivers()))
+                s.close()
+            fd = (vals[0] - vals[1]) / (2 * eps)
+            _say("fd", k, which, fd, g)
+            # truncation O(eps^2) relative; rounding of J (1e-14 J) over 2 eps
+            assert abs(fd - g) <= 1e-6 * abs(g) + 1e-14 * J0 / eps
+
+
+def test_autograd_function():
+    torch = pytest.importorskip("torch")
+    from paper_1607_03399_amd.autograd import receiver_traces
+
+    m, N, U0, src, rec = _problem()
+    s = _solver(m, N, 64, "rigid", "upwind", src, rec)
+    dt = s.stable_dt(0.5)
+    nsteps = 10
+    om = dg.Mesh(m.verts, m.wedges, m.c, m.rho, "rigid", "upwind")
+    data = 0.8 * adjoint.solve_traces(om, N, U0, dt, nsteps, src, rec)
+    c = torch.tensor(m.c, dtype=torch.float64, requires_grad=True)
+    rho = torch.tensor(m.rho, dtype=torch.float64, requires_grad=True)
+    tr = receiver_traces(s, c, rho, U0, nsteps, dt, checkpoint_every=3)
+    loss = 0.5 * ((tr - torch.as_tensor(data)) ** 2).sum()
+    loss.backward()
+    elems = [0, 6, 13]
+    J, gc_ref, gr_ref = adjoint.gradient_complex_step(om, N, U0, dt, nsteps, src, rec, data, elems=elems)
+    s.close()
+    assert abs(loss.item() - J) <= 1e-12 * J
+    assert _rel(c.grad.numpy()[elems], gc_ref) <= TOL[64]
+    assert _rel(rho.grad.numpy()[elems], gr_ref) <= TOL[64]
+
+
+def test_unsupported_configurations():
+    m, N, U0, src, rec = _problem()
+    s = _solver(m, N, 64, "rigid", "upwind", src, rec)
+    s.set_fields(U0)
+    dt = s.stable_dt(0.5)
+    with pytest.raises(ValueError):
+        s.adjoint_gradient(4, dt, np.zeros((3, len(rec))))
+    s.set_mass("lumped")
+    with pytest.raises(wdg.WdgError) as e:
+        s.adjoint_gradient(4, dt, np.zeros((4, len(rec))))
+    assert e.value.code == -11
+    s.close()
+    v, w, t, c, rho = inputs.split_columns(inputs.layered_config(2, 2, 0.3, seed=4), [1])
+    s = wdg.Solver(2, 64, device=0)
+    s.set_mesh(v, w, t)
+    s.set_material(c, rho)
+    s.set_receivers(rec)
+    s.set_fields(np.zeros((s.K, 4, s.NPmax)))
+    with pytest.raises(wdg.WdgError) as e:
+        s.adjoint_gradient(4, dt, np.zeros((4, len(rec))))
+    assert e.value.code == -11
+    s.close()
