@@ -121,8 +121,9 @@ def adjoint_benchmark(steps: int, every: int):
     FP32: 16 seeded receivers record p for ``steps`` steps; the data come from
     a wave speed with a seeded 10 % Gaussian anomaly; the gradient with respect
     to every element's c and rho by the discrete adjoint with checkpoints every
-    ``every`` steps.  Times the forward solve and the gradient call (which
-    recomputes its forward states itself) on the same GPU."""
+    ``every`` steps.  Times the forward solve (which keeps the checkpoints)
+    and the gradient call (reverse sweep, recomputing the forward segment by
+    segment from the checkpoints) on the same GPU."""
     from paper_1607_03399_amd import inputs
     from paper_1607_03399_amd import wdg
 
@@ -150,16 +151,16 @@ def adjoint_benchmark(steps: int, every: int):
     s.synchronize()
     s.set_fields(zeros)
     s.time = 0.0
+    # forward solve keeping its checkpoints (the forward of the autograd Function)
     t0 = time.perf_counter()
+    s.adjoint_record(every, steps)
     s.step(steps, dt)
     s.synchronize()
     fwd = time.perf_counter() - t0
     traces = s.read_receivers()
     w = traces - data
-    s.set_fields(zeros)
-    s.time = 0.0
     t0 = time.perf_counter()
-    gc, gr = s.adjoint_gradient(steps, dt, w, every)
+    gc, gr = s.adjoint_gradient_recorded(w)
     adj = time.perf_counter() - t0
     s.close()
     if not (np.all(np.isfinite(gc)) and np.all(np.isfinite(gr))):

@@ -169,13 +169,33 @@ int wdg_energy(wdg_ctx* ctx, double* E);
  * the operator is E-skew up to its E-symmetric penalty part (Sec. 2).
  * Forward states are kept every checkpoint_every steps and recomputed
  * segment by segment on the device; device memory used: about
- * (nsteps/checkpoint_every + checkpoint_every + 15) states of
- * num_nodes x 4 values.  Fields, time and receiver history are unchanged on
+ * nsteps/checkpoint_every + 10 checkpoint_every + 10 states of num_nodes x 4
+ * values (nsteps/checkpoint_every + checkpoint_every + 19 under a tight
+ * wdg_set_adjoint_memory_limit).  Fields, time and receiver history are unchanged on
  * return.  Meshes of wedges with the exact mass only (tetrahedra, mortars or
  * WDG_MASS_LUMPED: WDG_ERR_UNSUPPORTED); needs receivers (else
  * WDG_ERR_STATE); WDG_ERR_OOM if the buffers do not fit. */
 int wdg_adjoint_gradient(wdg_ctx* ctx, int64_t nsteps, double dt, const double* weights, int64_t checkpoint_every,
                          double* grad_c, double* grad_rho);
+/* The same gradient for a solve that wdg_step has already run: after
+ * wdg_adjoint_record, wdg_step keeps the state at the start of every
+ * checkpoint_every-th step (device memory: ceil(max_steps / checkpoint_every)
+ * states, kept by the context), so the gradient call skips the forward sweep.
+ * The recording covers the steps since the record call; it ends (and
+ * wdg_adjoint_gradient_recorded returns WDG_ERR_STATE) when a step of another
+ * size runs, max_steps is exceeded, or the fields, time, material, boundary,
+ * flux, mass or receivers are set.  weights: recorded steps x nrec (row n:
+ * the traces after recorded step n); nsteps (may be NULL) receives the number
+ * of recorded steps.  Fields and time are unchanged by the gradient call. */
+int wdg_adjoint_record(wdg_ctx* ctx, int64_t checkpoint_every, int64_t max_steps);
+int wdg_adjoint_gradient_recorded(wdg_ctx* ctx, const double* weights, double* grad_c, double* grad_rho,
+                                  int64_t* nsteps);
+/* Device-memory budget of the reverse sweep in bytes (0, the default: 85% of
+ * the free memory at the call).  Within budget the forward recomputation of
+ * a checkpoint segment keeps all its stage data (10 states per step); else it
+ * keeps the step-start states and every step recomputes its stages (one more
+ * forward pass).  Both give identical results. */
+int wdg_set_adjoint_memory_limit(wdg_ctx* ctx, int64_t bytes);
 
 /* Per-launch timing of the stage kernels with HIP events on the context stream:
  * enable = 1 starts collecting (and clears), 0 stops.  read returns the summed

@@ -111,6 +111,14 @@ struct wdg_ctx {
   double* dRecBuf = nullptr;
   int64_t rec_cap = 0, rec_steps = 0;
   bool timing = false;
+  // forward recording for the adjoint (wdg_adjoint_record): the state at the
+  // start of every adj_every-th step since the recording began
+  bool recording = false;
+  int64_t adj_every = 0, adj_ncap = 0, adj_steps = 0;
+  double adj_t0 = 0.0, adj_dt = 0.0;
+  void* dAdjCp = nullptr;
+  size_t adj_cp_bytes = 0;
+  size_t adj_mem_limit = 0;  // 0: automatic
   // per stage: start, after the mortar kernel, after the wedge kernel, after the tet kernel
   std::vector<std::array<hipEvent_t, 4>> events;
   size_t events_used = 0;
@@ -161,6 +169,7 @@ void release_device(wdg_ctx* ctx) {
   ctx->own_state = true;
   dfree(ctx->dGeo);
   dfree(ctx->dL);
+  dfree(ctx->dAdjCp);
   dfree(ctx->dSrcVec);
   dfree(ctx->dAux);
   dfree(ctx->dMv);
@@ -1022,6 +1031,7 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
 
 int wdg_set_material(wdg_ctx* ctx, const double* c, const double* rho) {
   if (!ctx) return WDG_ERR_ARG;
+  ctx->recording = false;
   if (ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "set_material before set_mesh");
   if (!c || !rho) return fail(ctx, WDG_ERR_ARG, "null material array");
   for (int64_t k = 0; k < ctx->K; ++k)
@@ -1072,6 +1082,7 @@ int wdg_set_material(wdg_ctx* ctx, const double* c, const double* rho) {
 
 int wdg_set_boundary(wdg_ctx* ctx, int bc) {
   if (!ctx) return WDG_ERR_ARG;
+  ctx->recording = false;
   if (bc != WDG_BC_DIRICHLET_P0 && bc != WDG_BC_RIGID) return fail(ctx, WDG_ERR_ARG, "unknown boundary condition");
   ctx->bc = bc;
   return WDG_OK;
@@ -1079,6 +1090,7 @@ int wdg_set_boundary(wdg_ctx* ctx, int bc) {
 
 int wdg_set_flux(wdg_ctx* ctx, int flux) {
   if (!ctx) return WDG_ERR_ARG;
+  ctx->recording = false;
   if (flux != WDG_FLUX_UPWIND && flux != WDG_FLUX_CENTRAL) return fail(ctx, WDG_ERR_ARG, "unknown flux");
   ctx->flux = flux;
   return WDG_OK;
@@ -1086,6 +1098,7 @@ int wdg_set_flux(wdg_ctx* ctx, int flux) {
 
 int wdg_set_mass(wdg_ctx* ctx, int mass) {
   if (!ctx) return WDG_ERR_ARG;
+  ctx->recording = false;
   if (mass != WDG_MASS_EXACT && mass != WDG_MASS_LUMPED) return fail(ctx, WDG_ERR_ARG, "unknown mass treatment");
   ctx->mass = mass;
   // source vectors kappa (M^k)^-1 l(x_s) follow the mass treatment
@@ -1148,6 +1161,7 @@ int wdg_get_node_coords(const wdg_ctx* ctx, double* xyz) {
 
 int wdg_set_fields(wdg_ctx* ctx, const double* p, const double* ux, const double* uy, const double* uz) {
   if (!ctx) return WDG_ERR_ARG;
+  ctx->recording = false;
   if (ctx->state < kMaterial) return fail(ctx, WDG_ERR_STATE, "set_fields before set_material");
   if (!p || !ux || !uy || !uz) return fail(ctx, WDG_ERR_ARG, "null field array");
   if (ctx->host_only) return fail(ctx, WDG_ERR_STATE, "host-only context cannot hold fields");
@@ -1222,6 +1236,7 @@ int wdg_add_ricker_source(wdg_ctx* ctx, const double xyz[3], double f0, double t
 
 int wdg_set_receivers(wdg_ctx* ctx, int64_t n, const double* xyz) {
   if (!ctx) return WDG_ERR_ARG;
+  ctx->recording = false;
   if (ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "receivers before set_mesh");
   if (n < 0 || (n > 0 && !xyz)) return fail(ctx, WDG_ERR_ARG, "bad receivers");
   const RefOps& R = *ctx->ref;
@@ -1327,8 +1342,20 @@ int wdg_step(wdg_ctx* ctx, int64_t nsteps, double dt) {
   int rc = ensure_receiver_capacity(ctx, ctx->rec_steps + nsteps);
   if (rc) return rc;
   const double t0 = ctx->time;
+  const size_t SB = size_t(ctx->nodes()) * 4 * ctx->tsize();
   for (int64_t n = 0; n < nsteps; ++n) {
     const double tn = t0 + double(n) * dt;
+    if (ctx->recording) {
+      // checkpoint at the start of every adj_every-th recorded step
+      if (ctx->adj_steps == 0) ctx->adj_dt = dt;
+      const int64_t g = ctx->adj_steps / ctx->adj_every;
+      if (dt != ctx->adj_dt || ctx->adj_steps >= ctx->adj_ncap * ctx->adj_every) {
+        ctx->recording = false;
+      } else if (g > 0 && ctx->adj_steps % ctx->adj_every == 0) {
+        HIPCHK(hipMemcpyAsync(static_cast<unsigned char*>(ctx->dAdjCp) + size_t(g) * SB, ctx->dU[ctx->cur], SB,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+      }
+    }
     for (int s = 0; s < 5; ++s) {
       const int flags = (s == 0 ? 0 : wdg::kReadRes) | wdg::kWriteU;
       rc = launch_stage(ctx, ctx->dU[ctx->cur], ctx->dU[1 - ctx->cur], ctx->dRes, kRkA[s], kRkB[s], dt,
@@ -1341,6 +1368,7 @@ int wdg_step(wdg_ctx* ctx, int64_t nsteps, double dt) {
                                    ctx->dRecNN, ctx->dRecRows, ctx->dRecBuf + ctx->rec_steps * ctx->nrec, ctx->stream));
       ctx->rec_steps += 1;
     }
+    if (ctx->recording) ctx->adj_steps += 1;
   }
   ctx->time = t0 + double(nsteps) * dt;
   return WDG_OK;
@@ -1362,46 +1390,33 @@ struct DeviceScratch {
   }
 };
 
-// reference triangle mass, then the edge masses int l_q l_q' (1 -+ xi)/2 of the GLL basis
-std::vector<double> gradient_tables(const RefOps& R) {
-  std::vector<double> out(R.Mtri);
-  std::vector<double> x, w, l(R.Nq);
-  wdg::gauss_legendre(R.Nq + 1, x, w);
-  std::vector<double> Ma(R.Nq * R.Nq, 0.0), Mb(R.Nq * R.Nq, 0.0);
-  for (size_t g = 0; g < x.size(); ++g) {
-    R.line_basis(x[g], l.data());
-    for (int q = 0; q < R.Nq; ++q)
-      for (int qq = 0; qq < R.Nq; ++qq) {
-        Ma[q * R.Nq + qq] += w[g] * l[q] * l[qq] * 0.5 * (1.0 - x[g]);
-        Mb[q * R.Nq + qq] += w[g] * l[q] * l[qq] * 0.5 * (1.0 + x[g]);
-      }
-  }
-  out.insert(out.end(), Ma.begin(), Ma.end());
-  out.insert(out.end(), Mb.begin(), Mb.end());
-  return out;
-}
-
 }  // namespace
 
-int wdg_adjoint_gradient(wdg_ctx* ctx, int64_t nsteps, double dt, const double* weights, int64_t checkpoint_every,
-                         double* grad_c, double* grad_rho) {
-  if (!ctx) return WDG_ERR_ARG;
+namespace {
+
+int adjoint_supported(wdg_ctx* ctx) {
   if (ctx->state < kFields) return fail(ctx, WDG_ERR_STATE, "adjoint before set_fields");
-  if (nsteps < 1 || !(dt > 0) || !std::isfinite(dt) || checkpoint_every < 1 || !weights || !grad_c || !grad_rho)
-    return fail(ctx, WDG_ERR_ARG, "bad adjoint arguments");
   if (ctx->Kt > 0 || !ctx->mort.empty()) return fail(ctx, WDG_ERR_UNSUPPORTED, "adjoint: meshes of wedges only");
   if (ctx->mass != WDG_MASS_EXACT) return fail(ctx, WDG_ERR_UNSUPPORTED, "adjoint: exact mass only");
   if (ctx->nrec == 0) return fail(ctx, WDG_ERR_STATE, "adjoint without receivers");
-  if (!finite_all(weights, nsteps * ctx->nrec)) return fail(ctx, WDG_ERR_ARG, "non-finite adjoint weights");
-  HIPCHK(hipSetDevice(ctx->device));
+  return WDG_OK;
+}
+
+// Reverse sweep of the solve of nsteps steps from time t0 whose states at the
+// start of steps 0, C, 2C, ... are the states of cp.  Per segment (last
+// first) the forward is recomputed from its checkpoint; when the memory
+// budget allows, that pass keeps every stage input and stage right-hand side
+// of the segment, otherwise it keeps the step-start states and every step
+// recomputes its stages before its reverse stages.
+int adjoint_backward(wdg_ctx* ctx, const void* cp, int64_t C, int64_t nsteps, double dt, double t0,
+                     const double* weights, double* grad_c, double* grad_rho) {
   const int N = ctx->N, NP = ctx->NP(), nrec = int(ctx->nrec);
   const int64_t K = ctx->Kw;
   const size_t SB = size_t(ctx->nodes()) * 4 * ctx->tsize();
-  const int64_t C = std::min(checkpoint_every, nsteps);
   const int64_t ncp = (nsteps + C - 1) / C;
-  const double t0 = ctx->time;
   const int mflags = (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
                      (ctx->flux == WDG_FLUX_CENTRAL ? wdg::kCentral : 0);
+  hipStream_t st = ctx->stream;
 
   // receivers become point sources of the adjoint: kappa (M^k)^-1 l(x_r)
   std::vector<int64_t> rbase(nrec);
@@ -1414,97 +1429,105 @@ int wdg_adjoint_gradient(wdg_ctx* ctx, int64_t nsteps, double dt, const double* 
     const std::vector<double> v = mass_inverse_times(ctx, k, ctx->rho[k] * ctx->c[k] * ctx->c[k], rr, ss, tt);
     std::copy(v.begin(), v.end(), rvec.begin() + size_t(r) * NP);
   }
-  const std::vector<double> tabs = gradient_tables(*ctx->ref);
+  // memory: keep the whole segment's stage data (10 states per step) if it fits
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(hipMemGetInfo(&free_b, &total_b));
+  const size_t small = size_t(K) * (wdg::kGradStride + 2) * sizeof(double) + (size_t(nsteps) * nrec + rvec.size()) *
+                        sizeof(double) + rbase.size() * sizeof(int64_t);
+  const size_t fixed = 6 * SB + small + (size_t(256) << 20);
+  const size_t budget = ctx->adj_mem_limit ? ctx->adj_mem_limit : size_t(0.85 * double(free_b));
+  const bool keep = fixed + size_t(10 * C) * SB <= budget;
 
   DeviceScratch ds;
-  void *cp, *seg, *stg, *tmp, *adj, *pg, *pw, *pv, *pb, *pt;
-  HIPCHK(ds.alloc(SB * size_t(ncp), &cp));  // checkpoints: the state at the start of every segment
-  HIPCHK(ds.alloc(SB * size_t(C), &seg));   // states at the start of every step of one segment
-  HIPCHK(ds.alloc(SB * 9, &stg));           // stage inputs 1..4, stage right-hand sides 0..4
-  HIPCHK(ds.alloc(SB * 3, &tmp));           // forward ping-pong pair and residual
-  HIPCHK(ds.alloc(SB * 3, &adj));           // adjoint state and the ping-pong pair of stage vectors
+  void *store, *tmp, *adj, *pg, *pw, *pv, *pb;
+  HIPCHK(ds.alloc(SB * size_t(keep ? 10 * C : C + 9), &store));
+  HIPCHK(ds.alloc(SB * 3, &tmp));  // forward ping-pong pair and residual
+  HIPCHK(ds.alloc(SB * 3, &adj));  // adjoint state and the ping-pong pair of stage vectors
   HIPCHK(ds.alloc(size_t(K) * (wdg::kGradStride + 2) * sizeof(double), &pg));
   HIPCHK(ds.alloc(size_t(nsteps) * nrec * sizeof(double), &pw));
   HIPCHK(ds.alloc(rvec.size() * sizeof(double), &pv));
   HIPCHK(ds.alloc(rbase.size() * sizeof(int64_t), &pb));
-  HIPCHK(ds.alloc(tabs.size() * sizeof(double), &pt));
-  auto at = [SB](void* base, int64_t i) -> void* { return static_cast<unsigned char*>(base) + size_t(i) * SB; };
+  auto at = [SB](const void* base, int64_t i) -> void* {
+    return const_cast<unsigned char*>(static_cast<const unsigned char*>(base)) + size_t(i) * SB;
+  };
   double* gacc = static_cast<double*>(pg);
   double* gout = gacc + K * wdg::kGradStride;
   const double* dw = static_cast<const double*>(pw);
-  hipStream_t st = ctx->stream;
   HIPCHK(hipMemcpyAsync(pw, weights, size_t(nsteps) * nrec * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(pv, rvec.data(), rvec.size() * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(pb, rbase.data(), rbase.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(pt, tabs.data(), tabs.size() * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemsetAsync(gacc, 0, size_t(K) * wdg::kGradStride * sizeof(double), st));
   HIPCHK(hipMemsetAsync(adj, 0, SB * 3, st));
-  HIPCHK(hipMemcpyAsync(cp, ctx->dU[ctx->cur], SB, hipMemcpyDeviceToDevice, st));
-  const bool timing = ctx->timing;
-  ctx->timing = false;
-  struct Restore {
-    wdg_ctx* c;
-    bool t;
-    ~Restore() { c->timing = t; }
-  } restore{ctx, timing};
 
-  void* Si[5] = {nullptr, at(stg, 0), at(stg, 1), at(stg, 2), at(stg, 3)};
-  void* Ri[5] = {at(stg, 4), at(stg, 5), at(stg, 6), at(stg, 7), at(stg, 8)};
-  // one forward step X -> Y (Y may be null: not needed); with keep, the stage
-  // inputs go to Si[1..4] and the stage right-hand sides to Ri[0..4]
-  auto forward_step = [&](const void* X, void* Y, double tn, bool keep) -> int {
+  // store slots: keep: step i of the segment holds its start state (0), stage
+  // inputs 1..4 (1..4) and stage right-hand sides (5..9); otherwise the
+  // step-start states (0..C-1), then one step's stage inputs and right-hand sides
+  auto slot = [&](int64_t i, int k) -> void* {
+    if (keep) return at(store, 10 * i + k);
+    return k == 0 ? at(store, i) : at(store, C + k - 1);
+  };
+  // one forward step from X; stage s writes outs[s] (null: no state output)
+  // and, if routs, its right-hand side to routs[s]
+  auto forward_step = [&](const void* X, void* const* outs, void* const* routs, double tn) -> int {
     const void* in = X;
     for (int s = 0; s < 5; ++s) {
-      void* out = keep ? (s < 4 ? Si[s + 1] : nullptr) : (s == 4 ? Y : at(tmp, s & 1));
-      int flags = (s == 0 ? 0 : wdg::kReadRes) | (out ? wdg::kWriteU : 0) | (keep ? wdg::kWriteR : 0);
-      const int rc = launch_stage(ctx, in, out, at(tmp, 2), kRkA[s], kRkB[s], dt, tn + kRkC[s] * dt, flags, 1.0,
-                                  keep ? Ri[s] : nullptr, true);
+      const int flags = (s == 0 ? 0 : wdg::kReadRes) | (outs[s] ? wdg::kWriteU : 0) | (routs ? wdg::kWriteR : 0);
+      const int rc = launch_stage(ctx, in, outs[s], at(tmp, 2), kRkA[s], kRkB[s], dt, tn + kRkC[s] * dt, flags, 1.0,
+                                  routs ? routs[s] : nullptr, true);
       if (rc) return rc;
-      in = out;
-    }
-    return WDG_OK;
-  };
-  // the step-start states of segment g into seg; the state after it into next (if not null)
-  auto run_segment = [&](int64_t g, void* next) -> int {
-    const int64_t n0 = g * C, n1 = std::min(n0 + C, nsteps);
-    HIPCHK(hipMemcpyAsync(seg, at(cp, g), SB, hipMemcpyDeviceToDevice, st));
-    for (int64_t n = n0; n < n1; ++n) {
-      void* Y = n + 1 < n1 ? at(seg, n + 1 - n0) : next;
-      if (!Y) break;
-      const int rc = forward_step(at(seg, n - n0), Y, t0 + double(n) * dt, false);
-      if (rc) return rc;
+      in = outs[s];
     }
     return WDG_OK;
   };
 
-  // forward sweep: checkpoints (the last segment's states stay in seg)
-  for (int64_t g = 0; g < ncp; ++g) {
-    const int rc = run_segment(g, g + 1 < ncp ? at(cp, g + 1) : nullptr);
-    if (rc) return rc;
-  }
-  // reverse sweep
   void* Ua = at(adj, 0);
   int sc = 1;
   HIPCHK(wdg::launch_inject(ctx->bits, NP, nrec, static_cast<const int64_t*>(pb), static_cast<const double*>(pv),
                             dw + (nsteps - 1) * nrec, kRkB[4], Ua, at(adj, sc), st));
   for (int64_t g = ncp - 1; g >= 0; --g) {
-    if (g != ncp - 1) {
-      const int rc = run_segment(g, nullptr);
+    const int64_t n0 = g * C, n1 = std::min(n0 + C, nsteps);
+    HIPCHK(hipMemcpyAsync(slot(0, 0), at(cp, g), SB, hipMemcpyDeviceToDevice, st));
+    for (int64_t n = n0; n < n1; ++n) {
+      const int64_t i = n - n0;
+      void* next = n + 1 < n1 ? slot(i + 1, 0) : nullptr;
+      int rc;
+      if (keep) {
+        void* outs[5] = {slot(i, 1), slot(i, 2), slot(i, 3), slot(i, 4), next};
+        void* routs[5] = {slot(i, 5), slot(i, 6), slot(i, 7), slot(i, 8), slot(i, 9)};
+        rc = forward_step(slot(i, 0), outs, routs, t0 + double(n) * dt);
+      } else {
+        if (!next) break;
+        void* outs[5] = {at(tmp, 0), at(tmp, 1), at(tmp, 0), at(tmp, 1), next};
+        rc = forward_step(slot(i, 0), outs, nullptr, t0 + double(n) * dt);
+      }
       if (rc) return rc;
     }
-    const int64_t n0 = g * C, n1 = std::min(n0 + C, nsteps);
     for (int64_t n = n1 - 1; n >= n0; --n) {
-      void* Un = at(seg, n - n0);
-      int rc = forward_step(Un, nullptr, t0 + double(n) * dt, true);
-      if (rc) return rc;
+      const int64_t i = n - n0;
+      void* Us[5];
+      void* Rs[5];
+      if (keep) {
+        for (int s = 0; s < 5; ++s) {
+          Us[s] = slot(i, s);
+          Rs[s] = slot(i, 5 + s);
+        }
+      } else {
+        // the stage data of this step go to the shared slots 1..9
+        void* outs[5] = {slot(0, 1), slot(0, 2), slot(0, 3), slot(0, 4), nullptr};
+        void* routs[5] = {slot(0, 5), slot(0, 6), slot(0, 7), slot(0, 8), slot(0, 9)};
+        const int rc = forward_step(slot(i, 0), outs, routs, t0 + double(n) * dt);
+        if (rc) return rc;
+        Us[0] = slot(i, 0);
+        for (int s = 1; s < 5; ++s) Us[s] = outs[s - 1];
+        for (int s = 0; s < 5; ++s) Rs[s] = routs[s];
+      }
       for (int s = 4; s >= 0; --s) {
         void* sig = at(adj, sc);
-        HIPCHK(wdg::launch_grad_stage(N, ctx->bits, K, sig, s == 0 ? Un : Si[s], Ri[s], ctx->dGeo, ctx->dConn,
-                                      ctx->dAux, ctx->dMv, ctx->dM1, static_cast<const double*>(pt), dt, mflags,
-                                      gacc, st));
+        HIPCHK(wdg::launch_grad_stage(N, ctx->bits, K, sig, Us[s], Rs[s], ctx->dGeo, ctx->dConn, ctx->dAux, dt,
+                                      mflags, gacc, st));
         // U~ += dt A sig;  sig <- a_s sig + b_{s-1} U~  (b of the previous step's last stage at s = 0)
-        rc = launch_stage(ctx, sig, at(adj, 3 - sc), Ua, 1.0, s > 0 ? kRkB[s - 1] : kRkB[4], dt, 0.0,
-                          wdg::kReadRes | wdg::kWriteU, kRkA[s], nullptr, false);
+        const int rc = launch_stage(ctx, sig, at(adj, 3 - sc), Ua, 1.0, s > 0 ? kRkB[s - 1] : kRkB[4], dt, 0.0,
+                                    wdg::kReadRes | wdg::kWriteU, kRkA[s], nullptr, false);
         if (rc) return rc;
         sc = 3 - sc;
       }
@@ -1520,6 +1543,101 @@ int wdg_adjoint_gradient(wdg_ctx* ctx, int64_t nsteps, double dt, const double* 
   return WDG_OK;
 }
 
+// stage timing off for the duration of an adjoint call
+struct TimingOff {
+  wdg_ctx* c;
+  bool t;
+  explicit TimingOff(wdg_ctx* ctx) : c(ctx), t(ctx->timing) { ctx->timing = false; }
+  ~TimingOff() { c->timing = t; }
+};
+
+}  // namespace
+
+int wdg_adjoint_gradient(wdg_ctx* ctx, int64_t nsteps, double dt, const double* weights, int64_t checkpoint_every,
+                         double* grad_c, double* grad_rho) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (nsteps < 1 || !(dt > 0) || !std::isfinite(dt) || checkpoint_every < 1 || !weights || !grad_c || !grad_rho)
+    return fail(ctx, WDG_ERR_ARG, "bad adjoint arguments");
+  int rc = adjoint_supported(ctx);
+  if (rc) return rc;
+  if (!finite_all(weights, nsteps * ctx->nrec)) return fail(ctx, WDG_ERR_ARG, "non-finite adjoint weights");
+  HIPCHK(hipSetDevice(ctx->device));
+  TimingOff off(ctx);
+  const size_t SB = size_t(ctx->nodes()) * 4 * ctx->tsize();
+  const int64_t C = std::min(checkpoint_every, nsteps);
+  const int64_t ncp = (nsteps + C - 1) / C;
+  const double t0 = ctx->time;
+  hipStream_t st = ctx->stream;
+  DeviceScratch ds;
+  void *cp, *tmp;
+  HIPCHK(ds.alloc(SB * size_t(ncp), &cp));
+  HIPCHK(ds.alloc(SB * 4, &tmp));  // stage ping-pong pair, residual, step state
+  auto at = [SB](void* base, int64_t i) -> void* { return static_cast<unsigned char*>(base) + size_t(i) * SB; };
+  // forward sweep: checkpoint g holds the state at the start of step g C
+  HIPCHK(hipMemcpyAsync(cp, ctx->dU[ctx->cur], SB, hipMemcpyDeviceToDevice, st));
+  const void* x = cp;
+  for (int64_t n = 0; n < (ncp - 1) * C; ++n) {
+    const bool ck = (n + 1) % C == 0;
+    void* outs[5] = {at(tmp, 0), at(tmp, 1), at(tmp, 0), at(tmp, 1), ck ? at(cp, (n + 1) / C) : at(tmp, 3)};
+    const void* in = x;
+    for (int s = 0; s < 5; ++s) {
+      rc = launch_stage(ctx, in, outs[s], at(tmp, 2), kRkA[s], kRkB[s], dt, t0 + double(n) * dt + kRkC[s] * dt,
+                        (s == 0 ? 0 : wdg::kReadRes) | wdg::kWriteU);
+      if (rc) return rc;
+      in = outs[s];
+    }
+    x = outs[4];
+  }
+  return adjoint_backward(ctx, cp, C, nsteps, dt, t0, weights, grad_c, grad_rho);
+}
+
+int wdg_adjoint_record(wdg_ctx* ctx, int64_t checkpoint_every, int64_t max_steps) {
+  if (!ctx) return WDG_ERR_ARG;
+  ctx->recording = false;
+  if (checkpoint_every < 1 || max_steps < 1) return fail(ctx, WDG_ERR_ARG, "bad recording arguments");
+  int rc = adjoint_supported(ctx);
+  if (rc) return rc;
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t SB = size_t(ctx->nodes()) * 4 * ctx->tsize();
+  const int64_t ncap = (max_steps + checkpoint_every - 1) / checkpoint_every;
+  if (!ctx->dAdjCp || ctx->adj_cp_bytes != SB * size_t(ncap)) {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    dfree(ctx->dAdjCp);
+    ctx->adj_cp_bytes = 0;
+    HIPCHK(hipMalloc(&ctx->dAdjCp, SB * size_t(ncap)));
+    ctx->adj_cp_bytes = SB * size_t(ncap);
+  }
+  HIPCHK(hipMemcpyAsync(ctx->dAdjCp, ctx->dU[ctx->cur], SB, hipMemcpyDeviceToDevice, ctx->stream));
+  ctx->adj_every = checkpoint_every;
+  ctx->adj_ncap = ncap;
+  ctx->adj_steps = 0;
+  ctx->adj_t0 = ctx->time;
+  ctx->adj_dt = 0.0;
+  ctx->recording = true;
+  return WDG_OK;
+}
+
+int wdg_adjoint_gradient_recorded(wdg_ctx* ctx, const double* weights, double* grad_c, double* grad_rho,
+                                  int64_t* nsteps) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (!ctx->recording || ctx->adj_steps < 1) return fail(ctx, WDG_ERR_STATE, "no valid forward recording");
+  if (nsteps) *nsteps = ctx->adj_steps;
+  if (!weights || !grad_c || !grad_rho) return fail(ctx, WDG_ERR_ARG, "bad adjoint arguments");
+  int rc = adjoint_supported(ctx);
+  if (rc) return rc;
+  if (!finite_all(weights, ctx->adj_steps * ctx->nrec)) return fail(ctx, WDG_ERR_ARG, "non-finite adjoint weights");
+  HIPCHK(hipSetDevice(ctx->device));
+  TimingOff off(ctx);
+  return adjoint_backward(ctx, ctx->dAdjCp, ctx->adj_every, ctx->adj_steps, ctx->adj_dt, ctx->adj_t0, weights,
+                          grad_c, grad_rho);
+}
+
+int wdg_set_adjoint_memory_limit(wdg_ctx* ctx, int64_t bytes) {
+  if (!ctx || bytes < 0) return WDG_ERR_ARG;
+  ctx->adj_mem_limit = size_t(bytes);
+  return WDG_OK;
+}
+
 int wdg_get_time(const wdg_ctx* ctx, double* t) {
   if (!ctx || !t) return WDG_ERR_ARG;
   *t = ctx->time;
@@ -1528,6 +1646,7 @@ int wdg_get_time(const wdg_ctx* ctx, double* t) {
 
 int wdg_set_time(wdg_ctx* ctx, double t) {
   if (!ctx || !std::isfinite(t)) return WDG_ERR_ARG;
+  ctx->recording = false;
   ctx->time = t;
   return WDG_OK;
 }

@@ -109,12 +109,11 @@ int mortar_table_size(int N, int bits);
 // Adjoint gradient (wedge meshes).  Per reverse stage: accumulate into gacc
 // (kGradStride FP64 values per wedge) dt times the mass terms sig^T M R of the
 // pressure and of the velocity and the face integrals 1/2 int sig_p [p],
-// 1/2 int sig_un [u_n] of the forward stage input Us; tab holds the reference
-// triangle mass and the two edge masses (see launch_grad_stage's caller).
+// 1/2 int sig_un [u_n] of the forward stage input Us.
 constexpr int kGradStride = 12;
 hipError_t launch_grad_stage(int N, int bits, int64_t K, const void* sig, const void* Us, const void* Rs,
-                             const void* geo, const int* conn, const double* aux, const double* Mv, const double* M1,
-                             const double* tab, double dt, int flags, double* gacc, hipStream_t st);
+                             const void* geo, const int* conn, const double* aux, double dt, int flags, double* gacc,
+                             hipStream_t st);
 // Gradient with respect to c and rho from the accumulated terms and the penalty derivatives.
 hipError_t launch_grad_combine(int bits, int64_t K, const double* gacc, const void* geo, const int* conn,
                                const double* aux, int flags, double* gc, double* grho, hipStream_t st);

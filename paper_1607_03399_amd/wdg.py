@@ -76,6 +76,9 @@ def load_library() -> C.CDLL:
         "wdg_eval_rhs": (C.c_int, [vp, C.c_double, _dp, _dp]),
         "wdg_energy": (C.c_int, [vp, _dp]),
         "wdg_adjoint_gradient": (C.c_int, [vp, C.c_int64, C.c_double, _dp, C.c_int64, _dp, _dp]),
+        "wdg_adjoint_record": (C.c_int, [vp, C.c_int64, C.c_int64]),
+        "wdg_adjoint_gradient_recorded": (C.c_int, [vp, _dp, _dp, _dp, _i64p]),
+        "wdg_set_adjoint_memory_limit": (C.c_int, [vp, C.c_int64]),
         "wdg_get_element_data": (C.c_int, [vp, _dp, _dp]),
         "wdg_kernel_timing": (C.c_int, [vp, C.c_int]),
         "wdg_read_kernel_timing": (C.c_int, [vp, _dp, _i64p]),
@@ -299,6 +302,37 @@ class Solver:
         self._check(self._lib.wdg_adjoint_gradient(self._h, int(nsteps), float(dt), _ptr(w), int(checkpoint_every),
                                                    _ptr(gc), _ptr(gr)), "adjoint_gradient")
         return gc, gr
+
+    def adjoint_record(self, checkpoint_every: int, max_steps: int):
+        """Keep checkpoints of the following ``step`` calls for adjoint_gradient_recorded."""
+        self._check(self._lib.wdg_adjoint_record(self._h, int(checkpoint_every), int(max_steps)), "adjoint_record")
+        self.record_id = getattr(self, "record_id", 0) + 1
+
+    def recorded_steps(self) -> int:
+        """Steps of the current forward recording (0: none)."""
+        n = C.c_int64(0)
+        self._lib.wdg_adjoint_gradient_recorded(self._h, None, None, None, C.byref(n))
+        return n.value
+
+    def adjoint_gradient_recorded(self, weights):
+        """(dF/dc, dF/drho) of F = sum weights[n, r] p_r(after recorded step n) for
+        the solve recorded since adjoint_record (no forward sweep)."""
+        n = C.c_int64()
+        gc = np.zeros(self.K)
+        gr = np.zeros(self.K)
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        if w.ndim != 2 or w.shape[1] != getattr(self, "_nrec", 0):
+            raise ValueError("weights must be (recorded steps, nrec)")
+        # probe: the number of recorded steps (the call itself fails on the null arrays)
+        self._lib.wdg_adjoint_gradient_recorded(self._h, None, None, None, C.byref(n))
+        if n.value and w.shape[0] != n.value:
+            raise ValueError(f"weights must have {n.value} rows (recorded steps)")
+        self._check(self._lib.wdg_adjoint_gradient_recorded(self._h, _ptr(w), _ptr(gc), _ptr(gr), C.byref(n)),
+                    "adjoint_gradient_recorded")
+        return gc, gr
+
+    def set_adjoint_memory_limit(self, nbytes: int):
+        self._check(self._lib.wdg_set_adjoint_memory_limit(self._h, int(nbytes)), "set_adjoint_memory_limit")
 
     def kernel_timing(self, enable: bool):
         self._check(self._lib.wdg_kernel_timing(self._h, int(bool(enable))), "kernel_timing")

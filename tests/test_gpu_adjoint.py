@@ -83,6 +83,43 @@ def test_checkpoint_interval_does_not_change_the_gradient():
     assert np.array_equal(U_after[:, :, :U0.shape[2]], U0)  # the state is unchanged
 
 
+def test_recorded_forward_and_memory_modes_give_the_same_gradient():
+    """Checkpoints kept by the forward steps (recording) and both memory modes
+    of the reverse sweep (segment stage store / per-step recomputation) give
+    bitwise the same gradient as the self-contained call."""
+    m, N, U0, src, rec = _problem()
+    s = _solver(m, N, 64, "rigid", "upwind", src, rec)
+    s.set_fields(U0)
+    dt = s.stable_dt(0.5)
+    w = np.random.default_rng(9).standard_normal((11, len(rec)))
+    ref = s.adjoint_gradient(11, dt, w, checkpoint_every=4)
+    s.set_adjoint_memory_limit(1)  # forces per-step recomputation
+    low = s.adjoint_gradient(11, dt, w, checkpoint_every=4)
+    s.set_adjoint_memory_limit(0)
+    s.adjoint_record(4, 11)
+    s.step(6, dt)
+    s.step(5, dt)
+    U_end = s.get_fields()
+    assert s.recorded_steps() == 11
+    rec_g = s.adjoint_gradient_recorded(w)
+    assert np.array_equal(s.get_fields(), U_end)
+    for a in (low, rec_g):
+        assert np.array_equal(a[0], ref[0]) and np.array_equal(a[1], ref[1])
+    # the recording ends with a step of another size, and with set_fields
+    s.step(1, 0.5 * dt)
+    with pytest.raises(wdg.WdgError) as e:
+        s.adjoint_gradient_recorded(np.zeros((12, len(rec))))
+    assert e.value.name == "WDG_ERR_STATE"
+    s.set_fields(U0)
+    s.time = 0.0
+    s.adjoint_record(4, 8)
+    s.step(8, dt)
+    assert s.recorded_steps() == 8
+    s.step(1, dt)  # beyond max_steps
+    assert s.recorded_steps() == 0
+    s.close()
+
+
 def test_gradient_matches_central_differences():
     """Device-only check on a larger mesh (N=3): the adjoint gradient of the
     misfit against central differences of the device's own forward solve."""
