@@ -405,7 +405,7 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.rout = rout;
   L.Kw = ctx->Kw;
   L.Kt = ctx->Kt;
-  L.flags = flags | (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
+  L.flags = flags | (g != 1.0 ? wdg::kGamma : 0) | (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
             (ctx->flux == WDG_FLUX_CENTRAL ? wdg::kCentral : 0) | (ctx->mass == WDG_MASS_LUMPED ? wdg::kLumped : 0);
   if (ctx->timing) {
     // events only between kernels that actually run (an event adds a gap to the stream)

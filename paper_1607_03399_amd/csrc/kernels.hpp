@@ -55,6 +55,7 @@ enum StageFlags : int {
   kCentral = 8,    // else upwind flux
   kLumped = 16,    // Gauss-Lobatto mass in t: (M^1D)^-1 e_{0,N} becomes e_{0,N} / w_{0,N}
   kWriteR = 32,    // also store the stage right-hand side (sources included) to rout (wedges)
+  kGamma = 64,     // U_out = g U_in + b res' (else g = 1)
 };
 
 // One stage over the whole mesh.  State buffers hold wedges first (Kw x Np_wedge

@@ -175,7 +175,8 @@ __global__ void __launch_bounds__(256) tet_stage(StageLaunch A) {
     res[gi] = r;
     if (wu) {
       const V4<T> u = sU[le * NP + i];
-      Uout[gi] = V4<T>{cg * u.p + cb * r.p, cg * u.uz + cb * r.uz, cg * u.ux + cb * r.ux, cg * u.uy + cb * r.uy};
+      const T gg = (A.flags & kGamma) ? cg : T(1);
+      Uout[gi] = V4<T>{gg * u.p + cb * r.p, gg * u.uz + cb * r.uz, gg * u.ux + cb * r.ux, gg * u.uy + cb * r.uy};
     }
   }
 }

@@ -3,6 +3,8 @@
 // Runge-Kutta update of one stage (Sec. 4.2-4.3).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "ref_tables.inc"
 
@@ -459,25 +461,33 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
   const bool wr = (A.flags & kWriteR) != 0;
   const auto bout = chunk_rsrc(static_cast<V4<T>*>(A.Uout) + e0 * NP, int64_t(nE) * NP * V4B);
   const auto brout = chunk_rsrc(static_cast<V4<T>*>(A.rout) + e0 * NP, wr ? int64_t(nE) * NP * V4B : 0);
+  // U' = g U + b res' with g = 1 except in the adjoint sweep: two copies of the loop
+  auto update = [&](auto with_g) {
+    constexpr bool G = decltype(with_g)::value;
 #pragma unroll
-  for (int k = 0; k < C::UPD; ++k) {
-    const int idx = tid + 64 * k;
-    const int l = idx < nE * NP ? idx + (idx / NP) * (NPP - NP) : 0;
-    const V4<T> R = sR[l];
-    V4<T> q;
-    if constexpr (C::PREFETCH)
-      q = rprev[k];
-    else
-      q = bload<T>(bres_in, idx);
-    const V4<T> r{ca * q.p + dt * R.p, ca * q.uz + dt * R.uz, ca * q.ux + dt * R.ux, ca * q.uy + dt * R.uy};
-    bstore<T>(bres, idx, r);
-    if (wr) bstore<T>(brout, idx, R);
-    if (wu) {
-      const V4<T> u = sU[l];
-      bstore<T>(bout, idx,
-                V4<T>{cg * u.p + cb * r.p, cg * u.uz + cb * r.uz, cg * u.ux + cb * r.ux, cg * u.uy + cb * r.uy});
+    for (int k = 0; k < C::UPD; ++k) {
+      const int idx = tid + 64 * k;
+      const int l = idx < nE * NP ? idx + (idx / NP) * (NPP - NP) : 0;
+      const V4<T> R = sR[l];
+      V4<T> q;
+      if constexpr (C::PREFETCH)
+        q = rprev[k];
+      else
+        q = bload<T>(bres_in, idx);
+      const V4<T> r{ca * q.p + dt * R.p, ca * q.uz + dt * R.uz, ca * q.ux + dt * R.ux, ca * q.uy + dt * R.uy};
+      bstore<T>(bres, idx, r);
+      if (wr) bstore<T>(brout, idx, R);
+      if (wu) {
+        V4<T> u = sU[l];
+        if constexpr (G) u = V4<T>{cg * u.p, cg * u.uz, cg * u.ux, cg * u.uy};
+        bstore<T>(bout, idx, V4<T>{u.p + cb * r.p, u.uz + cb * r.uz, u.ux + cb * r.ux, u.uy + cb * r.uy});
+      }
     }
-  }
+  };
+  if (A.flags & kGamma)
+    update(std::true_type{});
+  else
+    update(std::false_type{});
 }
 
 template <int N, typename T>
