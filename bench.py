@@ -12,8 +12,9 @@ Prints one JSON line: DG node-updates per second per Runge-Kutta stage
 (elements x nodes x 5 x steps / wall time), the HBM-roofline fraction of the
 stage kernel (algorithmic bytes / average kernel time from HIP events on the
 solver stream), the adjoint leg (receiver-misfit gradient on 524288 wedges:
-gradient time over forward time) and the FP64 CPU oracle timed on a bounded
-sample.
+gradient time over forward time), the batched leg (48 independent problems
+of mixed orders and sizes: one batch against the problems one by one) and
+the FP64 CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -193,6 +194,85 @@ def adjoint_benchmark(steps: int, every: int):
     }
 
 
+def batch_benchmark(steps: int):
+    """48 independent problems (1k-60k wedges, N in {2,3,4,5}, own material,
+    source and time step), FP32: ``steps`` steps of each problem one after the
+    other (plain form), then all of them together as one batch (autotuned,
+    graph-replayed; setup untimed).  Both runs start from the same state and
+    must end in bitwise the same fields."""
+    from paper_1607_03399_amd import inputs
+    from paper_1607_03399_amd import wdg
+
+    specs = inputs.batch_problems()
+    solvers, dts, U0s = [], [], []
+    for N, mesh, xs in specs:
+        s = wdg.Solver(N, 32, device=0)
+        s.set_mesh(mesh.verts, mesh.wedges)
+        s.set_material(mesh.c, mesh.rho)
+        s.set_boundary("rigid")
+        s.set_flux("upwind")
+        s.add_ricker_source(xs, 10.0, 0.1, 1.0)
+        U = np.zeros((s.K, 4, s.NPmax))
+        U[:, 0] = inputs.gaussian_pulse(s.node_coords(), centre=xs, width=0.2)
+        solvers.append(s)
+        dts.append(s.stable_dt(0.5))
+        U0s.append(U)
+
+    def reset():
+        for s, U in zip(solvers, U0s):
+            s.set_fields(U)
+            s.time = 0.0
+
+    reset()
+    for s, dt in zip(solvers, dts):  # warm up every order's kernels
+        s.step(1, dt)
+    reset()
+    for s in solvers:
+        s.synchronize()
+    t0 = time.perf_counter()
+    for s, dt in zip(solvers, dts):
+        s.step(steps, dt)
+    for s in solvers:
+        s.synchronize()
+    seq = time.perf_counter() - t0
+    seq_fields = [s.get_fields() for s in solvers]
+    reset()
+    batch = wdg.Batch(32, device=0)
+    for s, dt in zip(solvers, dts):
+        batch.add(s, dt)
+    batch.prepare(autotune=True)
+    batch.step(1)  # first call captures the graph
+    reset()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    bat = time.perf_counter() - t0
+    same = all(np.array_equal(s.get_fields(), f) for s, f in zip(solvers, seq_fields))
+    orders = sorted({N for N, _, _ in specs})
+    tuned = {str(N): {"elements_per_block": batch.config(N)[0], "waves_per_simd": batch.config(N)[1],
+                      "tuned_stage_us": batch.config(N)[2]} for N in orders}
+    nodes = sum(s.K * s.Np for s in solvers)
+    batch.close()
+    for s in solvers:
+        s.close()
+    if not same:
+        raise RuntimeError("batched fields differ from the plain solves")
+    return {
+        "workload": "cfg4 batched: 48 seeded problems, 1k-60k wedges (log-uniform), N in {2,3,4,5}, per-layer "
+                    f"c in [1,3] and rho in [1,2.5], own Ricker source and time step each, FP32, {steps} steps",
+        "problems": len(specs),
+        "elements": int(sum(s.K for s in solvers)),
+        "nodes": int(nodes),
+        "steps": steps,
+        "sequential_s": seq,
+        "batched_s": bat,
+        "speedup": seq / bat,
+        "batched_node_updates_per_s": nodes * 5 * steps / bat,
+        "sequential_node_updates_per_s": nodes * 5 * steps / seq,
+        "identical_fields": same,
+        "tuned": tuned,
+    }
+
+
 def copy_bandwidth(nbytes: int = 512 << 20, reps: int = 10) -> float:
     """Device-to-device copy of nbytes (read + write) timed with events."""
     import torch
@@ -229,6 +309,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint leg (cfg2 runs the cfg5 receiver-misfit gradient after the forward bench)")
     ap.add_argument("--adjoint-steps", type=int, default=500)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched leg (cfg2 runs the cfg4 48-problem batch after the forward bench)")
+    ap.add_argument("--batch-steps", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain 512 MiB device copy first (HBM reference for counters and roofline)")
     args = ap.parse_args()
@@ -355,6 +438,8 @@ def main():
     s.close()
     if args.config == "cfg2" and bits == 32 and not args.no_adjoint:
         out["adjoint"] = adjoint_benchmark(args.adjoint_steps, 50)
+    if args.config == "cfg2" and bits == 32 and not args.no_batch:
+        out["batched"] = batch_benchmark(args.batch_steps)
     if not args.no_cpu_baseline and mesh is not None:
         out["cpu_baseline"] = cpu_baseline(mesh, N, dt, args.cpu_seconds, args.cpu_sample)
     print(json.dumps(out), flush=True)

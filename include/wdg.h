@@ -197,6 +197,45 @@ int wdg_adjoint_gradient_recorded(wdg_ctx* ctx, const double* weights, double* g
  * forward pass).  Both give identical results. */
 int wdg_set_adjoint_memory_limit(wdg_ctx* ctx, int64_t bytes);
 
+/* Batches: many independent problems (each a context with a wedge mesh of
+ * any order, its own material, sources, fields and time step) advanced
+ * together.  Each Runge-Kutta stage is one launch per polynomial order over
+ * a list of work items (problem, element chunk); one step
+ * is captured once as a HIP graph (five stages: a small kernel that writes
+ * every problem's stage record on the device -- buffers, coefficients,
+ * source amplitudes at the problem's own time -- then the per-order
+ * launches; then a step counter) and replayed.  Each stage launch covers all
+ * problems of one order: one block per element chunk of any problem.
+ *   wdg_batch_create: device and state precision (32 or 64) of the batch.
+ *   wdg_batch_add: a context on that device and precision, with fields set,
+ *     meshes of wedges only (else WDG_ERR_UNSUPPORTED); the batch keeps the
+ *     pointer (the caller keeps ownership and must not destroy or step the
+ *     context while a batch call runs).  index (may be NULL) receives its slot.
+ *   wdg_batch_prepare: groups the problems by order and lists their element
+ *     chunks problem by problem (one block per chunk, each XCD a contiguous
+ *     range); with autotune != 0 times, for every order, the stage kernel
+ *     compiled for 2 waves per SIMD (as the single-problem kernel) and for 1
+ *     (twice the registers: no spills at high order) on the real data
+ *     (launches that rewrite only the residual, which the next stage
+ *     overwrites anyway) and keeps the faster; then captures the step graph.
+ *     No problem may be added afterwards (WDG_ERR_STATE).
+ *   wdg_batch_step: nsteps steps of every problem from its current fields and
+ *     time (each with its own time step); afterwards wdg_get_fields and
+ *     wdg_get_time of each context show the new state.  Receiver traces are
+ *     not recorded by batch steps, and a forward recording (wdg_adjoint_record)
+ *     of a problem ends.
+ *   wdg_batch_config: elements per block, the chosen waves per SIMD of order N
+ *     and the tuned average stage time of that order (microseconds).
+ * Results are identical to wdg_step of each problem alone. */
+typedef struct wdg_batch wdg_batch;
+int wdg_batch_create(int device, int precision_bits, wdg_batch** out);
+int wdg_batch_destroy(wdg_batch* batch);
+const char* wdg_batch_last_error(const wdg_batch* batch);
+int wdg_batch_add(wdg_batch* batch, wdg_ctx* problem, double dt, int* index);
+int wdg_batch_prepare(wdg_batch* batch, int autotune);
+int wdg_batch_step(wdg_batch* batch, int64_t nsteps);
+int wdg_batch_config(const wdg_batch* batch, int N, int* elems_per_block, int* waves_per_simd, double* tuned_us);
+
 /* Per-launch timing of the stage kernels with HIP events on the context stream:
  * enable = 1 starts collecting (and clears), 0 stops.  read returns the summed
  * kernel time in milliseconds and the number of timed stages since the last

@@ -1828,4 +1828,321 @@ int wdg_reference_operator(int order_N, const char* name, double* out, int64_t c
   return WDG_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batches of independent problems
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+struct wdg_batch {
+  int device = 0, bits = 32;
+  hipStream_t stream = nullptr;
+  std::vector<wdg_ctx*> probs;
+  std::vector<double> dts;
+  struct Group {
+    int N = 0;
+    std::vector<int> members;  // problem indices
+    int wpe = 2, nwork = 0;
+    int2* dWork = nullptr;
+    float tuned_us = 0.0f;
+  };
+  std::vector<Group> groups;
+  wdg::StageLaunch* dProbs = nullptr;
+  wdg::BatchParam* dParam = nullptr;
+  int64_t* dCounter = nullptr;
+  double* dAmp = nullptr;  // source amplitudes [step][stage][problem][source]
+  int64_t amp_steps = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool ready = false;
+  mutable std::string err;
+};
+
+namespace {
+
+int bfail(const wdg_batch* b, int code, const std::string& msg) {
+  if (b) b->err = msg;
+  return code;
+}
+
+#define BHIPCHK(expr)                                                                            \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) {                                                                      \
+      return bfail(b, e_ == hipErrorOutOfMemory ? WDG_ERR_OOM : WDG_ERR_HIP,                     \
+                   std::string(#expr) + ": " + hipGetErrorString(e_));                           \
+    }                                                                                            \
+  } while (0)
+
+void batch_release(wdg_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  for (auto& g : b->groups) dfree(g.dWork);
+  dfree(b->dProbs);
+  dfree(b->dParam);
+  dfree(b->dCounter);
+  dfree(b->dAmp);
+  b->amp_steps = 0;
+  b->ready = false;
+}
+
+// work list of group g: (problem, chunk), problem-major
+std::vector<int2> batch_work(const wdg_batch* b, const wdg_batch::Group& g) {
+  std::vector<int2> w;
+  const int epb = wdg::wedge_chunk_elems(g.N, b->bits);
+  for (int p : g.members) {
+    const int nch = int((b->probs[p]->Kw + epb - 1) / epb);
+    for (int c = 0; c < nch; ++c) w.push_back(make_int2(p, c));
+  }
+  return w;
+}
+
+// the stage records of every problem (static fields) and the per-problem parameters
+int batch_upload_records(wdg_batch* b) {
+  const size_t np = b->probs.size();
+  std::vector<wdg::StageLaunch> L(np);
+  std::vector<wdg::BatchParam> P(np);
+  for (size_t i = 0; i < np; ++i) {
+    wdg_ctx* ctx = b->probs[i];
+    wdg::StageLaunch& A = L[i];
+    A = wdg::StageLaunch{};
+    A.Uin = ctx->dU[ctx->cur];
+    A.Uout = nullptr;
+    A.res = ctx->dRes;
+    A.geo = ctx->dGeo;
+    A.L = ctx->dL;
+    A.conn = ctx->dConn;
+    A.srcvec = ctx->dSrcVec;
+    A.nsrc = int(ctx->src.size());
+    for (int s = 0; s < A.nsrc; ++s) A.src_elem[s] = int(ctx->src[s].elem);
+    A.dt = b->dts[i];
+    A.g = 1.0;
+    A.Kw = ctx->Kw;
+    const int flags = (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
+                      (ctx->flux == WDG_FLUX_CENTRAL ? wdg::kCentral : 0) |
+                      (ctx->mass == WDG_MASS_LUMPED ? wdg::kLumped : 0);
+    A.flags = flags;  // a stage-1 launch without U write: the state of the autotuning runs
+    wdg::BatchParam& Q = P[i];
+    Q = wdg::BatchParam{};
+    Q.U[0] = ctx->dU[0];
+    Q.U[1] = ctx->dU[1];
+    Q.cur0 = ctx->cur;
+    Q.dt = b->dts[i];
+    Q.t0 = ctx->time;
+    Q.flags = flags;
+    Q.nsrc = A.nsrc;
+  }
+  BHIPCHK(hipMemcpyAsync(b->dProbs, L.data(), np * sizeof(wdg::StageLaunch), hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(hipMemcpyAsync(b->dParam, P.data(), np * sizeof(wdg::BatchParam), hipMemcpyHostToDevice, b->stream));
+  const int64_t zero = 0;
+  BHIPCHK(hipMemcpyAsync(b->dCounter, &zero, sizeof(zero), hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(hipStreamSynchronize(b->stream));
+  return WDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wdg_batch_create(int device, int precision_bits, wdg_batch** out) {
+  if (!out) return WDG_ERR_ARG;
+  *out = nullptr;
+  if (precision_bits != 32 && precision_bits != 64) return WDG_ERR_ARG;
+  wdg_batch* b = new (std::nothrow) wdg_batch;
+  if (!b) return WDG_ERR_OOM;
+  b->device = device;
+  b->bits = precision_bits;
+  if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&b->stream) != hipSuccess) {
+    delete b;
+    return WDG_ERR_HIP;
+  }
+  *out = b;
+  return WDG_OK;
+}
+
+int wdg_batch_destroy(wdg_batch* b) {
+  if (!b) return WDG_OK;
+  (void)hipSetDevice(b->device);
+  (void)hipStreamSynchronize(b->stream);
+  batch_release(b);
+  (void)hipStreamDestroy(b->stream);
+  delete b;
+  return WDG_OK;
+}
+
+const char* wdg_batch_last_error(const wdg_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+int wdg_batch_add(wdg_batch* b, wdg_ctx* ctx, double dt, int* index) {
+  if (!b || !ctx) return WDG_ERR_ARG;
+  if (b->ready) return bfail(b, WDG_ERR_STATE, "add after prepare");
+  if (ctx->host_only || ctx->device != b->device || ctx->bits != b->bits)
+    return bfail(b, WDG_ERR_ARG, "problem on another device or precision");
+  if (ctx->state < kFields) return bfail(b, WDG_ERR_STATE, "problem without fields");
+  if (ctx->Kt > 0 || !ctx->mort.empty() || ctx->Kw == 0) return bfail(b, WDG_ERR_UNSUPPORTED, "batch: wedge meshes only");
+  if (!(dt > 0) || !std::isfinite(dt)) return bfail(b, WDG_ERR_ARG, "bad time step");
+  for (wdg_ctx* q : b->probs)
+    if (q == ctx) return bfail(b, WDG_ERR_ARG, "problem added twice");
+  b->probs.push_back(ctx);
+  b->dts.push_back(dt);
+  if (index) *index = int(b->probs.size()) - 1;
+  return WDG_OK;
+}
+
+int wdg_batch_prepare(wdg_batch* b, int autotune) {
+  if (!b) return WDG_ERR_ARG;
+  if (b->probs.empty()) return bfail(b, WDG_ERR_STATE, "empty batch");
+  BHIPCHK(hipSetDevice(b->device));
+  batch_release(b);
+  b->groups.clear();
+  for (size_t i = 0; i < b->probs.size(); ++i) {
+    const int N = b->probs[i]->N;
+    auto it = std::find_if(b->groups.begin(), b->groups.end(), [N](const wdg_batch::Group& g) { return g.N == N; });
+    if (it == b->groups.end()) {
+      b->groups.emplace_back();
+      b->groups.back().N = N;
+      it = b->groups.end() - 1;
+    }
+    it->members.push_back(int(i));
+  }
+  const size_t np = b->probs.size();
+  BHIPCHK(hipMalloc(&b->dProbs, np * sizeof(wdg::StageLaunch)));
+  BHIPCHK(hipMalloc(&b->dParam, np * sizeof(wdg::BatchParam)));
+  BHIPCHK(hipMalloc(&b->dCounter, sizeof(int64_t)));
+  int rc = batch_upload_records(b);
+  if (rc) return rc;
+
+  // autotuner: per order, the register budget of the stage kernel (occupancy
+  // 2 as the single-problem kernel, or 1: no spills at high order), timed on
+  // the real data with launches that only rewrite the residual (harmless at a
+  // step boundary, where the next stage overwrites it before reading)
+  hipEvent_t e0, e1;
+  BHIPCHK(hipEventCreate(&e0));
+  BHIPCHK(hipEventCreate(&e1));
+  for (auto& g : b->groups) {
+    const std::vector<int2> w = batch_work(b, g);
+    g.nwork = int(w.size());
+    BHIPCHK(hipMalloc(&g.dWork, w.size() * sizeof(int2)));
+    BHIPCHK(hipMemcpyAsync(g.dWork, w.data(), w.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+    g.wpe = 2;
+    g.tuned_us = 0.0f;
+    if (!autotune) continue;
+    float best = 1e30f;
+    for (int wpe = 2; wpe >= 1; --wpe) {
+      BHIPCHK(wdg::launch_wedge_batch(g.N, b->bits, b->dProbs, g.dWork, g.nwork, wpe, b->stream));
+      BHIPCHK(hipEventRecord(e0, b->stream));
+      for (int r = 0; r < 3; ++r) BHIPCHK(wdg::launch_wedge_batch(g.N, b->bits, b->dProbs, g.dWork, g.nwork, wpe, b->stream));
+      BHIPCHK(hipEventRecord(e1, b->stream));
+      BHIPCHK(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      BHIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      ms /= 3.0f;
+      if (ms < best) {
+        best = ms;
+        g.wpe = wpe;
+      }
+    }
+    g.tuned_us = best * 1e3f;
+  }
+  BHIPCHK(hipEventDestroy(e0));
+  BHIPCHK(hipEventDestroy(e1));
+  BHIPCHK(hipStreamSynchronize(b->stream));
+
+  b->ready = true;
+  return WDG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// one step as a graph: per stage the record kernel, then one launch per order;
+// then the step counter.  The amplitude table pointer is part of the graph.
+int batch_capture(wdg_batch* b) {
+  if (b->exec) BHIPCHK(hipGraphExecDestroy(b->exec));
+  if (b->graph) BHIPCHK(hipGraphDestroy(b->graph));
+  b->exec = nullptr;
+  b->graph = nullptr;
+  const int np = int(b->probs.size());
+  BHIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t cap = hipSuccess;
+  for (int s = 0; s < 5 && cap == hipSuccess; ++s) {
+    cap = wdg::launch_batch_prepare(np, b->dProbs, b->dParam, b->dCounter, s, kRkA[s], kRkB[s], b->dAmp, b->stream);
+    for (auto& g : b->groups)
+      if (cap == hipSuccess) cap = wdg::launch_wedge_batch(g.N, b->bits, b->dProbs, g.dWork, g.nwork, g.wpe, b->stream);
+  }
+  if (cap == hipSuccess) cap = wdg::launch_batch_advance(b->dCounter, b->stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t end = hipStreamEndCapture(b->stream, &graph);
+  BHIPCHK(cap);
+  BHIPCHK(end);
+  b->graph = graph;
+  BHIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return WDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wdg_batch_step(wdg_batch* b, int64_t nsteps) {
+  if (!b) return WDG_ERR_ARG;
+  if (!b->ready) return bfail(b, WDG_ERR_STATE, "step before prepare");
+  if (nsteps < 0) return bfail(b, WDG_ERR_ARG, "negative step count");
+  BHIPCHK(hipSetDevice(b->device));
+  for (wdg_ctx* ctx : b->probs) {
+    BHIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->recording = false;
+  }
+  // the problems' current buffers and times (the graph reads them from device memory)
+  int rc = batch_upload_records(b);
+  if (rc) return rc;
+  if (nsteps == 0) return WDG_OK;
+  // source amplitudes of every stage, evaluated as wdg_step does
+  const int np = int(b->probs.size());
+  if (nsteps > b->amp_steps || !b->exec) {
+    BHIPCHK(hipStreamSynchronize(b->stream));
+    dfree(b->dAmp);
+    b->amp_steps = 0;
+    BHIPCHK(hipMalloc(&b->dAmp, size_t(nsteps) * 5 * np * wdg::kMaxSources * sizeof(double)));
+    b->amp_steps = nsteps;
+    rc = batch_capture(b);
+    if (rc) return rc;
+  }
+  std::vector<double> amp(size_t(nsteps) * 5 * np * wdg::kMaxSources, 0.0);
+  for (int p = 0; p < np; ++p) {
+    const wdg_ctx* ctx = b->probs[p];
+    const double t0 = ctx->time, dt = b->dts[p];
+    for (int64_t n = 0; n < nsteps; ++n) {
+      const double tn = t0 + double(n) * dt;
+      for (int s = 0; s < 5; ++s)
+        for (size_t k = 0; k < ctx->src.size(); ++k)
+          amp[((size_t(n) * 5 + s) * np + p) * wdg::kMaxSources + k] = ctx->src[k].value(tn + kRkC[s] * dt);
+    }
+  }
+  BHIPCHK(hipMemcpyAsync(b->dAmp, amp.data(), amp.size() * sizeof(double), hipMemcpyHostToDevice, b->stream));
+  for (int64_t n = 0; n < nsteps; ++n) BHIPCHK(hipGraphLaunch(b->exec, b->stream));
+  BHIPCHK(hipStreamSynchronize(b->stream));
+  for (size_t i = 0; i < b->probs.size(); ++i) {
+    wdg_ctx* ctx = b->probs[i];
+    ctx->cur = int((ctx->cur + 5 * nsteps) & 1);
+    ctx->time = ctx->time + double(nsteps) * b->dts[i];
+  }
+  return WDG_OK;
+}
+
+int wdg_batch_config(const wdg_batch* b, int N, int* elems_per_block, int* waves_per_simd, double* tuned_us) {
+  if (!b) return WDG_ERR_ARG;
+  for (const auto& g : b->groups)
+    if (g.N == N) {
+      if (elems_per_block) *elems_per_block = wdg::wedge_chunk_elems(N, b->bits);
+      if (waves_per_simd) *waves_per_simd = g.wpe;
+      if (tuned_us) *tuned_us = g.tuned_us;
+      return WDG_OK;
+    }
+  return bfail(b, WDG_ERR_ARG, "no problem of that order in the batch");
+}
+
 }  // extern "C"

@@ -107,6 +107,29 @@ hipError_t launch_tet_stage(int N, int bits, const StageLaunch& a, hipStream_t s
 // Vinv (Np_tri x Np_tri: triangle Lagrange values -> Legendre-product modes P_a(r) P_b(s),
 // a+b <= N, a outer), P = (M^tri)^-1 Vinv^T (Np_tri x Np_tri).
 int mortar_table_size(int N, int bits);
+// Batches of independent wedge meshes (one launch per order and stage).
+// Per-problem parameters of the stage records written on the device.
+struct BatchParam {
+  void* U[2];        // the problem's ping-pong state buffers
+  int64_t cur0;      // buffer index holding the state at batch step 0
+  double dt, t0;     // time step; time at batch step 0
+  int flags;         // boundary / flux / mass flags
+  int nsrc;
+};
+// Elements per chunk of the wedge stage kernel (work granularity).
+int wedge_chunk_elems(int N, int bits);
+// One stage of every problem of order N: one block per chunk (problem, chunk)
+// of work; wpe (1 or 2) selects the register budget of the kernel.
+hipError_t launch_wedge_batch(int N, int bits, const StageLaunch* probs, const int2* work, int nwork, int wpe,
+                              hipStream_t st);
+// Stage s (coefficients a, b) of batch step *counter: writes the
+// stage-dependent fields of every problem's stage record; source amplitudes
+// come from amp[((step * 5 + s) * nprob + problem) * kMaxSources + source],
+// tabulated on the host with the single-problem driver's own arithmetic.
+hipError_t launch_batch_prepare(int nprob, StageLaunch* probs, const BatchParam* par, const int64_t* counter, int s,
+                                double a, double b, const double* amp, hipStream_t st);
+hipError_t launch_batch_advance(int64_t* counter, hipStream_t st);
+
 // Adjoint gradient (wedge meshes).  Per reverse stage: accumulate into gacc
 // (kGradStride FP64 values per wedge) dt times the mass terms sig^T M R of the
 // pressure and of the velocity and the face integrals 1/2 int sig_p [p],

@@ -73,7 +73,7 @@ __device__ __forceinline__ T pick(const double* tab, int j, int stride, int col)
 #endif
 // MODE 0: wedges only; 1: tetrahedra across triangular faces; 2: also mortars
 template <int N, typename T, int MODE>
-__global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageLaunch A) {
+__device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chunk) {
   constexpr bool HYB = MODE >= 1;
   using C = Cfg<N, T>;
   using RT = gen::RefTables<N>;
@@ -93,11 +93,6 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
   const T* __restrict__ Lm = static_cast<const T*>(A.L);
   const int* __restrict__ conn = A.conn;
 
-  // XCD-aware mapping: consecutive workgroups go to different XCDs, so give
-  // every XCD one contiguous range of chunks (face neighbours share its L2).
-  const int nb = gridDim.x, bid = blockIdx.x;
-  const int qd = nb / 8, rm = nb % 8, xcd = bid % 8, kk = bid / 8;
-  const int chunk = xcd < rm ? xcd * (qd + 1) + kk : rm * (qd + 1) + (xcd - rm) * qd + kk;
   const int64_t e0 = int64_t(chunk) * EPB;
   const int64_t left = A.Kw - e0;
   const int nE = left < EPB ? int(left) : EPB;
@@ -490,6 +485,47 @@ __global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageL
     update(std::false_type{});
 }
 
+// XCD-aware mapping: consecutive workgroups go to different XCDs, so give
+// every XCD one contiguous range of chunks (face neighbours share its L2).
+__device__ __forceinline__ int xcd_chunk(int bid, int nb) {
+  const int qd = nb / 8, rm = nb % 8, xcd = bid % 8, kk = bid / 8;
+  return xcd < rm ? xcd * (qd + 1) + kk : rm * (qd + 1) + (xcd - rm) * qd + kk;
+}
+
+template <int N, typename T, int MODE>
+__global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageLaunch A) {
+  wedge_stage_chunk<N, T, MODE>(A, xcd_chunk(blockIdx.x, gridDim.x));
+}
+
+// Many independent meshes of one order in one launch: block b takes chunk
+// w = (problem, chunk) of a problem-major list, every XCD one contiguous range
+// of it (face neighbours share an L2).  The stage record of each problem
+// (buffers, coefficients, time step, source amplitudes) is in device memory,
+// written by the batch preparation kernel of the stage.  WPE is the
+// occupancy the register allocation aims at (1: up to 512 registers, no
+// spills at high order; 2: as the single-problem kernel), chosen per order by
+// the batch autotuner.
+template <int N, typename T, int WPE>
+__global__ void __launch_bounds__(64, WPE)
+    wedge_batch_stage(const StageLaunch* __restrict__ probs, const int2* __restrict__ work, int nwork) {
+  const int w = xcd_chunk(blockIdx.x, gridDim.x);
+  if (w >= nwork) return;
+  const int2 it = work[w];
+  wedge_stage_chunk<N, T, 0>(probs[it.x], it.y);  // the record is wave-uniform: scalar loads
+}
+
+template <int N, typename T>
+hipError_t launch_wedge_batch_t(const StageLaunch* probs, const int2* work, int nwork, int wpe, hipStream_t st) {
+  if (nwork <= 0) return hipSuccess;
+  if (wpe == 1)
+    hipLaunchKernelGGL((wedge_batch_stage<N, T, 1>), dim3(unsigned(nwork)), dim3(Cfg<N, T>::BS), 0, st, probs, work,
+                       nwork);
+  else
+    hipLaunchKernelGGL((wedge_batch_stage<N, T, 2>), dim3(unsigned(nwork)), dim3(Cfg<N, T>::BS), 0, st, probs, work,
+                       nwork);
+  return hipGetLastError();
+}
+
 template <int N, typename T>
 hipError_t launch_wedge_stage_t(const StageLaunch& a, hipStream_t st) {
   using C = Cfg<N, T>;
@@ -505,6 +541,23 @@ hipError_t launch_wedge_stage_t(const StageLaunch& a, hipStream_t st) {
 }
 
 }  // namespace
+
+int wedge_chunk_elems(int N, int bits) {
+  int epb = 0;
+#define WDG_EPB(n, T) epb = Cfg<n, T>::EPB
+  WDG_DISPATCH_N(N, bits, WDG_EPB)
+#undef WDG_EPB
+  return epb;
+}
+
+hipError_t launch_wedge_batch(int N, int bits, const StageLaunch* probs, const int2* work, int nwork, int wpe,
+                              hipStream_t st) {
+  hipError_t err = hipErrorInvalidValue;
+#define WDG_STAGE(n, T) err = launch_wedge_batch_t<n, T>(probs, work, nwork, wpe, st)
+  WDG_DISPATCH_N(N, bits, WDG_STAGE)
+#undef WDG_STAGE
+  return err;
+}
 
 hipError_t launch_wedge_stage(int N, int bits, const StageLaunch& a, hipStream_t st) {
   hipError_t err = hipErrorInvalidValue;

@@ -206,6 +206,28 @@ def adjoint_problem(mesh: WedgeMesh, nrec: int = 16, seed: int = 0, amplitude: f
     return rec, (xs, 60.0, 0.02, 1.0), mesh.c * (1.0 + amplitude * bump)
 
 
+def batch_problems(n: int = 48, seed: int = 0, kmin: int = 1000, kmax: int = 60000):
+    """Independent problems of the batched workload: sizes log-uniform in
+    [kmin, kmax] wedges (nx x nx base, 4 to 16 layers, random smooth
+    interfaces), orders drawn from {2, 3, 4, 5}, seeded per-layer wave speed
+    in [1, 3] and density in [1, 2.5], and a Ricker source position inside.
+    Returns a list of (N, WedgeMesh, source xyz)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        target = float(np.exp(rng.uniform(np.log(kmin), np.log(kmax))))
+        layers = int(rng.integers(4, 17))
+        nx = max(2, int(round(np.sqrt(target / (2 * layers)))))
+        N = int(rng.choice([2, 3, 4, 5]))
+        v, w = layered_mesh(nx, nx, layers, smooth_interfaces(layers, 0.3, seed * 1000 + i))
+        cl = rng.uniform(1.0, 3.0, layers)
+        rl = rng.uniform(1.0, 2.5, layers)
+        lay = np.arange(len(w)) % layers
+        mesh = WedgeMesh(v, w, cl[lay], rl[lay], layers, f"batch{i}")
+        out.append((N, mesh, rng.uniform(0.2, 0.8, 3)))
+    return out
+
+
 def cfg3_hybrid_mesh(tet_layers: int = 5):
     """32x32 base (2048 triangles) x 24 layers with random smooth interfaces;
     the lowest ``tet_layers`` layers split into tetrahedra (3 per prism):

@@ -84,6 +84,13 @@ def load_library() -> C.CDLL:
         "wdg_read_kernel_timing": (C.c_int, [vp, _dp, _i64p]),
         "wdg_read_kernel_timing_split": (C.c_int, [vp, _dp, _i64p]),
         "wdg_reference_operator": (C.c_int, [C.c_int, C.c_char_p, _dp, C.c_int64, _i64p]),
+        "wdg_batch_create": (C.c_int, [C.c_int, C.c_int, C.POINTER(vp)]),
+        "wdg_batch_destroy": (C.c_int, [vp]),
+        "wdg_batch_last_error": (C.c_char_p, [vp]),
+        "wdg_batch_add": (C.c_int, [vp, vp, C.c_double, C.POINTER(C.c_int)]),
+        "wdg_batch_prepare": (C.c_int, [vp, C.c_int]),
+        "wdg_batch_step": (C.c_int, [vp, C.c_int64]),
+        "wdg_batch_config": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -357,3 +364,54 @@ class Solver:
         lift = np.zeros((self.Kw, self.NT, self.NT))
         self._check(self._lib.wdg_get_element_data(self._h, _ptr(geo), _ptr(lift)), "get_element_data")
         return geo, lift
+
+
+class Batch:
+    """Many independent problems (Solver objects on one device and precision)
+    advanced together: one launch per polynomial order and stage, one step
+    replayed as a HIP graph (see wdg_batch_* in wdg.h)."""
+
+    def __init__(self, precision: int = 32, device: int = 0):
+        self._lib = load_library()
+        h = C.c_void_p()
+        rc = self._lib.wdg_batch_create(device, precision, C.byref(h))
+        if rc:
+            raise WdgError(rc, "wdg_batch_create")
+        self._h = h
+        self.problems = []
+
+    def _check(self, rc: int, what: str):
+        if rc:
+            msg = self._lib.wdg_batch_last_error(self._h)
+            raise WdgError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def add(self, solver: Solver, dt: float) -> int:
+        idx = C.c_int()
+        self._check(self._lib.wdg_batch_add(self._h, solver._h, float(dt), C.byref(idx)), "batch_add")
+        self.problems.append(solver)
+        return idx.value
+
+    def prepare(self, autotune: bool = True):
+        self._check(self._lib.wdg_batch_prepare(self._h, int(bool(autotune))), "batch_prepare")
+
+    def step(self, nsteps: int):
+        self._check(self._lib.wdg_batch_step(self._h, int(nsteps)), "batch_step")
+
+    def config(self, N: int):
+        """(elements per block, waves per SIMD chosen by the autotuner, tuned stage microseconds)."""
+        e = C.c_int()
+        w = C.c_int()
+        us = C.c_double()
+        self._check(self._lib.wdg_batch_config(self._h, int(N), C.byref(e), C.byref(w), C.byref(us)), "batch_config")
+        return e.value, w.value, us.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.wdg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

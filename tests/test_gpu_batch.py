@@ -1,0 +1,119 @@
+"""Batched launch of independent problems (through the C ABI): the fields
+after batch steps equal those of each problem stepped alone (the same stage
+arithmetic), for meshes of different orders, sizes, materials, sources and
+time steps; one small problem also against the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import dg, lsrk
+from paper_1607_03399_amd import inputs
+from paper_1607_03399_amd import wdg
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _problem(N, nx, layers, seed, bits, src):
+    m = inputs.layered_config(nx, layers, 0.3, seed=seed)
+    s = wdg.Solver(N, bits, device=0)
+    s.set_mesh(m.verts, m.wedges)
+    s.set_material(m.c, m.rho)
+    s.set_boundary("rigid" if seed % 2 else "dirichlet")
+    s.set_flux("upwind" if seed % 3 else "central")
+    s.add_ricker_source(src, 8.0, 0.05, 1.0)
+    x = s.node_coords()
+    U = np.zeros((s.K, 4, s.NPmax))
+    U[:, 0] = inputs.gaussian_pulse(x, centre=src, width=0.2)
+    s.set_fields(U)
+    return m, s, U, s.stable_dt(0.5) * (0.8 + 0.05 * seed)
+
+
+SPECS = [(2, 3, 2, 1, [0.4, 0.5, 0.5]), (3, 4, 3, 2, [0.5, 0.3, 0.6]), (4, 2, 3, 3, [0.6, 0.6, 0.4]),
+         (5, 2, 2, 4, [0.3, 0.4, 0.5]), (3, 5, 2, 5, [0.5, 0.5, 0.5]), (2, 7, 3, 6, [0.7, 0.2, 0.3])]
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("autotune", [True, False])
+def test_batch_equals_single_problem_steps(bits, autotune):
+    batch = wdg.Batch(bits, device=0)
+    probs = []
+    for (N, nx, layers, seed, src) in SPECS:
+        m, s, U, dt = _problem(N, nx, layers, seed, bits, src)
+        batch.add(s, dt)
+        probs.append((N, nx, layers, seed, src, s, U, dt))
+    batch.prepare(autotune=autotune)
+    for N in sorted({p[0] for p in probs}):
+        _say("batch config N", N, batch.config(N))
+    batch.step(7)
+    batch.step(5)  # a second call continues from the state the first left
+    for (N, nx, layers, seed, src, s, U, dt) in probs:
+        got = s.get_fields()
+        assert abs(s.time - 12 * dt) <= 1e-12 * 12 * dt
+        assert s.time == (0.0 + 7 * dt) + 5 * dt
+        m, r, U2, dt2 = _problem(N, nx, layers, seed, bits, src)
+        assert dt2 == dt
+        r.step(7, dt)
+        r.step(5, dt)
+        ref = r.get_fields()
+        r.close()
+        _say("problem", N, nx, layers, "max abs diff", float(np.abs(got - ref).max()))
+        assert np.array_equal(got, ref)
+    batch.close()
+    for p in probs:
+        p[5].close()
+
+
+def test_batch_matches_oracle():
+    N, nx, layers, seed, src = 2, 2, 2, 7, [0.4, 0.5, 0.5]
+    batch = wdg.Batch(64, device=0)
+    m, s, U, dt = _problem(N, nx, layers, seed, 64, src)
+    m2, s2, U2, dt2 = _problem(3, 3, 2, 8, 64, [0.5, 0.5, 0.5])
+    batch.add(s, dt)
+    batch.add(s2, dt2)
+    batch.prepare()
+    batch.step(20)
+    got = s.get_fields()
+    om = dg.Mesh(m.verts, m.wedges, m.c, m.rho, "rigid" if seed % 2 else "dirichlet",
+                 "upwind" if seed % 3 else "central")
+    ops = dg.build_operators(om, N)
+    source = dg.make_point_source(om, N, src, 8.0, 0.05, 1.0)
+
+    def f(t, V):
+        out = dg.rhs(ops, V)
+        out[source.elem, 0] += source.value(t) * source.vec
+        return out
+
+    ref, _ = lsrk.integrate(f, U[:, :, :ops.M.shape[1]], dt, 20)
+    err = np.linalg.norm(got[:, :, :ref.shape[2]] - ref) / np.linalg.norm(ref)
+    _say("batch vs oracle", err)
+    assert err <= 1e-12
+    batch.close()
+    s.close()
+    s2.close()
+
+
+def test_batch_rejects_hybrid_and_late_adds():
+    batch = wdg.Batch(64, device=0)
+    v, w, t, c, rho = inputs.split_columns(inputs.layered_config(2, 2, 0.3, seed=4), [1])
+    h = wdg.Solver(2, 64, device=0)
+    h.set_mesh(v, w, t)
+    h.set_material(c, rho)
+    h.set_fields(np.zeros((h.K, 4, h.NPmax)))
+    with pytest.raises(wdg.WdgError) as e:
+        batch.add(h, 1e-3)
+    assert e.value.name == "WDG_ERR_UNSUPPORTED"
+    m, s, U, dt = _problem(2, 2, 2, 1, 64, [0.5, 0.5, 0.5])
+    batch.add(s, dt)
+    batch.prepare(autotune=False)
+    m2, s2, U2, dt2 = _problem(2, 2, 2, 2, 64, [0.5, 0.5, 0.5])
+    with pytest.raises(wdg.WdgError) as e:
+        batch.add(s2, dt2)
+    assert e.value.name == "WDG_ERR_STATE"
+    batch.close()
+    for q in (h, s, s2):
+        q.close()
