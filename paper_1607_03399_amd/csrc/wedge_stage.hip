@@ -492,8 +492,10 @@ __device__ __forceinline__ int xcd_chunk(int bid, int nb) {
   return xcd < rm ? xcd * (qd + 1) + kk : rm * (qd + 1) + (xcd - rm) * qd + kk;
 }
 
+// From N = 4 on, one wavefront per SIMD: the lane's triangle slice (15+
+// nodes x 4 equations, twice) then fits in registers instead of spilling.
 template <int N, typename T, int MODE>
-__global__ void __launch_bounds__(64, WDG_STAGE_WAVES_PER_EU) wedge_stage(StageLaunch A) {
+__global__ void __launch_bounds__(64, (N >= 4 ? 1 : WDG_STAGE_WAVES_PER_EU)) wedge_stage(StageLaunch A) {
   wedge_stage_chunk<N, T, MODE>(A, xcd_chunk(blockIdx.x, gridDim.x));
 }
 
