@@ -303,6 +303,8 @@ def main():
                          "39312 wedges + 29520 tetrahedra (20%% of the columns split), N=4; cfg3-layers: "
                          "38912 wedges + 30720 tetrahedra (lowest 5 of 24 layers split), N=4")
     ap.add_argument("--precision", type=int, default=32, choices=[32, 64])
+    ap.add_argument("--layer-march", action="store_true",
+                    help="stage kernel variant reading vertical neighbours inside a chunk from LDS")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -364,6 +366,7 @@ def main():
     s.set_material(c, rho)
     s.set_boundary("rigid")
     s.set_flux("upwind")
+    s.set_layer_march(args.layer_march)
     s.add_ricker_source([0.5, 0.5, 0.5], 10.0, 0.1, 1.0)
     s.set_fields(initial_state(s))
     s.bind_torch()

@@ -76,6 +76,7 @@ struct wdg_ctx {
   std::vector<double> geoT;   // Kt x kTetGeoStride (FP64 master copy)
   std::vector<double> c, rho;
   int bc = WDG_BC_RIGID, flux = WDG_FLUX_UPWIND, mass = WDG_MASS_EXACT;
+  bool layer_march = false;
   double time = 0.0;
 
   hipStream_t stream = nullptr;
@@ -405,7 +406,7 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.rout = rout;
   L.Kw = ctx->Kw;
   L.Kt = ctx->Kt;
-  L.flags = flags | (g != 1.0 ? wdg::kGamma : 0) | (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
+  L.flags = flags | (g != 1.0 ? wdg::kGamma : 0) | (ctx->layer_march ? wdg::kLayerMarch : 0) | (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
             (ctx->flux == WDG_FLUX_CENTRAL ? wdg::kCentral : 0) | (ctx->mass == WDG_MASS_LUMPED ? wdg::kLumped : 0);
   if (ctx->timing) {
     // events only between kernels that actually run (an event adds a gap to the stream)
@@ -1114,6 +1115,12 @@ int wdg_set_mass(wdg_ctx* ctx, int mass) {
     if (rc) return rc;
     return upload_sources(ctx);
   }
+  return WDG_OK;
+}
+
+int wdg_set_layer_march(wdg_ctx* ctx, int on) {
+  if (!ctx) return WDG_ERR_ARG;
+  ctx->layer_march = on != 0;
   return WDG_OK;
 }
 

@@ -58,6 +58,7 @@ enum StageFlags : int {
   kLumped = 16,    // Gauss-Lobatto mass in t: (M^1D)^-1 e_{0,N} becomes e_{0,N} / w_{0,N}
   kWriteR = 32,    // also store the stage right-hand side (sources included) to rout (wedges)
   kGamma = 64,     // U_out = g U_in + b res' (else g = 1)
+  kLayerMarch = 128,  // wedge meshes: vertical neighbours inside a chunk from LDS
 };
 
 // One stage over the whole mesh.  State buffers hold wedges first (Kw x Np_wedge

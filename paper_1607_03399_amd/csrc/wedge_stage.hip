@@ -71,10 +71,12 @@ __device__ __forceinline__ T pick(const double* tab, int j, int stride, int col)
 #ifndef WDG_STAGE_WAVES_PER_EU
 #define WDG_STAGE_WAVES_PER_EU 2
 #endif
-// MODE 0: wedges only; 1: tetrahedra across triangular faces; 2: also mortars
+// MODE 0: wedges only; 1: tetrahedra across triangular faces; 2: also mortars;
+// 3: wedges only, vertical neighbours inside the chunk read from LDS (layer marching)
 template <int N, typename T, int MODE>
 __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chunk) {
-  constexpr bool HYB = MODE >= 1;
+  constexpr bool HYB = MODE == 1 || MODE == 2;
+  constexpr bool MARCH = MODE == 3;
   using C = Cfg<N, T>;
   using RT = gen::RefTables<N>;
   constexpr int NT = C::NT, Nq = C::Nq, NP = C::NP, NPP = C::NPP, EPB = C::EPB;
@@ -151,6 +153,10 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chun
   }
   // triangular-face neighbour nodes: the 2 NT face nodes of the element are
   // shared out over its Nq lanes (surplus slots redo the last node)
+  // Layer marching (MODE 3): a chunk is a run of consecutive layers of one
+  // column, so the wedge below or above usually sits in the same chunk; its
+  // face nodes are then read from the staged chunk after the barrier instead
+  // of being gathered from memory.
   V4<T> gt[per];
 #pragma unroll
   for (int t = 0; t < per; ++t) {
@@ -169,7 +175,9 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chun
       const bool tet = src >= A.Kw;
       gt[t] = Uin[tet ? A.Kw * NP + (src - A.Kw) * TDim<N>::NP + tet_face_node<N>(tf, fn) : src * NP + nlev * NT + fn];
     } else {
-      gt[t] = Uin[src * NP + nlev * NT + fn];
+      const bool in_chunk = MARCH && nbr >= 0 && src >= e0 && src < e0 + nE;
+      gt[t] = V4<T>{T(0), T(0), T(0), T(0)};
+      if (!in_chunk) gt[t] = Uin[src * NP + nlev * NT + fn];
     }
   }
 #pragma unroll
@@ -188,6 +196,20 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chun
     sX[idx < EPB * VG ? EPB * VL + idx : EPB * C::XPE] = rG[k];
   }
   __syncthreads();
+  if constexpr (MARCH) {
+#pragma unroll
+    for (int t = 0; t < per; ++t) {
+      const int fraw = j * per + t;
+      const int fnode = fraw < 2 * NT ? fraw : 2 * NT - 1;
+      const int face = fnode >= NT ? 1 : 0;
+      const int nbr = face ? cn[1] : cn[0];
+      const int64_t ln = int64_t(nbr) - e0;
+      if (nbr >= 0 && ln >= 0 && ln < nE) {
+        const int nlev = ((code >> (6 + face)) & 1) ? N : 0;
+        gt[t] = sU[int(ln) * NPP + nlev * NT + face_perm<N>((code >> (3 * face)) & 7, fnode - face * NT)];
+      }
+    }
+  }
 
   const V4<T>* el = sU + le * NPP;
   const T* g = reinterpret_cast<const T*>(sG) + le * kGeoStride;
@@ -535,6 +557,8 @@ hipError_t launch_wedge_stage_t(const StageLaunch& a, hipStream_t st) {
   if (nchunks <= 0) return hipSuccess;
   if (a.nmort > 0)
     hipLaunchKernelGGL((wedge_stage<N, T, 2>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
+  else if (a.Kt == 0 && (a.flags & kLayerMarch))
+    hipLaunchKernelGGL((wedge_stage<N, T, 3>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
   else if (a.Kt > 0)
     hipLaunchKernelGGL((wedge_stage<N, T, 1>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
   else

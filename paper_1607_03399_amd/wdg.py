@@ -60,6 +60,7 @@ def load_library() -> C.CDLL:
         "wdg_set_boundary": (C.c_int, [vp, C.c_int]),
         "wdg_set_flux": (C.c_int, [vp, C.c_int]),
         "wdg_set_mass": (C.c_int, [vp, C.c_int]),
+        "wdg_set_layer_march": (C.c_int, [vp, C.c_int]),
         "wdg_num_nodes": (C.c_int, [vp, _i64p]),
         "wdg_get_node_coords": (C.c_int, [vp, _dp]),
         "wdg_set_fields": (C.c_int, [vp, _dp, _dp, _dp, _dp]),
@@ -184,6 +185,9 @@ class Solver:
 
     def set_flux(self, flux: str):
         self._check(self._lib.wdg_set_flux(self._h, FLUX[flux]), "set_flux")
+
+    def set_layer_march(self, on: bool):
+        self._check(self._lib.wdg_set_layer_march(self._h, int(bool(on))), "set_layer_march")
 
     def set_mass(self, mass: str):
         """'exact' (default, energy stable) or 'lumped' (Gauss-Lobatto in t, for comparison)."""
