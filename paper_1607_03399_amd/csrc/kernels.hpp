@@ -12,7 +12,7 @@ namespace wdg {
 //   9 kappa, 10 1/rho, 11 rho c, 12..15 bottom (J_f, n), 16..19 top (J_f, n),
 //   20+4e.. quad face e: J_f at first/second edge vertex, n_x, n_y,
 //   32..36 rho c + (rho c of the neighbour, or own on the boundary) per face
-//   (bottom, top, quad 0..2), 37..39 unused.
+//   (bottom, top, quad 0..2), 37..39 J_tri h_v / 2 (the M^{tri,k} weights).
 constexpr int kGeoStride = 40;
 // Per-element FP64 auxiliary record: 0..2 J_tri h_v / 2 (M^{tri,k} weights), 3 J_tri, 4 kappa, 5 rho.
 constexpr int kAuxStride = 8;

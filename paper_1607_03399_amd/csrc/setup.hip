@@ -75,6 +75,10 @@ __global__ void __launch_bounds__(64) setup_kernel(int NT, int LS, int64_t K, co
         gf[22 + 4 * ed] = dy / ell;
         gf[23 + 4 * ed] = -dx / ell;
       }
+      // M^{tri,k} = sum_v cw_v M_v: its weights for the stage kernel's lift
+      gf[37] = cw[0];
+      gf[38] = cw[1];
+      gf[39] = cw[2];
       for (int i = 0; i < kGeoStride; ++i) geo[k * kGeoStride + i] = T(gf[i]);
       double* ax = aux + k * kAuxStride;
       ax[0] = cw[0];

@@ -68,6 +68,14 @@ __device__ __forceinline__ T pick(const double* tab, int j, int stride, int col)
 //   update:  R goes through LDS so that the low-storage Runge-Kutta update
 //            reads and writes res and U with fully coalesced accesses
 // ---------------------------------------------------------------------------
+// L^{tri,k} built per stage from the three mass weights in the geometry
+// record (1) instead of read from its stored copy (0).  Building it saves its
+// NT^2 values of memory traffic per element and stage but costs a Cholesky
+// factorisation and NT column solves per element: on MI355X it measured 1%
+// slower at N = 3 and 14% slower at N = 4, so the stored copy is the default.
+#ifndef WDG_LIFT_OTF
+#define WDG_LIFT_OTF 0
+#endif
 #ifndef WDG_STAGE_WAVES_PER_EU
 #define WDG_STAGE_WAVES_PER_EU 2
 #endif
@@ -122,9 +130,9 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chun
     cn[4] = c1.x;
     cn[5] = c1.y;
   }
-  constexpr int SU = (EPB * NP + 63) / 64, SL = (EPB * VL + 63) / 64, SG = (EPB * VG + 63) / 64;
+  constexpr int SU = (EPB * NP + 63) / 64, SL = WDG_LIFT_OTF ? 0 : (EPB * VL + 63) / 64, SG = (EPB * VG + 63) / 64;
   constexpr int V4B = 4 * int(sizeof(T));
-  V4<T> rU[SU], rL[SL], rG[SG];
+  V4<T> rU[SU], rL[SL > 0 ? SL : 1], rG[SG];
   {
     const auto bu = chunk_rsrc(Uin + e0 * NP, int64_t(nE) * NP * V4B);
     const auto bl = chunk_rsrc(Lm + e0 * Dim<N>::LS, int64_t(nE) * VL * V4B);
@@ -213,6 +221,65 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chun
 
   const V4<T>* el = sU + le * NPP;
   const T* g = reinterpret_cast<const T*>(sG) + le * kGeoStride;
+
+  if constexpr (WDG_LIFT_OTF) {
+    // L^{tri,k} = (M^{tri,k})^-1 M^tri from the element's three mass weights
+    // (M^{tri,k} = sum_v w_v M_v, Sec. 4.2): every lane of the element factors
+    // M^{tri,k} (Cholesky), then solves for the columns m = j, j + Nq, ... of
+    // L into the lift region; the barrier before phase 2 publishes them.
+    if (le < EPB) {
+      const T w0 = g[37], w1 = g[38], w2 = g[39];
+      T Lc[NT * (NT + 1) / 2], dinv[NT];
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+#pragma unroll
+        for (int k = 0; k <= i; ++k) {
+          T m = 0;
+          constexpr_or_skip(RT::Mv[i * NT + k], m, w0);
+          constexpr_or_skip(RT::Mv[NT * NT + i * NT + k], m, w1);
+          constexpr_or_skip(RT::Mv[2 * NT * NT + i * NT + k], m, w2);
+#pragma unroll
+          for (int q = 0; q < k; ++q) m -= Lc[i * (i + 1) / 2 + q] * Lc[k * (k + 1) / 2 + q];
+          if (k == i) {
+            const T d = std::sqrt(m);
+            Lc[i * (i + 1) / 2 + i] = d;
+            dinv[i] = T(1) / d;
+          } else {
+            Lc[i * (i + 1) / 2 + k] = m * dinv[k];
+          }
+        }
+      }
+      T* Lf = reinterpret_cast<T*>(sL + le * VL);
+#pragma unroll
+      for (int mm = 0; mm < (NT + Nq - 1) / Nq; ++mm) {
+        const int m = j + mm * Nq;
+        if (m < NT) {
+          T y[NT];
+#pragma unroll
+          for (int i = 0; i < NT; ++i) {
+            T v = T(0);  // M^tri[i][m], m = j + mm Nq selected over the lane's j
+#pragma unroll
+            for (int jj = 0; jj < Nq; ++jj) {
+              const int c = mm * Nq + jj < NT ? mm * Nq + jj : NT - 1;
+              v = (j == jj) ? T(RT::Mtri[i * NT + c]) : v;
+            }
+#pragma unroll
+            for (int q = 0; q < i; ++q) v -= Lc[i * (i + 1) / 2 + q] * y[q];
+            y[i] = v * dinv[i];
+          }
+#pragma unroll
+          for (int i = NT - 1; i >= 0; --i) {
+            T v = y[i];
+#pragma unroll
+            for (int q = i + 1; q < NT; ++q) v -= Lc[q * (q + 1) / 2 + i] * y[q];
+            y[i] = v * dinv[i];
+          }
+#pragma unroll
+          for (int i = 0; i < NT; ++i) Lf[i * NT + m] = y[i];
+        }
+      }
+    }
+  }
 
   // pre-lift accumulators of the four equations on this level
   T Bp[NT], Bz[NT], Bx[NT], By[NT];
