@@ -134,9 +134,10 @@ def adjoint_benchmark(steps: int, every: int):
     FP32: 16 seeded receivers record p for ``steps`` steps; the data come from
     a wave speed with a seeded 10 % Gaussian anomaly; the gradient with respect
     to every element's c and rho by the discrete adjoint with checkpoints every
-    ``every`` steps.  Times the forward solve (which keeps the checkpoints)
-    and the gradient call (reverse sweep, recomputing the forward segment by
-    segment from the checkpoints) on the same GPU."""
+    ``every`` steps.  After an untimed warm-up pass (allocations), times the
+    forward solve (which keeps the checkpoints) and the gradient call (reverse
+    sweep, recomputing the forward segment by segment from the checkpoints)
+    on the same GPU."""
     from paper_1607_03399_amd import inputs
     from paper_1607_03399_amd import wdg
 
@@ -158,9 +159,15 @@ def adjoint_benchmark(steps: int, every: int):
     s.step(steps, dt)
     data = s.read_receivers()
     s.set_material(mesh.c, mesh.rho)
+    # warm-up pass (untimed): kernels, the checkpoint buffers and the reverse
+    # sweep's state buffers are allocated here and kept by the solver, as in
+    # repeated gradient evaluations (a fresh allocation of ~170 GB can take
+    # seconds on this driver once other large buffers have been freed)
     s.set_fields(U0)
     s.time = 0.0
-    s.step(2, dt)  # warm up the kernels
+    s.adjoint_record(every, steps)
+    s.step(steps, dt)
+    s.adjoint_gradient_recorded(s.read_receivers() - data)
     s.synchronize()
     s.set_fields(U0)
     s.time = 0.0

@@ -202,7 +202,10 @@ int wdg_adjoint_gradient_recorded(wdg_ctx* ctx, const double* weights, double* g
  * the free memory at the call).  Within budget the forward recomputation of
  * a checkpoint segment keeps all its stage data (10 states per step); else it
  * keeps the step-start states and every step recomputes its stages (one more
- * forward pass).  Both give identical results. */
+ * forward pass).  Both give identical results.  The sweep's state buffers
+ * stay allocated in the context for later gradient calls (reallocating tens
+ * of GB per call can cost more than the sweep); this call and wdg_destroy
+ * release them. */
 int wdg_set_adjoint_memory_limit(wdg_ctx* ctx, int64_t bytes);
 
 /* Batches: many independent problems (each a context with a wedge mesh of

@@ -120,6 +120,10 @@ struct wdg_ctx {
   void* dAdjCp = nullptr;
   size_t adj_cp_bytes = 0;
   size_t adj_mem_limit = 0;  // 0: automatic
+  // state buffers of the reverse sweep, kept for later gradient calls (a
+  // fresh allocation of this size costs more than the sweep on some drivers)
+  void* dAdjStore = nullptr;
+  size_t adj_store_bytes = 0;
   // per stage: start, after the mortar kernel, after the wedge kernel, after the tet kernel
   std::vector<std::array<hipEvent_t, 4>> events;
   size_t events_used = 0;
@@ -171,6 +175,9 @@ void release_device(wdg_ctx* ctx) {
   dfree(ctx->dGeo);
   dfree(ctx->dL);
   dfree(ctx->dAdjCp);
+  dfree(ctx->dAdjStore);
+  ctx->adj_store_bytes = 0;
+  ctx->adj_cp_bytes = 0;
   dfree(ctx->dSrcVec);
   dfree(ctx->dAux);
   dfree(ctx->dMv);
@@ -1441,15 +1448,27 @@ int adjoint_backward(wdg_ctx* ctx, const void* cp, int64_t C, int64_t nsteps, do
   HIPCHK(hipMemGetInfo(&free_b, &total_b));
   const size_t small = size_t(K) * (wdg::kGradStride + 2) * sizeof(double) + (size_t(nsteps) * nrec + rvec.size()) *
                         sizeof(double) + rbase.size() * sizeof(int64_t);
-  const size_t fixed = 6 * SB + small + (size_t(256) << 20);
-  const size_t budget = ctx->adj_mem_limit ? ctx->adj_mem_limit : size_t(0.85 * double(free_b));
-  const bool keep = fixed + size_t(10 * C) * SB <= budget;
+  const size_t fixed = small + (size_t(256) << 20);
+  const size_t avail = free_b + ctx->adj_store_bytes;  // the kept buffers count as available
+  const size_t budget = ctx->adj_mem_limit ? ctx->adj_mem_limit : size_t(0.85 * double(avail));
+  const bool keep = fixed + size_t(10 * C + 6) * SB <= budget;
+  // stage store, then the forward ping-pong pair and residual (3), then the
+  // adjoint state and the ping-pong pair of stage vectors (3)
+  const size_t nstore = size_t(keep ? 10 * C : C + 9);
+  const size_t need = (nstore + 6) * SB;
+  if (ctx->adj_store_bytes < need || ctx->adj_store_bytes > need + need / 2) {
+    HIPCHK(hipStreamSynchronize(st));
+    dfree(ctx->dAdjStore);
+    ctx->adj_store_bytes = 0;
+    HIPCHK(hipMalloc(&ctx->dAdjStore, need));
+    ctx->adj_store_bytes = need;
+  }
 
   DeviceScratch ds;
-  void *store, *tmp, *adj, *pg, *pw, *pv, *pb;
-  HIPCHK(ds.alloc(SB * size_t(keep ? 10 * C : C + 9), &store));
-  HIPCHK(ds.alloc(SB * 3, &tmp));  // forward ping-pong pair and residual
-  HIPCHK(ds.alloc(SB * 3, &adj));  // adjoint state and the ping-pong pair of stage vectors
+  void *pg, *pw, *pv, *pb;
+  void* const store = ctx->dAdjStore;
+  void* const tmp = static_cast<unsigned char*>(store) + nstore * SB;
+  void* const adj = static_cast<unsigned char*>(tmp) + 3 * SB;
   HIPCHK(ds.alloc(size_t(K) * (wdg::kGradStride + 2) * sizeof(double), &pg));
   HIPCHK(ds.alloc(size_t(nsteps) * nrec * sizeof(double), &pw));
   HIPCHK(ds.alloc(rvec.size() * sizeof(double), &pv));
@@ -1642,6 +1661,12 @@ int wdg_adjoint_gradient_recorded(wdg_ctx* ctx, const double* weights, double* g
 int wdg_set_adjoint_memory_limit(wdg_ctx* ctx, int64_t bytes) {
   if (!ctx || bytes < 0) return WDG_ERR_ARG;
   ctx->adj_mem_limit = size_t(bytes);
+  if (ctx->dAdjStore) {
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    dfree(ctx->dAdjStore);
+    ctx->adj_store_bytes = 0;
+  }
   return WDG_OK;
 }
 
