@@ -215,8 +215,9 @@ int wdg_set_adjoint_memory_limit(wdg_ctx* ctx, int64_t bytes);
  * is captured once as a HIP graph (five stages: a small kernel that writes
  * every problem's stage record on the device -- buffers, coefficients,
  * source amplitudes at the problem's own time -- then the per-order
- * launches; then a step counter) and replayed.  Each stage launch covers all
- * problems of one order: one block per element chunk of any problem.
+ * launches, which run concurrently on one stream per order; then a step
+ * counter) and replayed.  Each stage launch covers all problems of one order:
+ * one block per element chunk of any problem.
  *   wdg_batch_create: device and state precision (32 or 64) of the batch.
  *   wdg_batch_add: a context on that device and precision, with fields set,
  *     meshes of wedges only (else WDG_ERR_UNSUPPORTED); the batch keeps the

@@ -1887,6 +1887,9 @@ struct wdg_batch {
   int64_t amp_steps = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // one side stream per further order: the orders of a stage run concurrently
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> events;
   bool ready = false;
   mutable std::string err;
 };
@@ -1912,6 +1915,10 @@ void batch_release(wdg_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
+  for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+  for (hipStream_t q : b->side) (void)hipStreamDestroy(q);
+  b->events.clear();
+  b->side.clear();
   for (auto& g : b->groups) dfree(g.dWork);
   dfree(b->dProbs);
   dfree(b->dParam);
@@ -2039,6 +2046,8 @@ int wdg_batch_prepare(wdg_batch* b, int autotune) {
     }
     it->members.push_back(int(i));
   }
+  std::sort(b->groups.begin(), b->groups.end(),
+            [](const wdg_batch::Group& x, const wdg_batch::Group& y) { return x.N > y.N; });
   const size_t np = b->probs.size();
   BHIPCHK(hipMalloc(&b->dProbs, np * sizeof(wdg::StageLaunch)));
   BHIPCHK(hipMalloc(&b->dParam, np * sizeof(wdg::BatchParam)));
@@ -2098,12 +2107,37 @@ int batch_capture(wdg_batch* b) {
   b->exec = nullptr;
   b->graph = nullptr;
   const int np = int(b->probs.size());
+  const int ng = int(b->groups.size());
+  // side streams (default priority) and fork/join events, per stage and order
+  while (int(b->side.size()) < ng - 1) {
+    hipStream_t q = nullptr;
+    BHIPCHK(hipStreamCreate(&q));
+    b->side.push_back(q);
+  }
+  while (int(b->events.size()) < 5 * (ng + 1)) {
+    hipEvent_t e = nullptr;
+    BHIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    b->events.push_back(e);
+  }
   BHIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   hipError_t cap = hipSuccess;
+  auto ok = [&cap](hipError_t e) {
+    if (cap == hipSuccess) cap = e;
+  };
   for (int s = 0; s < 5 && cap == hipSuccess; ++s) {
-    cap = wdg::launch_batch_prepare(np, b->dProbs, b->dParam, b->dCounter, s, kRkA[s], kRkB[s], b->dAmp, b->stream);
-    for (auto& g : b->groups)
-      if (cap == hipSuccess) cap = wdg::launch_wedge_batch(g.N, b->bits, b->dProbs, g.dWork, g.nwork, g.wpe, b->stream);
+    ok(wdg::launch_batch_prepare(np, b->dProbs, b->dParam, b->dCounter, s, kRkA[s], kRkB[s], b->dAmp, b->stream));
+    hipEvent_t fork = b->events[s * (ng + 1)];
+    ok(hipEventRecord(fork, b->stream));
+    // the orders are independent within a stage: all but the first on side streams
+    for (int gi = 1; gi < ng; ++gi) {
+      const auto& g = b->groups[gi];
+      ok(hipStreamWaitEvent(b->side[gi - 1], fork, 0));
+      ok(wdg::launch_wedge_batch(g.N, b->bits, b->dProbs, g.dWork, g.nwork, g.wpe, b->side[gi - 1]));
+      ok(hipEventRecord(b->events[s * (ng + 1) + gi], b->side[gi - 1]));
+    }
+    const auto& g0 = b->groups[0];
+    ok(wdg::launch_wedge_batch(g0.N, b->bits, b->dProbs, g0.dWork, g0.nwork, g0.wpe, b->stream));
+    for (int gi = 1; gi < ng; ++gi) ok(hipStreamWaitEvent(b->stream, b->events[s * (ng + 1) + gi], 0));
   }
   if (cap == hipSuccess) cap = wdg::launch_batch_advance(b->dCounter, b->stream);
   hipGraph_t graph = nullptr;
