@@ -383,7 +383,8 @@ int upload_sources(wdg_ctx* ctx) {
 
 // one Runge-Kutta stage (or, with a = 0, dt = 1, no U write, a plain RHS)
 int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a, double b, double dt, double tstage,
-                 int flags, double g = 1.0, void* rout = nullptr, bool sources = true) {
+                 int flags, double g = 1.0, void* rout = nullptr, bool sources = true, const void* gUs = nullptr,
+                 const void* gRs = nullptr, double* gacc = nullptr) {
   wdg::StageLaunch L{};
   L.Uin = Uin;
   L.Uout = Uout;
@@ -411,6 +412,9 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.dt = dt;
   L.g = g;
   L.rout = rout;
+  L.gUs = gUs;
+  L.gRs = gRs;
+  L.gacc = gacc;
   L.Kw = ctx->Kw;
   L.Kt = ctx->Kt;
   L.flags = flags | (g != 1.0 ? wdg::kGamma : 0) | (ctx->layer_march ? wdg::kLayerMarch : 0) | (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
@@ -1549,11 +1553,11 @@ int adjoint_backward(wdg_ctx* ctx, const void* cp, int64_t C, int64_t nsteps, do
       }
       for (int s = 4; s >= 0; --s) {
         void* sig = at(adj, sc);
-        HIPCHK(wdg::launch_grad_stage(N, ctx->bits, K, sig, Us[s], Rs[s], ctx->dGeo, ctx->dConn, ctx->dAux, dt,
-                                      mflags, gacc, st));
-        // U~ += dt A sig;  sig <- a_s sig + b_{s-1} U~  (b of the previous step's last stage at s = 0)
+        // U~ += dt A sig;  sig <- a_s sig + b_{s-1} U~  (b of the previous step's last stage at s = 0);
+        // the same kernel accumulates the stage's gradient terms from Us[s], Rs[s]
         const int rc = launch_stage(ctx, sig, at(adj, 3 - sc), Ua, 1.0, s > 0 ? kRkB[s - 1] : kRkB[4], dt, 0.0,
-                                    wdg::kReadRes | wdg::kWriteU, kRkA[s], nullptr, false);
+                                    wdg::kReadRes | wdg::kWriteU | wdg::kGrad, kRkA[s], nullptr, false, Us[s], Rs[s],
+                                    gacc);
         if (rc) return rc;
         sc = 3 - sc;
       }

@@ -59,6 +59,7 @@ enum StageFlags : int {
   kWriteR = 32,    // also store the stage right-hand side (sources included) to rout (wedges)
   kGamma = 64,     // U_out = g U_in + b res' (else g = 1)
   kLayerMarch = 128,  // wedge meshes: vertical neighbours inside a chunk from LDS
+  kGrad = 256,        // wedge meshes, adjoint sweep: also accumulate the stage's gradient terms
 };
 
 // One stage over the whole mesh.  State buffers hold wedges first (Kw x Np_wedge
@@ -86,6 +87,10 @@ struct StageLaunch {
   // res' = a res + dt rhs;  U_out = g U_in + b res'  (the forward stages use g = 1)
   double a, b, dt, g;
   void* rout;  // kWriteR: the right-hand side, same layout as res
+  // kGrad: forward stage input and its right-hand side, gradient accumulators
+  const void* gUs;
+  const void* gRs;
+  double* gacc;
   int64_t Kw, Kt;
   int flags;
 };
@@ -133,14 +138,11 @@ hipError_t launch_batch_prepare(int nprob, StageLaunch* probs, const BatchParam*
                                 double a, double b, const double* amp, hipStream_t st);
 hipError_t launch_batch_advance(int64_t* counter, hipStream_t st);
 
-// Adjoint gradient (wedge meshes).  Per reverse stage: accumulate into gacc
-// (kGradStride FP64 values per wedge) dt times the mass terms sig^T M R of the
-// pressure and of the velocity and the face integrals 1/2 int sig_p [p],
-// 1/2 int sig_un [u_n] of the forward stage input Us.
+// Adjoint gradient (wedge meshes).  Per reverse stage the stage kernel (kGrad)
+// accumulates into gacc (kGradStride FP64 values per wedge) dt times the mass
+// terms sig^T M R of the pressure and of the velocity and the face integrals
+// 1/2 int sig_p [p], 1/2 int sig_un [u_n] of the forward stage input Us.
 constexpr int kGradStride = 12;
-hipError_t launch_grad_stage(int N, int bits, int64_t K, const void* sig, const void* Us, const void* Rs,
-                             const void* geo, const int* conn, const double* aux, double dt, int flags, double* gacc,
-                             hipStream_t st);
 // Gradient with respect to c and rho from the accumulated terms and the penalty derivatives.
 hipError_t launch_grad_combine(int bits, int64_t K, const double* gacc, const void* geo, const int* conn,
                                const double* aux, int flags, double* gc, double* grho, hipStream_t st);

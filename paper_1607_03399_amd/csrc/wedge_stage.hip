@@ -3,6 +3,7 @@
 // Runge-Kutta update of one stage (Sec. 4.2-4.3).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <type_traits>
 
 #include "device_common.hpp"
@@ -53,6 +54,255 @@ __device__ __forceinline__ T pick(const double* tab, int j, int stride, int col)
   return v;
 }
 
+
+// Gradient terms of one reverse stage of the adjoint sweep (MODE 4), run by
+// the stage kernel after its update.  The stage input (the adjoint stage
+// vector sig) is still staged in sU; the forward stage input Us and its
+// right-hand side Rs are staged into the freed LDS regions.  Per wedge it
+// accumulates dt times the mass terms sig_p^T M R_p, sig_u^T M R_u (as
+// dJ/dc = 2/(c kappa) m_p, dJ/drho = m_p/(rho kappa) + m_u) and the face
+// integrals 1/2 int sig_p [p], 1/2 int sig_un [u_n] of Us per face
+// (gacc slots 2..6 and 7..11), which the combine kernel turns into the
+// penalty derivatives.  M^k = (sum_v w_v M_v) (x) M^1D and the face masses
+// are literals (reference triangle, 1D, edge masses).
+template <int N, typename T>
+__device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, int nE, int tid, int le, int j,
+                                              bool active, int64_t e, V4<T>* sU, V4<T>* sX) {
+  using C = Cfg<N, T>;
+  using RT = gen::RefTables<N>;
+  constexpr int NT = C::NT, Nq = C::Nq, NP = C::NP, NPP = C::NPP, EPB = C::EPB;
+  constexpr int V4B = 4 * int(sizeof(T));
+  constexpr int SU = (EPB * NP + 63) / 64;
+  constexpr int GS = kGradStride + 1;  // partial sums per lane (odd: fewer bank conflicts)
+  static_assert(EPB * 3 * Nq * Nq * 2 <= EPB * NPP * 4, "jump scratch fits the state region");
+  static_assert(EPB * Nq * GS * 8 <= EPB * C::XPE * 4 * int(sizeof(T)), "partial sums fit the second region");
+  const bool lane_ok = le < EPB;
+  const T bsign = (A.flags & kDirichlet) ? T(-1) : T(1);
+  const int lb = (lane_ok ? le : 0) * NPP + j * NT;
+  const V4<T>* __restrict__ Us = static_cast<const V4<T>*>(A.gUs);
+  const T* __restrict__ g = static_cast<const T*>(A.geo) + e * kGeoStride;
+  const int* __restrict__ cn = A.conn + e * kConnStride;
+  const int code = cn[5];
+
+  V4<T> sg[NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) sg[i] = sU[lb + i];
+  // neighbour nodes of the forward stage input on the quadrilateral faces (this level)
+  V4<T> gq[3][Nq];
+#pragma unroll
+  for (int ed = 0; ed < 3; ++ed) {
+    const int nbr = cn[2 + ed];
+    const int ned = (code >> (8 + 2 * ed)) & 3;
+    const V4<T>* nb_el = Us + (nbr >= 0 ? int64_t(nbr) : e) * NP + j * NT;
+#pragma unroll
+    for (int q = 0; q < Nq; ++q) {
+      const int ni = ned == 0 ? edge_node(N, 0, N - q) : (ned == 1 ? edge_node(N, 1, N - q) : edge_node(N, 2, N - q));
+      gq[ed][q] = nb_el[ni];
+    }
+  }
+  __syncthreads();  // the update and the reads of sig are done
+  {
+    const int64_t bytes = int64_t(nE) * NP * V4B;
+    const auto bu = chunk_rsrc(Us + e0 * NP, bytes);
+    const auto br = chunk_rsrc(static_cast<const V4<T>*>(A.gRs) + e0 * NP, bytes);
+    V4<T> a[SU], b[SU];
+#pragma unroll
+    for (int k = 0; k < SU; ++k) {
+      a[k] = bload<T>(bu, tid + 64 * k);
+      b[k] = bload<T>(br, tid + 64 * k);
+    }
+#pragma unroll
+    for (int k = 0; k < SU; ++k) {
+      const int idx = tid + 64 * k;
+      const int l = idx < EPB * NP ? idx + (idx / NP) * (NPP - NP) : EPB * NPP;
+      sX[l] = a[k];  // Us
+      sU[l] = b[k];  // Rs
+    }
+  }
+  __syncthreads();
+  double part[kGradStride];
+#pragma unroll
+  for (int k = 0; k < kGradStride; ++k) part[k] = 0.0;
+  const V4<T>* sUs = sX;
+  const V4<T>* sRs = sU;
+
+  // triangular faces: lane 0 the bottom, lane N the top (own level)
+  if (lane_ok && (j == 0 || j == N)) {
+    const int face = j == 0 ? 0 : 1;
+    const int nbr = cn[face];
+    const int pc = (code >> (3 * face)) & 7;
+    const int nlev = ((code >> (6 + face)) & 1) ? N : 0;
+    const T Jf = g[12 + 4 * face], nx = g[13 + 4 * face], ny = g[14 + 4 * face], nz = g[15 + 4 * face];
+    T jp[NT], jn[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const V4<T> own = sUs[lb + i];
+      const T pm = own.p, unm = nx * own.ux + ny * own.uy + nz * own.uz;
+      T pp = bsign * pm, unp = -bsign * unm;  // mirror state
+      if (nbr >= 0) {
+        const V4<T> v = Us[int64_t(nbr) * NP + nlev * NT + face_perm<N>(pc, i)];
+        pp = v.p;
+        unp = nx * v.ux + ny * v.uy + nz * v.uz;
+      }
+      jp[i] = pp - pm;
+      jn[i] = unp - unm;
+    }
+    T sp = 0, sn = 0;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      T mp = 0, mn = 0;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        constexpr_or_skip(RT::Mtri[i * NT + k], mp, jp[k]);
+        constexpr_or_skip(RT::Mtri[i * NT + k], mn, jn[k]);
+      }
+      sp += sg[i].p * mp;
+      sn += (nx * sg[i].ux + ny * sg[i].uy + nz * sg[i].uz) * mn;
+    }
+    part[2 + face] = 0.5 * double(Jf) * double(sp);
+    part[7 + face] = 0.5 * double(Jf) * double(sn);
+  }
+
+  // quadrilateral faces: jumps of this level (to LDS below); the adjoint
+  // trace times the edge mass stays in registers
+  T jq[3][Nq][2], ap[3][Nq], an[3][Nq];
+#pragma unroll
+  for (int ed = 0; ed < 3; ++ed) {
+    const int nbr = cn[2 + ed];
+    const T Ja = g[20 + 4 * ed], Jb = g[21 + 4 * ed], nx = g[22 + 4 * ed], ny = g[23 + 4 * ed];
+    T sp[Nq], sn[Nq];
+#pragma unroll
+    for (int q = 0; q < Nq; ++q) {
+      const int i = edge_node(N, ed, q);
+      const V4<T> own = sUs[lb + i];
+      const T pm = own.p, unm = nx * own.ux + ny * own.uy;
+      T pp = bsign * pm, unp = -bsign * unm;
+      if (nbr >= 0) {
+        pp = gq[ed][q].p;
+        unp = nx * gq[ed][q].ux + ny * gq[ed][q].uy;
+      }
+      jq[ed][q][0] = pp - pm;
+      jq[ed][q][1] = unp - unm;
+      sp[q] = sg[i].p;
+      sn[q] = nx * sg[i].ux + ny * sg[i].uy;
+    }
+#pragma unroll
+    for (int qq = 0; qq < Nq; ++qq) {
+      T vpa = 0, vna = 0, vpb = 0, vnb = 0;
+#pragma unroll
+      for (int q = 0; q < Nq; ++q) {
+        constexpr_or_skip(RT::Ma[q * Nq + qq], vpa, sp[q]);
+        constexpr_or_skip(RT::Ma[q * Nq + qq], vna, sn[q]);
+        constexpr_or_skip(RT::Mb[q * Nq + qq], vpb, sp[q]);
+        constexpr_or_skip(RT::Mb[q * Nq + qq], vnb, sn[q]);
+      }
+      ap[ed][qq] = Ja * vpa + Jb * vpb;
+      an[ed][qq] = Ja * vna + Jb * vnb;
+    }
+  }
+
+  T m1[Nq];
+#pragma unroll
+  for (int m = 0; m < Nq; ++m) m1[m] = pick<Nq, T>(RT::M1, j, Nq, m);
+  if (lane_ok) {
+    // mass terms on this level: sig^T (M^{tri,k} (x) M^1D) R, M^{tri,k} = sum_v w_v M_v
+    const T w0 = g[37], w1 = g[38], w2 = g[39];
+    T y[4][NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+      for (int m = 0; m < Nq; ++m) {
+        const V4<T> r = sRs[le * NPP + m * NT + i];
+        a0 += m1[m] * r.p;
+        a1 += m1[m] * r.ux;
+        a2 += m1[m] * r.uy;
+        a3 += m1[m] * r.uz;
+      }
+      y[0][i] = a0;
+      y[1][i] = a1;
+      y[2][i] = a2;
+      y[3][i] = a3;
+    }
+    T mp = 0, mu = 0;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      T z0 = 0, z1 = 0, z2 = 0, z3 = 0;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        T m = 0;
+        constexpr_or_skip(RT::Mv[i * NT + k], m, w0);
+        constexpr_or_skip(RT::Mv[NT * NT + i * NT + k], m, w1);
+        constexpr_or_skip(RT::Mv[2 * NT * NT + i * NT + k], m, w2);
+        z0 += m * y[0][k];
+        z1 += m * y[1][k];
+        z2 += m * y[2][k];
+        z3 += m * y[3][k];
+      }
+      mp += sg[i].p * z0;
+      mu += sg[i].ux * z1 + sg[i].uy * z2 + sg[i].uz * z3;
+    }
+    part[0] = double(mp);
+    part[1] = double(mu);
+  }
+  __syncthreads();  // Us and Rs in LDS are consumed
+  T* const sJ = reinterpret_cast<T*>(sU);  // quadrilateral-face jumps [wedge][edge][level][node][p, u_n]
+  if (lane_ok) {
+#pragma unroll
+    for (int ed = 0; ed < 3; ++ed)
+#pragma unroll
+      for (int q = 0; q < Nq; ++q) {
+        T* sj = sJ + (((le * 3 + ed) * Nq + j) * Nq + q) * 2;
+        sj[0] = jq[ed][q][0];
+        sj[1] = jq[ed][q][1];
+      }
+  }
+  __syncthreads();
+  double* const sPart = reinterpret_cast<double*>(sX);
+  if (lane_ok) {
+    // quadrilateral faces: couple the levels through M^1D
+#pragma unroll
+    for (int ed = 0; ed < 3; ++ed) {
+      T sp = 0, sn = 0;
+#pragma unroll
+      for (int m = 0; m < Nq; ++m) {
+        const T* sj = sJ + ((le * 3 + ed) * Nq + m) * Nq * 2;
+        T tp = 0, tn = 0;
+#pragma unroll
+        for (int qq = 0; qq < Nq; ++qq) {
+          tp += ap[ed][qq] * sj[2 * qq];
+          tn += an[ed][qq] * sj[2 * qq + 1];
+        }
+        sp += m1[m] * tp;
+        sn += m1[m] * tn;
+      }
+      part[4 + ed] = 0.5 * double(sp);
+      part[9 + ed] = 0.5 * double(sn);
+    }
+#pragma unroll
+    for (int k = 0; k < kGradStride; ++k) sPart[(le * Nq + j) * GS + k] = part[k];
+  }
+  __syncthreads();
+  if (active && j == 0) {
+    double tot[kGradStride];
+#pragma unroll
+    for (int k = 0; k < kGradStride; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < Nq; ++l) s += sPart[(le * Nq + l) * GS + k];
+      tot[k] = s;
+    }
+    const double kap = double(g[9]), irho = double(g[10]);
+    const double c = std::sqrt(kap * irho);
+    double* ga = A.gacc + e * kGradStride;
+    const double dt = A.dt;
+    ga[0] += dt * 2.0 / (c * kap) * tot[0];
+    ga[1] += dt * (tot[0] * irho / kap + tot[1]);
+#pragma unroll
+    for (int k = 2; k < kGradStride; ++k) ga[k] += dt * tot[k];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Fused stage kernel
 //
@@ -80,7 +330,8 @@ __device__ __forceinline__ T pick(const double* tab, int j, int stride, int col)
 #define WDG_STAGE_WAVES_PER_EU 2
 #endif
 // MODE 0: wedges only; 1: tetrahedra across triangular faces; 2: also mortars;
-// 3: wedges only, vertical neighbours inside the chunk read from LDS (layer marching)
+// 3: wedges only, vertical neighbours inside the chunk read from LDS (layer marching);
+// 4: wedges only, adjoint stage with its gradient terms (grad_epilogue)
 template <int N, typename T, int MODE>
 __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chunk) {
   constexpr bool HYB = MODE == 1 || MODE == 2;
@@ -572,6 +823,7 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chun
     update(std::true_type{});
   else
     update(std::false_type{});
+  if constexpr (MODE == 4) grad_epilogue<N, T>(A, e0, nE, tid, le, j, active, e, sU, sX);
 }
 
 // XCD-aware mapping: consecutive workgroups go to different XCDs, so give
@@ -624,6 +876,8 @@ hipError_t launch_wedge_stage_t(const StageLaunch& a, hipStream_t st) {
   if (nchunks <= 0) return hipSuccess;
   if (a.nmort > 0)
     hipLaunchKernelGGL((wedge_stage<N, T, 2>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
+  else if (a.Kt == 0 && (a.flags & kGrad))
+    hipLaunchKernelGGL((wedge_stage<N, T, 4>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
   else if (a.Kt == 0 && (a.flags & kLayerMarch))
     hipLaunchKernelGGL((wedge_stage<N, T, 3>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
   else if (a.Kt > 0)
