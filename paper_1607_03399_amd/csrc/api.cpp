@@ -14,6 +14,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.hpp"
@@ -101,6 +102,7 @@ struct wdg_ctx {
   int32_t* dMortI = nullptr;
   void* dMortG = nullptr;
   void* dMortTab = nullptr;
+  void* dMortC = nullptr;
   void* dMortB = nullptr;
   void* dMortF = nullptr;
   std::vector<Source> src;
@@ -192,6 +194,7 @@ void release_device(wdg_ctx* ctx) {
   dfree(ctx->dMortI);
   dfree(ctx->dMortG);
   dfree(ctx->dMortTab);
+  dfree(ctx->dMortC);
   dfree(ctx->dMortB);
   dfree(ctx->dMortF);
   dfree(ctx->dRecBase);
@@ -399,6 +402,7 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.mortI = ctx->dMortI;
   L.mortG = ctx->dMortG;
   L.mortTab = ctx->dMortTab;
+  L.mortC = ctx->dMortC;
   L.mortB = ctx->dMortB;
   L.mortF = ctx->dMortF;
   L.nmort = int64_t(ctx->mort.size());
@@ -484,38 +488,40 @@ void legendre_all(int N, double x, double* P) {
   for (int n = 1; n < N; ++n) P[n + 1] = ((2.0 * n + 1.0) * x * P[n] - n * P[n - 1]) / (n + 1.0);
 }
 
-// Reference tables of the mortar quadrature, in the layout of wdg::mortar_table_size
-std::vector<double> mortar_tables(const RefOps& R, int bits) {
-  const int N = R.N, NT = R.NT, Nq = R.Nq, NX = wdg::mort_nx(R.N, bits);
+// Reference tables of the mortar outputs, in the layout of wdg::mortar_table_size
+std::vector<double> mortar_tables(const RefOps& R) {
+  const int NT = R.NT, Nq = R.Nq;
   std::vector<double> out;
-  std::vector<double> xg, wg, tg, wt;
-  wdg::gauss_legendre(NX, xg, wg);
-  wdg::gauss_legendre(Nq, tg, wt);
-  out.insert(out.end(), xg.begin(), xg.end());
-  out.insert(out.end(), wg.begin(), wg.end());
-  out.insert(out.end(), tg.begin(), tg.end());
-  out.insert(out.end(), wt.begin(), wt.end());
-  out.insert(out.end(), R.t.begin(), R.t.end());
-  for (int m = 0; m < Nq; ++m)
-    for (int mm = 0; mm < Nq; ++mm) out.push_back(m == mm ? 0.0 : 1.0 / (R.t[m] - R.t[mm]));
   std::vector<double> Minv1(Nq * Nq, 0.0);
   for (int i = 0; i < Nq; ++i) Minv1[i * Nq + i] = 1.0;
   wdg::solve_dense(Nq, Nq, R.M1, Minv1);
   out.insert(out.end(), Minv1.begin(), Minv1.end());
-  std::vector<double> E(NX * Nq);
-  for (int a = 0; a < NX; ++a) R.line_basis(xg[a], &E[a * Nq]);
-  out.insert(out.end(), E.begin(), E.end());
   std::vector<double> MtriInv(NT * NT, 0.0);
   for (int i = 0; i < NT; ++i) MtriInv[i * NT + i] = 1.0;
   wdg::solve_dense(NT, NT, R.Mtri, MtriInv);
   for (int e = 0; e < 3; ++e)
-    for (int a = 0; a < NX; ++a)
-      for (int i = 0; i < NT; ++i) {
-        double acc = 0.0;
-        for (int q = 0; q < Nq; ++q) acc += MtriInv[i * NT + R.edge_nodes[e][q]] * E[a * Nq + q];
-        out.push_back(acc);
-      }
-  // Legendre-product modes P_a(r) P_b(s), a + b <= N (a outer), at the triangle nodes
+    for (int i = 0; i < NT; ++i)
+      for (int q = 0; q < Nq; ++q) out.push_back(MtriInv[i * NT + R.edge_nodes[e][q]]);
+  out.insert(out.end(), MtriInv.begin(), MtriInv.end());
+  return out;
+}
+
+// Coupling matrices of the mortars (FP64, once per mesh).  Per mortar and side
+// of the diagonal, C = int b b^T dA over that side of the quadrilateral, with
+// b = (wedge face Lagrange basis l_q(xi) l_m(t), level-major; the tetrahedron
+// face's Lagrange basis) and dA the physical area element of the wedge face.
+// The side is integrated in the wedge face's (xi, t) coordinates: mort_nx(N)
+// Gauss points in xi times Nq Gauss points in t between the bottom (top) and
+// the diagonal, exact in t at fixed xi (degree <= 2N); lower triangles packed
+// by columns, both sides per mortar, wdg::mort_core_stride values each.
+std::vector<double> mortar_cores(const RefOps& R, const std::vector<MortarHost>& mort) {
+  const int N = R.N, NT = R.NT, Nq = R.Nq, NW = Nq * Nq, n = wdg::mort_core_n(N), NX = wdg::mort_nx(N);
+  const int CS = wdg::mort_core_stride(N), NPK = n * (n + 1) / 2;
+  std::vector<double> xg, wg, tg, wt;
+  wdg::gauss_legendre(NX, xg, wg);
+  wdg::gauss_legendre(Nq, tg, wt);
+  // tetrahedron face nodal basis = Legendre products P_a(r) P_b(s) (a + b <= N)
+  // combined by the inverse of their Vandermonde at the triangle nodes
   std::vector<double> V(NT * NT), Vinv(NT * NT, 0.0), Pr(N + 1), Ps(N + 1);
   for (int i = 0; i < NT; ++i) {
     legendre_all(N, R.r[i], Pr.data());
@@ -525,16 +531,78 @@ std::vector<double> mortar_tables(const RefOps& R, int bits) {
       for (int b = 0; a + b <= N; ++b) V[i * NT + md++] = Pr[a] * Ps[b];
   }
   for (int i = 0; i < NT; ++i) Vinv[i * NT + i] = 1.0;
-  wdg::solve_dense(NT, NT, V, Vinv);  // Vinv[md][i]: nodal values -> modal coefficients
-  out.insert(out.end(), Vinv.begin(), Vinv.end());
-  // P = (M^tri)^-1 Vinv^T maps modal moments to the equivalent nodal face flux
-  for (int i = 0; i < NT; ++i)
-    for (int md = 0; md < NT; ++md) {
-      double acc = 0.0;
-      for (int m = 0; m < NT; ++m) acc += MtriInv[i * NT + m] * Vinv[md * NT + m];
-      out.push_back(acc);
+  wdg::solve_dense(NT, NT, V, Vinv);  // Vinv[md][i]
+  std::vector<double> lxi(size_t(NX) * Nq);
+  for (int a = 0; a < NX; ++a) R.line_basis(xg[a], &lxi[size_t(a) * Nq]);
+  const size_t nm = mort.size();
+  std::vector<double> out(nm * CS, 0.0);
+  auto work = [&](size_t m0, size_t m1) {
+    std::vector<double> b(n), lt(Nq), pr(N + 1), ps(N + 1), ph(NT);
+    for (size_t m = m0; m < m1; ++m) {
+      const MortarHost& M = mort[m];
+      for (int side = 0; side < 2; ++side) {
+        double* C = &out[m * CS + size_t(side) * NPK];
+        const double* lm = M.lam[side];
+        for (int a = 0; a < NX; ++a) {
+          const double xi = xg[a];
+          const double zb = M.zba * 0.5 * (1.0 - xi) + M.zbb * 0.5 * (1.0 + xi);
+          const double zt = M.zta * 0.5 * (1.0 - xi) + M.ztb * 0.5 * (1.0 + xi);
+          const double h = zt - zb;
+          const double zd = M.diag == 0 ? M.zba * 0.5 * (1.0 - xi) + M.ztb * 0.5 * (1.0 + xi)
+                                        : M.zbb * 0.5 * (1.0 + xi) + M.zta * 0.5 * (1.0 - xi);
+          const double td = (2.0 * zd - zb - zt) / h;
+          const double lo = side == 0 ? -1.0 : td, hi = side == 0 ? td : 1.0;
+          for (int g = 0; g < Nq; ++g) {
+            const double t = 0.5 * (lo + hi) + 0.5 * (hi - lo) * tg[g];
+            const double w = wg[a] * wt[g] * 0.5 * (hi - lo) * 0.25 * M.ell * h;
+            const double z = zb * 0.5 * (1.0 - t) + zt * 0.5 * (1.0 + t);
+            R.line_basis(t, lt.data());
+            for (int lev = 0; lev < Nq; ++lev)
+              for (int q = 0; q < Nq; ++q) b[lev * Nq + q] = lt[lev] * lxi[size_t(a) * Nq + q];
+            const double l1 = lm[3] * xi + lm[4] * z + lm[5], l2 = lm[6] * xi + lm[7] * z + lm[8];
+            legendre_all(N, 2.0 * l1 - 1.0, pr.data());
+            legendre_all(N, 2.0 * l2 - 1.0, ps.data());
+            int md = 0;
+            for (int aa = 0; aa <= N; ++aa)
+              for (int bb = 0; aa + bb <= N; ++bb) ph[md++] = pr[aa] * ps[bb];
+            for (int i = 0; i < NT; ++i) {
+              double v = 0.0;
+              for (int k = 0; k < NT; ++k) v += Vinv[k * NT + i] * ph[k];
+              b[NW + i] = v;
+            }
+            int o = 0;
+            for (int c = 0; c < n; ++c) {
+              const double wc = w * b[c];
+              for (int r = c; r < n; ++r) C[o++] += wc * b[r];
+            }
+          }
+        }
+      }
     }
+  };
+  const size_t nthr = std::min<size_t>(std::max(1u, std::thread::hardware_concurrency()), 16);
+  if (nm < 256 || nthr == 1) {
+    work(0, nm);
+  } else {
+    std::vector<std::thread> pool;
+    const size_t per = (nm + nthr - 1) / nthr;
+    for (size_t t = 0; t < nthr; ++t) {
+      const size_t m0 = t * per, m1 = std::min(nm, m0 + per);
+      if (m0 < m1) pool.emplace_back(work, m0, m1);
+    }
+    for (auto& th : pool) th.join();
+  }
   return out;
+}
+
+// FP64 values in the device precision
+std::vector<unsigned char> to_precision(const std::vector<double>& v, int bits) {
+  std::vector<unsigned char> buf(v.size() * size_t(bits / 8));
+  for (size_t i = 0; i < v.size(); ++i) {
+    if (bits == 32) reinterpret_cast<float*>(buf.data())[i] = float(v[i]);
+    else reinterpret_cast<double*>(buf.data())[i] = v[i];
+  }
+  return buf;
 }
 
 // mortar value records (geometry, and the impedance sums of the current material)
@@ -1023,17 +1091,19 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
       o[5] = int32_t(M.t[1]);
       o[6] = M.tf[1];
     }
-    const std::vector<double> tabs = mortar_tables(R, ctx->bits);
-    if (int(tabs.size()) != wdg::mortar_table_size(ctx->N, ctx->bits))
-      return fail(ctx, WDG_ERR_HIP, "mortar table layout");
+    const std::vector<double> tabs = mortar_tables(R);
+    if (int(tabs.size()) != wdg::mortar_table_size(ctx->N)) return fail(ctx, WDG_ERR_HIP, "mortar table layout");
+    const std::vector<unsigned char> tabT = to_precision(tabs, ctx->bits);
+    const std::vector<unsigned char> cores = to_precision(mortar_cores(R, ctx->mort), ctx->bits);
     HIPCHK(hipMalloc(&ctx->dMortI, mi.size() * sizeof(int32_t)));
     HIPCHK(hipMalloc(&ctx->dMortG, nm * wdg::kMortGeoStride * sizeof(double)));
-    HIPCHK(hipMalloc(&ctx->dMortTab, tabs.size() * sizeof(double)));
+    HIPCHK(hipMalloc(&ctx->dMortTab, tabT.size()));
+    HIPCHK(hipMalloc(&ctx->dMortC, cores.size()));
     HIPCHK(hipMalloc(&ctx->dMortB, nm * 2 * Nq * NTP * ts));
     HIPCHK(hipMalloc(&ctx->dMortF, nm * 2 * 2 * NT * ts));
     HIPCHK(hipMemcpyAsync(ctx->dMortI, mi.data(), mi.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(hipMemcpyAsync(ctx->dMortTab, tabs.data(), tabs.size() * sizeof(double), hipMemcpyHostToDevice,
-                          ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->dMortTab, tabT.data(), tabT.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->dMortC, cores.data(), cores.size(), hipMemcpyHostToDevice, ctx->stream));
     int rc = upload_mortar_geometry(ctx);
     if (rc) return rc;
   }

@@ -43,12 +43,18 @@ constexpr int kMortIntStride = 8;
 // below / above the diagonal as affine functions of (xi, z) (3 per vertex: xi, z, 1),
 // 25/26 1/(area/2) of those faces, 27/28 rho c of the wedge plus that of the tetrahedron.
 constexpr int kMortGeoStride = 32;
-// Gauss points along the edge of a mortar face: the integrand is rational in
-// the edge parameter; on layered meshes with interfaces perturbed by 0.3 of
-// the layer thickness 4N + 8 points reach FP64 rounding and 2N + 4 leave a
-// relative error of at most 2e-8 in the right-hand side (N = 2..5), below
-// FP32 rounding.
-constexpr int mort_nx(int N, int bits) { return bits == 64 ? 4 * N + 8 : 2 * N + 4; }
+// Gauss points along the edge of a mortar face (the host's integration of the
+// coupling matrices): the integrand is rational in the edge parameter; on
+// layered meshes with interfaces perturbed by 0.3 of the layer thickness
+// 4N + 8 points reach FP64 rounding.
+constexpr int mort_nx(int N) { return 4 * N + 8; }
+// Coupling matrix of one side of a mortar: the (N+1)^2 wedge face nodes
+// (level-major) and the Np_tri tetrahedron face nodes; both sides' lower
+// triangles (packed by columns) per mortar, padded to a multiple of 4 values.
+__host__ __device__ constexpr int mort_core_n(int N) { return (N + 1) * (N + 1) + (N + 1) * (N + 2) / 2; }
+__host__ __device__ constexpr int mort_core_stride(int N) {
+  return (mort_core_n(N) * (mort_core_n(N) + 1) + 3) / 4 * 4;
+}
 
 enum StageFlags : int {
   kReadRes = 1,    // res = a res + dt rhs (else res = dt rhs)
@@ -77,7 +83,8 @@ struct StageLaunch {
   const void* srcvec;  // kMaxSources x Np_wedge (a tetrahedron source uses the first Np_tet)
   const int* mortI;    // mortars: kMortIntStride ints each
   const void* mortG;   // kMortGeoStride FP64 values each
-  const void* mortTab; // FP64 reference tables of the mortar quadrature (see mortar_table_size)
+  const void* mortTab; // reference tables of the mortar outputs, type T (see mortar_table_size)
+  const void* mortC;   // per mortar: mort_core_stride values of type T (coupling matrices)
   void* mortB;         // per mortar: wedge pre-lift contributions [p, u][Nq][Np_tri padded to 4]
   void* mortF;         // per mortar side: equivalent nodal tetrahedron-face flux [p, u][Np_tri]
   int64_t nmort;
@@ -107,14 +114,10 @@ hipError_t launch_material(int bits, int64_t K, const double* dc, const double* 
 hipError_t launch_mortar_stage(int N, int bits, const StageLaunch& a, hipStream_t st);
 hipError_t launch_wedge_stage(int N, int bits, const StageLaunch& a, hipStream_t st);
 hipError_t launch_tet_stage(int N, int bits, const StageLaunch& a, hipStream_t st);
-// Number of FP64 values of the mortar reference tables of order N for the given
-// state precision; the host fills them in this order: xg, wg (mort_nx Gauss points along
-// the edge), tg, wt (Nq Gauss points in t), tgll (Nq GLL nodes), 1/(tgll_m - tgll_mm)
-// (Nq x Nq, diagonal unused), Minv1 (Nq x Nq), Eedge (mort_nx x Nq: GLL Lagrange basis
-// at xg), A (3 x mort_nx x Np_tri: (M^tri)^-1 restricted to the edge nodes times Eedge),
-// Vinv (Np_tri x Np_tri: triangle Lagrange values -> Legendre-product modes P_a(r) P_b(s),
-// a+b <= N, a outer), P = (M^tri)^-1 Vinv^T (Np_tri x Np_tri).
-int mortar_table_size(int N, int bits);
+// Number of values of the mortar reference tables of order N, in this order:
+// Minv1 (Nq x Nq, (M^1D)^-1), ME (3 x Np_tri x Nq: (M^tri)^-1 restricted to the
+// columns of edge e's nodes, [e][i][q]), MTI (Np_tri x Np_tri, (M^tri)^-1).
+int mortar_table_size(int N);
 // Batches of independent wedge meshes (one launch per order and stage).
 // Per-problem parameters of the stage records written on the device.
 struct BatchParam {
