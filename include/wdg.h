@@ -266,10 +266,12 @@ int wdg_read_kernel_timing_split(wdg_ctx* ctx, double* ms3, int64_t* launches);
  *   12..15 bottom face (J_f, n_x, n_y, n_z), 16..19 top face,
  *   20+4e..23+4e quad face on edge e (J_f at its first and second vertex, n_x, n_y),
  *   32..36 rho c of the element plus rho c across each face (bottom, top, quads),
- *   37..39 unused
+ *   37..39 J_tri h_v / 2, the weights of M^{tri,k} = sum_v (J_tri h_v / 2) M_v
  * (Lemma 1; face Jacobians and normals of Sec. 4.2).  lift: nw x Np_tri x
  * Np_tri, the triangular lift L^{tri,k} = (M^{tri,k})^-1 M^tri (Sec. 4.2),
- * row-major.  Either pointer may be NULL. */
+ * row-major (for N <= 4 the device keeps the lower triangle of
+ * (M^{tri,k})^-1 and the product with M^tri is formed here, in FP64).
+ * Either pointer may be NULL. */
 int wdg_get_element_data(const wdg_ctx* ctx, double* geo, double* lift);
 
 /* Host-side reference operators of order N (no context, no device), for

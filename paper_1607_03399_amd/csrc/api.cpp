@@ -1878,9 +1878,27 @@ int wdg_get_element_data(const wdg_ctx* ctx, double* geo, double* lift) {
     int rc = fetch(ctx->dGeo, size_t(ctx->Kw) * wdg::kGeoStride, geo, wdg::kGeoStride, wdg::kGeoStride);
     if (rc) return rc;
   }
-  if (lift) {
+  if (lift && !wdg::lift_packed(ctx->N)) {
     int rc = fetch(ctx->dL, size_t(ctx->Kw) * LS, lift, LS, NT * NT);
     if (rc) return rc;
+  } else if (lift) {
+    // L^{tri,k} = (M^{tri,k})^-1 M^tri from the stored lower triangle of the inverse
+    const int NPK = NT * (NT + 1) / 2;
+    std::vector<double> pk(size_t(ctx->Kw) * NPK);
+    int rc = fetch(ctx->dL, size_t(ctx->Kw) * LS, pk.data(), LS, NPK);
+    if (rc) return rc;
+    const RefOps& R = *ctx->ref;
+    std::vector<double> Mi(size_t(NT) * NT);
+    for (int64_t k = 0; k < ctx->Kw; ++k) {
+      for (int r = 0; r < NT; ++r)
+        for (int c = 0; c <= r; ++c) Mi[r * NT + c] = Mi[c * NT + r] = pk[size_t(k) * NPK + r * (r + 1) / 2 + c];
+      for (int r = 0; r < NT; ++r)
+        for (int c = 0; c < NT; ++c) {
+          double v = 0.0;
+          for (int m = 0; m < NT; ++m) v += Mi[r * NT + m] * R.Mtri[m * NT + c];
+          lift[(size_t(k) * NT + r) * NT + c] = v;
+        }
+    }
   }
   return WDG_OK;
 }

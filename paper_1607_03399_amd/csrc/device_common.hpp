@@ -18,9 +18,22 @@ struct Dim {
   static constexpr int NT = (N + 1) * (N + 2) / 2;
   static constexpr int Nq = N + 1;
   static constexpr int NP = NT * Nq;
-  // per-element stride of L^{tri,k}: padded to whole 4-vectors
-  static constexpr int LS = (NT * NT + 3) / 4 * 4;
+  // Per-element triangular operator: for N <= 4 (M^{tri,k})^-1, stored as its
+  // lower triangle row by row (symmetric), applied after the literal M^tri;
+  // for N = 5 the lift L^{tri,k} = (M^{tri,k})^-1 M^tri itself, row-major
+  // (there the extra M^tri product costs more registers than the smaller
+  // record saves).  Padded to whole 4-vectors.
+  static constexpr bool PACKED = N <= 4;
+  static constexpr int NPK = NT * (NT + 1) / 2;
+  static constexpr int LS = ((PACKED ? NPK : NT * NT) + 3) / 4 * 4;
 };
+
+// row of entry f of a lower triangle stored row by row (entry (r, c) at r (r + 1) / 2 + c)
+__host__ __device__ constexpr int tri_row(int f) {
+  int r = 0;
+  while ((r + 1) * (r + 2) / 2 <= f) ++r;
+  return r;
+}
 
 __host__ __device__ constexpr int tri_idx(int N, int a, int b) { return b * (N + 1) - b * (b - 1) / 2 + a; }
 // triangle node q (0..N) along edge e, from its first to its second vertex

@@ -75,7 +75,7 @@ struct StageLaunch {
   void* Uout;
   void* res;
   const void* geo;   // wedges
-  const void* L;
+  const void* L;     // wedges: triangular operator record (lift_packed, lift_stride)
   const int* conn;
   const void* geoT;  // tetrahedra
   const int* connT;
@@ -102,7 +102,10 @@ struct StageLaunch {
   int flags;
 };
 
-// Per-element stride (values) of the stored triangular lift: Np_tri^2 padded to a multiple of 4.
+// Whether order N stores (M^{tri,k})^-1 as its lower triangle (N <= 4) instead
+// of the lift L^{tri,k} = (M^{tri,k})^-1 M^tri (Np_tri^2 values, row-major).
+constexpr bool lift_packed(int N) { return N <= 4; }
+// Per-element stride (values) of that record, padded to a multiple of 4.
 int lift_stride(int N);
 
 hipError_t launch_setup(int N, int bits, int64_t K, const double* dX, const double* dMv, const double* dMtri,

@@ -1,5 +1,5 @@
 // Setup and diagnostic kernels of libwdg: FP64 geometric factors and
-// triangular lifts of the wedges (Lemma 1, Sec. 4.2), material records,
+// triangular operators of the wedges (Lemma 1, Sec. 4.2), material records,
 // receiver sampling and the discrete energies.
 #include <hip/hip_runtime.h>
 
@@ -17,6 +17,7 @@ template <typename T>
 __global__ void __launch_bounds__(64) setup_kernel(int NT, int LS, int64_t K, const double* __restrict__ X,
                                                    const double* __restrict__ Mv, const double* __restrict__ Mtri,
                                                    T* __restrict__ geo, T* __restrict__ L, double* __restrict__ aux) {
+  const bool packed = Mtri == nullptr;  // store (M^{tri,k})^-1 packed, else L^{tri,k}
   __shared__ double Aug[kMaxNT * 2 * kMaxNT];
   __shared__ double fac[kMaxNT];
   const int tid = threadIdx.x;
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(64) setup_kernel(int NT, int LS, int64_t K, co
         gf[22 + 4 * ed] = dy / ell;
         gf[23 + 4 * ed] = -dx / ell;
       }
-      // M^{tri,k} = sum_v cw_v M_v: its weights for the stage kernel's lift
+      // M^{tri,k} = sum_v cw_v M_v: its weights (the adjoint's mass terms)
       gf[37] = cw[0];
       gf[38] = cw[1];
       gf[39] = cw[2];
@@ -90,14 +91,15 @@ __global__ void __launch_bounds__(64) setup_kernel(int NT, int LS, int64_t K, co
       ax[6] = 0.0;
       ax[7] = 0.0;
     }
-    // [ M^{tri,k} | M^tri ], M^{tri,k} = sum_v (J_tri h_v / 2) int l_a l_b lambda_v
+    // [ M^{tri,k} | I ] (packed) or [ M^{tri,k} | M^tri ],
+    // M^{tri,k} = sum_v (J_tri h_v / 2) int l_a l_b lambda_v
     for (int idx = tid; idx < NT * W; idx += 64) {
       const int r = idx / W, c = idx - r * W;
       double v;
       if (c < NT) {
         v = cw[0] * Mv[r * NT + c] + cw[1] * Mv[NT * NT + r * NT + c] + cw[2] * Mv[2 * NT * NT + r * NT + c];
       } else {
-        v = Mtri[r * NT + (c - NT)];
+        v = packed ? ((c - NT == r) ? 1.0 : 0.0) : Mtri[r * NT + (c - NT)];
       }
       Aug[idx] = v;
     }
@@ -116,9 +118,13 @@ __global__ void __launch_bounds__(64) setup_kernel(int NT, int LS, int64_t K, co
       }
       __syncthreads();
     }
+    // (M^{tri,k})^-1 is symmetric: its lower triangle, row by row; or L^{tri,k} row-major
     for (int idx = tid; idx < LS; idx += 64) {
       double v = 0.0;
-      if (idx < NT * NT) {
+      if (packed && idx < NT * (NT + 1) / 2) {
+        const int r = tri_row(idx), c = idx - r * (r + 1) / 2;
+        v = 0.5 * (Aug[r * W + NT + c] + Aug[c * W + NT + r]);
+      } else if (!packed && idx < NT * NT) {
         const int r = idx / NT, c = idx - r * NT;
         v = Aug[r * W + NT + c];
       }
@@ -256,11 +262,13 @@ hipError_t launch_energy_tet_t(int64_t Kt, const void* U, const double* aux, con
 
 int lift_stride(int N) {
   const int NT = (N + 1) * (N + 2) / 2;
-  return (NT * NT + 3) / 4 * 4;
+  return ((lift_packed(N) ? NT * (NT + 1) / 2 : NT * NT) + 3) / 4 * 4;
 }
 
 hipError_t launch_setup(int N, int bits, int64_t K, const double* dX, const double* dMv, const double* dMtri,
                         void* dGeo, void* dL, double* dAux, hipStream_t st) {
+  if (lift_packed(N)) dMtri = nullptr;
+  else if (!dMtri) return hipErrorInvalidValue;
   const int NT = (N + 1) * (N + 2) / 2;
   const int LS = lift_stride(N);
   int64_t nb = K < 65536 ? K : 65536;

@@ -16,7 +16,7 @@ namespace {
 // holds EPB = 64 / Nq elements (fewer where the LDS would exceed 64 KiB).  LDS
 // holds the staged state (per-element stride NPP, odd in 4-vectors, so that the
 // elements of a wavefront fall on different banks) and a second region that
-// first holds the triangular lifts, geometry records and triangular-face
+// first holds the inverse triangular masses, geometry records and triangular-face
 // fluxes, and afterwards the right-hand side on its way to the coalesced
 // update.
 template <int N, typename T>
@@ -317,14 +317,9 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
 //            scale by kappa, 1/rho; sources
 //   update:  R goes through LDS so that the low-storage Runge-Kutta update
 //            reads and writes res and U with fully coalesced accesses
-// ---------------------------------------------------------------------------
-// L^{tri,k} built per stage from the three mass weights in the geometry
-// record (1) instead of read from its stored copy (0).  Building it saves its
-// NT^2 values of memory traffic per element and stage but costs a Cholesky
-// factorisation and NT column solves per element: on MI355X it measured 1%
-// slower at N = 3 and 14% slower at N = 4, so the stored copy is the default.
-#ifndef WDG_LIFT_OTF
-#define WDG_LIFT_OTF 0
+// highest order whose quadrilateral-face fluxes are added after M^tri (edge masses)
+#ifndef WDG_QM_MAX_N
+#define WDG_QM_MAX_N 4
 #endif
 #ifndef WDG_STAGE_WAVES_PER_EU
 #define WDG_STAGE_WAVES_PER_EU 2
@@ -381,9 +376,9 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chun
     cn[4] = c1.x;
     cn[5] = c1.y;
   }
-  constexpr int SU = (EPB * NP + 63) / 64, SL = WDG_LIFT_OTF ? 0 : (EPB * VL + 63) / 64, SG = (EPB * VG + 63) / 64;
+  constexpr int SU = (EPB * NP + 63) / 64, SL = (EPB * VL + 63) / 64, SG = (EPB * VG + 63) / 64;
   constexpr int V4B = 4 * int(sizeof(T));
-  V4<T> rU[SU], rL[SL > 0 ? SL : 1], rG[SG];
+  V4<T> rU[SU], rL[SL], rG[SG];
   {
     const auto bu = chunk_rsrc(Uin + e0 * NP, int64_t(nE) * NP * V4B);
     const auto bl = chunk_rsrc(Lm + e0 * Dim<N>::LS, int64_t(nE) * VL * V4B);
@@ -473,67 +468,15 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chun
   const V4<T>* el = sU + le * NPP;
   const T* g = reinterpret_cast<const T*>(sG) + le * kGeoStride;
 
-  if constexpr (WDG_LIFT_OTF) {
-    // L^{tri,k} = (M^{tri,k})^-1 M^tri from the element's three mass weights
-    // (M^{tri,k} = sum_v w_v M_v, Sec. 4.2): every lane of the element factors
-    // M^{tri,k} (Cholesky), then solves for the columns m = j, j + Nq, ... of
-    // L into the lift region; the barrier before phase 2 publishes them.
-    if (le < EPB) {
-      const T w0 = g[37], w1 = g[38], w2 = g[39];
-      T Lc[NT * (NT + 1) / 2], dinv[NT];
-#pragma unroll
-      for (int i = 0; i < NT; ++i) {
-#pragma unroll
-        for (int k = 0; k <= i; ++k) {
-          T m = 0;
-          constexpr_or_skip(RT::Mv[i * NT + k], m, w0);
-          constexpr_or_skip(RT::Mv[NT * NT + i * NT + k], m, w1);
-          constexpr_or_skip(RT::Mv[2 * NT * NT + i * NT + k], m, w2);
-#pragma unroll
-          for (int q = 0; q < k; ++q) m -= Lc[i * (i + 1) / 2 + q] * Lc[k * (k + 1) / 2 + q];
-          if (k == i) {
-            const T d = std::sqrt(m);
-            Lc[i * (i + 1) / 2 + i] = d;
-            dinv[i] = T(1) / d;
-          } else {
-            Lc[i * (i + 1) / 2 + k] = m * dinv[k];
-          }
-        }
-      }
-      T* Lf = reinterpret_cast<T*>(sL + le * VL);
-#pragma unroll
-      for (int mm = 0; mm < (NT + Nq - 1) / Nq; ++mm) {
-        const int m = j + mm * Nq;
-        if (m < NT) {
-          T y[NT];
-#pragma unroll
-          for (int i = 0; i < NT; ++i) {
-            T v = T(0);  // M^tri[i][m], m = j + mm Nq selected over the lane's j
-#pragma unroll
-            for (int jj = 0; jj < Nq; ++jj) {
-              const int c = mm * Nq + jj < NT ? mm * Nq + jj : NT - 1;
-              v = (j == jj) ? T(RT::Mtri[i * NT + c]) : v;
-            }
-#pragma unroll
-            for (int q = 0; q < i; ++q) v -= Lc[i * (i + 1) / 2 + q] * y[q];
-            y[i] = v * dinv[i];
-          }
-#pragma unroll
-          for (int i = NT - 1; i >= 0; --i) {
-            T v = y[i];
-#pragma unroll
-            for (int q = i + 1; q < NT; ++q) v -= Lc[q * (q + 1) / 2 + i] * y[q];
-            y[i] = v * dinv[i];
-          }
-#pragma unroll
-          for (int i = 0; i < NT; ++i) Lf[i * NT + m] = y[i];
-        }
-      }
-    }
-  }
-
   // pre-lift accumulators of the four equations on this level
   T Bp[NT], Bz[NT], Bx[NT], By[NT];
+  // Quadrilateral-face fluxes: lifted by E_e (dense Np_tri x Nq) into the
+  // pre-lift sums, or (QM) kept as (F_p, F_u) per edge node and added after the
+  // reference mass M^tri is applied, where E_e becomes the Nq x Nq edge mass
+  // on the edge's own nodes (M^tri E_e = int_edge l l_q (1 -+ xi) / 2).  QM
+  // saves VALU work where the registers for the kept fluxes are free.
+  constexpr bool QM = Dim<N>::PACKED && N <= WDG_QM_MAX_N;
+  T qf[QM ? 3 : 1][QM ? Nq : 1][2];
 
   if (active) {
     const T tzJ = g[4];
@@ -593,24 +536,31 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chun
         const T jp = pp - pm, jun = unp - unm;
         const T Fp = T(0.5) * (taup * jp - jun);
         const T Fu = T(0.5) * (tauu * jun - jp);
-        fpa[q] = Ja * Fp;
-        fpb[q] = Jb * Fp;
-        fua[q] = Ja * Fu;
-        fub[q] = Jb * Fu;
-      }
-#pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        T sp = 0, su = 0;
-#pragma unroll
-        for (int q = 0; q < Nq; ++q) {
-          constexpr_or_skip(RT::Ea[(ed * NT + i) * Nq + q], sp, fpa[q]);
-          constexpr_or_skip(RT::Eb[(ed * NT + i) * Nq + q], sp, fpb[q]);
-          constexpr_or_skip(RT::Ea[(ed * NT + i) * Nq + q], su, fua[q]);
-          constexpr_or_skip(RT::Eb[(ed * NT + i) * Nq + q], su, fub[q]);
+        if constexpr (QM) {
+          qf[ed][q][0] = Fp;
+          qf[ed][q][1] = Fu;
+        } else {
+          fpa[q] = Ja * Fp;
+          fpb[q] = Jb * Fp;
+          fua[q] = Ja * Fu;
+          fub[q] = Jb * Fu;
         }
-        Bp[i] += sp;
-        Bx[i] += nx * su;
-        By[i] += ny * su;
+      }
+      if constexpr (!QM) {
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+          T sp = 0, su = 0;
+#pragma unroll
+          for (int q = 0; q < Nq; ++q) {
+            constexpr_or_skip(RT::Ea[(ed * NT + i) * Nq + q], sp, fpa[q]);
+            constexpr_or_skip(RT::Eb[(ed * NT + i) * Nq + q], sp, fpb[q]);
+            constexpr_or_skip(RT::Ea[(ed * NT + i) * Nq + q], su, fua[q]);
+            constexpr_or_skip(RT::Eb[(ed * NT + i) * Nq + q], su, fub[q]);
+          }
+          Bp[i] += sp;
+          Bx[i] += nx * su;
+          By[i] += ny * su;
+        }
       }
     }
 
@@ -711,10 +661,86 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chun
       }
     }
 
-    // triangular lift L^{tri,k} on this level: R = L B
+    // triangular lift on this level, R = L^{tri,k} B with L^{tri,k} = (M^{tri,k})^-1 M^tri
+    // (Sec. 4.2).  N <= 4: the reference mass as literals, then the element's
+    // inverse mass, stored as its lower triangle (symmetric: each off-diagonal
+    // entry serves two rows); N = 5: the stored L^{tri,k}.
+    if constexpr (Dim<N>::PACKED) {
 #pragma unroll
-    for (int i = 0; i < NT; ++i) Rp[i] = Rz[i] = Rx[i] = Ry[i] = T(0);
-    {
+      for (int i = 0; i < NT; ++i) {
+        T sp = 0, sz = 0, sx = 0, sy = 0;
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
+          constexpr_or_skip(RT::Mtri[i * NT + m], sp, Bp[m]);
+          constexpr_or_skip(RT::Mtri[i * NT + m], sz, Bz[m]);
+          constexpr_or_skip(RT::Mtri[i * NT + m], sx, Bx[m]);
+          constexpr_or_skip(RT::Mtri[i * NT + m], sy, By[m]);
+        }
+        Rp[i] = sp;
+        Rz[i] = sz;
+        Rx[i] = sx;
+        Ry[i] = sy;
+      }
+      if constexpr (QM) {
+#pragma unroll
+        for (int ed = 0; ed < 3; ++ed) {
+          const T Ja = MODE == 2 && cn[2 + ed] <= -2 ? T(0) : g[20 + 4 * ed];
+          const T Jb = MODE == 2 && cn[2 + ed] <= -2 ? T(0) : g[21 + 4 * ed];
+          const T nx = g[22 + 4 * ed], ny = g[23 + 4 * ed];
+#pragma unroll
+          for (int qq = 0; qq < Nq; ++qq) {
+            T pa = 0, pb = 0, ua = 0, ub = 0;
+#pragma unroll
+            for (int q = 0; q < Nq; ++q) {
+              constexpr_or_skip(RT::Ma[qq * Nq + q], pa, qf[ed][q][0]);
+              constexpr_or_skip(RT::Mb[qq * Nq + q], pb, qf[ed][q][0]);
+              constexpr_or_skip(RT::Ma[qq * Nq + q], ua, qf[ed][q][1]);
+              constexpr_or_skip(RT::Mb[qq * Nq + q], ub, qf[ed][q][1]);
+            }
+            const T vp = Ja * pa + Jb * pb, vu = Ja * ua + Jb * ub;
+            const int i = edge_node(N, ed, qq);
+            Rp[i] += vp;
+            Rx[i] += nx * vu;
+            Ry[i] += ny * vu;
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        Bp[i] = Rp[i];
+        Bz[i] = Rz[i];
+        Bx[i] = Rx[i];
+        By[i] = Ry[i];
+        Rp[i] = Rz[i] = Rx[i] = Ry[i] = T(0);
+      }
+      {
+        const V4<T>* Lv = sL + le * VL;
+#pragma unroll
+        for (int c = 0; c < VL; ++c) {
+          const V4<T> l4 = Lv[c];
+          const T lv[4] = {l4.p, l4.uz, l4.ux, l4.uy};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int f = 4 * c + k;
+            if (f < Dim<N>::NPK) {
+              const int i = tri_row(f), m = f - i * (i + 1) / 2;
+              Rp[i] += lv[k] * Bp[m];
+              Rz[i] += lv[k] * Bz[m];
+              Rx[i] += lv[k] * Bx[m];
+              Ry[i] += lv[k] * By[m];
+              if (m != i) {
+                Rp[m] += lv[k] * Bp[i];
+                Rz[m] += lv[k] * Bz[i];
+                Rx[m] += lv[k] * Bx[i];
+                Ry[m] += lv[k] * By[i];
+              }
+            }
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NT; ++i) Rp[i] = Rz[i] = Rx[i] = Ry[i] = T(0);
       const V4<T>* Lv = sL + le * VL;
 #pragma unroll
       for (int c = 0; c < VL; ++c) {
