@@ -274,6 +274,22 @@ int wdg_read_kernel_timing_split(wdg_ctx* ctx, double* ms3, int64_t* launches);
  * Either pointer may be NULL. */
 int wdg_get_element_data(const wdg_ctx* ctx, double* geo, double* lift);
 
+/* Test hook (host only, no device work): the mortar faces of the mesh (a
+ * wedge quadrilateral covered by two tetrahedron triangles) and their
+ * coupling matrices, integrated on the host in FP64 on the common refinement
+ * (Sec. 3.1 and 5; the integrals of the flux on such a face).  Per mortar,
+ * faces receives 7 values: wedge, edge e of its quadrilateral, diagonal (0:
+ * from the edge's first bottom vertex to the second top vertex, 1: the
+ * other), then tetrahedron and face below and above the diagonal (global
+ * element ids, wedges first).  couplings receives per mortar and side of the
+ * diagonal the lower triangle, packed by columns, of the symmetric
+ * n x n matrix int b b^T dA over that side, n = (N+1)^2 + Np_tri, with b the
+ * wedge face's Lagrange basis (GLL level m, edge node q, index m (N+1) + q)
+ * followed by the tetrahedron face's (face node i): 2 n (n+1)/2 values per
+ * mortar.  At most cap mortars are written (either pointer may be NULL);
+ * *count receives the number of mortars. */
+int wdg_mortar_couplings(const wdg_ctx* ctx, int64_t cap, int64_t* faces, double* couplings, int64_t* count);
+
 /* Host-side reference operators of order N (no context, no device), for
  * inspection.  name: "r","s" (triangle nodes), "t" (GLL nodes), "Dr","Ds"
  * (Np_tri x Np_tri), "Dt","M1" (Nq x Nq), "Mtri", "Mv0","Mv1","Mv2"

@@ -1856,6 +1856,34 @@ int wdg_read_kernel_timing(wdg_ctx* ctx, double* total_ms, int64_t* launches) {
   return rc;
 }
 
+int wdg_mortar_couplings(const wdg_ctx* ctx, int64_t cap, int64_t* faces, double* couplings, int64_t* count) {
+  if (!ctx || !count || cap < 0) return WDG_ERR_ARG;
+  if (ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "no mesh");
+  const int64_t nm = int64_t(ctx->mort.size());
+  *count = nm;
+  const int64_t take = std::min(cap, nm);
+  if (faces)
+    for (int64_t m = 0; m < take; ++m) {
+      const MortarHost& M = ctx->mort[m];
+      int64_t* o = faces + 7 * m;
+      o[0] = M.k;
+      o[1] = M.e;
+      o[2] = M.diag;
+      o[3] = M.t[0];
+      o[4] = M.tf[0];
+      o[5] = M.t[1];
+      o[6] = M.tf[1];
+    }
+  if (couplings && take > 0) {
+    const int n = wdg::mort_core_n(ctx->N), npk = n * (n + 1) / 2, CS = wdg::mort_core_stride(ctx->N);
+    const std::vector<MortarHost> part(ctx->mort.begin(), ctx->mort.begin() + take);
+    const std::vector<double> c = mortar_cores(*ctx->ref, part);
+    for (int64_t m = 0; m < take; ++m)
+      std::copy(c.begin() + m * CS, c.begin() + m * CS + 2 * npk, couplings + m * 2 * npk);
+  }
+  return WDG_OK;
+}
+
 int wdg_get_element_data(const wdg_ctx* ctx, double* geo, double* lift) {
   if (!ctx) return WDG_ERR_ARG;
   if (ctx->host_only || ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "no device mesh");

@@ -81,6 +81,7 @@ def load_library() -> C.CDLL:
         "wdg_adjoint_gradient_recorded": (C.c_int, [vp, _dp, _dp, _dp, _i64p]),
         "wdg_set_adjoint_memory_limit": (C.c_int, [vp, C.c_int64]),
         "wdg_get_element_data": (C.c_int, [vp, _dp, _dp]),
+        "wdg_mortar_couplings": (C.c_int, [vp, C.c_int64, C.POINTER(C.c_int64), _dp, C.POINTER(C.c_int64)]),
         "wdg_kernel_timing": (C.c_int, [vp, C.c_int]),
         "wdg_read_kernel_timing": (C.c_int, [vp, _dp, _i64p]),
         "wdg_read_kernel_timing_split": (C.c_int, [vp, _dp, _i64p]),
@@ -361,6 +362,19 @@ class Solver:
         n = C.c_int64()
         self._check(self._lib.wdg_read_kernel_timing_split(self._h, _ptr(ms), C.byref(n)), "read_kernel_timing_split")
         return float(ms[0]), float(ms[1]), float(ms[2]), n.value
+
+    def mortar_couplings(self):
+        """(faces (nmort, 7) int64, couplings (nmort, 2, n (n+1)/2)) of the mortar
+        faces, integrated on the host (see wdg_mortar_couplings)."""
+        cnt = C.c_int64()
+        self._check(self._lib.wdg_mortar_couplings(self._h, 0, None, None, C.byref(cnt)), "mortar_couplings")
+        nm = cnt.value
+        n = (self.N + 1) ** 2 + self.NT
+        faces = np.zeros((nm, 7), dtype=np.int64)
+        cp = np.zeros((nm, 2, n * (n + 1) // 2))
+        fp = faces.ctypes.data_as(C.POINTER(C.c_int64))
+        self._check(self._lib.wdg_mortar_couplings(self._h, nm, fp, _ptr(cp), C.byref(cnt)), "mortar_couplings")
+        return faces, cp
 
     def element_data(self):
         """(geo (Kw,40), lift (Kw,Np_tri,Np_tri)) of the wedges, built by the device setup kernel."""
