@@ -27,7 +27,16 @@ struct Cfg {
   static constexpr int XPE = (VL + VG + VF) > NPP ? (VL + VG + VF) : NPP;
   static constexpr int per_elem = (NPP + XPE) * 4 * int(sizeof(T));
   static constexpr int EPB_FULL = 64 / Nq;
-  static constexpr int EPB = EPB_FULL * per_elem <= 65536 ? EPB_FULL : 65536 / per_elem;
+  static constexpr int EPB_LDS = EPB_FULL * per_elem <= 65536 ? EPB_FULL : 65536 / per_elem;
+  // Kernels that run one wavefront per SIMD (N >= 4; N = 3 in FP64, by its
+  // registers) keep all four SIMDs of a CU busy only if four blocks fit in the
+  // 160 KiB of LDS: at most 40 KiB per block (N = 5 FP32: 10 -> 9 elements,
+  // 740 -> 620 us per stage on 73 728 wedges; N = 3 FP64: 16 -> 15, 497 -> 459 us
+  // on cfg2).  With two wavefronts per SIMD (N <= 3, FP32) the same rule cost
+  // 2 % at N = 3, so there the block keeps 64 / Nq elements.
+  static constexpr bool ONE_WAVE = N >= 4 || (N == 3 && sizeof(T) == 8);
+  static constexpr int EPB_CAP = ONE_WAVE ? 40960 / per_elem : 64;
+  static constexpr int EPB = EPB_LDS < EPB_CAP ? EPB_LDS : EPB_CAP;
   static constexpr int BS = 64;
   // 4-vectors of the chunk each lane carries through the coalesced update
   static constexpr int UPD = (EPB * NP + BS - 1) / BS;
