@@ -13,7 +13,9 @@ namespace {
 // Lane (element, node i); a block of 256 lanes holds EPB = 256 / Np
 // tetrahedra per chunk and loops over chunks (persistent), so the reference
 // operators Dr, Ds, Dt and LIFT are staged in LDS once per block where they
-// fit (read from memory otherwise).  Per chunk:
+// fit (read from memory otherwise).  Each lane loads its share of the next
+// chunk's state, geometry and connectivity, and its node's previous residual,
+// before the current chunk's work.  Per chunk:
 //   1. node i stores (p, r.u, s.u, t.u) with r.u = r_x u_x + r_y u_y + r_z u_z
 //      (and likewise s, t), so that div u = D_r(r.u) + D_s(s.u) + D_t(t.u);
 //      the 4 Np_tri face nodes are shared out over the lanes, whose fluxes
@@ -50,7 +52,22 @@ __global__ void __launch_bounds__(256) tet_stage(StageLaunch A) {
 
   const T* gops = static_cast<const T*>(A.opsT);
   if constexpr (C::OPS_LDS) {
-    for (int idx = threadIdx.x; idx < C::NOPS; idx += C::BS) sOps[idx] = gops[idx];
+    // eight loads in flight per lane before their stores: a few L2 round trips
+    // instead of one per value
+    constexpr int OPL = (C::NOPS + C::BS - 1) / C::BS;
+    for (int b = 0; b < OPL; b += 8) {
+      T v[8];
+#pragma unroll
+      for (int l = 0; l < 8; ++l) {
+        const int idx = threadIdx.x + C::BS * (b + l);
+        v[l] = gops[idx < C::NOPS ? idx : 0];
+      }
+#pragma unroll
+      for (int l = 0; l < 8; ++l) {
+        const int idx = threadIdx.x + C::BS * (b + l);
+        if (idx < C::NOPS) sOps[idx] = v[l];
+      }
+    }
   }
   const T* ops = C::OPS_LDS ? static_cast<const T*>(sOps) : gops;
   const T* Dr = ops;
@@ -70,20 +87,60 @@ __global__ void __launch_bounds__(256) tet_stage(StageLaunch A) {
   const T tau_on = (A.flags & kCentral) ? T(0) : T(1);
   const bool rd = (A.flags & kReadRes) != 0, wu = (A.flags & kWriteU) != 0;
   const int64_t nchunks = (A.Kt + EPB - 1) / EPB;
+  // A chunk's state, geometry and connectivity are loaded one chunk ahead,
+  // while the current chunk computes (one node, GL geometry and CL
+  // connectivity values per lane).
+  static_assert(EPB * NP <= C::BS, "one node per lane");
+  constexpr int GL = (EPB * kTetGeoStride + C::BS - 1) / C::BS, CL = (EPB * kTetConnStride + C::BS - 1) / C::BS;
+  struct Pre {
+    V4<T> u;
+    T g[GL];
+    int c[CL];
+  };
+  // (indices past the chunk read its first value, a valid address; those
+  // values are never stored)
+  auto fetch = [&](int64_t c) -> Pre {
+    const int64_t f0 = c * EPB;
+    const int n = int(A.Kt - f0 < EPB ? A.Kt - f0 : EPB);
+    Pre p;
+    p.u = Uin[tb + f0 * NP + (tid < n * NP ? tid : 0)];
+#pragma unroll
+    for (int l = 0; l < GL; ++l) {
+      const int idx = tid + C::BS * l;
+      p.g[l] = geo[f0 * kTetGeoStride + (idx < n * kTetGeoStride ? idx : 0)];
+    }
+#pragma unroll
+    for (int l = 0; l < CL; ++l) {
+      const int idx = tid + C::BS * l;
+      p.c[l] = conn[f0 * kTetConnStride + (idx < n * kTetConnStride ? idx : 0)];
+    }
+    return p;
+  };
+  Pre pre{};
+  if (int64_t(blockIdx.x) < nchunks) pre = fetch(blockIdx.x);
 
   for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
     const int64_t e0 = chunk * EPB;
     const int nE = int(A.Kt - e0 < EPB ? A.Kt - e0 : EPB);
+    const bool active = tid < EPB * NP && le < nE;
+    const int64_t e = e0 + le;
+    const int64_t gi = tb + e * NP + i;
+    // the previous residual of this lane's node, read early
+    V4<T> rprev{T(0), T(0), T(0), T(0)};
+    if (rd && active) rprev = res[gi];
     __syncthreads();  // the previous chunk is done with LDS
-    for (int idx = tid; idx < nE * NP; idx += C::BS) sU[idx] = Uin[tb + e0 * NP + idx];
-    for (int idx = tid; idx < nE * kTetGeoStride; idx += C::BS) sG[idx] = geo[e0 * kTetGeoStride + idx];
-    for (int idx = tid; idx < nE * kTetConnStride; idx += C::BS) sC[idx] = conn[e0 * kTetConnStride + idx];
+    if (tid < nE * NP) sU[tid] = pre.u;
+#pragma unroll
+    for (int l = 0; l < GL; ++l)
+      if (tid + C::BS * l < nE * kTetGeoStride) sG[tid + C::BS * l] = pre.g[l];
+#pragma unroll
+    for (int l = 0; l < CL; ++l)
+      if (tid + C::BS * l < nE * kTetConnStride) sC[tid + C::BS * l] = pre.c[l];
+    if (chunk + gridDim.x < nchunks) pre = fetch(chunk + gridDim.x);
     __syncthreads();
 
-    const bool active = tid < EPB * NP && le < nE;
     const T* g = sG + le * kTetGeoStride;
     const int* cn = sC + le * kTetConnStride;
-    const int64_t e = e0 + le;
     if (active) {
       const V4<T> v = sU[le * NP + i];
       sW[le * NP + i] = Q4<T>{v.p, g[0] * v.ux + g[1] * v.uy + g[2] * v.uz, g[3] * v.ux + g[4] * v.uy + g[5] * v.uz,
@@ -162,15 +219,13 @@ __global__ void __launch_bounds__(256) tet_stage(StageLaunch A) {
     for (int s = 0; s < A.nsrc; ++s)
       if (A.src_elem[s] == A.Kw + e) Rp += T(A.src_amp[s]) * static_cast<const T*>(A.srcvec)[s * NPW + i];
 
-    const int64_t gi = tb + e * NP + i;
     const T ca = T(A.a), cb = T(A.b), dtt = T(A.dt), cg = T(A.g);
     V4<T> r{dtt * Rp, dtt * Rz, dtt * Rx, dtt * Ry};
     if (rd) {
-      const V4<T> q = res[gi];
-      r.p += ca * q.p;
-      r.uz += ca * q.uz;
-      r.ux += ca * q.ux;
-      r.uy += ca * q.uy;
+      r.p += ca * rprev.p;
+      r.uz += ca * rprev.uz;
+      r.ux += ca * rprev.ux;
+      r.uy += ca * rprev.uy;
     }
     res[gi] = r;
     if (wu) {
@@ -181,12 +236,19 @@ __global__ void __launch_bounds__(256) tet_stage(StageLaunch A) {
   }
 }
 
+#ifndef WDG_TET_BLOCKS
+#define WDG_TET_BLOCKS 2048
+#endif
+constexpr int64_t kTetBlocks = WDG_TET_BLOCKS;
+
 template <int N, typename T>
 hipError_t launch_tet_stage_t(const StageLaunch& a, hipStream_t st) {
   if (a.Kt <= 0) return hipSuccess;
   using TC = TCfg<N, T>;
   const int64_t tchunks = (a.Kt + TC::EPB - 1) / TC::EPB;
-  const unsigned grid = unsigned(tchunks < 2048 ? tchunks : 2048);
+  // persistent over chunks: each block stages the operators once (1024 blocks,
+  // the resident count at four per CU, measured 1 us slower on cfg3)
+  const unsigned grid = unsigned(tchunks < kTetBlocks ? tchunks : kTetBlocks);
   hipLaunchKernelGGL((tet_stage<N, T>), dim3(grid), dim3(TC::BS), 0, st, a);
   return hipGetLastError();
 }
