@@ -106,10 +106,11 @@ def test_rhs_parity(N, bits):
 
 
 @pytest.mark.parametrize("bits", [64, 32])
-def test_rhs_parity_permuted_vertices_and_ragged_sizes(bits):
+@pytest.mark.parametrize("N", [3, 5])
+def test_rhs_parity_permuted_vertices_and_ragged_sizes(N, bits):
     """Nontrivial face permutations; element counts that leave a ragged last
-    workgroup; a single element with only boundary faces."""
-    N = 3
+    workgroup (16 or 15 wedges per block at N = 3, 9 or 4 at N = 5); a single
+    element with only boundary faces."""
     for K_cut in (1, 7, 65, 131):
         base = _rotated(inputs.layered_config(4, 5, 0.3, seed=3), seed=K_cut)
         w = base.wedges[:K_cut]
@@ -117,7 +118,7 @@ def test_rhs_parity_permuted_vertices_and_ragged_sizes(bits):
         remap = -np.ones(len(base.verts), dtype=np.int64)
         remap[used] = np.arange(len(used))
         m = inputs.WedgeMesh(base.verts[used], remap[w], base.c[:K_cut], base.rho[:K_cut], base.layers)
-        _say("ragged", bits, K_cut)
+        _say("ragged", N, bits, K_cut)
         s = _solver(m, N, bits)
         U = np.random.default_rng(K_cut).standard_normal((m.K, 4, s.Np))
         got = s.eval_rhs(U)
