@@ -40,11 +40,18 @@ struct Cfg {
   static constexpr int BS = 64;
   // 4-vectors of the chunk each lane carries through the coalesced update
   static constexpr int UPD = (EPB * NP + BS - 1) / BS;
-  // prefetch the previous residual into registers when that costs at most 40 of them
+  // Prefetch the previous residual into registers when that costs at most 40
+  // of them, or 80 for the one-wavefront-per-SIMD kernels, which have 512
+  // (per stage: N = 4 on 73 728 wedges 145 -> 131 us, N = 5 621 -> 581 us,
+  // N = 3 FP64 on cfg2 460 -> 387 us)
 #ifndef WDG_PREFETCH_REGS
 #define WDG_PREFETCH_REGS 40
 #endif
-  static constexpr bool PREFETCH = UPD * 4 * int(sizeof(T)) / 4 <= WDG_PREFETCH_REGS;
+#ifndef WDG_PREFETCH_REGS_ONE_WAVE
+#define WDG_PREFETCH_REGS_ONE_WAVE 80
+#endif
+  static constexpr bool PREFETCH =
+      UPD * 4 * int(sizeof(T)) / 4 <= (ONE_WAVE ? WDG_PREFETCH_REGS_ONE_WAVE : WDG_PREFETCH_REGS);
 };
 
 // acc1 += c x1; acc2 += c x2 for a reference-operator entry c known at
