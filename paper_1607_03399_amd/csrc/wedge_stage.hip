@@ -32,7 +32,7 @@ struct Cfg {
   // registers) keep all four SIMDs of a CU busy only if four blocks fit in the
   // 160 KiB of LDS: at most 40 KiB per block (N = 5 FP32: 10 -> 9 elements,
   // 740 -> 620 us per stage on 73 728 wedges; N = 3 FP64: 16 -> 15, 497 -> 459 us
-  // on cfg2).  With two wavefronts per SIMD (N <= 3, FP32) the same rule cost
+  // on 262 144 wedges).  With two wavefronts per SIMD (N <= 3, FP32) the same rule cost
   // 2 % at N = 3, so there the block keeps 64 / Nq elements.
   static constexpr bool ONE_WAVE = N >= 4 || (N == 3 && sizeof(T) == 8);
   static constexpr int EPB_CAP = ONE_WAVE ? 40960 / per_elem : 64;
@@ -43,7 +43,7 @@ struct Cfg {
   // Prefetch the previous residual into registers when that costs at most 40
   // of them, or 80 for the one-wavefront-per-SIMD kernels, which have 512
   // (per stage: N = 4 on 73 728 wedges 145 -> 131 us, N = 5 621 -> 581 us,
-  // N = 3 FP64 on cfg2 460 -> 387 us)
+  // N = 3 FP64 on 262 144 wedges 460 -> 387 us)
 #ifndef WDG_PREFETCH_REGS
 #define WDG_PREFETCH_REGS 40
 #endif
