@@ -330,8 +330,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         if int(os.environ.get("RANK", "0")) == 0:
-            print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                       "not part of this build)", "n_gpus": args.gpus}), flush=True)
+            print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 (the library does not "
+                                       "shard a mesh across GPUs)", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
     import torch
