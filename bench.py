@@ -9,12 +9,16 @@ pressure pulse (width 0.2), 200 steps of the five-stage low-storage
 Runge-Kutta scheme.  Inputs are synthetic (seeded).
 
 Prints one JSON line: DG node-updates per second per Runge-Kutta stage
-(elements x nodes x 5 x steps / wall time), the HBM-roofline fraction of the
-stage kernel (algorithmic bytes / average kernel time from HIP events on the
-solver stream), the adjoint leg (receiver-misfit gradient on 524288 wedges:
-gradient time over forward time), the batched leg (48 independent problems
-of mixed orders and sizes: one batch against the problems one by one) and
-the FP64 CPU oracle timed on a bounded sample.
+(elements x nodes x 5 x steps / wall time); the HBM-roofline fraction of the
+dominant stage kernel (its algorithmic bytes per launch, as the hot-path
+scope table counts them, over its average duration from HIP events on the
+solver stream) beside a measured device-copy rate; further forward legs
+(the column-split hybrid mesh with wedge, tetrahedron and mortar kernels,
+524288 wedges, orders 4 and 5, FP64); the adjoint leg (receiver-misfit
+gradient on 524288 wedges: gradient time over forward time); the batched
+leg (48 independent problems of mixed orders and sizes: one batch against
+the problems one by one); and the FP64 CPU oracle timed on bounded samples,
+one process and all cores.
 """
 from __future__ import annotations
 
@@ -58,6 +62,36 @@ def stage_bytes(N: int, bits: int, reads_res: bool) -> int:
     return state * (3 + int(reads_res)) + 40 * ts + LS * ts + 8 * 4
 
 
+def survey_stage_bytes(N: int, bits: int) -> int:
+    """Algorithmic HBM bytes of one stage for one wedge as the hot-path scope
+    table counts them (the roofline's reference figure): state read, residual
+    read and written, state written (4 fields x Np values each, the residual
+    read counted in every stage), about 41 geometry and material values, five
+    neighbour ids and the packed face codes (28 B), and L^{tri,k} stored whole
+    (Np_tri^2 values).  N = 3 FP32: 3152 B; N = 2/4/5: 1488/5892/10020 B;
+    FP64 N = 3: 6276 B."""
+    NT = (N + 1) * (N + 2) // 2
+    NP = NT * (N + 1)
+    ts = bits // 8
+    return 16 * NP * ts + 41 * ts + 28 + NT * NT * ts
+
+
+def mortar_bytes(N: int, bits: int) -> int:
+    """Algorithmic HBM bytes of one stage for one mortar face (a wedge
+    quadrilateral against two tetrahedron triangles): both packed coupling
+    matrices, the gathered face nodes ((N+1)^2 wedge + 2 Np_tri tetrahedron
+    4-vectors), the outputs (wedge pre-lift contributions [p, u][Nq][Np_tri
+    padded to 4] and both tetrahedron-face fluxes [p, u][Np_tri]), the integer
+    record (8 int32) and the six FP64 geometry values the kernel reads."""
+    NT = (N + 1) * (N + 2) // 2
+    Nq = N + 1
+    ts = bits // 8
+    n = Nq * Nq + NT
+    core = (n * (n + 1) + 3) // 4 * 4
+    ntp = (NT + 3) // 4 * 4
+    return core * ts + (Nq * Nq + 2 * NT) * 4 * ts + (2 * Nq * ntp + 4 * NT) * ts + 32 + 48
+
+
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "wedge_stage_cfg2_traffic.json")
 # sources the wedge stage kernel is compiled from (its traffic record is tied to them)
 KERNEL_SOURCES = [os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1607_03399_amd", "csrc", f)
@@ -83,18 +117,21 @@ def measured_traffic(config: str):
     return float(rec["bytes_per_launch"])
 
 
-def cpu_baseline(mesh, N: int, dt: float, seconds: float, sample: int):
-    """The FP64 oracle on the first ``sample`` elements (a block of whole
-    columns) of the same workload: untimed setup, then Runge-Kutta stages
-    (right-hand side + update) until ``seconds`` have elapsed."""
+def _oracle_stages(block: int, sample: int, seconds: float, dt: float, N: int, config: str):
+    """The FP64 oracle on wedges [block * sample, (block + 1) * sample) of the
+    workload mesh (whole columns): untimed setup, then Runge-Kutta stages
+    (right-hand side + update) until ``seconds`` have elapsed.  Returns
+    (elements, nodes per element, stages, wall seconds, CPU seconds)."""
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
     from oracle import dg, lsrk
+    from paper_1607_03399_amd import inputs
 
+    mesh = inputs.cfg2_mesh() if config == "cfg2" else inputs.cfg5_mesh()
     om = dg.Mesh(mesh.verts, mesh.wedges, mesh.c, mesh.rho, "rigid", "upwind")
-    elems = np.arange(min(sample, mesh.K))
+    elems = np.arange(block * sample, min((block + 1) * sample, mesh.K))
     ops = dg.build_operators(om, N, elems=elems)
     NP = ops.M.shape[1]
-    rng = np.random.default_rng(0)
+    rng = np.random.default_rng(block)
     U = rng.standard_normal((mesh.K, 4, NP))
     res = np.zeros((len(elems), 4, NP))
     stages = 0
@@ -108,16 +145,74 @@ def cpu_baseline(mesh, N: int, dt: float, seconds: float, sample: int):
         stages += 1
         if time.perf_counter() - t0 >= seconds and s == 4:
             break
-    wall = time.perf_counter() - t0
-    cpu = time.process_time() - c0
-    return {
-        "value": len(elems) * NP * stages / wall,
+    return len(elems), NP, stages, time.perf_counter() - t0, time.process_time() - c0
+
+
+def _host_cpu():
+    """Core count available to this process and the processor as lscpu names it."""
+    ncpu = len(os.sched_getaffinity(0))
+    info = {}
+    try:
+        import subprocess
+
+        out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)",
+                             "CPU max MHz"):
+                info[k.strip()] = v.strip()
+    except Exception:
+        pass
+    return ncpu, info
+
+
+def cpu_baseline(config: str, N: int, dt: float, seconds: float, sample: int, workers: int):
+    """The FP64 oracle as it stands, on the GPU machine's host: one process on the
+    first ``sample`` wedges (whole columns), then ``workers`` processes at
+    once, each on its own block of ``sample`` wedges, for the same time
+    (every process single-threaded: the oracle's einsums run on one core).
+    The worker processes are started fresh (spawn), not forked from this
+    process, which holds a GPU context."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    ncpu, info = _host_cpu()
+    ne, NP, stages, wall, cpu = _oracle_stages(0, sample, seconds, dt, N, config)
+    one = ne * NP * stages / wall
+    out = {
+        "value": one,
         "unit": "node-updates/s",
         "cores": max(1, int(round(cpu / wall))),
         "kind": "oracle",
-        "sample": f"first {len(elems)} wedges ({len(elems) // mesh.layers} whole columns) of the same mesh, "
-                  f"{stages} stages, {wall:.1f} s wall",
+        "sample": f"first {ne} wedges (whole columns) of the same mesh, {stages} stages, {wall:.1f} s wall, "
+                  "single process",
+        "nproc": ncpu,
+        "lscpu": info,
     }
+    if workers > 1:
+        env_keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+        saved = {k: os.environ.get(k) for k in env_keys}
+        for k in env_keys:
+            os.environ[k] = "1"
+        try:
+            with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+                futs = [ex.submit(_oracle_stages, b, sample, seconds, dt, N, config) for b in range(workers)]
+                rs = [f.result() for f in futs]
+        finally:
+            for k, v in saved.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+        total = sum(r[0] * r[1] * r[2] / r[3] for r in rs)
+        out["all_cores"] = {
+            "value": total,
+            "unit": "node-updates/s",
+            "cores": workers,
+            "sample": f"{workers} processes, each on its own block of {sample} wedges (whole columns), "
+                      f"{min(r[2] for r in rs)}-{max(r[2] for r in rs)} stages in about {seconds:.0f} s each",
+        }
+    return out
 
 
 def initial_state(s):
@@ -302,20 +397,134 @@ def copy_bandwidth(nbytes: int = 512 << 20, reps: int = 10) -> float:
     return 2 * nbytes / sec / 1e9
 
 
+CONFIGS = {
+    "cfg2": "262144 wedges (64x64 base x 32 layers), N=3",
+    "cfg5": "524288 wedges (128x128 base x 16 layers), N=3",
+    "cfg3": "hybrid: 39312 wedges + 29520 tetrahedra (20% of 32x32x24 columns split), N=4",
+    "cfg3-layers": "hybrid: 38912 wedges + 30720 tetrahedra (lowest 5 of 24 layers split), N=4",
+    "order4": "73728 wedges (48x48 base x 16 layers), N=4",
+    "order5": "73728 wedges (48x48 base x 16 layers), N=5",
+}
+
+
+def workload(config: str):
+    """(N, verts, wedges, tets, c, rho, wedge mesh or None, description) of a configuration."""
+    from paper_1607_03399_amd import inputs
+
+    if config == "cfg3":
+        verts, wedges, tets, c, rho = inputs.cfg3_columns_mesh()
+        return 4, verts, wedges, tets, c, rho, None, (
+            "cfg3: 32x32 base x 24 layers, a seeded 20% of the columns split into 3 tetrahedra per prism "
+            f"(nonconforming faces on the common refinement): {len(wedges)} wedges + {len(tets)} tetrahedra, "
+            "N=4 (75/35 nodes), banded c and rho, rigid walls, upwind flux, Ricker source f0=10, initial "
+            "Gaussian pulse (width 0.2), LSRK(5,4), CFL 0.5")
+    if config == "cfg3-layers":
+        verts, wedges, tets, c, rho = inputs.cfg3_hybrid_mesh()
+        return 4, verts, wedges, tets, c, rho, None, (
+            "cfg3 (layer-split variant): 32x32 base x 24 layers, lowest 5 layers split into 3 tetrahedra per "
+            f"prism: {len(wedges)} wedges + {len(tets)} tetrahedra, N=4 (75/35 nodes), banded c and rho, "
+            "rigid walls, upwind flux, Ricker source f0=10, initial Gaussian pulse (width 0.2), LSRK(5,4), "
+            "CFL 0.5")
+    if config in ("order4", "order5"):
+        N = int(config[-1])
+        mesh = inputs.layered_config(48, 16, 0.3, 0, config)
+        dims = "48x48x16"
+    else:
+        N = 3
+        mesh = inputs.cfg2_mesh() if config == "cfg2" else inputs.cfg5_mesh()
+        dims = "64x64x32" if config == "cfg2" else "128x128x16"
+    desc = (f"{config}: layered vertically mapped wedges, {mesh.K} elements ({dims}), N={N} "
+            f"({(N + 1) ** 2 * (N + 2) // 2} nodes/wedge), banded c and rho, rigid walls, upwind flux, Ricker "
+            "source f0=10, initial Gaussian pulse (width 0.2), LSRK(5,4), CFL 0.5")
+    return N, mesh.verts, mesh.wedges, np.zeros((0, 4), np.int64), mesh.c, mesh.rho, mesh, desc
+
+
+def forward_leg(config: str, bits: int, steps: int, warmup: int, layer_march: bool = False):
+    """Time ``steps`` steps of a configuration (after ``warmup`` steps) on a
+    torch-bound state and stream; per-kernel averages from HIP events on that
+    stream.  Returns (result dict, time step, wedge mesh or None)."""
+    import torch
+
+    from paper_1607_03399_amd import wdg
+
+    N, verts, wedges, tets, c, rho, mesh, desc = workload(config)
+    Kw, Kt = len(wedges), len(tets)
+    s = wdg.Solver(N, bits, device=0)
+    s.set_mesh(verts, wedges, tets)
+    s.set_material(c, rho)
+    s.set_boundary("rigid")
+    s.set_flux("upwind")
+    s.set_layer_march(layer_march)
+    s.add_ricker_source([0.5, 0.5, 0.5], 10.0, 0.1, 1.0)
+    s.set_fields(initial_state(s))
+    s.bind_torch()
+    dt = s.stable_dt(0.5)
+    s.step(warmup, dt)
+    s.synchronize()
+    torch.cuda.synchronize()
+    s.kernel_timing(True)
+    t0 = time.perf_counter()
+    s.step(steps, dt)
+    s.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    w_ms, t_ms, m_ms, nlaunch = s.read_kernel_timing_split()
+    s.kernel_timing(False)
+    U = s.get_fields()
+    nmort = s.mortar_count() if Kt else 0
+    s.close()
+    if not np.all(np.isfinite(U)):
+        raise RuntimeError("non-finite fields")
+    assert nlaunch == 5 * steps, (nlaunch, 5 * steps)
+    NPw = (N + 1) ** 2 * (N + 2) // 2
+    NPt = (N + 1) * (N + 2) * (N + 3) // 6
+    nodes = Kw * NPw + Kt * NPt
+    kernels = {}
+    if Kw:
+        avg = w_ms * 1e3 / nlaunch
+        rec_bytes = Kw * (stage_bytes(N, bits, False) + 4 * stage_bytes(N, bits, True)) / 5
+        kernels["wedge_stage"] = {"avg_us": avg, "bytes_per_launch": Kw * survey_stage_bytes(N, bits),
+                                  "GBs": Kw * survey_stage_bytes(N, bits) / avg / 1e3,
+                                  "record_bytes_per_launch": rec_bytes, "record_GBs": rec_bytes / avg / 1e3}
+    if Kt:
+        avg = t_ms * 1e3 / nlaunch
+        tb = Kt * (tet_stage_bytes(N, bits, False) + 4 * tet_stage_bytes(N, bits, True)) / 5
+        kernels["tet_stage"] = {"avg_us": avg, "bytes_per_launch": tb, "GBs": tb / avg / 1e3}
+    if nmort:
+        avg = m_ms * 1e3 / nlaunch
+        mb = nmort * mortar_bytes(N, bits)
+        kernels["mortar_kernel"] = {"avg_us": avg, "mortars": nmort, "bytes_per_launch": mb, "GBs": mb / avg / 1e3}
+    leg = {
+        "workload": desc,
+        "precision": bits,
+        "elements": Kw + Kt,
+        "wedges": Kw,
+        "tetrahedra": Kt,
+        "order": N,
+        "nodes": nodes,
+        "dt": dt,
+        "steps": steps,
+        "ms_per_step": wall * 1e3 / steps,
+        "node_updates_per_s": nodes * 5 * steps / wall,
+        "kernels": kernels,
+    }
+    return leg, dt, mesh
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="cfg2", choices=["cfg2", "cfg5", "cfg3", "cfg3-layers"],
-                    help="cfg2 (default): 262144 wedges, N=3; cfg5: 524288 wedges, N=3; cfg3: hybrid "
-                         "39312 wedges + 29520 tetrahedra (20%% of the columns split), N=4; cfg3-layers: "
-                         "38912 wedges + 30720 tetrahedra (lowest 5 of 24 layers split), N=4")
+    ap.add_argument("--config", default="cfg2", choices=sorted(CONFIGS),
+                    help="; ".join(f"{k}: {v}" for k, v in CONFIGS.items()) + " (default cfg2)")
     ap.add_argument("--precision", type=int, default=32, choices=[32, 64])
     ap.add_argument("--layer-march", action="store_true",
                     help="stage kernel variant reading vertical neighbours inside a chunk from LDS")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="processes of the all-core oracle figure (default: the host's cores, at most 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint leg (cfg2 runs the cfg5 receiver-misfit gradient after the forward bench)")
@@ -323,8 +532,12 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched leg (cfg2 runs the cfg4 48-problem batch after the forward bench)")
     ap.add_argument("--batch-steps", type=int, default=300)
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="time a plain 512 MiB device copy first (HBM reference for counters and roofline)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the other forward configurations (cfg2 runs cfg3, cfg5, order 4 and 5 and FP64 "
+                         "cfg2 for 20 steps each)")
+    ap.add_argument("--leg-steps", type=int, default=20)
+    ap.add_argument("--no-copy-calibration", action="store_true",
+                    help="skip the plain 512 MiB device copy (the measured HBM reference of the roofline)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -334,108 +547,32 @@ def main():
                                        "shard a mesh across GPUs)", "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
-    import torch
-
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-    from paper_1607_03399_amd import inputs
-    from paper_1607_03399_amd import wdg
+    import torch  # noqa: F401  (device memory and streams of the bound state)
 
-    copy_gbs = None
-    if args.copy_calibration:
-        copy_gbs = copy_bandwidth()
-
+    copy_gbs = None if args.no_copy_calibration else copy_bandwidth()
     bits = args.precision
-    if args.config == "cfg3":
-        N = 4
-        verts, wedges, tets, c, rho = inputs.cfg3_columns_mesh()
-        mesh = None
-        desc = ("cfg3: 32x32 base x 24 layers, a seeded 20% of the columns split into 3 tetrahedra per prism "
-                f"(nonconforming faces on the common refinement): {len(wedges)} wedges + {len(tets)} tetrahedra, "
-                "N=4 (75/35 nodes), banded c and rho, rigid walls, upwind flux, Ricker source f0=10, initial "
-                "Gaussian pulse (width 0.2), LSRK(5,4), CFL 0.5")
-    elif args.config == "cfg3-layers":
-        N = 4
-        verts, wedges, tets, c, rho = inputs.cfg3_hybrid_mesh()
-        mesh = None
-        desc = ("cfg3 (layer-split variant): 32x32 base x 24 layers, lowest 5 layers split into 3 tetrahedra per "
-                f"prism: {len(wedges)} wedges + {len(tets)} tetrahedra, N=4 (75/35 nodes), banded c and rho, "
-                "rigid walls, upwind flux, Ricker source f0=10, initial Gaussian pulse (width 0.2), LSRK(5,4), "
-                "CFL 0.5")
-    else:
-        N = 3
-        mesh = inputs.cfg2_mesh() if args.config == "cfg2" else inputs.cfg5_mesh()
-        verts, wedges, tets, c, rho = mesh.verts, mesh.wedges, np.zeros((0, 4), np.int64), mesh.c, mesh.rho
-        desc = (f"{args.config}: layered vertically mapped wedges, {len(wedges)} elements "
-                f"({'64x64x32' if args.config == 'cfg2' else '128x128x16'}), N=3 (40 nodes/wedge), "
-                "banded c and rho, rigid walls, upwind flux, Ricker source f0=10, initial Gaussian pulse (width 0.2), "
-                "LSRK(5,4), CFL 0.5")
-    Kw, Kt = len(wedges), len(tets)
-    s = wdg.Solver(N, bits, device=0)
-    s.set_mesh(verts, wedges, tets)
-    s.set_material(c, rho)
-    s.set_boundary("rigid")
-    s.set_flux("upwind")
-    s.set_layer_march(args.layer_march)
-    s.add_ricker_source([0.5, 0.5, 0.5], 10.0, 0.1, 1.0)
-    s.set_fields(initial_state(s))
-    s.bind_torch()
-    dt = s.stable_dt(0.5)
-
-    s.step(args.warmup, dt)
-    s.synchronize()
-    torch.cuda.synchronize()
-    s.kernel_timing(True)
-    t0 = time.perf_counter()
-    s.step(args.steps, dt)
-    s.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    w_ms, t_ms, m_ms, nlaunch = s.read_kernel_timing_split()
-    s.kernel_timing(False)
-    U = s.get_fields()
-    if not np.all(np.isfinite(U)):
-        raise RuntimeError("non-finite fields")
-
-    launches_expected = 5 * args.steps
-    assert nlaunch == launches_expected, (nlaunch, launches_expected)
-    nodes = Kw * s.Np + Kt * s.Npt
-    value = nodes * 5 * args.steps / wall
-    wbytes = Kw * args.steps * (stage_bytes(N, bits, False) + 4 * stage_bytes(N, bits, True))
-    tbytes = Kt * args.steps * (tet_stage_bytes(N, bits, False) + 4 * tet_stage_bytes(N, bits, True))
-    kernels = {}
-    if Kw:
-        kernels["wedge_stage"] = {"avg_us": w_ms * 1e3 / nlaunch, "GBs": wbytes / (w_ms / 1e3) / 1e9}
-    if Kt:
-        kernels["tet_stage"] = {"avg_us": t_ms * 1e3 / nlaunch, "GBs": tbytes / (t_ms / 1e3) / 1e9}
-    if m_ms > 0:
-        kernels["mortar_kernel"] = {"avg_us": m_ms * 1e3 / nlaunch}
-    dominant = max((k for k in kernels if "GBs" in kernels[k]), key=lambda k: kernels[k]["avg_us"])
+    main_leg, dt, mesh = forward_leg(args.config, bits, args.steps, args.warmup, args.layer_march)
+    kernels = main_leg["kernels"]
+    dominant = max(kernels, key=lambda k: kernels[k]["avg_us"])
     achieved = kernels[dominant]["GBs"]
-    dtype = "f32" if bits == 32 else "f64"
-
+    N = main_leg["order"]
     out = {
-        "metric": f"DG node-updates/s per RK stage ({'wedge' if not Kt else 'wedge+tet'} N={N}, FP{bits})",
-        "value": value,
+        "metric": f"DG node-updates/s per RK stage ({'wedge' if not main_leg['tetrahedra'] else 'wedge+tet'} "
+                  f"N={N}, FP{bits})",
+        "value": main_leg["node_updates_per_s"],
         "unit": "node-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": main_leg["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": dtype,
+        "dtype": "f32" if bits == 32 else "f64",
         "data": "synthetic",
-        "config": {
-            "workload": desc,
-            "elements": Kw + Kt,
-            "wedges": Kw,
-            "tetrahedra": Kt,
-            "order": N,
-            "nodes": nodes,
-            "dt": dt,
-            "kernels": kernels,
-        },
+        "config": {k: main_leg[k] for k in ("workload", "elements", "wedges", "tetrahedra", "order", "nodes", "dt",
+                                            "kernels")},
         "roofline": {
             "bound": "hbm",
             "kernel": dominant,
@@ -444,16 +581,27 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(args.config) if bits == 32 else None,
+            "bytes_per_launch": kernels[dominant]["bytes_per_launch"],
             "measured_copy_GBs": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
         },
     }
-    s.close()
-    if args.config == "cfg2" and bits == 32 and not args.no_adjoint:
+    if dominant == "wedge_stage":
+        out["roofline"]["record_frac"] = kernels[dominant]["record_GBs"] / HBM_PEAK_GBS
+    default_run = args.config == "cfg2" and bits == 32
+    if default_run and not args.no_legs:
+        legs = {}
+        for name, cfg, b in (("cfg3", "cfg3", 32), ("cfg5_forward", "cfg5", 32), ("order4", "order4", 32),
+                             ("order5", "order5", 32), ("cfg2_fp64", "cfg2", 64)):
+            legs[name], _, _ = forward_leg(cfg, b, args.leg_steps, 3)
+        out["legs"] = legs
+    if default_run and not args.no_adjoint:
         out["adjoint"] = adjoint_benchmark(args.adjoint_steps, 50)
-    if args.config == "cfg2" and bits == 32 and not args.no_batch:
+    if default_run and not args.no_batch:
         out["batched"] = batch_benchmark(args.batch_steps)
-    if not args.no_cpu_baseline and mesh is not None:
-        out["cpu_baseline"] = cpu_baseline(mesh, N, dt, args.cpu_seconds, args.cpu_sample)
+    if not args.no_cpu_baseline and mesh is not None and args.config in ("cfg2", "cfg5"):
+        workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
+        out["cpu_baseline"] = cpu_baseline(args.config, N, dt, args.cpu_seconds, args.cpu_sample, workers)
     print(json.dumps(out), flush=True)
 
 

@@ -112,6 +112,15 @@ int wdg_set_mass(wdg_ctx* ctx, int mass);
  * cache hits issued early, the chunk reads wait for the staging barrier). */
 int wdg_set_layer_march(wdg_ctx* ctx, int on);
 
+/* Launch shape of the tetrahedron stage kernel (meshes with tetrahedra).
+ * The kernel is persistent: each block stages the reference operators once
+ * and then loops over chunks of tetrahedra (chunk c, c + blocks, ...).
+ * blocks > 0 caps the number of blocks, so that each block runs about
+ * chunks / blocks chunks; 0 restores the default cap (2048).  The chunks are
+ * independent, so results are bitwise the same for every cap.  Negative
+ * values: WDG_ERR_ARG. */
+int wdg_set_tet_blocks(wdg_ctx* ctx, int blocks);
+
 /* Total number of nodes (sum over elements of Np). */
 int wdg_num_nodes(const wdg_ctx* ctx, int64_t* n);
 /* Physical node coordinates, num_nodes x 3, in the node order above. */

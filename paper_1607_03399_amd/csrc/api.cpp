@@ -78,6 +78,7 @@ struct wdg_ctx {
   std::vector<double> c, rho;
   int bc = WDG_BC_RIGID, flux = WDG_FLUX_UPWIND, mass = WDG_MASS_EXACT;
   bool layer_march = false;
+  int tet_blocks = 0;  // persistent blocks of the tetrahedron kernel (0: default)
   double time = 0.0;
 
   hipStream_t stream = nullptr;
@@ -421,6 +422,7 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.gacc = gacc;
   L.Kw = ctx->Kw;
   L.Kt = ctx->Kt;
+  L.tet_blocks = ctx->tet_blocks;
   L.flags = flags | (g != 1.0 ? wdg::kGamma : 0) | (ctx->layer_march ? wdg::kLayerMarch : 0) | (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
             (ctx->flux == WDG_FLUX_CENTRAL ? wdg::kCentral : 0) | (ctx->mass == WDG_MASS_LUMPED ? wdg::kLumped : 0);
   if (ctx->timing) {
@@ -1205,6 +1207,13 @@ int wdg_set_layer_march(wdg_ctx* ctx, int on) {
   return WDG_OK;
 }
 
+int wdg_set_tet_blocks(wdg_ctx* ctx, int blocks) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (blocks < 0) return fail(ctx, WDG_ERR_ARG, "negative block count");
+  ctx->tet_blocks = blocks;
+  return WDG_OK;
+}
+
 int wdg_num_nodes(const wdg_ctx* ctx, int64_t* n) {
   if (!ctx || !n) return WDG_ERR_ARG;
   if (ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "no mesh");
@@ -1300,6 +1309,7 @@ int wdg_bind_device_state(wdg_ctx* ctx, void* d_U, void* d_res, void* hip_stream
 
 int wdg_add_ricker_source(wdg_ctx* ctx, const double xyz[3], double f0, double t0, double amp, int* id) {
   if (!ctx) return WDG_ERR_ARG;
+  ctx->recording = false;  // the recorded forward no longer matches the problem
   if (ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "source before set_mesh");
   if (!xyz || !(f0 > 0) || !std::isfinite(t0) || !std::isfinite(amp)) return fail(ctx, WDG_ERR_ARG, "bad source");
   if (ctx->src.size() >= size_t(wdg::kMaxSources)) return fail(ctx, WDG_ERR_ARG, "too many sources");
@@ -2154,6 +2164,9 @@ int wdg_batch_prepare(wdg_batch* b, int autotune) {
   if (!b) return WDG_ERR_ARG;
   if (b->probs.empty()) return bfail(b, WDG_ERR_STATE, "empty batch");
   BHIPCHK(hipSetDevice(b->device));
+  // the autotuner's launches rewrite every problem's residual on the batch
+  // stream: work still queued on a problem's own stream must finish first
+  for (wdg_ctx* q : b->probs) BHIPCHK(hipStreamSynchronize(q->stream));
   batch_release(b);
   b->groups.clear();
   for (size_t i = 0; i < b->probs.size(); ++i) {

@@ -100,6 +100,7 @@ struct StageLaunch {
   double* gacc;
   int64_t Kw, Kt;
   int flags;
+  int tet_blocks;  // tetrahedron kernel: number of persistent blocks (0: default)
 };
 
 // Whether order N stores (M^{tri,k})^-1 as its lower triangle (N <= 4) instead

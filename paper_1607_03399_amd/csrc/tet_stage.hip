@@ -249,7 +249,8 @@ hipError_t launch_tet_stage_t(const StageLaunch& a, hipStream_t st) {
   // persistent over chunks: each block stages the operators once (1024 blocks,
   // the resident count at four per CU, measured 1 us slower on the N = 4
   // hybrid mesh of 29 520 tetrahedra)
-  const unsigned grid = unsigned(tchunks < kTetBlocks ? tchunks : kTetBlocks);
+  const int64_t cap = a.tet_blocks > 0 ? int64_t(a.tet_blocks) : kTetBlocks;
+  const unsigned grid = unsigned(tchunks < cap ? tchunks : cap);
   hipLaunchKernelGGL((tet_stage<N, T>), dim3(grid), dim3(TC::BS), 0, st, a);
   return hipGetLastError();
 }

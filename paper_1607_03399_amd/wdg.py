@@ -61,6 +61,7 @@ def load_library() -> C.CDLL:
         "wdg_set_flux": (C.c_int, [vp, C.c_int]),
         "wdg_set_mass": (C.c_int, [vp, C.c_int]),
         "wdg_set_layer_march": (C.c_int, [vp, C.c_int]),
+        "wdg_set_tet_blocks": (C.c_int, [vp, C.c_int]),
         "wdg_num_nodes": (C.c_int, [vp, _i64p]),
         "wdg_get_node_coords": (C.c_int, [vp, _dp]),
         "wdg_set_fields": (C.c_int, [vp, _dp, _dp, _dp, _dp]),
@@ -189,6 +190,10 @@ class Solver:
 
     def set_layer_march(self, on: bool):
         self._check(self._lib.wdg_set_layer_march(self._h, int(bool(on))), "set_layer_march")
+
+    def set_tet_blocks(self, blocks: int):
+        """Cap on the persistent blocks of the tetrahedron kernel (0: default)."""
+        self._check(self._lib.wdg_set_tet_blocks(self._h, int(blocks)), "set_tet_blocks")
 
     def set_mass(self, mass: str):
         """'exact' (default, energy stable) or 'lumped' (Gauss-Lobatto in t, for comparison)."""
@@ -362,6 +367,12 @@ class Solver:
         n = C.c_int64()
         self._check(self._lib.wdg_read_kernel_timing_split(self._h, _ptr(ms), C.byref(n)), "read_kernel_timing_split")
         return float(ms[0]), float(ms[1]), float(ms[2]), n.value
+
+    def mortar_count(self) -> int:
+        """Number of mortar faces (wedge quadrilaterals covered by two tetrahedron triangles)."""
+        cnt = C.c_int64()
+        self._check(self._lib.wdg_mortar_couplings(self._h, 0, None, None, C.byref(cnt)), "mortar_couplings")
+        return cnt.value
 
     def mortar_couplings(self):
         """(faces (nmort, 7) int64, couplings (nmort, 2, n (n+1)/2)) of the mortar

@@ -117,6 +117,14 @@ def test_recorded_forward_and_memory_modes_give_the_same_gradient():
     assert s.recorded_steps() == 8
     s.step(1, dt)  # beyond max_steps
     assert s.recorded_steps() == 0
+    # a source added after the recording ends it (the recorded forward had none)
+    s.set_fields(U0)
+    s.time = 0.0
+    s.adjoint_record(4, 8)
+    s.step(3, dt)
+    assert s.recorded_steps() == 3
+    s.add_ricker_source([0.5, 0.5, 0.5], 4.0, 0.1, 1.0)
+    assert s.recorded_steps() == 0
     s.close()
 
 
@@ -208,3 +216,76 @@ def test_unsupported_configurations():
         s.adjoint_gradient(4, dt, np.zeros((4, len(rec))))
     assert e.value.code == -11
     s.close()
+
+
+def test_cfg5_gradient_central_differences_and_fp32():
+    """The receiver-misfit gradient at full size (128 x 128 x 16 = 524 288
+    wedges, N = 3; 16 receivers, data from a 10 % Gaussian anomaly in c; 100
+    steps, checkpoints every 50), on 8 seeded elements within 0.05 of the
+    source: the FP64 adjoint against central differences of the FP64 device
+    forward (one context, material reset between solves), and the FP32
+    adjoint against the FP64 adjoint with the same misfit weights."""
+    m = inputs.cfg5_mesh()
+    rec, src, c_true = inputs.adjoint_problem(m)
+    nsteps, every = 100, 50
+    cent = m.verts[m.wedges].mean(axis=1)
+    near = np.nonzero(np.linalg.norm(cent - np.asarray(src[0]), axis=1) < 0.05)[0]
+    elems = np.sort(np.random.default_rng(12).choice(near, 8, replace=False))
+
+    def solver(bits):
+        s = wdg.Solver(3, bits, device=0)
+        s.set_mesh(m.verts, m.wedges)
+        s.set_boundary("rigid")
+        s.set_flux("upwind")
+        s.add_ricker_source(*src)
+        s.set_receivers(rec)
+        s.set_material(m.c, m.rho)
+        return s
+
+    s = solver(64)
+    dt = s.stable_dt(0.5)
+    U0 = np.zeros((s.K, 4, s.NPmax))
+    U0[:, 0] = inputs.gaussian_pulse(s.node_coords(), width=0.2)
+
+    def traces(c, rho):
+        s.set_material(c, rho)
+        s.set_fields(U0)
+        s.time = 0.0
+        s.step(nsteps, dt)
+        return s.read_receivers()
+
+    _say("cfg5 data")
+    data = traces(c_true, m.rho)
+    base = traces(m.c, m.rho)
+    w = base - data
+    J = lambda tr: 0.5 * float(np.sum((tr - data) ** 2))
+    J0 = J(base)
+    assert J0 > 0
+    s.set_material(m.c, m.rho)
+    s.set_fields(U0)
+    s.time = 0.0
+    gc, gr = s.adjoint_gradient(nsteps, dt, w, every)
+    _say("cfg5 J", J0, "elements", elems)
+    for k in elems:
+        for which, g in (("c", gc[k]), ("rho", gr[k])):
+            vals = []
+            for sgn in (1, -1):
+                c, rho = m.c.copy(), m.rho.copy()
+                arr = c if which == "c" else rho
+                eps = 1e-3 * arr[k]
+                arr[k] += sgn * eps
+                vals.append(J(traces(c, rho)))
+            fd = (vals[0] - vals[1]) / (2 * eps)
+            _say("   fd", k, which, fd, "adjoint", g, "rel", abs(fd - g) / abs(g))
+            # truncation (eps / value)^2 ~ 1e-6 relative; rounding of the FP64
+            # forward (~1e-15 J) over 2 eps
+            assert abs(fd - g) <= 1e-5 * abs(g) + 1e-13 * J0 / eps
+    s.close()
+    s32 = solver(32)
+    s32.set_fields(U0)
+    gc32, gr32 = s32.adjoint_gradient(nsteps, dt, w, every)
+    s32.close()
+    ec, er = _rel(gc32[elems], gc[elems]), _rel(gr32[elems], gr[elems])
+    eall = max(_rel(gc32, gc), _rel(gr32, gr))
+    _say("cfg5 FP32 vs FP64 adjoint: sampled c", ec, "rho", er, "all elements", eall)
+    assert ec <= TOL[32] and er <= TOL[32]

@@ -1,7 +1,7 @@
 """Batched launch of independent problems (through the C ABI): the fields
 after batch steps equal those of each problem stepped alone (the same stage
 arithmetic), for meshes of different orders, sizes, materials, sources and
-time steps; one small problem also against the FP64 oracle."""
+time steps; one problem of every order also against the FP64 oracle."""
 import sys
 
 import numpy as np
@@ -10,6 +10,7 @@ import pytest
 from oracle import dg, lsrk
 from paper_1607_03399_amd import inputs
 from paper_1607_03399_amd import wdg
+from parity import TOL, check
 
 pytestmark = pytest.mark.gpu
 
@@ -68,33 +69,40 @@ def test_batch_equals_single_problem_steps(bits, autotune):
         p[5].close()
 
 
-def test_batch_matches_oracle():
-    N, nx, layers, seed, src = 2, 2, 2, 7, [0.4, 0.5, 0.5]
-    batch = wdg.Batch(64, device=0)
-    m, s, U, dt = _problem(N, nx, layers, seed, 64, src)
-    m2, s2, U2, dt2 = _problem(3, 3, 2, 8, 64, [0.5, 0.5, 0.5])
-    batch.add(s, dt)
-    batch.add(s2, dt2)
+ORACLE_SPECS = [(2, 2, 2, 7, [0.4, 0.5, 0.5]), (3, 3, 2, 8, [0.5, 0.5, 0.5]), (4, 2, 3, 9, [0.6, 0.4, 0.5]),
+                (5, 2, 2, 10, [0.5, 0.6, 0.4])]
+
+
+@pytest.mark.parametrize("bits", [64, 32])
+def test_batch_matches_oracle(bits):
+    """One problem of each order N = 2..5 in one batch (autotuned), each
+    against the FP64 oracle after 20 steps, element by element."""
+    batch = wdg.Batch(bits, device=0)
+    probs = []
+    for (N, nx, layers, seed, src) in ORACLE_SPECS:
+        m, s, U, dt = _problem(N, nx, layers, seed, bits, src)
+        batch.add(s, dt)
+        probs.append((N, seed, src, m, s, U, dt))
     batch.prepare()
     batch.step(20)
-    got = s.get_fields()
-    om = dg.Mesh(m.verts, m.wedges, m.c, m.rho, "rigid" if seed % 2 else "dirichlet",
-                 "upwind" if seed % 3 else "central")
-    ops = dg.build_operators(om, N)
-    source = dg.make_point_source(om, N, src, 8.0, 0.05, 1.0)
+    for (N, seed, src, m, s, U, dt) in probs:
+        got = s.get_fields()
+        om = dg.Mesh(m.verts, m.wedges, m.c, m.rho, "rigid" if seed % 2 else "dirichlet",
+                     "upwind" if seed % 3 else "central")
+        ops = dg.build_operators(om, N)
+        source = dg.make_point_source(om, N, src, 8.0, 0.05, 1.0)
 
-    def f(t, V):
-        out = dg.rhs(ops, V)
-        out[source.elem, 0] += source.value(t) * source.vec
-        return out
+        def f(t, V):
+            out = dg.rhs(ops, V)
+            out[source.elem, 0] += source.value(t) * source.vec
+            return out
 
-    ref, _ = lsrk.integrate(f, U[:, :, :ops.M.shape[1]], dt, 20)
-    err = np.linalg.norm(got[:, :, :ref.shape[2]] - ref) / np.linalg.norm(ref)
-    _say("batch vs oracle", err)
-    assert err <= 1e-12
+        ref, _ = lsrk.integrate(f, U[:, :, :ops.M.shape[1]], dt, 20)
+        err, emax = check(got[:, :, :ref.shape[2]], ref, TOL[bits], f"batch N={N} {bits}")
+        _say("batch vs oracle N", N, bits, "rel err", err, "worst element", emax)
     batch.close()
-    s.close()
-    s2.close()
+    for p in probs:
+        p[4].close()
 
 
 def test_batch_rejects_hybrid_and_late_adds():

@@ -1,35 +1,70 @@
-"""Layer marching (vertical neighbours inside a chunk read from the staged
-chunk) gives bitwise the fields of the default gather path, and so inherits
-its oracle parity."""
+"""Layer marching (the wedge below or above read from the staged chunk, a run
+of consecutive layers of one column; Sec. 7's layer-by-layer reuse of the
+previous layer's data) against the FP64 oracle after 100 steps, and bitwise
+against the default gather path."""
+import sys
+
 import numpy as np
 import pytest
 
+from oracle import dg, lsrk
 from paper_1607_03399_amd import inputs
 from paper_1607_03399_amd import wdg
+from parity import TOL, check
 
 pytestmark = pytest.mark.gpu
 
+CASES = [(1, 64, "rigid", "upwind"), (2, 32, "dirichlet", "central"), (3, 32, "rigid", "upwind"),
+         (4, 64, "rigid", "upwind"), (5, 32, "dirichlet", "upwind")]
+SRC = ([0.5, 0.4, 0.6], 6.0, 0.05, 1.0)
 
-@pytest.mark.parametrize("N,bits,bc,flux", [(1, 64, "rigid", "upwind"), (2, 32, "dirichlet", "central"),
-                                            (3, 32, "rigid", "upwind"), (4, 64, "rigid", "upwind"),
-                                            (5, 32, "dirichlet", "upwind")])
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _run(m, N, bits, bc, flux, march, nsteps):
+    s = wdg.Solver(N, bits, device=0)
+    s.set_mesh(m.verts, m.wedges)
+    s.set_material(m.c, m.rho)
+    s.set_boundary(bc)
+    s.set_flux(flux)
+    s.set_layer_march(march)
+    s.add_ricker_source(*SRC)
+    x = s.node_coords()
+    U = np.zeros((s.K, 4, s.NPmax))
+    U[:, 0] = inputs.gaussian_pulse(x, width=0.25)
+    U[:, 2] = 0.3 * inputs.gaussian_pulse(x, centre=(0.3, 0.6, 0.5), width=0.3)
+    dt = s.stable_dt(0.5)
+    s.set_fields(U)
+    s.step(nsteps, dt)
+    out = s.get_fields()
+    s.close()
+    return out, U, dt
+
+
+@pytest.mark.parametrize("N,bits,bc,flux", CASES)
 def test_layer_march_equals_gathers(N, bits, bc, flux):
     # 5 layers: chunks cut columns at varying layers, so both paths are taken
     m = inputs.layered_config(3, 5, 0.3, seed=N)
-    out = []
-    for march in (False, True):
-        s = wdg.Solver(N, bits, device=0)
-        s.set_mesh(m.verts, m.wedges)
-        s.set_material(m.c, m.rho)
-        s.set_boundary(bc)
-        s.set_flux(flux)
-        s.set_layer_march(march)
-        s.add_ricker_source([0.5, 0.4, 0.6], 6.0, 0.05, 1.0)
-        U = np.zeros((s.K, 4, s.NPmax))
-        U[:, 0] = inputs.gaussian_pulse(s.node_coords(), width=0.25)
-        U[:, 2] = 0.3 * inputs.gaussian_pulse(s.node_coords(), centre=(0.3, 0.6, 0.5), width=0.3)
-        s.set_fields(U)
-        s.step(15, s.stable_dt(0.5))
-        out.append(s.get_fields())
-        s.close()
-    assert np.array_equal(out[0], out[1])
+    a, _, _ = _run(m, N, bits, bc, flux, False, 15)
+    b, _, _ = _run(m, N, bits, bc, flux, True, 15)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("N,bits,bc,flux", CASES)
+def test_layer_march_100_steps_against_oracle(N, bits, bc, flux):
+    m = inputs.layered_config(3, 5, 0.3, seed=N)
+    got, U0, dt = _run(m, N, bits, bc, flux, True, 100)
+    om = dg.Mesh(m.verts, m.wedges, m.c, m.rho, bc, flux)
+    ops = dg.build_operators(om, N)
+    source = dg.make_point_source(om, N, *SRC)
+
+    def f(t, U):
+        out = dg.rhs(ops, U)
+        out[source.elem, 0] += source.value(t) * source.vec
+        return out
+
+    ref, _ = lsrk.integrate(f, U0, dt, 100)
+    err, emax = check(got, ref, TOL[bits], f"layer march N={N} {bits}")
+    _say("layer march", N, bits, bc, flux, "rel err", err, "worst element", emax)

@@ -10,10 +10,9 @@ import pytest
 from oracle import dg, lsrk
 from paper_1607_03399_amd import inputs
 from paper_1607_03399_amd import wdg
+from parity import TOL, check
 
 pytestmark = pytest.mark.gpu
-
-TOL = {64: 1e-12, 32: 1e-5}
 
 
 def _say(*a):
@@ -35,7 +34,7 @@ def _solver(m, N, bits, bc, flux, mass):
 
 
 @pytest.mark.parametrize("bits", [64, 32])
-@pytest.mark.parametrize("N", [1, 2, 3, 4])
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5])
 def test_lumped_rhs_parity(N, bits):
     m = inputs.layered_config(3, 3, 0.3, seed=N)
     for bc, flux in (("rigid", "upwind"), ("dirichlet", "central")):
@@ -44,9 +43,8 @@ def test_lumped_rhs_parity(N, bits):
         U = np.random.default_rng(30 + N).standard_normal((m.K, 4, s.Np))
         got = s.eval_rhs(U)
         ops = dg.build_operators(dg.Mesh(m.verts, m.wedges, m.c, m.rho, bc, flux), N, lumped=True)
-        err = _rel(got, dg.rhs(ops, U))
-        _say("   rel err", err)
-        assert err <= TOL[bits]
+        err, emax = check(got, dg.rhs(ops, U), TOL[bits], f"lumped N={N} {bits} {bc} {flux}")
+        _say("   rel err", err, "worst element", emax)
         s.close()
 
 
@@ -88,11 +86,10 @@ def test_lumped_energy_growth_on_device():
         E1 = s.energy()
         s.close()
         ref, _ = lsrk.integrate(lambda t, U: dg.rhs(ops, U), U0, dt, steps)
-        err = _rel(got, ref)
-        _say(mass, "E0", E0, "E1", E1, "rel err", err)
+        err, emax = check(got, ref, 1e-10, f"ablation {mass}")
+        _say(mass, "E0", E0, "E1", E1, "rel err", err, "worst element", emax)
         assert abs(E0 - dg.energy(ops, U0)) <= 1e-12 * E0
         assert abs(E1 - dg.energy(ops, ref)) <= 1e-10 * E1
-        assert err <= 1e-10
         energies[mass] = (E0, E1)
     E0, E1 = energies["exact"]
     assert E1 <= E0

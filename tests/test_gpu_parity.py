@@ -12,10 +12,9 @@ import pytest
 from oracle import dg, lsrk
 from paper_1607_03399_amd import inputs
 from paper_1607_03399_amd import wdg
+from parity import TOL, check
 
 pytestmark = pytest.mark.gpu
-
-TOL = {64: 1e-12, 32: 1e-5}
 
 
 def _say(*a):
@@ -99,9 +98,8 @@ def test_rhs_parity(N, bits):
         got = s.eval_rhs(U)
         ops = dg.build_operators(_omesh(m, bc, flux), N)
         ref = dg.rhs(ops, U)
-        err = _rel(got, ref)
-        _say("   rel err", err)
-        assert err <= TOL[bits]
+        err, emax = check(got, ref, TOL[bits], f"rhs N={N} {bits} {bc} {flux}")
+        _say("   rel err", err, "worst element", emax)
         s.close()
 
 
@@ -123,7 +121,7 @@ def test_rhs_parity_permuted_vertices_and_ragged_sizes(N, bits):
         U = np.random.default_rng(K_cut).standard_normal((m.K, 4, s.Np))
         got = s.eval_rhs(U)
         ref = dg.rhs(dg.build_operators(_omesh(m), N), U)
-        assert _rel(got, ref) <= TOL[bits]
+        check(got, ref, TOL[bits], f"ragged K={K_cut}")
         s.close()
 
 
@@ -178,7 +176,7 @@ def test_cfg1_100_steps_fp64():
     got, gtr, gE = _run_library(m, N, 64, U0, dt, 100, src=src, rec=rec)
     _say("cfg1 oracle")
     ref, rtr, rE = _run_oracle(m, N, U0, dt, 100, src=src, rec=rec)
-    assert _rel(got, ref) <= 1e-12
+    check(got, ref, 1e-12, "cfg1 100 steps")
     assert gtr.shape == (100, 3)
     assert np.abs(gtr - rtr).max() <= 1e-12 * np.abs(rtr).max()
     assert abs(gE - rE) <= 1e-12 * rE
@@ -197,9 +195,8 @@ def test_fp32_100_steps_n3():
     got, _, _ = _run_library(m, N, 32, U0, dt, 100)
     _say("fp32 oracle")
     ref, _, _ = _run_oracle(m, N, U0, dt, 100)
-    err = _rel(got, ref)
-    _say("   rel err", err)
-    assert err <= 1e-5
+    err, emax = check(got, ref, 1e-5, "fp32 100 steps")
+    _say("   rel err", err, "worst element", emax)
 
 
 def test_dirichlet_steps_fp64_and_energy_decay():
@@ -211,7 +208,7 @@ def test_dirichlet_steps_fp64_and_energy_decay():
     dt = dg.stable_dt(om, N, 0.5)
     got, _, gE = _run_library(m, N, 64, U0, dt, 40, bc="dirichlet")
     ref, _, rE = _run_oracle(m, N, U0, dt, 40, bc="dirichlet")
-    assert _rel(got, ref) <= 1e-12
+    check(got, ref, 1e-12, "dirichlet 40 steps")
     assert abs(gE - rE) <= 1e-12 * rE
 
 
@@ -288,9 +285,8 @@ def test_cfg2_full_size_sampled_rhs_and_energy():
     _say("cfg2 oracle sample")
     ops = dg.build_operators(_omesh(m), N, elems=sample)
     ref = dg.rhs(ops, U)
-    err = _rel(got[sample], ref)
-    _say("   sampled rel err", err)
-    assert err <= 1e-5
+    err, emax = check(got[sample], ref, 1e-5, "cfg2 sampled rhs")
+    _say("   sampled rel err", err, "worst element", emax)
     U0 = np.zeros_like(U)
     U0[:, 0] = inputs.gaussian_pulse(s.node_coords(), width=0.1)
     s.set_fields(U0)
