@@ -113,13 +113,24 @@ int wdg_set_mass(wdg_ctx* ctx, int mass);
 int wdg_set_layer_march(wdg_ctx* ctx, int on);
 
 /* Launch shape of the tetrahedron stage kernel (meshes with tetrahedra).
- * The kernel is persistent: each block stages the reference operators once
- * and then loops over chunks of tetrahedra (chunk c, c + blocks, ...).
+ * The kernel is persistent: each block loads the reference operators once
+ * (into registers on the matrix-core variant, into LDS on the vector one) and
+ * then loops over chunks of tetrahedra (chunk c, c + blocks, ...).
  * blocks > 0 caps the number of blocks, so that each block runs about
- * chunks / blocks chunks; 0 restores the default cap (2048).  The chunks are
- * independent, so results are bitwise the same for every cap.  Negative
- * values: WDG_ERR_ARG. */
+ * chunks / blocks chunks; 0 restores the default cap (the blocks resident on
+ * the device at once for the matrix-core variant, 2048 for the vector one).
+ * The chunks are independent, so results are bitwise the same for every cap.
+ * Negative values: WDG_ERR_ARG. */
 int wdg_set_tet_blocks(wdg_ctx* ctx, int blocks);
+
+/* How the tetrahedron stage kernel applies the reference operators D_r, D_s,
+ * D_t and LIFT of the affine tetrahedra (Sec. 3.1; standard nodal DG).
+ * WDG_TET_MFMA (default): as dense products over a chunk of tetrahedra on the
+ * matrix cores (FP32 or FP64 MFMA, per the context precision).
+ * WDG_TET_VALU: as per-node dot products on the vector units.  Both compute
+ * the same stage up to rounding order.  Other values: WDG_ERR_ARG. */
+enum { WDG_TET_MFMA = 0, WDG_TET_VALU = 1 };
+int wdg_set_tet_kernel(wdg_ctx* ctx, int variant);
 
 /* Total number of nodes (sum over elements of Np). */
 int wdg_num_nodes(const wdg_ctx* ctx, int64_t* n);

@@ -27,44 +27,47 @@
 namespace wdg {
 namespace {
 
-// Per-wedge accumulator slots (FP64): 0 dJ/dc and 1 dJ/drho of the mass
-// terms; 2..6 sum dt 1/2 int sig_p [p], 7..11 sum dt 1/2 int sig_un [u_n]
-// over the faces (bottom, top, quadrilaterals 0..2).
+// Per-wedge accumulator slots (state precision): 0 dJ/dc and 1 dJ/drho of
+// the mass terms; 2..6 sum dt 1/2 int sig_p [p], 7..11 sum dt 1/2 int sig_un
+// [u_n] over the faces (bottom, top, quadrilaterals 0..2); FP32 records then
+// hold the Kahan compensations of the same slots (the sums are read as they
+// are: the compensation is below their last bit).
 static_assert(kGradStride == 12, "gradient record layout");
 
 // dJ/dZ of a wedge: every face's penalties depend on the impedances of both
 // sides (both are the own one on the boundary), with dtau_p/dZ = -tau_p^2/2
-// and dtau_u/dZ = 1/2; Z = rho c gives dZ/dc = rho, dZ/drho = c.
+// and dtau_u/dZ = 1/2; Z = rho c gives dZ/dc = rho, dZ/drho = c.  Arithmetic
+// in the state precision; the results are stored as FP64.
 template <typename T>
-__global__ void __launch_bounds__(256) grad_combine_kernel(int64_t K, const double* __restrict__ gacc,
+__global__ void __launch_bounds__(256) grad_combine_kernel(int64_t K, const T* __restrict__ gacc,
                                                            const T* __restrict__ geo, const int* __restrict__ conn,
-                                                           const double* __restrict__ aux, int flags,
-                                                           double* __restrict__ gc, double* __restrict__ grho) {
+                                                           int flags, double* __restrict__ gc,
+                                                           double* __restrict__ grho) {
   const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (k >= K) return;
-  const double* ga = gacc + k * kGradStride;
-  double gZ = 0.0;
+  const T* ga = gacc + k * kGradRecord<T>;
+  const T* g = geo + k * kGeoStride;
+  T gZ = 0;
   if (!(flags & kCentral)) {
     const int* cn = conn + k * kConnStride;
     const int code = cn[5];
     for (int f = 0; f < 5; ++f) {
-      const double zs = double(geo[k * kGeoStride + 32 + f]);
-      const double tp = 2.0 / zs;
-      const double own = -0.5 * tp * tp * ga[2 + f] - 0.5 * ga[7 + f];
-      double other = own;
+      const T tp = T(2) / g[32 + f];
+      const T own = -T(0.5) * tp * tp * ga[2 + f] - T(0.5) * ga[7 + f];
+      T other = own;
       const int nbr = cn[f];
       if (nbr >= 0) {
         const int nf = f < 2 ? ((code >> (6 + f)) & 1) : 2 + ((code >> (8 + 2 * (f - 2))) & 3);
-        const double* gn = gacc + int64_t(nbr) * kGradStride;
-        other = -0.5 * tp * tp * gn[2 + nf] - 0.5 * gn[7 + nf];
+        const T* gn = gacc + int64_t(nbr) * kGradRecord<T>;
+        other = -T(0.5) * tp * tp * gn[2 + nf] - T(0.5) * gn[7 + nf];
       }
       gZ += own + other;
     }
   }
-  const double kap = aux[k * kAuxStride + 4], rho = aux[k * kAuxStride + 5];
-  const double c = std::sqrt(kap / rho);
-  gc[k] = ga[0] + rho * gZ;
-  grho[k] = ga[1] + c * gZ;
+  const T kap = g[9], irho = g[10];
+  const T rho = T(1) / irho, c = std::sqrt(kap * irho);
+  gc[k] = double(ga[0] + rho * gZ);
+  grho[k] = double(ga[1] + c * gZ);
 }
 
 // One thread per node index; the receivers are visited in order by every
@@ -76,24 +79,24 @@ __global__ void __launch_bounds__(128) inject_kernel(int NP, int nrec, const int
   const int i = threadIdx.x;
   if (i >= NP) return;
   for (int r = 0; r < nrec; ++r) {
-    const double v = w[r] * vec[int64_t(r) * NP + i];
-    U[base[r] + i].p += T(v);
-    S[base[r] + i].p += T(sb * v);
+    const T v = T(w[r]) * T(vec[int64_t(r) * NP + i]);
+    U[base[r] + i].p += v;
+    S[base[r] + i].p += T(sb) * v;
   }
 }
 
 }  // namespace
 
-hipError_t launch_grad_combine(int bits, int64_t K, const double* gacc, const void* geo, const int* conn,
-                               const double* aux, int flags, double* gc, double* grho, hipStream_t st) {
+hipError_t launch_grad_combine(int bits, int64_t K, const void* gacc, const void* geo, const int* conn, int flags,
+                               double* gc, double* grho, hipStream_t st) {
   const unsigned nb = unsigned((K + 255) / 256);
   if (nb == 0) return hipSuccess;
   if (bits == 32)
-    hipLaunchKernelGGL(grad_combine_kernel<float>, dim3(nb), dim3(256), 0, st, K, gacc,
-                       static_cast<const float*>(geo), conn, aux, flags, gc, grho);
+    hipLaunchKernelGGL(grad_combine_kernel<float>, dim3(nb), dim3(256), 0, st, K, static_cast<const float*>(gacc),
+                       static_cast<const float*>(geo), conn, flags, gc, grho);
   else
-    hipLaunchKernelGGL(grad_combine_kernel<double>, dim3(nb), dim3(256), 0, st, K, gacc,
-                       static_cast<const double*>(geo), conn, aux, flags, gc, grho);
+    hipLaunchKernelGGL(grad_combine_kernel<double>, dim3(nb), dim3(256), 0, st, K, static_cast<const double*>(gacc),
+                       static_cast<const double*>(geo), conn, flags, gc, grho);
   return hipGetLastError();
 }
 

@@ -79,6 +79,7 @@ struct wdg_ctx {
   int bc = WDG_BC_RIGID, flux = WDG_FLUX_UPWIND, mass = WDG_MASS_EXACT;
   bool layer_march = false;
   int tet_blocks = 0;  // persistent blocks of the tetrahedron kernel (0: default)
+  bool tet_valu = false;  // tetrahedron products as per-node dot products (else MFMA)
   double time = 0.0;
 
   hipStream_t stream = nullptr;
@@ -388,7 +389,7 @@ int upload_sources(wdg_ctx* ctx) {
 // one Runge-Kutta stage (or, with a = 0, dt = 1, no U write, a plain RHS)
 int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a, double b, double dt, double tstage,
                  int flags, double g = 1.0, void* rout = nullptr, bool sources = true, const void* gUs = nullptr,
-                 const void* gRs = nullptr, double* gacc = nullptr) {
+                 const void* gRs = nullptr, void* gacc = nullptr) {
   wdg::StageLaunch L{};
   L.Uin = Uin;
   L.Uout = Uout;
@@ -423,7 +424,7 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.Kw = ctx->Kw;
   L.Kt = ctx->Kt;
   L.tet_blocks = ctx->tet_blocks;
-  L.flags = flags | (g != 1.0 ? wdg::kGamma : 0) | (ctx->layer_march ? wdg::kLayerMarch : 0) | (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
+  L.flags = flags | (g != 1.0 ? wdg::kGamma : 0) | (ctx->layer_march ? wdg::kLayerMarch : 0) | (ctx->tet_valu ? wdg::kTetValu : 0) | (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
             (ctx->flux == WDG_FLUX_CENTRAL ? wdg::kCentral : 0) | (ctx->mass == WDG_MASS_LUMPED ? wdg::kLumped : 0);
   if (ctx->timing) {
     // events only between kernels that actually run (an event adds a gap to the stream)
@@ -1214,6 +1215,13 @@ int wdg_set_tet_blocks(wdg_ctx* ctx, int blocks) {
   return WDG_OK;
 }
 
+int wdg_set_tet_kernel(wdg_ctx* ctx, int variant) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (variant != WDG_TET_MFMA && variant != WDG_TET_VALU) return fail(ctx, WDG_ERR_ARG, "unknown tetrahedron kernel");
+  ctx->tet_valu = variant == WDG_TET_VALU;
+  return WDG_OK;
+}
+
 int wdg_num_nodes(const wdg_ctx* ctx, int64_t* n) {
   if (!ctx || !n) return WDG_ERR_ARG;
   if (ctx->state < kMesh) return fail(ctx, WDG_ERR_STATE, "no mesh");
@@ -1560,8 +1568,10 @@ int adjoint_backward(wdg_ctx* ctx, const void* cp, int64_t C, int64_t nsteps, do
   auto at = [SB](const void* base, int64_t i) -> void* {
     return const_cast<unsigned char*>(static_cast<const unsigned char*>(base)) + size_t(i) * SB;
   };
-  double* gacc = static_cast<double*>(pg);
-  double* gout = gacc + K * wdg::kGradStride;
+  // gradient accumulators: kGradStride FP64 slots per wedge hold the FP64
+  // record or the FP32 record (sums and compensations) alike
+  void* gacc = pg;
+  double* gout = static_cast<double*>(pg) + K * wdg::kGradStride;
   const double* dw = static_cast<const double*>(pw);
   HIPCHK(hipMemcpyAsync(pw, weights, size_t(nsteps) * nrec * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(pv, rvec.data(), rvec.size() * sizeof(double), hipMemcpyHostToDevice, st));
@@ -1646,7 +1656,7 @@ int adjoint_backward(wdg_ctx* ctx, const void* cp, int64_t C, int64_t nsteps, do
                                   static_cast<const double*>(pv), dw + (n - 1) * nrec, kRkB[4], Ua, at(adj, sc), st));
     }
   }
-  HIPCHK(wdg::launch_grad_combine(ctx->bits, K, gacc, ctx->dGeo, ctx->dConn, ctx->dAux, mflags, gout, gout + K, st));
+  HIPCHK(wdg::launch_grad_combine(ctx->bits, K, gacc, ctx->dGeo, ctx->dConn, mflags, gout, gout + K, st));
   HIPCHK(hipMemcpyAsync(grad_c, gout, size_t(K) * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(grad_rho, gout + K, size_t(K) * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));

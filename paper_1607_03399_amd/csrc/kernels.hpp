@@ -66,6 +66,7 @@ enum StageFlags : int {
   kGamma = 64,     // U_out = g U_in + b res' (else g = 1)
   kLayerMarch = 128,  // wedge meshes: vertical neighbours inside a chunk from LDS
   kGrad = 256,        // wedge meshes, adjoint sweep: also accumulate the stage's gradient terms
+  kTetValu = 512,     // tetrahedra: per-node dot products on the vector units (else MFMA)
 };
 
 // One stage over the whole mesh.  State buffers hold wedges first (Kw x Np_wedge
@@ -97,7 +98,7 @@ struct StageLaunch {
   // kGrad: forward stage input and its right-hand side, gradient accumulators
   const void* gUs;
   const void* gRs;
-  double* gacc;
+  void* gacc;  // kGrad: gradient accumulators (kGradRecord values of the state precision per wedge)
   int64_t Kw, Kt;
   int flags;
   int tet_blocks;  // tetrahedron kernel: number of persistent blocks (0: default)
@@ -146,13 +147,17 @@ hipError_t launch_batch_prepare(int nprob, StageLaunch* probs, const BatchParam*
 hipError_t launch_batch_advance(int64_t* counter, hipStream_t st);
 
 // Adjoint gradient (wedge meshes).  Per reverse stage the stage kernel (kGrad)
-// accumulates into gacc (kGradStride FP64 values per wedge) dt times the mass
-// terms sig^T M R of the pressure and of the velocity and the face integrals
+// accumulates into gacc (per wedge: kGradStride values of the state precision;
+// FP32 also their kGradStride Kahan compensations) dt times the mass terms
+// sig^T M R of the pressure and of the velocity and the face integrals
 // 1/2 int sig_p [p], 1/2 int sig_un [u_n] of the forward stage input Us.
 constexpr int kGradStride = 12;
-// Gradient with respect to c and rho from the accumulated terms and the penalty derivatives.
-hipError_t launch_grad_combine(int bits, int64_t K, const double* gacc, const void* geo, const int* conn,
-                               const double* aux, int flags, double* gc, double* grho, hipStream_t st);
+template <typename T>
+constexpr int kGradRecord = sizeof(T) == 4 ? 2 * kGradStride : kGradStride;  // values per wedge
+// Gradient with respect to c and rho from the accumulated terms and the penalty
+// derivatives, in the state precision; written to gc and grho as FP64.
+hipError_t launch_grad_combine(int bits, int64_t K, const void* gacc, const void* geo, const int* conn, int flags,
+                               double* gc, double* grho, hipStream_t st);
 // Receiver injection: for receiver r (first node base[r], vector vec[r] of NP values),
 // U += w[r] vec[r] and S += sb w[r] vec[r] on the pressure.
 hipError_t launch_inject(int bits, int NP, int nrec, const int64_t* base, const double* vec, const double* w,

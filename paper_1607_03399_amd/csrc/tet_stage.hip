@@ -236,6 +236,314 @@ __global__ void __launch_bounds__(256) tet_stage(StageLaunch A) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tetrahedron stage kernel on the matrix cores (default)
+//
+// The same stage as tet_stage, with the reference-operator products of a chunk
+// of EPB tetrahedra done as dense contractions on MFMA (16x16x4, FP32 or
+// FP64):
+//   [D_r p, D_r(r.u)], [D_s p, D_s(s.u)], [D_t p, D_t(t.u)]
+//       = D_o (Np x Np) times the chunk's (p, o.u) column pairs (2 EPB columns),
+//   LIFT (Np x 4 Np_tri) times the chunk's face fluxes
+//       (J_f/J) (F_p, F_u n_x, F_u n_y, F_u n_z) (4 EPB columns).
+// A block holds one wavefront per 16-row tile of the operators (Np rows
+// padded to a multiple of 16); each wavefront keeps its rows of D_r, D_s, D_t
+// and LIFT in registers (the MFMA A operand) for the whole persistent kernel,
+// so only the chunk's data (the B operand) is read from LDS: one value per
+// lane per MFMA, against three operator values and a 4-vector per node and
+// operator column in the per-node dot products of tet_stage.  The pointwise
+// parts (geometry, fluxes, scaling, sources, update) run over the chunk's
+// nodes on all lanes.
+// ---------------------------------------------------------------------------
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+template <typename T>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<float> {
+  using type = f32x4_t;
+};
+template <>
+struct MfmaAcc<double> {
+  using type = f64x4_t;
+};
+
+// D += A B for a 16x4 A and a 4x16 B: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and holds D[mfma_row<T>(l / 16, r)][l % 16], r = 0..3
+// (FP32: rows 4 (l / 16) + r; FP64: rows 4 r + l / 16)
+template <typename T>
+__device__ __forceinline__ int mfma_row(int lk, int r) {
+  return sizeof(T) == 4 ? 4 * lk + r : 4 * r + lk;
+}
+template <typename T>
+__device__ __forceinline__ typename MfmaAcc<T>::type mfma16x16x4(T a, T b, typename MfmaAcc<T>::type c) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int N, typename T>
+struct MCfg {
+  static constexpr int NT = TDim<N>::NT, NP = TDim<N>::NP, FN = 4 * NT;
+  static constexpr int RT = (NP + 15) / 16;  // row tiles: one wavefront each
+  static constexpr int BS = 64 * RT;
+  // tetrahedra per chunk: the (p, o.u) column pairs fill whole 16-column tiles
+  static constexpr int EPB = N <= 2 ? 16 : 8;
+  static constexpr int KV = (NP + 3) / 4, KL = (FN + 3) / 4;  // k-steps
+  static constexpr int VCT = 2 * EPB / 16, LCT = 4 * EPB / 16;  // column tiles
+  static constexpr int NN = EPB * NP, NPL = (NN + BS - 1) / BS;  // nodes per lane
+  static constexpr int NF = EPB * FN, FPL = (NF + BS - 1) / BS;  // face nodes per lane
+  static constexpr int GL = (EPB * kTetGeoStride + BS - 1) / BS, CL = (EPB * kTetConnStride + BS - 1) / BS;
+  static_assert(2 * EPB % 16 == 0, "whole column tiles");
+};
+
+template <int N, typename T>
+__global__ void __launch_bounds__((MCfg<N, T>::BS)) tet_stage_mfma(StageLaunch A) {
+  using C = MCfg<N, T>;
+  using Acc = typename MfmaAcc<T>::type;
+  constexpr int NT = C::NT, NP = C::NP, EPB = C::EPB, BS = C::BS, FN = C::FN;
+  constexpr int NPW = Dim<N>::NP;
+  constexpr int V4B = 4 * int(sizeof(T));
+  __shared__ V4<T> sU[C::NN];
+  __shared__ Q4<T> sW[C::NN];
+  __shared__ V4<T> sF[C::NF];
+  __shared__ V4<T> sD[2 * C::NN];  // per node: D_r p, D_s p, D_t p, div u; lifted F_p, F_u n_x, F_u n_y, F_u n_z
+  __shared__ T sG[EPB * kTetGeoStride];
+  __shared__ int sC[EPB * kTetConnStride];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  // this wavefront's 16 operator rows as MFMA A operands, kept for the whole kernel
+  const T* __restrict__ gops = static_cast<const T*>(A.opsT);
+  const int orow = wave * 16 + lr;
+  T aD[3][C::KV], aL[C::KL];
+#pragma unroll
+  for (int o = 0; o < 3; ++o) {
+#pragma unroll
+    for (int ks = 0; ks < C::KV; ++ks) {
+      const int col = 4 * ks + lk;
+      const bool ok = orow < NP && col < NP;
+      const T v = gops[ok ? o * NP * NP + orow * NP + col : 0];
+      aD[o][ks] = ok ? v : T(0);
+    }
+  }
+#pragma unroll
+  for (int ks = 0; ks < C::KL; ++ks) {
+    const int col = 4 * ks + lk;
+    const bool ok = orow < NP && col < FN;
+    const T v = gops[ok ? 3 * NP * NP + orow * FN + col : 0];
+    aL[ks] = ok ? v : T(0);
+  }
+
+  const V4<T>* __restrict__ Uin = static_cast<const V4<T>*>(A.Uin);
+  const T* __restrict__ geo = static_cast<const T*>(A.geoT);
+  const int* __restrict__ conn = A.connT;
+  const int64_t tb = A.Kw * NPW;  // first tetrahedron node
+  const T bsign = (A.flags & kDirichlet) ? T(-1) : T(1);
+  const T tau_on = (A.flags & kCentral) ? T(0) : T(1);
+  const bool rd = (A.flags & kReadRes) != 0, wu = (A.flags & kWriteU) != 0;
+  const int64_t nchunks = (A.Kt + EPB - 1) / EPB;
+
+  // the next chunk's state (through the buffer's range check: zeros past the
+  // last tetrahedron), geometry and connectivity (indices past the chunk read
+  // its first value; never stored)
+  struct Pre {
+    V4<T> u[C::NPL];
+    T g[C::GL];
+    int c[C::CL];
+  };
+  auto fetch = [&](int64_t ch) -> Pre {
+    const int64_t f0 = ch * EPB;
+    const int n = int(A.Kt - f0 < EPB ? A.Kt - f0 : EPB);
+    Pre p;
+    const auto bu = chunk_rsrc(Uin + tb + f0 * NP, int64_t(n) * NP * V4B);
+#pragma unroll
+    for (int l = 0; l < C::NPL; ++l) p.u[l] = bload<T>(bu, tid + BS * l);
+#pragma unroll
+    for (int l = 0; l < C::GL; ++l) {
+      const int idx = tid + BS * l;
+      p.g[l] = geo[f0 * kTetGeoStride + (idx < n * kTetGeoStride ? idx : 0)];
+    }
+#pragma unroll
+    for (int l = 0; l < C::CL; ++l) {
+      const int idx = tid + BS * l;
+      p.c[l] = conn[f0 * kTetConnStride + (idx < n * kTetConnStride ? idx : 0)];
+    }
+    return p;
+  };
+  Pre pre{};
+  if (int64_t(blockIdx.x) < nchunks) pre = fetch(blockIdx.x);
+
+  for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+    const int64_t e0 = chunk * EPB;
+    const int nE = int(A.Kt - e0 < EPB ? A.Kt - e0 : EPB);
+    const int nn = nE * NP;
+    V4<T>* const res_chunk = static_cast<V4<T>*>(A.res) + tb + e0 * NP;
+    const auto bres_in = chunk_rsrc(res_chunk, rd ? int64_t(nn) * V4B : 0);
+    const auto bres = chunk_rsrc(res_chunk, int64_t(nn) * V4B);
+    const auto bout = chunk_rsrc(static_cast<V4<T>*>(A.Uout) + tb + e0 * NP, int64_t(nn) * V4B);
+    // the previous residual of this lane's nodes, read early (zeros in the first stage)
+    V4<T> rprev[C::NPL];
+#pragma unroll
+    for (int l = 0; l < C::NPL; ++l) rprev[l] = bload<T>(bres_in, tid + BS * l);
+    __syncthreads();  // the previous chunk is done with LDS
+#pragma unroll
+    for (int l = 0; l < C::NPL; ++l)
+      if (tid + BS * l < C::NN) sU[tid + BS * l] = pre.u[l];
+#pragma unroll
+    for (int l = 0; l < C::GL; ++l)
+      if (tid + BS * l < EPB * kTetGeoStride) sG[tid + BS * l] = pre.g[l];
+#pragma unroll
+    for (int l = 0; l < C::CL; ++l)
+      if (tid + BS * l < EPB * kTetConnStride) sC[tid + BS * l] = pre.c[l];
+    if (chunk + gridDim.x < nchunks) pre = fetch(chunk + gridDim.x);
+    __syncthreads();
+
+    // (p, r.u, s.u, t.u) per node: div u = D_r (r.u) + D_s (s.u) + D_t (t.u)
+#pragma unroll
+    for (int l = 0; l < C::NPL; ++l) {
+      const int n = tid + BS * l;
+      if (n < C::NN) {
+        const T* g = sG + (n / NP) * kTetGeoStride;
+        const V4<T> v = sU[n];
+        sW[n] = Q4<T>{v.p, g[0] * v.ux + g[1] * v.uy + g[2] * v.uz, g[3] * v.ux + g[4] * v.uy + g[5] * v.uz,
+                      g[6] * v.ux + g[7] * v.uy + g[8] * v.uz};
+      }
+    }
+    // face fluxes (J_f / J) (F_p, F_u n) at the 4 Np_tri face nodes of every tetrahedron
+#pragma unroll
+    for (int l = 0; l < C::FPL; ++l) {
+      const int q = tid + BS * l;
+      if (q < C::NF) {
+        const int le = q / FN, qq = q - le * FN;
+        const int f = qq / NT, m = qq - f * NT;
+        V4<T> out{T(0), T(0), T(0), T(0)};
+        if (le < nE) {
+          const int64_t e = e0 + le;
+          const T* g = sG + le * kTetGeoStride;
+          const int* cn = sC + le * kTetConnStride;
+          const int code = cn[4];
+          const int nbr = cn[f];
+          const T w_in = nbr >= 0 ? T(1) : T(0);
+          const int pc = (code >> (5 * f)) & 7, nf = (code >> (5 * f + 3)) & 3;
+          const int fn = face_perm<N>(pc, m);
+          const int64_t src = nbr >= 0 ? int64_t(nbr) : A.Kw + e;
+          const int64_t gi = src >= A.Kw ? tb + (src - A.Kw) * NP + tet_face_node<N>(nf, fn)
+                                         : src * NPW + (nf == 1 ? N * NT : 0) + fn;
+          const V4<T> own = sU[le * NP + tet_face_node<N>(f, m)];
+          const V4<T> nb = Uin[gi];
+          const T Fs = g[12 + 4 * f], nx = g[13 + 4 * f], ny = g[14 + 4 * f], nz = g[15 + 4 * f];
+          const T zs = g[28 + f];
+          const T taup = tau_on * T(2) / zs;
+          const T tauu = tau_on * zs * T(0.5);
+          const T pm = own.p;
+          const T unm = nx * own.ux + ny * own.uy + nz * own.uz;
+          const T pb = bsign * pm, ub = -bsign * unm;
+          const T pp = pb + w_in * (nb.p - pb);
+          const T unp = ub + w_in * ((nx * nb.ux + ny * nb.uy + nz * nb.uz) - ub);
+          const T jp = pp - pm, jun = unp - unm;
+          T Fp = T(0.5) * (taup * jp - jun), Fu = T(0.5) * (tauu * jun - jp);
+          if (nbr <= -2) {
+            // mortar side: the equivalent nodal flux of the common refinement
+            const T* mf = static_cast<const T*>(A.mortF) + int64_t(-2 - nbr) * 2 * NT;
+            Fp = mf[m];
+            Fu = mf[NT + m];
+          }
+          const T su = Fs * Fu;
+          out = V4<T>{Fs * Fp, su * nx, su * ny, su * nz};
+        }
+        sF[q] = out;
+      }
+    }
+    __syncthreads();
+
+    // reference-operator products on the matrix cores: this wavefront's rows
+    // 16 w .. 16 w + 15 of every column tile
+    {
+      const T* sWf = reinterpret_cast<const T*>(sW);
+      const T* sFf = reinterpret_cast<const T*>(sF);
+      T* sDf = reinterpret_cast<T*>(sD);
+#pragma unroll
+      for (int ct = 0; ct < C::VCT; ++ct) {
+        const int col = ct * 16 + lr;  // column (tetrahedron, p or o.u) of this lane's B and D values
+        const int ce = col >> 1, which = col & 1;
+        Acc acc[3];
+#pragma unroll
+        for (int o = 0; o < 3; ++o) acc[o] = Acc{T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int ks = 0; ks < C::KV; ++ks) {
+          const int k = 4 * ks + lk;
+          // rows k >= Np of B meet zero columns of A: any finite value will do
+          const int base = (ce * NP + (k < NP ? k : 0)) * 4;
+#pragma unroll
+          for (int o = 0; o < 3; ++o) acc[o] = mfma16x16x4<T>(aD[o][ks], sWf[base + (which ? 1 + o : 0)], acc[o]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = wave * 16 + mfma_row<T>(lk, r);
+          if (i < NP) {
+            T* d = sDf + (ce * NP + i) * 8;
+            if (which == 0) {
+              d[0] = acc[0][r];
+              d[1] = acc[1][r];
+              d[2] = acc[2][r];
+            } else {
+              d[3] = acc[0][r] + acc[1][r] + acc[2][r];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int ct = 0; ct < C::LCT; ++ct) {
+        const int col = ct * 16 + lr;  // column (tetrahedron, component) of the fluxes
+        const int ce = col >> 2, cc = col & 3;
+        Acc acc = Acc{T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int ks = 0; ks < C::KL; ++ks) {
+          const int k = 4 * ks + lk;
+          acc = mfma16x16x4<T>(aL[ks], sFf[(ce * FN + (k < FN ? k : 0)) * 4 + cc], acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = wave * 16 + mfma_row<T>(lk, r);
+          if (i < NP) sDf[(ce * NP + i) * 8 + 4 + cc] = acc[r];
+        }
+      }
+    }
+    __syncthreads();
+
+    // right-hand side, sources and the low-storage update, node-contiguous
+    const T ca = T(A.a), cb = T(A.b), dtt = T(A.dt), cg = (A.flags & kGamma) ? T(A.g) : T(1);
+#pragma unroll
+    for (int l = 0; l < C::NPL; ++l) {
+      const int n = tid + BS * l;
+      if (n < nn) {
+        const int le = n / NP, i = n - le * NP;
+        const int64_t e = e0 + le;
+        const T* g = sG + le * kTetGeoStride;
+        const T* d = reinterpret_cast<const T*>(sD) + n * 8;
+        const T kap = g[9], irho = g[10];
+        T Rp = kap * (d[4] - d[3]);
+        const T Rx = irho * (d[5] - (g[0] * d[0] + g[3] * d[1] + g[6] * d[2]));
+        const T Ry = irho * (d[6] - (g[1] * d[0] + g[4] * d[1] + g[7] * d[2]));
+        const T Rz = irho * (d[7] - (g[2] * d[0] + g[5] * d[1] + g[8] * d[2]));
+        for (int s = 0; s < A.nsrc; ++s)
+          if (A.src_elem[s] == A.Kw + e) Rp += T(A.src_amp[s]) * static_cast<const T*>(A.srcvec)[s * NPW + i];
+        const V4<T> q = rprev[l];
+        const V4<T> r{ca * q.p + dtt * Rp, ca * q.uz + dtt * Rz, ca * q.ux + dtt * Rx, ca * q.uy + dtt * Ry};
+        bstore<T>(bres, n, r);
+        if (wu) {
+          const V4<T> u = sU[n];
+          bstore<T>(bout, n, V4<T>{cg * u.p + cb * r.p, cg * u.uz + cb * r.uz, cg * u.ux + cb * r.ux,
+                                   cg * u.uy + cb * r.uy});
+        }
+      }
+    }
+  }
+}
+
 #ifndef WDG_TET_BLOCKS
 #define WDG_TET_BLOCKS 2048
 #endif
@@ -250,8 +558,26 @@ hipError_t launch_tet_stage_t(const StageLaunch& a, hipStream_t st) {
   // the resident count at four per CU, measured 1 us slower on the N = 4
   // hybrid mesh of 29 520 tetrahedra)
   const int64_t cap = a.tet_blocks > 0 ? int64_t(a.tet_blocks) : kTetBlocks;
-  const unsigned grid = unsigned(tchunks < cap ? tchunks : cap);
-  hipLaunchKernelGGL((tet_stage<N, T>), dim3(grid), dim3(TC::BS), 0, st, a);
+  if (a.flags & kTetValu) {
+    const unsigned grid = unsigned(tchunks < cap ? tchunks : cap);
+    hipLaunchKernelGGL((tet_stage<N, T>), dim3(grid), dim3(TC::BS), 0, st, a);
+  } else {
+    using MC = MCfg<N, T>;
+    const int64_t mchunks = (a.Kt + MC::EPB - 1) / MC::EPB;
+    // every block loads its wavefronts' operator rows once: by default launch
+    // only the blocks that are resident at once on the device
+    static const int64_t resident = [] {
+      int per_cu = 0, dev = 0, cus = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, tet_stage_mfma<N, T>, MC::BS, 0) != hipSuccess ||
+          hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return kTetBlocks;
+      return int64_t(per_cu > 0 ? per_cu : 1) * int64_t(cus > 0 ? cus : 1);
+    }();
+    const int64_t mcap = a.tet_blocks > 0 ? int64_t(a.tet_blocks) : resident;
+    const unsigned grid = unsigned(mchunks < mcap ? mchunks : mcap);
+    hipLaunchKernelGGL((tet_stage_mfma<N, T>), dim3(grid), dim3(MC::BS), 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -71,6 +71,26 @@ __device__ __forceinline__ T pick(const double* tab, int j, int stride, int col)
 }
 
 
+// Adds one stage's gradient terms x[kGradStride] of wedge e to its
+// accumulators across the reverse sweep: FP64 in place; FP32 as Kahan
+// (compensated) sums, the record holding the sums, then their compensations.
+template <typename T>
+__device__ __forceinline__ void grad_accumulate(void* gacc, int64_t e, const T* x) {
+  T* ga = static_cast<T*>(gacc) + e * kGradRecord<T>;
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int k = 0; k < kGradStride; ++k) ga[k] += x[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < kGradStride; ++k) {
+      const T y = x[k] - ga[kGradStride + k];
+      const T t = ga[k] + y;
+      ga[kGradStride + k] = (t - ga[k]) - y;
+      ga[k] = t;
+    }
+  }
+}
+
 // Gradient terms of one reverse stage of the adjoint sweep (MODE 4), run by
 // the stage kernel after its update.  The stage input (the adjoint stage
 // vector sig) is still staged in sU; the forward stage input Us and its
@@ -91,7 +111,7 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
   constexpr int SU = (EPB * NP + 63) / 64;
   constexpr int GS = kGradStride + 1;  // partial sums per lane (odd: fewer bank conflicts)
   static_assert(EPB * 3 * Nq * Nq * 2 <= EPB * NPP * 4, "jump scratch fits the state region");
-  static_assert(EPB * Nq * GS * 8 <= EPB * C::XPE * 4 * int(sizeof(T)), "partial sums fit the second region");
+  static_assert(EPB * Nq * GS <= EPB * C::XPE * 4, "partial sums fit the second region");
   const bool lane_ok = le < EPB;
   const T bsign = (A.flags & kDirichlet) ? T(-1) : T(1);
   const int lb = (lane_ok ? le : 0) * NPP + j * NT;
@@ -136,9 +156,9 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
     }
   }
   __syncthreads();
-  double part[kGradStride];
+  T part[kGradStride];
 #pragma unroll
-  for (int k = 0; k < kGradStride; ++k) part[k] = 0.0;
+  for (int k = 0; k < kGradStride; ++k) part[k] = T(0);
   const V4<T>* sUs = sX;
   const V4<T>* sRs = sU;
 
@@ -175,8 +195,8 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
       sp += sg[i].p * mp;
       sn += (nx * sg[i].ux + ny * sg[i].uy + nz * sg[i].uz) * mn;
     }
-    part[2 + face] = 0.5 * double(Jf) * double(sp);
-    part[7 + face] = 0.5 * double(Jf) * double(sn);
+    part[2 + face] = T(0.5) * Jf * sp;
+    part[7 + face] = T(0.5) * Jf * sn;
   }
 
   // quadrilateral faces: jumps of this level (to LDS below); the adjoint
@@ -258,8 +278,8 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
       mp += sg[i].p * z0;
       mu += sg[i].ux * z1 + sg[i].uy * z2 + sg[i].uz * z3;
     }
-    part[0] = double(mp);
-    part[1] = double(mu);
+    part[0] = mp;
+    part[1] = mu;
   }
   __syncthreads();  // Us and Rs in LDS are consumed
   T* const sJ = reinterpret_cast<T*>(sU);  // quadrilateral-face jumps [wedge][edge][level][node][p, u_n]
@@ -274,7 +294,7 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
       }
   }
   __syncthreads();
-  double* const sPart = reinterpret_cast<double*>(sX);
+  T* const sPart = reinterpret_cast<T*>(sX);
   if (lane_ok) {
     // quadrilateral faces: couple the levels through M^1D
 #pragma unroll
@@ -292,30 +312,31 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
         sp += m1[m] * tp;
         sn += m1[m] * tn;
       }
-      part[4 + ed] = 0.5 * double(sp);
-      part[9 + ed] = 0.5 * double(sn);
+      part[4 + ed] = T(0.5) * sp;
+      part[9 + ed] = T(0.5) * sn;
     }
 #pragma unroll
     for (int k = 0; k < kGradStride; ++k) sPart[(le * Nq + j) * GS + k] = part[k];
   }
   __syncthreads();
   if (active && j == 0) {
-    double tot[kGradStride];
+    T tot[kGradStride];
 #pragma unroll
     for (int k = 0; k < kGradStride; ++k) {
-      double s = 0.0;
+      T s = 0;
 #pragma unroll
       for (int l = 0; l < Nq; ++l) s += sPart[(le * Nq + l) * GS + k];
       tot[k] = s;
     }
-    const double kap = double(g[9]), irho = double(g[10]);
-    const double c = std::sqrt(kap * irho);
-    double* ga = A.gacc + e * kGradStride;
-    const double dt = A.dt;
-    ga[0] += dt * 2.0 / (c * kap) * tot[0];
-    ga[1] += dt * (tot[0] * irho / kap + tot[1]);
+    const T kap = g[9], irho = g[10];
+    const T c = std::sqrt(kap * irho);
+    const T dt = T(A.dt);
+    T x[kGradStride];
+    x[0] = dt * T(2) / (c * kap) * tot[0];
+    x[1] = dt * (tot[0] * irho / kap + tot[1]);
 #pragma unroll
-    for (int k = 2; k < kGradStride; ++k) ga[k] += dt * tot[k];
+    for (int k = 2; k < kGradStride; ++k) x[k] = dt * tot[k];
+    grad_accumulate<T>(A.gacc, e, x);
   }
 }
 

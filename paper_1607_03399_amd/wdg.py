@@ -62,6 +62,7 @@ def load_library() -> C.CDLL:
         "wdg_set_mass": (C.c_int, [vp, C.c_int]),
         "wdg_set_layer_march": (C.c_int, [vp, C.c_int]),
         "wdg_set_tet_blocks": (C.c_int, [vp, C.c_int]),
+        "wdg_set_tet_kernel": (C.c_int, [vp, C.c_int]),
         "wdg_num_nodes": (C.c_int, [vp, _i64p]),
         "wdg_get_node_coords": (C.c_int, [vp, _dp]),
         "wdg_set_fields": (C.c_int, [vp, _dp, _dp, _dp, _dp]),
@@ -194,6 +195,10 @@ class Solver:
     def set_tet_blocks(self, blocks: int):
         """Cap on the persistent blocks of the tetrahedron kernel (0: default)."""
         self._check(self._lib.wdg_set_tet_blocks(self._h, int(blocks)), "set_tet_blocks")
+
+    def set_tet_kernel(self, variant: str):
+        """'mfma' (default: operator products on the matrix cores) or 'valu' (per-node dot products)."""
+        self._check(self._lib.wdg_set_tet_kernel(self._h, {"mfma": 0, "valu": 1}[variant]), "set_tet_kernel")
 
     def set_mass(self, mass: str):
         """'exact' (default, energy stable) or 'lumped' (Gauss-Lobatto in t, for comparison)."""

@@ -10,6 +10,16 @@ within ten times the tolerance.  Arrays are element-major: (K, ...).
 import numpy as np
 
 TOL = {64: 1e-12, 32: 1e-5}
+# tetrahedron stage kernels: operator products on the matrix cores / as per-node dot products
+TET_KERNELS = ("mfma", "valu")
+
+
+def tet_chunk(N: int, kernel: str) -> int:
+    """Tetrahedra per chunk (the unit a persistent block loops over) of the
+    tetrahedron stage kernel."""
+    if kernel == "valu":
+        return 256 // ((N + 1) * (N + 2) * (N + 3) // 6)
+    return 16 if N <= 2 else 8
 ELEM_FACTOR = 10.0
 
 

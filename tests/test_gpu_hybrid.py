@@ -12,7 +12,7 @@ import pytest
 from oracle import dg, lsrk
 from paper_1607_03399_amd import inputs
 from paper_1607_03399_amd import wdg
-from parity import TOL, check
+from parity import TET_KERNELS as KERNELS, TOL, check, tet_chunk
 
 pytestmark = pytest.mark.gpu
 # even permutations of four vertices keep a tetrahedron's orientation
@@ -41,13 +41,14 @@ def _hybrid(nx=3, layers=4, tet_layers=2, seed=1, permute=None):
     return v, w, t, c, rho
 
 
-def _solver(mesh, N, bits, bc="rigid", flux="upwind"):
+def _solver(mesh, N, bits, bc="rigid", flux="upwind", kernel="mfma"):
     v, w, t, c, rho = mesh
     s = wdg.Solver(N, bits, device=0)
     s.set_mesh(v, w, t)
     s.set_material(c, rho)
     s.set_boundary(bc)
     s.set_flux(flux)
+    s.set_tet_kernel(kernel)
     return s
 
 
@@ -57,18 +58,21 @@ def _omesh(mesh, bc="rigid", flux="upwind"):
 
 
 def _compare_rhs(mesh, N, bits, bc, flux, seed):
-    """Relative L2 error of the library's right-hand side of a random state;
-    the per-element bound is asserted here."""
-    s = _solver(mesh, N, bits, bc, flux)
+    """Largest relative L2 error of the library's right-hand side of a random
+    state over both tetrahedron kernels; the per-element bound is asserted
+    here."""
     om = _omesh(mesh, bc, flux)
-    mask = dg.node_mask(om, N)[:, :s.NPmax]
-    U = np.random.default_rng(seed).standard_normal((om.K, 4, s.NPmax)) * mask[:, None, :]
-    got = s.eval_rhs(U)
-    Uo = np.zeros((om.K, 4, dg.node_mask(om, N).shape[1]))
-    Uo[:, :, :s.NPmax] = U
-    ref = dg.rhs(dg.build_operators(om, N), Uo)[:, :, :s.NPmax]
-    s.close()
-    return check(got, ref, TOL[bits], f"hybrid N={N} {bits} {bc} {flux}")[0]
+    mask = dg.node_mask(om, N)
+    U = np.random.default_rng(seed).standard_normal((om.K, 4, mask.shape[1])) * mask[:, None, :]
+    ref = dg.rhs(dg.build_operators(om, N), U)
+    worst = 0.0
+    for kernel in KERNELS:
+        s = _solver(mesh, N, bits, bc, flux, kernel)
+        got = s.eval_rhs(U[:, :, :s.NPmax])
+        s.close()
+        err = check(got, ref[:, :, :got.shape[2]], TOL[bits], f"hybrid N={N} {bits} {bc} {flux} {kernel}")[0]
+        worst = max(worst, err)
+    return worst
 
 
 @pytest.mark.parametrize("bits", [64, 32])
@@ -103,8 +107,8 @@ def test_tetrahedra_only_and_ragged(bits):
             assert _compare_rhs(mesh, N, bits, "dirichlet", "upwind", nx + N) <= TOL[bits]
 
 
-def _run(mesh, N, bits, U0, dt, nsteps, src, rec, tet_blocks=0):
-    s = _solver(mesh, N, bits)
+def _run(mesh, N, bits, U0, dt, nsteps, src, rec, tet_blocks=0, kernel="mfma"):
+    s = _solver(mesh, N, bits, kernel=kernel)
     s.set_tet_blocks(tet_blocks)
     s.add_ricker_source(*src)
     s.set_receivers(rec)
@@ -136,9 +140,9 @@ def _run_oracle(mesh, N, U0, dt, nsteps, src, rec):
     return U, np.array(tr), dg.energy(ops, U)
 
 
-@pytest.mark.parametrize("looped", [False, True])
+@pytest.mark.parametrize("looped,kernel", [(False, "mfma"), (True, "mfma"), (True, "valu")])
 @pytest.mark.parametrize("N,bits,nsteps", [(2, 64, 100), (4, 32, 100)])
-def test_hybrid_time_integration(N, bits, nsteps, looped):
+def test_hybrid_time_integration(N, bits, nsteps, looped, kernel):
     """Gaussian pulse plus a Ricker source inside the tetrahedral layer,
     receivers in both kinds of element: fields, traces and energy.  Looped:
     the tetrahedron kernel's persistent blocks are capped at a third of its
@@ -156,16 +160,16 @@ def test_hybrid_time_integration(N, bits, nsteps, looped):
     kinds = om.kinds()
     assert kinds[dg.locate(om, np.array(src[0]))[0]] == 1
     assert {int(kinds[dg.locate(om, r)[0]]) for r in rec} == {0, 1}
-    _say("hybrid steps library", N, bits)
-    nchunks = -(-len(mesh[2]) // (256 // ((N + 1) * (N + 2) * (N + 3) // 6)))
+    _say("hybrid steps library", N, bits, kernel)
+    nchunks = -(-len(mesh[2]) // tet_chunk(N, kernel))
     tet_blocks = max(1, nchunks // 3) if looped else 0
     assert not looped or nchunks >= 3 * tet_blocks
-    got, gtr, gE = _run(mesh, N, bits, U0, dt, nsteps, src, rec, tet_blocks)
+    got, gtr, gE = _run(mesh, N, bits, U0, dt, nsteps, src, rec, tet_blocks, kernel)
     _say("hybrid steps oracle", N, bits)
     ref, rtr, rE = _run_oracle(mesh, N, U0, dt, nsteps, src, rec)
     ref = ref[:, :, :got.shape[2]]
     tol = TOL[bits]
-    err, emax = check(got, ref, tol, f"hybrid steps N={N} {bits} blocks={tet_blocks}")
+    err, emax = check(got, ref, tol, f"hybrid steps N={N} {bits} blocks={tet_blocks} {kernel}")
     _say("   rel err", err, "worst element", emax)
     assert np.abs(gtr - rtr).max() <= tol * np.abs(rtr).max()
     assert abs(gE - rE) <= tol * rE

@@ -12,7 +12,7 @@ import pytest
 from oracle import dg, lsrk
 from paper_1607_03399_amd import inputs
 from paper_1607_03399_amd import wdg
-from parity import TOL, check
+from parity import TET_KERNELS as KERNELS, TOL, check, tet_chunk
 
 pytestmark = pytest.mark.gpu
 EVEN = [p for p in itertools.permutations(range(4))
@@ -40,13 +40,14 @@ def _columns(nx=3, layers=3, cols=(4, 9), seed=1, permute=None):
     return v, w, t, c, rho
 
 
-def _solver(mesh, N, bits, bc="rigid", flux="upwind"):
+def _solver(mesh, N, bits, bc="rigid", flux="upwind", kernel="mfma"):
     v, w, t, c, rho = mesh
     s = wdg.Solver(N, bits, device=0)
     s.set_mesh(v, w, t)
     s.set_material(c, rho)
     s.set_boundary(bc)
     s.set_flux(flux)
+    s.set_tet_kernel(kernel)
     return s
 
 
@@ -56,14 +57,20 @@ def _omesh(mesh, bc="rigid", flux="upwind"):
 
 
 def _compare_rhs(mesh, N, bits, bc, flux, seed):
-    s = _solver(mesh, N, bits, bc, flux)
+    """Largest relative L2 error over both tetrahedron kernels (matrix cores,
+    vector units); the per-element bound is asserted here."""
     om = _omesh(mesh, bc, flux)
     mask = dg.node_mask(om, N)
     U = np.random.default_rng(seed).standard_normal((om.K, 4, mask.shape[1])) * mask[:, None, :]
-    got = s.eval_rhs(U[:, :, :s.NPmax])
-    ref = dg.rhs(dg.build_operators(om, N), U)[:, :, :s.NPmax]
-    s.close()
-    return check(got, ref, TOL[bits], f"mortar N={N} {bits} {bc} {flux}")[0]
+    ref = dg.rhs(dg.build_operators(om, N), U)
+    worst = 0.0
+    for kernel in KERNELS:
+        s = _solver(mesh, N, bits, bc, flux, kernel)
+        got = s.eval_rhs(U[:, :, :s.NPmax])
+        s.close()
+        err = check(got, ref[:, :, :got.shape[2]], TOL[bits], f"mortar N={N} {bits} {bc} {flux} {kernel}")[0]
+        worst = max(worst, err)
+    return worst
 
 
 @pytest.mark.parametrize("bits", [64, 32])
@@ -88,9 +95,9 @@ def test_mortar_rhs_parity_permuted_and_ragged(bits):
         assert _compare_rhs(mesh, N, bits, "rigid", "upwind", 9) <= TOL[bits]
 
 
-@pytest.mark.parametrize("looped", [False, True])
+@pytest.mark.parametrize("looped,kernel", [(False, "mfma"), (True, "mfma"), (True, "valu")])
 @pytest.mark.parametrize("N,bits", [(2, 64), (4, 32)])
-def test_mortar_time_integration(N, bits, looped):
+def test_mortar_time_integration(N, bits, looped, kernel):
     """Gaussian pulse and a Ricker source inside a split column, receivers in
     wedges and tetrahedra: fields, traces and energy after 100 steps.  Seven
     of the 18 columns are split (63 tetrahedra).  Looped: the tetrahedron
@@ -109,8 +116,8 @@ def test_mortar_time_integration(N, bits, looped):
     assert kinds[dg.locate(om, xs)[0]] == 1
     rec = np.array([[0.5, 0.5, 0.8], xs + [0.01, 0.0, 0.02], [0.8, 0.15, 0.3]])
     src = (xs, 5.0, 0.2, 1.0)
-    s = _solver(mesh, N, bits)
-    nchunks = -(-s.Kt // (256 // s.Npt))
+    s = _solver(mesh, N, bits, kernel=kernel)
+    nchunks = -(-s.Kt // tet_chunk(N, kernel))
     tet_blocks = max(1, nchunks // 3) if looped else 0
     assert not looped or nchunks >= 3 * tet_blocks
     s.set_tet_blocks(tet_blocks)
@@ -136,8 +143,8 @@ def test_mortar_time_integration(N, bits, looped):
                             after_step=lambda n, t, U: tr.append(np.einsum("rj,rj->r", rows, U[rel_el, 0])))
     rE = dg.energy(ops, ref)
     tol = TOL[bits]
-    err, emax = check(got, ref[:, :, :got.shape[2]], tol, f"mortar steps N={N} {bits} blocks={tet_blocks}")
-    _say("mortar steps", N, bits, "rel err", err, "worst element", emax)
+    err, emax = check(got, ref[:, :, :got.shape[2]], tol, f"mortar steps N={N} {bits} blocks={tet_blocks} {kernel}")
+    _say("mortar steps", N, bits, kernel, "rel err", err, "worst element", emax)
     rtr = np.array(tr)
     assert np.abs(gtr - rtr).max() <= tol * np.abs(rtr).max()
     assert abs(gE - rE) <= tol * rE
