@@ -353,7 +353,10 @@ def batch_benchmark(steps: int):
     same = all(np.array_equal(s.get_fields(), f) for s, f in zip(solvers, seq_fields))
     orders = sorted({N for N, _, _ in specs})
     tuned = {str(N): {"elements_per_block": batch.config(N)[0], "waves_per_simd": batch.config(N)[1],
-                      "tuned_stage_us": batch.config(N)[2]} for N in orders}
+                      "tuned_stage_us": batch.config(N)[2],
+                      "kernel": "node-lane" if N >= 4 else "level-lane",
+                      "candidates": [{"elements_per_block": e, "waves_per_simd": w, "median_stage_us": us}
+                                     for e, w, us in batch.trials(N)]} for N in orders}
     nodes = sum(s.K * s.Np for s in solvers)
     batch.close()
     for s in solvers:
@@ -439,7 +442,8 @@ def workload(config: str):
     return N, mesh.verts, mesh.wedges, np.zeros((0, 4), np.int64), mesh.c, mesh.rho, mesh, desc
 
 
-def forward_leg(config: str, bits: int, steps: int, warmup: int, layer_march: bool = False):
+def forward_leg(config: str, bits: int, steps: int, warmup: int, layer_march: bool = False, tet_kernel: str = "mfma",
+                wedge_kernel: str = "auto"):
     """Time ``steps`` steps of a configuration (after ``warmup`` steps) on a
     torch-bound state and stream; per-kernel averages from HIP events on that
     stream.  Returns (result dict, time step, wedge mesh or None)."""
@@ -455,6 +459,8 @@ def forward_leg(config: str, bits: int, steps: int, warmup: int, layer_march: bo
     s.set_boundary("rigid")
     s.set_flux("upwind")
     s.set_layer_march(layer_march)
+    s.set_tet_kernel(tet_kernel)
+    s.set_wedge_kernel(wedge_kernel)
     s.add_ricker_source([0.5, 0.5, 0.5], 10.0, 0.1, 1.0)
     s.set_fields(initial_state(s))
     s.bind_torch()
@@ -483,13 +489,15 @@ def forward_leg(config: str, bits: int, steps: int, warmup: int, layer_march: bo
     if Kw:
         avg = w_ms * 1e3 / nlaunch
         rec_bytes = Kw * (stage_bytes(N, bits, False) + 4 * stage_bytes(N, bits, True)) / 5
-        kernels["wedge_stage"] = {"avg_us": avg, "bytes_per_launch": Kw * survey_stage_bytes(N, bits),
+        kernels["wedge_stage"] = {"avg_us": avg, "variant": "node-lane" if N >= 4 and bits == 32 and
+                                  wedge_kernel == "auto" else "level-lane",
+                                  "bytes_per_launch": Kw * survey_stage_bytes(N, bits),
                                   "GBs": Kw * survey_stage_bytes(N, bits) / avg / 1e3,
                                   "record_bytes_per_launch": rec_bytes, "record_GBs": rec_bytes / avg / 1e3}
     if Kt:
         avg = t_ms * 1e3 / nlaunch
         tb = Kt * (tet_stage_bytes(N, bits, False) + 4 * tet_stage_bytes(N, bits, True)) / 5
-        kernels["tet_stage"] = {"avg_us": avg, "bytes_per_launch": tb, "GBs": tb / avg / 1e3}
+        kernels["tet_stage"] = {"avg_us": avg, "bytes_per_launch": tb, "GBs": tb / avg / 1e3, "variant": tet_kernel}
     if nmort:
         avg = m_ms * 1e3 / nlaunch
         mb = nmort * mortar_bytes(N, bits)
@@ -521,6 +529,11 @@ def main():
     ap.add_argument("--precision", type=int, default=32, choices=[32, 64])
     ap.add_argument("--layer-march", action="store_true",
                     help="stage kernel variant reading vertical neighbours inside a chunk from LDS")
+    ap.add_argument("--tet-kernel", default="mfma", choices=["mfma", "valu"],
+                    help="tetrahedron operator products on the matrix cores (default) or as per-node dot products")
+    ap.add_argument("--wedge-kernel", default="auto", choices=["auto", "level"],
+                    help="wedge stage kernel: auto (one lane per triangle node from order 4 on in FP32) or level "
+                         "(one lane per GLL level at every order)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--cpu-workers", type=int, default=0,
@@ -533,8 +546,8 @@ def main():
                     help="skip the batched leg (cfg2 runs the cfg4 48-problem batch after the forward bench)")
     ap.add_argument("--batch-steps", type=int, default=300)
     ap.add_argument("--no-legs", action="store_true",
-                    help="skip the other forward configurations (cfg2 runs cfg3, cfg5, order 4 and 5 and FP64 "
-                         "cfg2 for 20 steps each)")
+                    help="skip the other forward configurations (cfg2 runs cfg3 with both tetrahedron kernels, "
+                         "cfg5, order 4 and 5 and FP64 cfg2 for 20 steps each)")
     ap.add_argument("--leg-steps", type=int, default=20)
     ap.add_argument("--no-copy-calibration", action="store_true",
                     help="skip the plain 512 MiB device copy (the measured HBM reference of the roofline)")
@@ -552,7 +565,8 @@ def main():
 
     copy_gbs = None if args.no_copy_calibration else copy_bandwidth()
     bits = args.precision
-    main_leg, dt, mesh = forward_leg(args.config, bits, args.steps, args.warmup, args.layer_march)
+    main_leg, dt, mesh = forward_leg(args.config, bits, args.steps, args.warmup, args.layer_march, args.tet_kernel,
+                                     args.wedge_kernel)
     kernels = main_leg["kernels"]
     dominant = max(kernels, key=lambda k: kernels[k]["avg_us"])
     achieved = kernels[dominant]["GBs"]
@@ -591,9 +605,14 @@ def main():
     default_run = args.config == "cfg2" and bits == 32
     if default_run and not args.no_legs:
         legs = {}
-        for name, cfg, b in (("cfg3", "cfg3", 32), ("cfg5_forward", "cfg5", 32), ("order4", "order4", 32),
-                             ("order5", "order5", 32), ("cfg2_fp64", "cfg2", 64)):
-            legs[name], _, _ = forward_leg(cfg, b, args.leg_steps, 3)
+        for name, cfg, b, tk, wk in (("cfg3", "cfg3", 32, "mfma", "auto"), ("cfg3_tet_valu", "cfg3", 32, "valu", "auto"),
+                                     ("cfg3_wedge_level", "cfg3", 32, "mfma", "level"),
+                                     ("cfg5_forward", "cfg5", 32, "mfma", "auto"), ("order4", "order4", 32, "mfma", "auto"),
+                                     ("order4_wedge_level", "order4", 32, "mfma", "level"),
+                                     ("order5", "order5", 32, "mfma", "auto"),
+                                     ("order5_wedge_level", "order5", 32, "mfma", "level"),
+                                     ("cfg2_fp64", "cfg2", 64, "mfma", "auto")):
+            legs[name], _, _ = forward_leg(cfg, b, args.leg_steps, 3, tet_kernel=tk, wedge_kernel=wk)
         out["legs"] = legs
     if default_run and not args.no_adjoint:
         out["adjoint"] = adjoint_benchmark(args.adjoint_steps, 50)

@@ -132,6 +132,15 @@ int wdg_set_tet_blocks(wdg_ctx* ctx, int blocks);
 enum { WDG_TET_MFMA = 0, WDG_TET_VALU = 1 };
 int wdg_set_tet_kernel(wdg_ctx* ctx, int variant);
 
+/* Which wedge stage kernel runs (both compute the stage of Sec. 4.2-4.3 up to
+ * rounding order).  WDG_WEDGE_AUTO (default): from order 4 on in FP32, one
+ * lane per triangle node, which owns the node's vertical line of GLL levels;
+ * below order 4, in FP64, and for layer marching and the adjoint sweep, one
+ * lane per GLL level, which owns the level's triangular slice.  WDG_WEDGE_LEVEL: the
+ * level-lane kernel at every order.  Other values: WDG_ERR_ARG. */
+enum { WDG_WEDGE_AUTO = 0, WDG_WEDGE_LEVEL = 1 };
+int wdg_set_wedge_kernel(wdg_ctx* ctx, int variant);
+
 /* Total number of nodes (sum over elements of Np). */
 int wdg_num_nodes(const wdg_ctx* ctx, int64_t* n);
 /* Physical node coordinates, num_nodes x 3, in the node order above. */
@@ -245,19 +254,27 @@ int wdg_set_adjoint_memory_limit(wdg_ctx* ctx, int64_t bytes);
  *     context while a batch call runs).  index (may be NULL) receives its slot.
  *   wdg_batch_prepare: groups the problems by order and lists their element
  *     chunks problem by problem (one block per chunk, each XCD a contiguous
- *     range); with autotune != 0 times, for every order, the stage kernel
+ *     range); with autotune != 0 (the tuning of elements per block of
+ *     Sec. 6.3) times, for every order, each kernel shape that exists for it
+ *     -- orders 4 and 5 in FP32: the node-lane kernel (wdg_set_wedge_kernel)
+ *     at four element counts per block; otherwise the level-lane kernel
  *     compiled for 2 waves per SIMD (as the single-problem kernel) and for 1
- *     (twice the registers: no spills at high order) on the real data
- *     (launches that rewrite only the residual, which the next stage
- *     overwrites anyway) and keeps the faster; then captures the step graph.
- *     No problem may be added afterwards (WDG_ERR_STATE).
+ *     (twice the registers) -- on the real data, as the median of five
+ *     launches that rewrite only the residual (which the next stage
+ *     overwrites anyway), and keeps the fastest; without autotuning the first
+ *     candidate (the single-problem kernel's shape).  Then it captures the
+ *     step graph.  No problem may be added afterwards (WDG_ERR_STATE).
  *   wdg_batch_step: nsteps steps of every problem from its current fields and
  *     time (each with its own time step); afterwards wdg_get_fields and
  *     wdg_get_time of each context show the new state.  Receiver traces are
  *     not recorded by batch steps, and a forward recording (wdg_adjoint_record)
  *     of a problem ends.
  *   wdg_batch_config: elements per block, the chosen waves per SIMD of order N
- *     and the tuned average stage time of that order (microseconds).
+ *     and the tuned median stage time of that order (microseconds).
+ *   wdg_batch_trials: the autotuner's candidates for order N in the order
+ *     tried: elements per block, waves per SIMD and median stage time
+ *     (microseconds); up to cap of them are written, *count receives their
+ *     number (0 without autotuning).
  * Results are identical to wdg_step of each problem alone. */
 typedef struct wdg_batch wdg_batch;
 int wdg_batch_create(int device, int precision_bits, wdg_batch** out);
@@ -267,6 +284,8 @@ int wdg_batch_add(wdg_batch* batch, wdg_ctx* problem, double dt, int* index);
 int wdg_batch_prepare(wdg_batch* batch, int autotune);
 int wdg_batch_step(wdg_batch* batch, int64_t nsteps);
 int wdg_batch_config(const wdg_batch* batch, int N, int* elems_per_block, int* waves_per_simd, double* tuned_us);
+int wdg_batch_trials(const wdg_batch* batch, int N, int64_t cap, int* elems_per_block, int* waves_per_simd,
+                     double* stage_us, int64_t* count);
 
 /* Per-launch timing of the stage kernels with HIP events on the context stream:
  * enable = 1 starts collecting (and clears), 0 stops.  read returns the summed

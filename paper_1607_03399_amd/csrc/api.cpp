@@ -80,6 +80,7 @@ struct wdg_ctx {
   bool layer_march = false;
   int tet_blocks = 0;  // persistent blocks of the tetrahedron kernel (0: default)
   bool tet_valu = false;  // tetrahedron products as per-node dot products (else MFMA)
+  bool wedge_level = false;  // N >= 4: the level-lane wedge kernel instead of the node-lane one
   double time = 0.0;
 
   hipStream_t stream = nullptr;
@@ -97,6 +98,7 @@ struct wdg_ctx {
   int32_t* dConn = nullptr;
   void* dGeoT = nullptr;
   void* dOpsT = nullptr;
+  void* dOpsW = nullptr;  // N >= 4: reference rows of the node-lane wedge kernel
   double* dAuxT = nullptr;
   double* dMt = nullptr;
   int32_t* dConnT = nullptr;
@@ -190,6 +192,7 @@ void release_device(wdg_ctx* ctx) {
   dfree(ctx->dConn);
   dfree(ctx->dGeoT);
   dfree(ctx->dOpsT);
+  dfree(ctx->dOpsW);
   dfree(ctx->dAuxT);
   dfree(ctx->dMt);
   dfree(ctx->dConnT);
@@ -387,6 +390,19 @@ int upload_sources(wdg_ctx* ctx) {
 }
 
 // one Runge-Kutta stage (or, with a = 0, dt = 1, no U write, a plain RHS)
+// Whether the wedges of a stage with these flags run on the node-lane kernel
+// (orders 4 and 5 in FP32, except layer marching and the adjoint sweep, which
+// only the level-lane kernel implements).
+bool node_kernel(const wdg_ctx* ctx, int flags) {
+  return ctx->N >= 4 && ctx->bits == 32 && !ctx->wedge_level && !(flags & (wdg::kLayerMarch | wdg::kGrad));
+}
+
+hipError_t launch_wedges(const wdg_ctx* ctx, const wdg::StageLaunch& L) {
+  if (node_kernel(ctx, L.flags))
+    return wdg::launch_wedge_node_stage(ctx->N, ctx->bits, wdg::wedge_node_epb(ctx->N, ctx->bits, 0), L, ctx->stream);
+  return wdg::launch_wedge_stage(ctx->N, ctx->bits, L, ctx->stream);
+}
+
 int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a, double b, double dt, double tstage,
                  int flags, double g = 1.0, void* rout = nullptr, bool sources = true, const void* gUs = nullptr,
                  const void* gRs = nullptr, void* gacc = nullptr) {
@@ -400,6 +416,7 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.geoT = ctx->dGeoT;
   L.connT = ctx->dConnT;
   L.opsT = ctx->dOpsT;
+  L.opsW = ctx->dOpsW;
   L.srcvec = ctx->dSrcVec;
   L.mortI = ctx->dMortI;
   L.mortG = ctx->dMortG;
@@ -440,7 +457,7 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
       HIPCHK(wdg::launch_mortar_stage(ctx->N, ctx->bits, L, ctx->stream));
       HIPCHK(hipEventRecord(ev[1], ctx->stream));
     }
-    HIPCHK(wdg::launch_wedge_stage(ctx->N, ctx->bits, L, ctx->stream));
+    HIPCHK(launch_wedges(ctx, L));
     if (has_t) {
       HIPCHK(hipEventRecord(ev[2], ctx->stream));
       HIPCHK(wdg::launch_tet_stage(ctx->N, ctx->bits, L, ctx->stream));
@@ -449,7 +466,7 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
     return WDG_OK;
   }
   HIPCHK(wdg::launch_mortar_stage(ctx->N, ctx->bits, L, ctx->stream));
-  HIPCHK(wdg::launch_wedge_stage(ctx->N, ctx->bits, L, ctx->stream));
+  HIPCHK(launch_wedges(ctx, L));
   HIPCHK(wdg::launch_tet_stage(ctx->N, ctx->bits, L, ctx->stream));
   return WDG_OK;
 }
@@ -1051,6 +1068,22 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
     HIPCHK(hipFree(dX));
     HIPCHK(hipFree(dMtri));
   }
+  if (Kw > 0 && ctx->N >= 4) {
+    // node-lane kernel: D_r, D_s, then E^a and E^b of the three edges ([edge][i][q])
+    std::vector<double> ops;
+    ops.insert(ops.end(), R.Dr.begin(), R.Dr.end());
+    ops.insert(ops.end(), R.Ds.begin(), R.Ds.end());
+    for (int e = 0; e < 3; ++e) ops.insert(ops.end(), R.Ea[e].begin(), R.Ea[e].end());
+    for (int e = 0; e < 3; ++e) ops.insert(ops.end(), R.Eb[e].begin(), R.Eb[e].end());
+    std::vector<unsigned char> buf(ops.size() * ts);
+    for (size_t i = 0; i < ops.size(); ++i) {
+      if (ctx->bits == 32) reinterpret_cast<float*>(buf.data())[i] = float(ops[i]);
+      else reinterpret_cast<double*>(buf.data())[i] = ops[i];
+    }
+    HIPCHK(hipMalloc(&ctx->dOpsW, buf.size()));
+    HIPCHK(hipMemcpyAsync(ctx->dOpsW, buf.data(), buf.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
   if (Kt > 0) {
     const TetOps& Tt = *ctx->tref;
     const int NPt = Tt.NP, NT = R.NT;
@@ -1212,6 +1245,14 @@ int wdg_set_tet_blocks(wdg_ctx* ctx, int blocks) {
   if (!ctx) return WDG_ERR_ARG;
   if (blocks < 0) return fail(ctx, WDG_ERR_ARG, "negative block count");
   ctx->tet_blocks = blocks;
+  return WDG_OK;
+}
+
+int wdg_set_wedge_kernel(wdg_ctx* ctx, int variant) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (variant != WDG_WEDGE_AUTO && variant != WDG_WEDGE_LEVEL)
+    return fail(ctx, WDG_ERR_ARG, "unknown wedge kernel");
+  ctx->wedge_level = variant == WDG_WEDGE_LEVEL;
   return WDG_OK;
 }
 
@@ -1927,8 +1968,13 @@ int wdg_get_element_data(const wdg_ctx* ctx, double* geo, double* lift) {
     if (rc) return rc;
   }
   if (lift && !wdg::lift_packed(ctx->N)) {
-    int rc = fetch(ctx->dL, size_t(ctx->Kw) * LS, lift, LS, NT * NT);
+    // the record holds L^{tri,k} column by column
+    std::vector<double> cm(size_t(ctx->Kw) * NT * NT);
+    int rc = fetch(ctx->dL, size_t(ctx->Kw) * LS, cm.data(), LS, NT * NT);
     if (rc) return rc;
+    for (int64_t k = 0; k < ctx->Kw; ++k)
+      for (int r = 0; r < NT; ++r)
+        for (int c = 0; c < NT; ++c) lift[(size_t(k) * NT + r) * NT + c] = cm[(size_t(k) * NT + c) * NT + r];
   } else if (lift) {
     // L^{tri,k} = (M^{tri,k})^-1 M^tri from the stored lower triangle of the inverse
     const int NPK = NT * (NT + 1) / 2;
@@ -2012,12 +2058,18 @@ struct wdg_batch {
   hipStream_t stream = nullptr;
   std::vector<wdg_ctx*> probs;
   std::vector<double> dts;
+  struct Trial {
+    int epb, wpe;
+    float us;  // median stage time of the order's launch, microseconds
+  };
   struct Group {
     int N = 0;
     std::vector<int> members;  // problem indices
-    int wpe = 2, nwork = 0;
+    bool node = false;         // node-lane kernel (orders 4, 5 in FP32), else level-lane
+    int epb = 0, wpe = 2, nwork = 0;
     int2* dWork = nullptr;
     float tuned_us = 0.0f;
+    std::vector<Trial> trials;  // the autotuner's candidates, in the order tried
   };
   std::vector<Group> groups;
   wdg::StageLaunch* dProbs = nullptr;
@@ -2068,10 +2120,9 @@ void batch_release(wdg_batch* b) {
   b->ready = false;
 }
 
-// work list of group g: (problem, chunk), problem-major
-std::vector<int2> batch_work(const wdg_batch* b, const wdg_batch::Group& g) {
+// work list of group g at epb elements per chunk: (problem, chunk), problem-major
+std::vector<int2> batch_work(const wdg_batch* b, const wdg_batch::Group& g, int epb) {
   std::vector<int2> w;
-  const int epb = wdg::wedge_chunk_elems(g.N, b->bits);
   for (int p : g.members) {
     const int nch = int((b->probs[p]->Kw + epb - 1) / epb);
     for (int c = 0; c < nch; ++c) w.push_back(make_int2(p, c));
@@ -2094,6 +2145,7 @@ int batch_upload_records(wdg_batch* b) {
     A.geo = ctx->dGeo;
     A.L = ctx->dL;
     A.conn = ctx->dConn;
+    A.opsW = ctx->dOpsW;
     A.srcvec = ctx->dSrcVec;
     A.nsrc = int(ctx->src.size());
     for (int s = 0; s < A.nsrc; ++s) A.src_elem[s] = int(ctx->src[s].elem);
@@ -2120,6 +2172,13 @@ int batch_upload_records(wdg_batch* b) {
   BHIPCHK(hipMemcpyAsync(b->dCounter, &zero, sizeof(zero), hipMemcpyHostToDevice, b->stream));
   BHIPCHK(hipStreamSynchronize(b->stream));
   return WDG_OK;
+}
+
+// one stage of group g's problems on stream st with the given kernel shape
+hipError_t launch_group(const wdg_batch* b, const wdg_batch::Group& g, int epb, int wpe, const int2* work, int nwork,
+                        hipStream_t st) {
+  if (g.node) return wdg::launch_wedge_node_batch(g.N, b->bits, epb, b->dProbs, work, nwork, st);
+  return wdg::launch_wedge_batch(g.N, b->bits, b->dProbs, work, nwork, wpe, st);
 }
 
 }  // namespace
@@ -2198,41 +2257,73 @@ int wdg_batch_prepare(wdg_batch* b, int autotune) {
   int rc = batch_upload_records(b);
   if (rc) return rc;
 
-  // autotuner: per order, the register budget of the stage kernel (occupancy
-  // 2 as the single-problem kernel, or 1: no spills at high order), timed on
-  // the real data with launches that only rewrite the residual (harmless at a
-  // step boundary, where the next stage overwrites it before reading)
-  hipEvent_t e0, e1;
-  BHIPCHK(hipEventCreate(&e0));
-  BHIPCHK(hipEventCreate(&e1));
+  // autotuner (the paper tunes its elements per block, Sec. 6.3): per order,
+  // the kernel shapes that exist for it -- the node-lane kernel (orders 4, 5
+  // in FP32) at kNodeEpbVariants element counts per block, the level-lane
+  // kernel at its register budgets (occupancy 2 as the single-problem kernel,
+  // or 1: no spills at high order) -- each timed on the real data as the
+  // median of kTuneReps launches that only rewrite the residual (harmless at
+  // a step boundary, where the next stage overwrites it before reading)
+  constexpr int kTuneReps = 5;
+  std::array<hipEvent_t, kTuneReps + 1> ev{};
+  for (auto& e : ev) BHIPCHK(hipEventCreate(&e));
+  int2* dTry = nullptr;
+  size_t try_cap = 0;
   for (auto& g : b->groups) {
-    const std::vector<int2> w = batch_work(b, g);
+    g.node = g.N >= 4 && b->bits == 32;
+    std::vector<std::pair<int, int>> cand;  // (elements per block, waves per SIMD)
+    if (g.node) {
+      for (int k = 0; k < wdg::kNodeEpbVariants; ++k) cand.emplace_back(wdg::wedge_node_epb(g.N, b->bits, k), 2);
+    } else {
+      cand.emplace_back(wdg::wedge_chunk_elems(g.N, b->bits), 2);
+      cand.emplace_back(wdg::wedge_chunk_elems(g.N, b->bits), 1);
+    }
+    g.trials.clear();
+    size_t pick = 0;
+    if (autotune) {
+      float best = 1e30f;
+      for (size_t c = 0; c < cand.size(); ++c) {
+        const std::vector<int2> w = batch_work(b, g, cand[c].first);
+        if (w.size() > try_cap) {
+          BHIPCHK(hipStreamSynchronize(b->stream));
+          dfree(dTry);
+          try_cap = 0;
+          BHIPCHK(hipMalloc(&dTry, w.size() * sizeof(int2)));
+          try_cap = w.size();
+        }
+        BHIPCHK(hipMemcpyAsync(dTry, w.data(), w.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+        const int nw = int(w.size());
+        BHIPCHK(launch_group(b, g, cand[c].first, cand[c].second, dTry, nw, b->stream));  // warm-up
+        BHIPCHK(hipEventRecord(ev[0], b->stream));
+        for (int r = 0; r < kTuneReps; ++r) {
+          BHIPCHK(launch_group(b, g, cand[c].first, cand[c].second, dTry, nw, b->stream));
+          BHIPCHK(hipEventRecord(ev[r + 1], b->stream));
+        }
+        BHIPCHK(hipEventSynchronize(ev[kTuneReps]));
+        std::array<float, kTuneReps> t{};
+        for (int r = 0; r < kTuneReps; ++r) BHIPCHK(hipEventElapsedTime(&t[r], ev[r], ev[r + 1]));
+        std::sort(t.begin(), t.end());
+        const float med = t[kTuneReps / 2];
+        g.trials.push_back({cand[c].first, cand[c].second, med * 1e3f});
+        if (med < best) {
+          best = med;
+          pick = c;
+        }
+      }
+      g.tuned_us = best * 1e3f;
+    } else {
+      g.tuned_us = 0.0f;
+    }
+    g.epb = cand[pick].first;
+    g.wpe = cand[pick].second;
+    const std::vector<int2> w = batch_work(b, g, g.epb);
     g.nwork = int(w.size());
     BHIPCHK(hipMalloc(&g.dWork, w.size() * sizeof(int2)));
     BHIPCHK(hipMemcpyAsync(g.dWork, w.data(), w.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
-    g.wpe = 2;
-    g.tuned_us = 0.0f;
-    if (!autotune) continue;
-    float best = 1e30f;
-    for (int wpe = 2; wpe >= 1; --wpe) {
-      BHIPCHK(wdg::launch_wedge_batch(g.N, b->bits, b->dProbs, g.dWork, g.nwork, wpe, b->stream));
-      BHIPCHK(hipEventRecord(e0, b->stream));
-      for (int r = 0; r < 3; ++r) BHIPCHK(wdg::launch_wedge_batch(g.N, b->bits, b->dProbs, g.dWork, g.nwork, wpe, b->stream));
-      BHIPCHK(hipEventRecord(e1, b->stream));
-      BHIPCHK(hipEventSynchronize(e1));
-      float ms = 0.0f;
-      BHIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      ms /= 3.0f;
-      if (ms < best) {
-        best = ms;
-        g.wpe = wpe;
-      }
-    }
-    g.tuned_us = best * 1e3f;
   }
-  BHIPCHK(hipEventDestroy(e0));
-  BHIPCHK(hipEventDestroy(e1));
   BHIPCHK(hipStreamSynchronize(b->stream));
+  dfree(dTry);
+  for (auto& e : ev) BHIPCHK(hipEventDestroy(e));
 
   b->ready = true;
   return WDG_OK;
@@ -2275,11 +2366,11 @@ int batch_capture(wdg_batch* b) {
     for (int gi = 1; gi < ng; ++gi) {
       const auto& g = b->groups[gi];
       ok(hipStreamWaitEvent(b->side[gi - 1], fork, 0));
-      ok(wdg::launch_wedge_batch(g.N, b->bits, b->dProbs, g.dWork, g.nwork, g.wpe, b->side[gi - 1]));
+      ok(launch_group(b, g, g.epb, g.wpe, g.dWork, g.nwork, b->side[gi - 1]));
       ok(hipEventRecord(b->events[s * (ng + 1) + gi], b->side[gi - 1]));
     }
     const auto& g0 = b->groups[0];
-    ok(wdg::launch_wedge_batch(g0.N, b->bits, b->dProbs, g0.dWork, g0.nwork, g0.wpe, b->stream));
+    ok(launch_group(b, g0, g0.epb, g0.wpe, g0.dWork, g0.nwork, b->stream));
     for (int gi = 1; gi < ng; ++gi) ok(hipStreamWaitEvent(b->stream, b->events[s * (ng + 1) + gi], 0));
   }
   if (cap == hipSuccess) cap = wdg::launch_batch_advance(b->dCounter, b->stream);
@@ -2346,9 +2437,25 @@ int wdg_batch_config(const wdg_batch* b, int N, int* elems_per_block, int* waves
   if (!b) return WDG_ERR_ARG;
   for (const auto& g : b->groups)
     if (g.N == N) {
-      if (elems_per_block) *elems_per_block = wdg::wedge_chunk_elems(N, b->bits);
+      if (elems_per_block) *elems_per_block = g.epb;
       if (waves_per_simd) *waves_per_simd = g.wpe;
       if (tuned_us) *tuned_us = g.tuned_us;
+      return WDG_OK;
+    }
+  return bfail(b, WDG_ERR_ARG, "no problem of that order in the batch");
+}
+
+int wdg_batch_trials(const wdg_batch* b, int N, int64_t cap, int* elems_per_block, int* waves_per_simd,
+                     double* stage_us, int64_t* count) {
+  if (!b || !count || cap < 0) return WDG_ERR_ARG;
+  for (const auto& g : b->groups)
+    if (g.N == N) {
+      *count = int64_t(g.trials.size());
+      for (int64_t k = 0; k < cap && k < *count; ++k) {
+        if (elems_per_block) elems_per_block[k] = g.trials[k].epb;
+        if (waves_per_simd) waves_per_simd[k] = g.trials[k].wpe;
+        if (stage_us) stage_us[k] = g.trials[k].us;
+      }
       return WDG_OK;
     }
   return bfail(b, WDG_ERR_ARG, "no problem of that order in the batch");

@@ -18,12 +18,12 @@ struct Dim {
   static constexpr int NT = (N + 1) * (N + 2) / 2;
   static constexpr int Nq = N + 1;
   static constexpr int NP = NT * Nq;
-  // Per-element triangular operator: for N <= 4 (M^{tri,k})^-1, stored as its
+  // Per-element triangular operator: for N <= 3 (M^{tri,k})^-1, stored as its
   // lower triangle row by row (symmetric), applied after the literal M^tri;
-  // for N = 5 the lift L^{tri,k} = (M^{tri,k})^-1 M^tri itself, row-major
-  // (there the extra M^tri product costs more registers than the smaller
-  // record saves).  Padded to whole 4-vectors.
-  static constexpr bool PACKED = N <= 4;
+  // for N >= 4 the lift L^{tri,k} = (M^{tri,k})^-1 M^tri itself, column by
+  // column (the node-lane kernel reads a row per lane, coalesced across the
+  // element's lanes).  Padded to whole 4-vectors.
+  static constexpr bool PACKED = N <= 3;
   static constexpr int NPK = NT * (NT + 1) / 2;
   static constexpr int LS = ((PACKED ? NPK : NT * NT) + 3) / 4 * 4;
 };

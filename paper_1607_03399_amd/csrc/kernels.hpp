@@ -81,6 +81,7 @@ struct StageLaunch {
   const void* geoT;  // tetrahedra
   const int* connT;
   const void* opsT;  // tetrahedron operators: Dr, Ds, Dt (Np x Np each), LIFT (Np x 4 Np_tri)
+  const void* opsW;  // N >= 4 wedges: reference rows D_r, D_s (Np_tri x Np_tri), E^a, E^b ([edge][Np_tri][N+1])
   const void* srcvec;  // kMaxSources x Np_wedge (a tetrahedron source uses the first Np_tet)
   const int* mortI;    // mortars: kMortIntStride ints each
   const void* mortG;   // kMortGeoStride FP64 values each
@@ -104,9 +105,10 @@ struct StageLaunch {
   int tet_blocks;  // tetrahedron kernel: number of persistent blocks (0: default)
 };
 
-// Whether order N stores (M^{tri,k})^-1 as its lower triangle (N <= 4) instead
-// of the lift L^{tri,k} = (M^{tri,k})^-1 M^tri (Np_tri^2 values, row-major).
-constexpr bool lift_packed(int N) { return N <= 4; }
+// Whether order N stores (M^{tri,k})^-1 as its lower triangle (N <= 3) instead
+// of the lift L^{tri,k} = (M^{tri,k})^-1 M^tri (Np_tri^2 values, column by
+// column: entry (r, c) at c Np_tri + r).
+constexpr bool lift_packed(int N) { return N <= 3; }
 // Per-element stride (values) of that record, padded to a multiple of 4.
 int lift_stride(int N);
 
@@ -119,6 +121,16 @@ hipError_t launch_material(int bits, int64_t K, const double* dc, const double* 
 hipError_t launch_mortar_stage(int N, int bits, const StageLaunch& a, hipStream_t st);
 hipError_t launch_wedge_stage(int N, int bits, const StageLaunch& a, hipStream_t st);
 hipError_t launch_tet_stage(int N, int bits, const StageLaunch& a, hipStream_t st);
+// N >= 4, FP32: the wedge stage with one lane per triangle node
+// (wedge_node.hip), epb elements per block, one of
+// wedge_node_epb(N, bits, 0..kNodeEpbVariants-1) (index 0: the default; 0
+// returned where there is no such kernel).  Not for layer marching or the
+// adjoint sweep.
+constexpr int kNodeEpbVariants = 4;
+int wedge_node_epb(int N, int bits, int idx);
+hipError_t launch_wedge_node_stage(int N, int bits, int epb, const StageLaunch& a, hipStream_t st);
+hipError_t launch_wedge_node_batch(int N, int bits, int epb, const StageLaunch* probs, const int2* work, int nwork,
+                                   hipStream_t st);
 // Number of values of the mortar reference tables of order N, in this order:
 // Minv1 (Nq x Nq, (M^1D)^-1), ME (3 x Np_tri x Nq: (M^tri)^-1 restricted to the
 // columns of edge e's nodes, [e][i][q]), MTI (Np_tri x Np_tri, (M^tri)^-1).

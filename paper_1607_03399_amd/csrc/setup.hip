@@ -118,14 +118,14 @@ __global__ void __launch_bounds__(64) setup_kernel(int NT, int LS, int64_t K, co
       }
       __syncthreads();
     }
-    // (M^{tri,k})^-1 is symmetric: its lower triangle, row by row; or L^{tri,k} row-major
+    // (M^{tri,k})^-1 is symmetric: its lower triangle, row by row; or L^{tri,k} column by column
     for (int idx = tid; idx < LS; idx += 64) {
       double v = 0.0;
       if (packed && idx < NT * (NT + 1) / 2) {
         const int r = tri_row(idx), c = idx - r * (r + 1) / 2;
         v = 0.5 * (Aug[r * W + NT + c] + Aug[c * W + NT + r]);
       } else if (!packed && idx < NT * NT) {
-        const int r = idx / NT, c = idx - r * NT;
+        const int c = idx / NT, r = idx - c * NT;
         v = Aug[r * W + NT + c];
       }
       L[k * LS + idx] = T(v);

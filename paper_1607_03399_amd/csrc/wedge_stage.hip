@@ -787,7 +787,7 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chun
         for (int k = 0; k < 4; ++k) {
           const int f = 4 * c + k;
           if (f < NT * NT) {
-            const int i = f / NT, m = f % NT;
+            const int m = f / NT, i = f % NT;  // the record holds L^{tri,k} column by column
             Rp[i] += lv[k] * Bp[m];
             Rz[i] += lv[k] * Bz[m];
             Rx[i] += lv[k] * Bx[m];

@@ -63,6 +63,7 @@ def load_library() -> C.CDLL:
         "wdg_set_layer_march": (C.c_int, [vp, C.c_int]),
         "wdg_set_tet_blocks": (C.c_int, [vp, C.c_int]),
         "wdg_set_tet_kernel": (C.c_int, [vp, C.c_int]),
+        "wdg_set_wedge_kernel": (C.c_int, [vp, C.c_int]),
         "wdg_num_nodes": (C.c_int, [vp, _i64p]),
         "wdg_get_node_coords": (C.c_int, [vp, _dp]),
         "wdg_set_fields": (C.c_int, [vp, _dp, _dp, _dp, _dp]),
@@ -95,6 +96,7 @@ def load_library() -> C.CDLL:
         "wdg_batch_prepare": (C.c_int, [vp, C.c_int]),
         "wdg_batch_step": (C.c_int, [vp, C.c_int64]),
         "wdg_batch_config": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _dp]),
+        "wdg_batch_trials": (C.c_int, [vp, C.c_int, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_int), _dp, _i64p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -199,6 +201,10 @@ class Solver:
     def set_tet_kernel(self, variant: str):
         """'mfma' (default: operator products on the matrix cores) or 'valu' (per-node dot products)."""
         self._check(self._lib.wdg_set_tet_kernel(self._h, {"mfma": 0, "valu": 1}[variant]), "set_tet_kernel")
+
+    def set_wedge_kernel(self, variant: str):
+        """'auto' (default: one lane per triangle node from order 4 on) or 'level' (one lane per GLL level)."""
+        self._check(self._lib.wdg_set_wedge_kernel(self._h, {"auto": 0, "level": 1}[variant]), "set_wedge_kernel")
 
     def set_mass(self, mass: str):
         """'exact' (default, energy stable) or 'lumped' (Gauss-Lobatto in t, for comparison)."""
@@ -438,6 +444,17 @@ class Batch:
         us = C.c_double()
         self._check(self._lib.wdg_batch_config(self._h, int(N), C.byref(e), C.byref(w), C.byref(us)), "batch_config")
         return e.value, w.value, us.value
+
+    def trials(self, N: int):
+        """The autotuner's candidates of order N: [(elements per block, waves per SIMD, median stage us)]."""
+        n = C.c_int64()
+        self._check(self._lib.wdg_batch_trials(self._h, int(N), 0, None, None, None, C.byref(n)), "batch_trials")
+        k = n.value
+        e = (C.c_int * max(k, 1))()
+        w = (C.c_int * max(k, 1))()
+        us = np.zeros(max(k, 1))
+        self._check(self._lib.wdg_batch_trials(self._h, int(N), k, e, w, _ptr(us), C.byref(n)), "batch_trials")
+        return [(int(e[i]), int(w[i]), float(us[i])) for i in range(k)]
 
     def close(self):
         if getattr(self, "_h", None):

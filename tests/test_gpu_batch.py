@@ -49,7 +49,15 @@ def test_batch_equals_single_problem_steps(bits, autotune):
         probs.append((N, nx, layers, seed, src, s, U, dt))
     batch.prepare(autotune=autotune)
     for N in sorted({p[0] for p in probs}):
-        _say("batch config N", N, batch.config(N))
+        _say("batch config N", N, batch.config(N), batch.trials(N))
+        if autotune:
+            # the node-lane kernel at four block sizes, else two register budgets
+            tr = batch.trials(N)
+            assert len(tr) == (4 if N >= 4 and bits == 32 else 2)
+            e, w, us = batch.config(N)
+            assert (e, w) == min(tr, key=lambda t: t[2])[:2] and us == min(t[2] for t in tr)
+        else:
+            assert batch.trials(N) == []
     batch.step(7)
     batch.step(5)  # a second call continues from the state the first left
     for (N, nx, layers, seed, src, s, U, dt) in probs:

@@ -29,6 +29,9 @@ def _run(m, N, bits, bc, flux, march, nsteps):
     s.set_material(m.c, m.rho)
     s.set_boundary(bc)
     s.set_flux(flux)
+    # marching is a mode of the level-lane kernel: the gather path it is
+    # compared with bit for bit is that kernel too
+    s.set_wedge_kernel("level")
     s.set_layer_march(march)
     s.add_ricker_source(*SRC)
     x = s.node_coords()

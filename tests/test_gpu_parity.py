@@ -25,13 +25,20 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def _solver(m, N, bits, bc="rigid", flux="upwind"):
+def _solver(m, N, bits, bc="rigid", flux="upwind", wedge="auto"):
     s = wdg.Solver(N, bits, device=0)
     s.set_mesh(m.verts, m.wedges)
     s.set_material(m.c, m.rho)
     s.set_boundary(bc)
     s.set_flux(flux)
+    s.set_wedge_kernel(wedge)
     return s
+
+
+def _wedge_kernels(N, bits):
+    """Wedge stage kernels of an order: the level-lane kernel runs at every
+    order, the node-lane kernel (the default) from order 4 on in FP32."""
+    return ("auto", "level") if N >= 4 and bits == 32 else ("auto",)
 
 
 def _omesh(m, bc="rigid", flux="upwind"):
@@ -55,7 +62,8 @@ def _rotated(m, seed=0):
 def test_element_data_matches_oracle():
     """Setup kernel (FP64 on the device): geometric factors and L^{tri,k}."""
     m = inputs.layered_config(3, 3, 0.3, seed=1)
-    for N, bits, tol in ((2, 64, 1e-12), (3, 32, 2e-6)):
+    # orders 4 and 5 store L^{tri,k} itself, column by column
+    for N, bits, tol in ((2, 64, 1e-12), (3, 32, 2e-6), (4, 32, 2e-6), (5, 64, 1e-11)):
         _say("element data", N, bits)
         s = _solver(m, N, bits)
         geo, lift = s.element_data()
@@ -91,24 +99,26 @@ def test_element_data_matches_oracle():
 def test_rhs_parity(N, bits):
     m = inputs.layered_config(3, 3, 0.3, seed=N)  # 54 wedges, curved, banded c and rho
     for bc, flux in (("rigid", "upwind"), ("dirichlet", "central")):
-        _say("rhs", N, bits, bc, flux)
-        s = _solver(m, N, bits, bc, flux)
-        rng = np.random.default_rng(10 + N)
-        U = rng.standard_normal((m.K, 4, s.Np))
-        got = s.eval_rhs(U)
         ops = dg.build_operators(_omesh(m, bc, flux), N)
+        rng = np.random.default_rng(10 + N)
+        U = rng.standard_normal((m.K, 4, ops.M.shape[1]))
         ref = dg.rhs(ops, U)
-        err, emax = check(got, ref, TOL[bits], f"rhs N={N} {bits} {bc} {flux}")
-        _say("   rel err", err, "worst element", emax)
-        s.close()
+        for wedge in _wedge_kernels(N, bits):
+            _say("rhs", N, bits, bc, flux, wedge)
+            s = _solver(m, N, bits, bc, flux, wedge)
+            got = s.eval_rhs(U)
+            err, emax = check(got, ref, TOL[bits], f"rhs N={N} {bits} {bc} {flux} {wedge}")
+            _say("   rel err", err, "worst element", emax)
+            s.close()
 
 
 @pytest.mark.parametrize("bits", [64, 32])
-@pytest.mark.parametrize("N", [3, 5])
+@pytest.mark.parametrize("N", [3, 4, 5])
 def test_rhs_parity_permuted_vertices_and_ragged_sizes(N, bits):
     """Nontrivial face permutations; element counts that leave a ragged last
-    workgroup (16 or 15 wedges per block at N = 3, 9 or 4 at N = 5); a single
-    element with only boundary faces."""
+    workgroup (16 or 15 wedges per block at N = 3; 12 per block of the
+    node-lane kernel at N = 4, 9 at N = 5, 4 of the level-lane kernel at
+    N = 5 in FP64); a single element with only boundary faces."""
     for K_cut in (1, 7, 65, 131):
         base = _rotated(inputs.layered_config(4, 5, 0.3, seed=3), seed=K_cut)
         w = base.wedges[:K_cut]
