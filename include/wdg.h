@@ -187,6 +187,19 @@ int wdg_synchronize(wdg_ctx* ctx);
  * in4 (4 * num_nodes: p block, u_x block, u_y block, u_z block), sources
  * included, written to out4 (same layout).  The context state is unchanged. */
 int wdg_eval_rhs(wdg_ctx* ctx, double t, const double* in4, double* out4);
+/* wdg_eval_rhs without any device allocation, for callers that cannot
+ * allocate (code that must not call hipMalloc: tight serving loops, harnesses
+ * that forbid it).  Same arguments, layout and result as wdg_eval_rhs; the
+ * state is staged through a 32 MiB device array of the library, which each
+ * GPU the library runs on holds until the process ends.  A mesh whose
+ * staging does not fit (more nodes than wdg_eval_rhs_noalloc_max_nodes
+ * reports for the precision: 524 288 in FP32, 349 525 in FP64) returns
+ * WDG_ERR_ARG.  All calls on one GPU share that array: calls that overlap on
+ * one GPU (from several host threads) race; each call waits for its stream
+ * before returning.  No hipMalloc, hipFree or allocating library call. */
+int wdg_eval_rhs_noalloc(wdg_ctx* ctx, double t, const double* in4, double* out4);
+/* Largest node count wdg_eval_rhs_noalloc accepts for precision_bits 32 or 64. */
+int wdg_eval_rhs_noalloc_max_nodes(int precision_bits, int64_t* n);
 /* E = 1/2 sum_k (p^T M^k p / kappa + rho u^T M^k u) (integrand of eq. estab),
  * M^k = M^{tri,k} (x) M^1D (Sec. 4.2), evaluated on the device. */
 int wdg_energy(wdg_ctx* ctx, double* E);

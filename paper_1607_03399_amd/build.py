@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libwdg.so")
-SOURCES = ["wedge_stage.hip", "wedge_node.hip", "tet_stage.hip", "mortar.hip", "adjoint.hip", "batch.hip", "setup.hip", "api.cpp", "refops.cpp"]
+SOURCES = ["wedge_stage.hip", "wedge_node.hip", "tet_stage.hip", "mortar.hip", "adjoint.hip", "batch.hip", "noalloc.hip", "setup.hip", "api.cpp", "refops.cpp"]
 ARCH = "gfx950"
 
 

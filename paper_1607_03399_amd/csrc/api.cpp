@@ -680,6 +680,26 @@ bool finite_all(const double* a, int64_t n) {
 
 }  // namespace
 
+namespace wdg {
+
+int ctx_rhs_view(wdg_ctx* ctx, RhsView* v) {
+  if (!ctx || !v) return WDG_ERR_ARG;
+  if (ctx->state < kMaterial || ctx->host_only) return fail(ctx, WDG_ERR_STATE, "eval_rhs before set_material");
+  v->device = ctx->device;
+  v->bits = ctx->bits;
+  v->nodes = ctx->nodes();
+  v->stream = ctx->stream;
+  return WDG_OK;
+}
+
+int ctx_eval_rhs_device(wdg_ctx* ctx, double t, const void* dIn, void* dOut) {
+  return launch_stage(ctx, dIn, nullptr, dOut, 0.0, 0.0, 1.0, t, 0);
+}
+
+int ctx_fail(wdg_ctx* ctx, int code, const char* msg) { return fail(ctx, code, msg); }
+
+}  // namespace wdg
+
 extern "C" {
 
 int wdg_create(int order_N, int precision_bits, int device, wdg_ctx** out) {

@@ -5,7 +5,11 @@
 
 #include <cstdint>
 
+struct wdg_ctx;
+
 namespace wdg {
+
+using wdg_ctx_fwd = ::wdg_ctx;
 
 // Per-element record of geometric factors and material (values of type T):
 //   0 r_x, 1 r_y, 2 s_x, 3 s_y, 4 t_zJ, 5/6 t_xJ at t=-1/+1, 7/8 t_yJ at t=-1/+1,
@@ -183,5 +187,22 @@ hipError_t launch_energy(int N, int bits, int64_t K, const void* U, const double
 // Tetrahedron energies (U points at the first tetrahedron node), added to the same partial sums layout.
 hipError_t launch_energy_tet(int N, int bits, int64_t Kt, const void* U, const double* auxT, const double* Mt,
                              double* partial, int* nblocks, hipStream_t st);
+
+// Hooks of the host runtime for entry points defined outside api.cpp.
+struct RhsView {
+  int device;
+  int bits;
+  int64_t nodes;
+  hipStream_t stream;
+};
+// Fills *v for a device context that may evaluate its right-hand side (state
+// at least material); else returns the WDG_ERR_* code with the context message set.
+int ctx_rhs_view(wdg_ctx_fwd* ctx, RhsView* v);
+// The right-hand side of the device state dIn (node 4-vectors of the
+// context's precision) at time t into dOut (same layout), sources included,
+// enqueued on the context stream; neither buffer may alias the context state.
+int ctx_eval_rhs_device(wdg_ctx_fwd* ctx, double t, const void* dIn, void* dOut);
+// Sets the context message and returns code.
+int ctx_fail(wdg_ctx_fwd* ctx, int code, const char* msg);
 
 }  // namespace wdg

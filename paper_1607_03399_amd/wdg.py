@@ -78,6 +78,8 @@ def load_library() -> C.CDLL:
         "wdg_set_time": (C.c_int, [vp, C.c_double]),
         "wdg_synchronize": (C.c_int, [vp]),
         "wdg_eval_rhs": (C.c_int, [vp, C.c_double, _dp, _dp]),
+        "wdg_eval_rhs_noalloc": (C.c_int, [vp, C.c_double, _dp, _dp]),
+        "wdg_eval_rhs_noalloc_max_nodes": (C.c_int, [C.c_int, _i64p]),
         "wdg_energy": (C.c_int, [vp, _dp]),
         "wdg_adjoint_gradient": (C.c_int, [vp, C.c_int64, C.c_double, _dp, C.c_int64, _dp, _dp]),
         "wdg_adjoint_record": (C.c_int, [vp, C.c_int64, C.c_int64]),
@@ -120,6 +122,16 @@ def reference_operator(N: int, name: str) -> np.ndarray:
     out = np.zeros(n.value)
     lib.wdg_reference_operator(N, name.encode(), _ptr(out), n.value, C.byref(n))
     return out
+
+
+def eval_rhs_noalloc_max_nodes(precision: int) -> int:
+    """Largest node count wdg_eval_rhs_noalloc stages in its fixed device array."""
+    lib = load_library()
+    n = C.c_int64()
+    rc = lib.wdg_eval_rhs_noalloc_max_nodes(int(precision), C.byref(n))
+    if rc:
+        raise WdgError(rc, "eval_rhs_noalloc_max_nodes")
+    return n.value
 
 
 class Solver:
@@ -311,6 +323,13 @@ class Solver:
         inp = self._flatten(U)  # field blocks
         out = np.zeros_like(inp)
         self._check(self._lib.wdg_eval_rhs(self._h, float(t), _ptr(inp), _ptr(out)), "eval_rhs")
+        return self._unflatten(out)
+
+    def eval_rhs_noalloc(self, U, t: float = 0.0) -> np.ndarray:
+        """eval_rhs staged through the library's fixed device array (no device allocation)."""
+        inp = self._flatten(U)
+        out = np.zeros_like(inp)
+        self._check(self._lib.wdg_eval_rhs_noalloc(self._h, float(t), _ptr(inp), _ptr(out)), "eval_rhs_noalloc")
         return self._unflatten(out)
 
     def energy(self) -> float:
