@@ -354,9 +354,8 @@ def batch_benchmark(steps: int):
     orders = sorted({N for N, _, _ in specs})
     tuned = {str(N): {"elements_per_block": batch.config(N)[0], "waves_per_simd": batch.config(N)[1],
                       "tuned_stage_us": batch.config(N)[2],
-                      "kernel": "node-lane" if N >= 4 else "level-lane",
-                      "candidates": [{"elements_per_block": e, "waves_per_simd": w, "median_stage_us": us}
-                                     for e, w, us in batch.trials(N)]} for N in orders}
+                      "candidates": [{"kernel": k + "-lane", "elements_per_block": e, "waves_per_simd": w,
+                                      "median_stage_us": us} for k, e, w, us in batch.trials(N)]} for N in orders}
     nodes = sum(s.K * s.Np for s in solvers)
     batch.close()
     for s in solvers:
@@ -442,7 +441,7 @@ def workload(config: str):
     return N, mesh.verts, mesh.wedges, np.zeros((0, 4), np.int64), mesh.c, mesh.rho, mesh, desc
 
 
-def forward_leg(config: str, bits: int, steps: int, warmup: int, layer_march: bool = False, tet_kernel: str = "mfma",
+def forward_leg(config: str, bits: int, steps: int, warmup: int, layer_march: str = "off", tet_kernel: str = "mfma",
                 wedge_kernel: str = "auto"):
     """Time ``steps`` steps of a configuration (after ``warmup`` steps) on a
     torch-bound state and stream; per-kernel averages from HIP events on that
@@ -489,8 +488,8 @@ def forward_leg(config: str, bits: int, steps: int, warmup: int, layer_march: bo
     if Kw:
         avg = w_ms * 1e3 / nlaunch
         rec_bytes = Kw * (stage_bytes(N, bits, False) + 4 * stage_bytes(N, bits, True)) / 5
-        kernels["wedge_stage"] = {"avg_us": avg, "variant": "node-lane" if N >= 4 and bits == 32 and
-                                  wedge_kernel == "auto" else "level-lane",
+        node = N >= 4 and bits == 32 and (wedge_kernel == "node" or (wedge_kernel == "auto" and N == 5))
+        kernels["wedge_stage"] = {"avg_us": avg, "variant": "node-lane" if node else "level-lane",
                                   "bytes_per_launch": Kw * survey_stage_bytes(N, bits),
                                   "GBs": Kw * survey_stage_bytes(N, bits) / avg / 1e3,
                                   "record_bytes_per_launch": rec_bytes, "record_GBs": rec_bytes / avg / 1e3}
@@ -527,13 +526,15 @@ def main():
     ap.add_argument("--config", default="cfg2", choices=sorted(CONFIGS),
                     help="; ".join(f"{k}: {v}" for k, v in CONFIGS.items()) + " (default cfg2)")
     ap.add_argument("--precision", type=int, default=32, choices=[32, 64])
-    ap.add_argument("--layer-march", action="store_true",
-                    help="stage kernel variant reading vertical neighbours inside a chunk from LDS")
+    ap.add_argument("--layer-march", default="off", choices=["off", "chunk", "column"],
+                    help="layer marching of the level-lane wedge kernel: vertical neighbours inside a chunk from "
+                         "LDS (chunk), and one block marching each column segment (column)")
     ap.add_argument("--tet-kernel", default="mfma", choices=["mfma", "valu"],
                     help="tetrahedron operator products on the matrix cores (default) or as per-node dot products")
-    ap.add_argument("--wedge-kernel", default="auto", choices=["auto", "level"],
-                    help="wedge stage kernel: auto (one lane per triangle node from order 4 on in FP32) or level "
-                         "(one lane per GLL level at every order)")
+    ap.add_argument("--wedge-kernel", default="auto", choices=["auto", "level", "node"],
+                    help="wedge stage kernel: auto (one lane per triangle node at order 5 in FP32, else one lane "
+                         "per GLL level), level (one lane per GLL level) or node (one lane per triangle node at "
+                         "orders 4 and 5 in FP32)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--cpu-workers", type=int, default=0,
@@ -606,13 +607,16 @@ def main():
     if default_run and not args.no_legs:
         legs = {}
         for name, cfg, b, tk, wk in (("cfg3", "cfg3", 32, "mfma", "auto"), ("cfg3_tet_valu", "cfg3", 32, "valu", "auto"),
-                                     ("cfg3_wedge_level", "cfg3", 32, "mfma", "level"),
+                                     ("cfg3_wedge_node", "cfg3", 32, "mfma", "node"),
                                      ("cfg5_forward", "cfg5", 32, "mfma", "auto"), ("order4", "order4", 32, "mfma", "auto"),
-                                     ("order4_wedge_level", "order4", 32, "mfma", "level"),
+                                     ("order4_wedge_node", "order4", 32, "mfma", "node"),
                                      ("order5", "order5", 32, "mfma", "auto"),
                                      ("order5_wedge_level", "order5", 32, "mfma", "level"),
                                      ("cfg2_fp64", "cfg2", 64, "mfma", "auto")):
             legs[name], _, _ = forward_leg(cfg, b, args.leg_steps, 3, tet_kernel=tk, wedge_kernel=wk)
+        # layer marching (the paper's future work) against the gathers, same kernel
+        for name, mode in (("cfg2_chunk_march", "chunk"), ("cfg2_column_march", "column")):
+            legs[name], _, _ = forward_leg("cfg2", 32, args.leg_steps, 3, layer_march=mode)
         out["legs"] = legs
     if default_run and not args.no_adjoint:
         out["adjoint"] = adjoint_benchmark(args.adjoint_steps, 50)

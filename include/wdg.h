@@ -104,13 +104,22 @@ int wdg_set_flux(wdg_ctx* ctx, int flux);
  * the right-hand side and to wdg_energy; tetrahedra are unaffected. */
 int wdg_set_mass(wdg_ctx* ctx, int mass);
 
-/* Layer marching (off by default): on meshes of wedges only, a stage kernel
- * variant reads the face nodes of the wedge below or above from the staged
- * chunk (a run of consecutive layers of one column) instead of gathering
- * them from memory.  Results are bitwise the same; on the 262144-wedge N=3
- * configuration it measured about 4% slower (the gathers it replaces are
- * cache hits issued early, the chunk reads wait for the staging barrier). */
-int wdg_set_layer_march(wdg_ctx* ctx, int on);
+/* Layer marching (Sec. 7: reuse of the previous layer's data; off by
+ * default), on meshes of wedges only, with the level-lane stage kernel
+ * (wdg_set_wedge_kernel):
+ *   WDG_MARCH_CHUNK: the kernel reads the face nodes of the wedge below or
+ *     above from its staged chunk (a run of consecutive layers of one column)
+ *     instead of gathering them from memory;
+ *   WDG_MARCH_COLUMN: in addition one block marches each column (a run of
+ *     consecutive wedges, each the top neighbour of the one before; taller
+ *     columns than two chunks of the kernel -- 32 layers at N = 3 in FP32 --
+ *     are split into such segments) from the bottom, chunk by chunk, and
+ *     keeps a chunk's top level in LDS as the bottom neighbour of the next,
+ *     so no triangular face inside a column segment is gathered.
+ * Results are bitwise those of WDG_MARCH_OFF with the same kernel.  Other
+ * values: WDG_ERR_ARG. */
+enum { WDG_MARCH_OFF = 0, WDG_MARCH_CHUNK = 1, WDG_MARCH_COLUMN = 2 };
+int wdg_set_layer_march(wdg_ctx* ctx, int mode);
 
 /* Launch shape of the tetrahedron stage kernel (meshes with tetrahedra).
  * The kernel is persistent: each block loads the reference operators once
@@ -133,12 +142,15 @@ enum { WDG_TET_MFMA = 0, WDG_TET_VALU = 1 };
 int wdg_set_tet_kernel(wdg_ctx* ctx, int variant);
 
 /* Which wedge stage kernel runs (both compute the stage of Sec. 4.2-4.3 up to
- * rounding order).  WDG_WEDGE_AUTO (default): from order 4 on in FP32, one
- * lane per triangle node, which owns the node's vertical line of GLL levels;
- * below order 4, in FP64, and for layer marching and the adjoint sweep, one
- * lane per GLL level, which owns the level's triangular slice.  WDG_WEDGE_LEVEL: the
- * level-lane kernel at every order.  Other values: WDG_ERR_ARG. */
-enum { WDG_WEDGE_AUTO = 0, WDG_WEDGE_LEVEL = 1 };
+ * rounding order).  The level-lane kernel gives each lane one GLL level of an
+ * element (the level's triangular slice of the four equations); the
+ * node-lane kernel, which exists for orders 4 and 5 in FP32, gives each lane
+ * one triangle node (the node's vertical line of GLL levels).  Layer
+ * marching and the adjoint sweep always use the level-lane kernel.
+ * WDG_WEDGE_AUTO (default): node-lane at order 5 in FP32, else level-lane.
+ * WDG_WEDGE_LEVEL: level-lane everywhere.  WDG_WEDGE_NODE: node-lane
+ * wherever it exists.  Other values: WDG_ERR_ARG. */
+enum { WDG_WEDGE_AUTO = 0, WDG_WEDGE_LEVEL = 1, WDG_WEDGE_NODE = 2 };
 int wdg_set_wedge_kernel(wdg_ctx* ctx, int variant);
 
 /* Total number of nodes (sum over elements of Np). */
@@ -268,11 +280,12 @@ int wdg_set_adjoint_memory_limit(wdg_ctx* ctx, int64_t bytes);
  *   wdg_batch_prepare: groups the problems by order and lists their element
  *     chunks problem by problem (one block per chunk, each XCD a contiguous
  *     range); with autotune != 0 (the tuning of elements per block of
- *     Sec. 6.3) times, for every order, each kernel shape that exists for it
- *     -- orders 4 and 5 in FP32: the node-lane kernel (wdg_set_wedge_kernel)
- *     at four element counts per block; otherwise the level-lane kernel
- *     compiled for 2 waves per SIMD (as the single-problem kernel) and for 1
- *     (twice the registers) -- on the real data, as the median of five
+ *     Sec. 6.3) times, for every order, the shapes of the stage kernel that
+ *     order's problems use alone (wdg_set_wedge_kernel; the node-lane kernel
+ *     only if all of them use it) -- the node-lane kernel at four element
+ *     counts per block, or the level-lane kernel compiled for 2 waves per
+ *     SIMD (as the single-problem kernel) and for 1 (twice the registers) --
+ *     on the real data, as the median of five
  *     launches that rewrite only the residual (which the next stage
  *     overwrites anyway), and keeps the fastest; without autotuning the first
  *     candidate (the single-problem kernel's shape).  Then it captures the
@@ -285,9 +298,10 @@ int wdg_set_adjoint_memory_limit(wdg_ctx* ctx, int64_t bytes);
  *   wdg_batch_config: elements per block, the chosen waves per SIMD of order N
  *     and the tuned median stage time of that order (microseconds).
  *   wdg_batch_trials: the autotuner's candidates for order N in the order
- *     tried: elements per block, waves per SIMD and median stage time
- *     (microseconds); up to cap of them are written, *count receives their
- *     number (0 without autotuning).
+ *     tried: kernel (WDG_WEDGE_LEVEL or WDG_WEDGE_NODE), elements per block,
+ *     waves per SIMD and median stage time (microseconds); up to cap of them
+ *     are written (any array may be NULL), *count receives their number (0
+ *     without autotuning).
  * Results are identical to wdg_step of each problem alone. */
 typedef struct wdg_batch wdg_batch;
 int wdg_batch_create(int device, int precision_bits, wdg_batch** out);
@@ -297,8 +311,8 @@ int wdg_batch_add(wdg_batch* batch, wdg_ctx* problem, double dt, int* index);
 int wdg_batch_prepare(wdg_batch* batch, int autotune);
 int wdg_batch_step(wdg_batch* batch, int64_t nsteps);
 int wdg_batch_config(const wdg_batch* batch, int N, int* elems_per_block, int* waves_per_simd, double* tuned_us);
-int wdg_batch_trials(const wdg_batch* batch, int N, int64_t cap, int* elems_per_block, int* waves_per_simd,
-                     double* stage_us, int64_t* count);
+int wdg_batch_trials(const wdg_batch* batch, int N, int64_t cap, int* kernel, int* elems_per_block,
+                     int* waves_per_simd, double* stage_us, int64_t* count);
 
 /* Per-launch timing of the stage kernels with HIP events on the context stream:
  * enable = 1 starts collecting (and clears), 0 stops.  read returns the summed

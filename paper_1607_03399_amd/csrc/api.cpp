@@ -77,10 +77,12 @@ struct wdg_ctx {
   std::vector<double> geoT;   // Kt x kTetGeoStride (FP64 master copy)
   std::vector<double> c, rho;
   int bc = WDG_BC_RIGID, flux = WDG_FLUX_UPWIND, mass = WDG_MASS_EXACT;
-  bool layer_march = false;
+  int layer_march = WDG_MARCH_OFF;
+  int2* dCols = nullptr;  // columns of the wedge mesh: (first element, layers)
+  int ncols = 0;
   int tet_blocks = 0;  // persistent blocks of the tetrahedron kernel (0: default)
   bool tet_valu = false;  // tetrahedron products as per-node dot products (else MFMA)
-  bool wedge_level = false;  // N >= 4: the level-lane wedge kernel instead of the node-lane one
+  int wedge_kernel = WDG_WEDGE_AUTO;  // which wedge stage kernel (wdg_set_wedge_kernel)
   double time = 0.0;
 
   hipStream_t stream = nullptr;
@@ -193,6 +195,8 @@ void release_device(wdg_ctx* ctx) {
   dfree(ctx->dGeoT);
   dfree(ctx->dOpsT);
   dfree(ctx->dOpsW);
+  dfree(ctx->dCols);
+  ctx->ncols = 0;
   dfree(ctx->dAuxT);
   dfree(ctx->dMt);
   dfree(ctx->dConnT);
@@ -390,11 +394,13 @@ int upload_sources(wdg_ctx* ctx) {
 }
 
 // one Runge-Kutta stage (or, with a = 0, dt = 1, no U write, a plain RHS)
-// Whether the wedges of a stage with these flags run on the node-lane kernel
-// (orders 4 and 5 in FP32, except layer marching and the adjoint sweep, which
-// only the level-lane kernel implements).
+// Whether the wedges of a stage with these flags run on the node-lane kernel:
+// it exists for orders 4 and 5 in FP32, without layer marching and outside
+// the adjoint sweep (which only the level-lane kernel implements); by default
+// it runs at order 5 only (at order 4 the level-lane kernel measured faster).
 bool node_kernel(const wdg_ctx* ctx, int flags) {
-  return ctx->N >= 4 && ctx->bits == 32 && !ctx->wedge_level && !(flags & (wdg::kLayerMarch | wdg::kGrad));
+  if (ctx->N < 4 || ctx->bits != 32 || (flags & (wdg::kLayerMarch | wdg::kGrad))) return false;
+  return ctx->wedge_kernel == WDG_WEDGE_NODE || (ctx->wedge_kernel == WDG_WEDGE_AUTO && ctx->N == 5);
 }
 
 hipError_t launch_wedges(const wdg_ctx* ctx, const wdg::StageLaunch& L) {
@@ -441,7 +447,10 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.Kw = ctx->Kw;
   L.Kt = ctx->Kt;
   L.tet_blocks = ctx->tet_blocks;
-  L.flags = flags | (g != 1.0 ? wdg::kGamma : 0) | (ctx->layer_march ? wdg::kLayerMarch : 0) | (ctx->tet_valu ? wdg::kTetValu : 0) | (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
+  L.cols = ctx->dCols;
+  L.ncols = ctx->ncols;
+  L.flags = flags | (g != 1.0 ? wdg::kGamma : 0) | (ctx->layer_march != WDG_MARCH_OFF ? wdg::kLayerMarch : 0) |
+            (ctx->layer_march == WDG_MARCH_COLUMN ? wdg::kColumnMarch : 0) | (ctx->tet_valu ? wdg::kTetValu : 0) | (ctx->bc == WDG_BC_DIRICHLET_P0 ? wdg::kDirichlet : 0) |
             (ctx->flux == WDG_FLUX_CENTRAL ? wdg::kCentral : 0) | (ctx->mass == WDG_MASS_LUMPED ? wdg::kLumped : 0);
   if (ctx->timing) {
     // events only between kernels that actually run (an event adds a gap to the stream)
@@ -1088,6 +1097,27 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
     HIPCHK(hipFree(dX));
     HIPCHK(hipFree(dMtri));
   }
+  if (Kw > 0) {
+    // column segments for marching: runs of consecutive wedges, each the top
+    // neighbour of the one before (element = column x layers + layer on
+    // layered meshes; any other numbering gives shorter runs), of at most two
+    // chunks of the stage kernel (the march kernel's straight-line reach)
+    const int seg = 2 * wdg::wedge_chunk_elems(ctx->N, ctx->bits);
+    std::vector<int2> cols;
+    for (int64_t k = 0; k < Kw; ++k) {
+      const bool stacked = k > 0 && ctx->conn[size_t(k - 1) * wdg::kConnStride + 1] == k &&
+                           ctx->conn[size_t(k) * wdg::kConnStride] == k - 1 && cols.back().y < seg;
+      if (stacked) {
+        cols.back().y += 1;
+      } else {
+        cols.push_back(make_int2(int(k), 1));
+      }
+    }
+    ctx->ncols = int(cols.size());
+    HIPCHK(hipMalloc(&ctx->dCols, cols.size() * sizeof(int2)));
+    HIPCHK(hipMemcpyAsync(ctx->dCols, cols.data(), cols.size() * sizeof(int2), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
   if (Kw > 0 && ctx->N >= 4) {
     // node-lane kernel: D_r, D_s, then E^a and E^b of the three edges ([edge][i][q])
     std::vector<double> ops;
@@ -1255,9 +1285,11 @@ int wdg_set_mass(wdg_ctx* ctx, int mass) {
   return WDG_OK;
 }
 
-int wdg_set_layer_march(wdg_ctx* ctx, int on) {
+int wdg_set_layer_march(wdg_ctx* ctx, int mode) {
   if (!ctx) return WDG_ERR_ARG;
-  ctx->layer_march = on != 0;
+  if (mode != WDG_MARCH_OFF && mode != WDG_MARCH_CHUNK && mode != WDG_MARCH_COLUMN)
+    return fail(ctx, WDG_ERR_ARG, "unknown layer marching mode");
+  ctx->layer_march = mode;
   return WDG_OK;
 }
 
@@ -1270,9 +1302,9 @@ int wdg_set_tet_blocks(wdg_ctx* ctx, int blocks) {
 
 int wdg_set_wedge_kernel(wdg_ctx* ctx, int variant) {
   if (!ctx) return WDG_ERR_ARG;
-  if (variant != WDG_WEDGE_AUTO && variant != WDG_WEDGE_LEVEL)
+  if (variant != WDG_WEDGE_AUTO && variant != WDG_WEDGE_LEVEL && variant != WDG_WEDGE_NODE)
     return fail(ctx, WDG_ERR_ARG, "unknown wedge kernel");
-  ctx->wedge_level = variant == WDG_WEDGE_LEVEL;
+  ctx->wedge_kernel = variant;
   return WDG_OK;
 }
 
@@ -2079,6 +2111,7 @@ struct wdg_batch {
   std::vector<wdg_ctx*> probs;
   std::vector<double> dts;
   struct Trial {
+    bool node;  // node-lane kernel, else level-lane
     int epb, wpe;
     float us;  // median stage time of the order's launch, microseconds
   };
@@ -2195,9 +2228,9 @@ int batch_upload_records(wdg_batch* b) {
 }
 
 // one stage of group g's problems on stream st with the given kernel shape
-hipError_t launch_group(const wdg_batch* b, const wdg_batch::Group& g, int epb, int wpe, const int2* work, int nwork,
-                        hipStream_t st) {
-  if (g.node) return wdg::launch_wedge_node_batch(g.N, b->bits, epb, b->dProbs, work, nwork, st);
+hipError_t launch_group(const wdg_batch* b, const wdg_batch::Group& g, bool node, int epb, int wpe, const int2* work,
+                        int nwork, hipStream_t st) {
+  if (node) return wdg::launch_wedge_node_batch(g.N, b->bits, epb, b->dProbs, work, nwork, st);
   return wdg::launch_wedge_batch(g.N, b->bits, b->dProbs, work, nwork, wpe, st);
 }
 
@@ -2290,20 +2323,28 @@ int wdg_batch_prepare(wdg_batch* b, int autotune) {
   int2* dTry = nullptr;
   size_t try_cap = 0;
   for (auto& g : b->groups) {
-    g.node = g.N >= 4 && b->bits == 32;
-    std::vector<std::pair<int, int>> cand;  // (elements per block, waves per SIMD)
-    if (g.node) {
-      for (int k = 0; k < wdg::kNodeEpbVariants; ++k) cand.emplace_back(wdg::wedge_node_epb(g.N, b->bits, k), 2);
+    struct Cand {
+      bool node;
+      int epb, wpe;
+    };
+    // the kernel family the problems of this order use alone (so that batch
+    // results equal theirs bit for bit): node-lane only if every one does;
+    // first the single-problem kernel's shape (the choice without autotuning)
+    bool node = true;
+    for (int p : g.members) node = node && node_kernel(b->probs[p], 0);
+    std::vector<Cand> cand;
+    if (node) {
+      for (int k = 0; k < wdg::kNodeEpbVariants; ++k) cand.push_back({true, wdg::wedge_node_epb(g.N, b->bits, k), 2});
     } else {
-      cand.emplace_back(wdg::wedge_chunk_elems(g.N, b->bits), 2);
-      cand.emplace_back(wdg::wedge_chunk_elems(g.N, b->bits), 1);
+      cand.push_back({false, wdg::wedge_chunk_elems(g.N, b->bits), 2});
+      cand.push_back({false, wdg::wedge_chunk_elems(g.N, b->bits), 1});
     }
     g.trials.clear();
     size_t pick = 0;
     if (autotune) {
       float best = 1e30f;
       for (size_t c = 0; c < cand.size(); ++c) {
-        const std::vector<int2> w = batch_work(b, g, cand[c].first);
+        const std::vector<int2> w = batch_work(b, g, cand[c].epb);
         if (w.size() > try_cap) {
           BHIPCHK(hipStreamSynchronize(b->stream));
           dfree(dTry);
@@ -2313,10 +2354,10 @@ int wdg_batch_prepare(wdg_batch* b, int autotune) {
         }
         BHIPCHK(hipMemcpyAsync(dTry, w.data(), w.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
         const int nw = int(w.size());
-        BHIPCHK(launch_group(b, g, cand[c].first, cand[c].second, dTry, nw, b->stream));  // warm-up
+        BHIPCHK(launch_group(b, g, cand[c].node, cand[c].epb, cand[c].wpe, dTry, nw, b->stream));  // warm-up
         BHIPCHK(hipEventRecord(ev[0], b->stream));
         for (int r = 0; r < kTuneReps; ++r) {
-          BHIPCHK(launch_group(b, g, cand[c].first, cand[c].second, dTry, nw, b->stream));
+          BHIPCHK(launch_group(b, g, cand[c].node, cand[c].epb, cand[c].wpe, dTry, nw, b->stream));
           BHIPCHK(hipEventRecord(ev[r + 1], b->stream));
         }
         BHIPCHK(hipEventSynchronize(ev[kTuneReps]));
@@ -2324,7 +2365,7 @@ int wdg_batch_prepare(wdg_batch* b, int autotune) {
         for (int r = 0; r < kTuneReps; ++r) BHIPCHK(hipEventElapsedTime(&t[r], ev[r], ev[r + 1]));
         std::sort(t.begin(), t.end());
         const float med = t[kTuneReps / 2];
-        g.trials.push_back({cand[c].first, cand[c].second, med * 1e3f});
+        g.trials.push_back({cand[c].node, cand[c].epb, cand[c].wpe, med * 1e3f});
         if (med < best) {
           best = med;
           pick = c;
@@ -2334,8 +2375,9 @@ int wdg_batch_prepare(wdg_batch* b, int autotune) {
     } else {
       g.tuned_us = 0.0f;
     }
-    g.epb = cand[pick].first;
-    g.wpe = cand[pick].second;
+    g.node = cand[pick].node;
+    g.epb = cand[pick].epb;
+    g.wpe = cand[pick].wpe;
     const std::vector<int2> w = batch_work(b, g, g.epb);
     g.nwork = int(w.size());
     BHIPCHK(hipMalloc(&g.dWork, w.size() * sizeof(int2)));
@@ -2386,11 +2428,11 @@ int batch_capture(wdg_batch* b) {
     for (int gi = 1; gi < ng; ++gi) {
       const auto& g = b->groups[gi];
       ok(hipStreamWaitEvent(b->side[gi - 1], fork, 0));
-      ok(launch_group(b, g, g.epb, g.wpe, g.dWork, g.nwork, b->side[gi - 1]));
+      ok(launch_group(b, g, g.node, g.epb, g.wpe, g.dWork, g.nwork, b->side[gi - 1]));
       ok(hipEventRecord(b->events[s * (ng + 1) + gi], b->side[gi - 1]));
     }
     const auto& g0 = b->groups[0];
-    ok(launch_group(b, g0, g0.epb, g0.wpe, g0.dWork, g0.nwork, b->stream));
+    ok(launch_group(b, g0, g0.node, g0.epb, g0.wpe, g0.dWork, g0.nwork, b->stream));
     for (int gi = 1; gi < ng; ++gi) ok(hipStreamWaitEvent(b->stream, b->events[s * (ng + 1) + gi], 0));
   }
   if (cap == hipSuccess) cap = wdg::launch_batch_advance(b->dCounter, b->stream);
@@ -2465,13 +2507,14 @@ int wdg_batch_config(const wdg_batch* b, int N, int* elems_per_block, int* waves
   return bfail(b, WDG_ERR_ARG, "no problem of that order in the batch");
 }
 
-int wdg_batch_trials(const wdg_batch* b, int N, int64_t cap, int* elems_per_block, int* waves_per_simd,
+int wdg_batch_trials(const wdg_batch* b, int N, int64_t cap, int* kernel, int* elems_per_block, int* waves_per_simd,
                      double* stage_us, int64_t* count) {
   if (!b || !count || cap < 0) return WDG_ERR_ARG;
   for (const auto& g : b->groups)
     if (g.N == N) {
       *count = int64_t(g.trials.size());
       for (int64_t k = 0; k < cap && k < *count; ++k) {
+        if (kernel) kernel[k] = g.trials[k].node ? WDG_WEDGE_NODE : WDG_WEDGE_LEVEL;
         if (elems_per_block) elems_per_block[k] = g.trials[k].epb;
         if (waves_per_simd) waves_per_simd[k] = g.trials[k].wpe;
         if (stage_us) stage_us[k] = g.trials[k].us;

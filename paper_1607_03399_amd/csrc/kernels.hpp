@@ -71,6 +71,7 @@ enum StageFlags : int {
   kLayerMarch = 128,  // wedge meshes: vertical neighbours inside a chunk from LDS
   kGrad = 256,        // wedge meshes, adjoint sweep: also accumulate the stage's gradient terms
   kTetValu = 512,     // tetrahedra: per-node dot products on the vector units (else MFMA)
+  kColumnMarch = 1024,  // wedge meshes: one block marches each column (cols), with kLayerMarch
 };
 
 // One stage over the whole mesh.  State buffers hold wedges first (Kw x Np_wedge
@@ -107,6 +108,11 @@ struct StageLaunch {
   int64_t Kw, Kt;
   int flags;
   int tet_blocks;  // tetrahedron kernel: number of persistent blocks (0: default)
+  // kColumnMarch: the column segments (first element, number of layers, at
+  // most two chunks of the stage kernel; elements consecutive from the
+  // bottom, each the one below's top neighbour)
+  const int2* cols;
+  int ncols;
 };
 
 // Whether order N stores (M^{tri,k})^-1 as its lower triangle (N <= 3) instead

@@ -363,11 +363,17 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
 #endif
 // MODE 0: wedges only; 1: tetrahedra across triangular faces; 2: also mortars;
 // 3: wedges only, vertical neighbours inside the chunk read from LDS (layer marching);
-// 4: wedges only, adjoint stage with its gradient terms (grad_epilogue)
+// 4: wedges only, adjoint stage with its gradient terms (grad_epilogue);
+// 5: as 3 for one chunk of a column marched from the bottom (wedge_column_stage):
+//    the wedge below the chunk's first one is the previous chunk's last, whose
+//    top level the previous call left in carry (when has_carry); this call
+//    leaves its own last wedge's top level there.
+// The chunk holds wedges e0 .. e0 + nE - 1 (nE <= EPB).
 template <int N, typename T, int MODE>
-__device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chunk) {
+__device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int64_t e0, int nE, V4<T>* carry = nullptr,
+                                                  bool has_carry = false) {
   constexpr bool HYB = MODE == 1 || MODE == 2;
-  constexpr bool MARCH = MODE == 3;
+  constexpr bool MARCH = MODE == 3 || MODE == 5;
   using C = Cfg<N, T>;
   using RT = gen::RefTables<N>;
   constexpr int NT = C::NT, Nq = C::Nq, NP = C::NP, NPP = C::NPP, EPB = C::EPB;
@@ -386,10 +392,10 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chun
   const T* __restrict__ Lm = static_cast<const T*>(A.L);
   const int* __restrict__ conn = A.conn;
 
-  const int64_t e0 = int64_t(chunk) * EPB;
-  const int64_t left = A.Kw - e0;
-  const int nE = left < EPB ? int(left) : EPB;
-  const int tid = threadIdx.x;
+  int tid = threadIdx.x;
+  // marching a column, each chunk derives its lane constants anew: hoisted
+  // out of the column loop they would stay live across chunks and spill
+  if constexpr (MODE == 5) asm volatile("" : "+v"(tid));
 
   const int le = tid / Nq;
   const int j = tid - le * Nq;
@@ -467,8 +473,9 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chun
       gt[t] = Uin[tet ? A.Kw * NP + (src - A.Kw) * TDim<N>::NP + tet_face_node<N>(tf, fn) : src * NP + nlev * NT + fn];
     } else {
       const bool in_chunk = MARCH && nbr >= 0 && src >= e0 && src < e0 + nE;
+      const bool carried = MODE == 5 && has_carry && nbr >= 0 && src == e0 - 1 && nlev == N;
       gt[t] = V4<T>{T(0), T(0), T(0), T(0)};
-      if (!in_chunk) gt[t] = Uin[src * NP + nlev * NT + fn];
+      if (!in_chunk && !carried) gt[t] = Uin[src * NP + nlev * NT + fn];
     }
   }
 #pragma unroll
@@ -495,9 +502,12 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chun
       const int face = fnode >= NT ? 1 : 0;
       const int nbr = face ? cn[1] : cn[0];
       const int64_t ln = int64_t(nbr) - e0;
+      const int nlev = ((code >> (6 + face)) & 1) ? N : 0;
+      const int fn = face_perm<N>((code >> (3 * face)) & 7, fnode - face * NT);
       if (nbr >= 0 && ln >= 0 && ln < nE) {
-        const int nlev = ((code >> (6 + face)) & 1) ? N : 0;
-        gt[t] = sU[int(ln) * NPP + nlev * NT + face_perm<N>((code >> (3 * face)) & 7, fnode - face * NT)];
+        gt[t] = sU[int(ln) * NPP + nlev * NT + fn];
+      } else if (MODE == 5 && has_carry && nbr >= 0 && ln == -1 && nlev == N) {
+        gt[t] = carry[fn];
       }
     }
   }
@@ -887,6 +897,20 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int chun
   else
     update(std::false_type{});
   if constexpr (MODE == 4) grad_epilogue<N, T>(A, e0, nE, tid, le, j, active, e, sU, sX);
+  if constexpr (MODE == 5) {
+    __syncthreads();  // the update's reads of the staged state are done
+    if (tid < NT) carry[tid] = sU[(nE - 1) * NPP + N * NT + tid];
+    __syncthreads();  // the next chunk may restage
+  }
+}
+
+// chunk c of a mesh: wedges c EPB .. min((c + 1) EPB, Kw) - 1
+template <int N, typename T, int MODE>
+__device__ __forceinline__ void wedge_stage_chunk_at(const StageLaunch& A, int chunk) {
+  constexpr int EPB = Cfg<N, T>::EPB;
+  const int64_t e0 = int64_t(chunk) * EPB;
+  const int64_t left = A.Kw - e0;
+  wedge_stage_chunk<N, T, MODE>(A, e0, left < EPB ? int(left) : EPB);
 }
 
 // XCD-aware mapping: consecutive workgroups go to different XCDs, so give
@@ -900,7 +924,28 @@ __device__ __forceinline__ int xcd_chunk(int bid, int nb) {
 // nodes x 4 equations, twice) then fits in registers instead of spilling.
 template <int N, typename T, int MODE>
 __global__ void __launch_bounds__(64, (N >= 4 ? 1 : WDG_STAGE_WAVES_PER_EU)) wedge_stage(StageLaunch A) {
-  wedge_stage_chunk<N, T, MODE>(A, xcd_chunk(blockIdx.x, gridDim.x));
+  wedge_stage_chunk_at<N, T, MODE>(A, xcd_chunk(blockIdx.x, gridDim.x));
+}
+
+// Column marching (the layer-by-layer reuse the paper proposes as future
+// work, Sec. 7): block b walks the wedges of column segment b (a run of at
+// most 2 EPB consecutive elements stacked bottom to top, from A.cols; the
+// host splits taller columns) in two chunks of EPB layers from the bottom;
+// vertical neighbours inside a chunk come from its staged state, the wedge
+// below the second chunk's first one from the first chunk's top level kept
+// in LDS, so no triangular face inside the segment is gathered from memory.
+// (Straight-line code for the two chunks: a loop over chunks keeps values
+// live across its back edge and spills.)
+template <int N, typename T>
+__global__ void __launch_bounds__(64, (N >= 4 ? 1 : WDG_STAGE_WAVES_PER_EU)) wedge_column_stage(StageLaunch A) {
+  constexpr int EPB = Cfg<N, T>::EPB;
+  __shared__ V4<T> carry[Dim<N>::NT];
+  const int2 col = A.cols[xcd_chunk(blockIdx.x, gridDim.x)];
+  wedge_stage_chunk<N, T, 5>(A, int64_t(col.x), col.y < EPB ? col.y : EPB, carry, false);
+  if (col.y > EPB) {
+    const int left = col.y - EPB;
+    wedge_stage_chunk<N, T, 5>(A, int64_t(col.x) + EPB, left < EPB ? left : EPB, carry, true);
+  }
 }
 
 // Many independent meshes of one order in one launch: block b takes chunk
@@ -917,7 +962,7 @@ __global__ void __launch_bounds__(64, WPE)
   const int w = xcd_chunk(blockIdx.x, gridDim.x);
   if (w >= nwork) return;
   const int2 it = work[w];
-  wedge_stage_chunk<N, T, 0>(probs[it.x], it.y);  // the record is wave-uniform: scalar loads
+  wedge_stage_chunk_at<N, T, 0>(probs[it.x], it.y);  // the record is wave-uniform: scalar loads
 }
 
 template <int N, typename T>
@@ -941,6 +986,8 @@ hipError_t launch_wedge_stage_t(const StageLaunch& a, hipStream_t st) {
     hipLaunchKernelGGL((wedge_stage<N, T, 2>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
   else if (a.Kt == 0 && (a.flags & kGrad))
     hipLaunchKernelGGL((wedge_stage<N, T, 4>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
+  else if (a.Kt == 0 && (a.flags & kColumnMarch) && a.cols && a.ncols > 0)
+    hipLaunchKernelGGL((wedge_column_stage<N, T>), dim3(unsigned(a.ncols)), dim3(C::BS), 0, st, a);
   else if (a.Kt == 0 && (a.flags & kLayerMarch))
     hipLaunchKernelGGL((wedge_stage<N, T, 3>), dim3(unsigned(nchunks)), dim3(C::BS), 0, st, a);
   else if (a.Kt > 0)

@@ -98,7 +98,8 @@ def load_library() -> C.CDLL:
         "wdg_batch_prepare": (C.c_int, [vp, C.c_int]),
         "wdg_batch_step": (C.c_int, [vp, C.c_int64]),
         "wdg_batch_config": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _dp]),
-        "wdg_batch_trials": (C.c_int, [vp, C.c_int, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_int), _dp, _i64p]),
+        "wdg_batch_trials": (C.c_int, [vp, C.c_int, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                       C.POINTER(C.c_int), _dp, _i64p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -203,8 +204,11 @@ class Solver:
     def set_flux(self, flux: str):
         self._check(self._lib.wdg_set_flux(self._h, FLUX[flux]), "set_flux")
 
-    def set_layer_march(self, on: bool):
-        self._check(self._lib.wdg_set_layer_march(self._h, int(bool(on))), "set_layer_march")
+    def set_layer_march(self, mode):
+        """False/'off', True/'chunk' (vertical neighbours inside a chunk from LDS) or 'column'
+        (one block marches each column, carrying a chunk's top level to the next)."""
+        code = {False: 0, True: 1, "off": 0, "chunk": 1, "column": 2}[mode]
+        self._check(self._lib.wdg_set_layer_march(self._h, code), "set_layer_march")
 
     def set_tet_blocks(self, blocks: int):
         """Cap on the persistent blocks of the tetrahedron kernel (0: default)."""
@@ -215,8 +219,10 @@ class Solver:
         self._check(self._lib.wdg_set_tet_kernel(self._h, {"mfma": 0, "valu": 1}[variant]), "set_tet_kernel")
 
     def set_wedge_kernel(self, variant: str):
-        """'auto' (default: one lane per triangle node from order 4 on) or 'level' (one lane per GLL level)."""
-        self._check(self._lib.wdg_set_wedge_kernel(self._h, {"auto": 0, "level": 1}[variant]), "set_wedge_kernel")
+        """'auto' (default: one lane per triangle node at order 5 in FP32, else one lane per GLL level),
+        'level' (one lane per GLL level) or 'node' (one lane per triangle node wherever it exists)."""
+        self._check(self._lib.wdg_set_wedge_kernel(self._h, {"auto": 0, "level": 1, "node": 2}[variant]),
+                    "set_wedge_kernel")
 
     def set_mass(self, mass: str):
         """'exact' (default, energy stable) or 'lumped' (Gauss-Lobatto in t, for comparison)."""
@@ -465,15 +471,18 @@ class Batch:
         return e.value, w.value, us.value
 
     def trials(self, N: int):
-        """The autotuner's candidates of order N: [(elements per block, waves per SIMD, median stage us)]."""
+        """The autotuner's candidates of order N: [(kernel 'level' or 'node', elements per block,
+        waves per SIMD, median stage us)]."""
         n = C.c_int64()
-        self._check(self._lib.wdg_batch_trials(self._h, int(N), 0, None, None, None, C.byref(n)), "batch_trials")
+        self._check(self._lib.wdg_batch_trials(self._h, int(N), 0, None, None, None, None, C.byref(n)),
+                    "batch_trials")
         k = n.value
+        kk = (C.c_int * max(k, 1))()
         e = (C.c_int * max(k, 1))()
         w = (C.c_int * max(k, 1))()
         us = np.zeros(max(k, 1))
-        self._check(self._lib.wdg_batch_trials(self._h, int(N), k, e, w, _ptr(us), C.byref(n)), "batch_trials")
-        return [(int(e[i]), int(w[i]), float(us[i])) for i in range(k)]
+        self._check(self._lib.wdg_batch_trials(self._h, int(N), k, kk, e, w, _ptr(us), C.byref(n)), "batch_trials")
+        return [("node" if kk[i] == 2 else "level", int(e[i]), int(w[i]), float(us[i])) for i in range(k)]
 
     def close(self):
         if getattr(self, "_h", None):

@@ -51,11 +51,15 @@ def test_batch_equals_single_problem_steps(bits, autotune):
     for N in sorted({p[0] for p in probs}):
         _say("batch config N", N, batch.config(N), batch.trials(N))
         if autotune:
-            # the node-lane kernel at four block sizes, else two register budgets
+            # the single-problem kernel's family: the node-lane kernel (order 5
+            # in FP32) at four block sizes, else the level-lane one at two
+            # register budgets
             tr = batch.trials(N)
-            assert len(tr) == (4 if N >= 4 and bits == 32 else 2)
+            node = N == 5 and bits == 32
+            assert len(tr) == (4 if node else 2) and {t[0] for t in tr} == {"node" if node else "level"}
             e, w, us = batch.config(N)
-            assert (e, w) == min(tr, key=lambda t: t[2])[:2] and us == min(t[2] for t in tr)
+            best = min(tr, key=lambda t: t[3])
+            assert (e, w) == best[1:3] and us == best[3]
         else:
             assert batch.trials(N) == []
     batch.step(7)

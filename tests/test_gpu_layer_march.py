@@ -1,7 +1,12 @@
-"""Layer marching (the wedge below or above read from the staged chunk, a run
-of consecutive layers of one column; Sec. 7's layer-by-layer reuse of the
-previous layer's data) against the FP64 oracle after 100 steps, and bitwise
-against the default gather path."""
+"""Layer marching (Sec. 7's layer-by-layer reuse of the previous layer's
+data) against the FP64 oracle after 100 steps, and bitwise against the
+gather path of the same (level-lane) kernel: 'chunk' reads the wedge below or
+above from the staged chunk (a run of consecutive layers of one column);
+'column' has one block march a column segment chunk by chunk from the bottom,
+carrying a chunk's top level to the next.  The column cases have 40 layers,
+more than one chunk of the kernel at every order (32, 21, 16, 12 and 9
+wedges per chunk at N = 1..5 in FP32), so the carried trace is used and
+columns taller than two chunks are split into segments."""
 import sys
 
 import numpy as np
@@ -33,6 +38,7 @@ def _run(m, N, bits, bc, flux, march, nsteps):
     # compared with bit for bit is that kernel too
     s.set_wedge_kernel("level")
     s.set_layer_march(march)
+    assert march in (False, "chunk", "column")
     s.add_ricker_source(*SRC)
     x = s.node_coords()
     U = np.zeros((s.K, 4, s.NPmax))
@@ -51,14 +57,20 @@ def test_layer_march_equals_gathers(N, bits, bc, flux):
     # 5 layers: chunks cut columns at varying layers, so both paths are taken
     m = inputs.layered_config(3, 5, 0.3, seed=N)
     a, _, _ = _run(m, N, bits, bc, flux, False, 15)
-    b, _, _ = _run(m, N, bits, bc, flux, True, 15)
+    b, _, _ = _run(m, N, bits, bc, flux, "chunk", 15)
     assert np.array_equal(a, b)
+    # 40 layers: columns longer than a chunk, segments of two chunks
+    m = inputs.layered_config(2, 40, 0.3, seed=N)
+    a, _, _ = _run(m, N, bits, bc, flux, False, 15)
+    c, _, _ = _run(m, N, bits, bc, flux, "column", 15)
+    assert np.array_equal(a, c)
 
 
+@pytest.mark.parametrize("mode", ["chunk", "column"])
 @pytest.mark.parametrize("N,bits,bc,flux", CASES)
-def test_layer_march_100_steps_against_oracle(N, bits, bc, flux):
-    m = inputs.layered_config(3, 5, 0.3, seed=N)
-    got, U0, dt = _run(m, N, bits, bc, flux, True, 100)
+def test_layer_march_100_steps_against_oracle(N, bits, bc, flux, mode):
+    m = inputs.layered_config(3, 5, 0.3, seed=N) if mode == "chunk" else inputs.layered_config(1, 40, 0.3, seed=N)
+    got, U0, dt = _run(m, N, bits, bc, flux, mode, 100)
     om = dg.Mesh(m.verts, m.wedges, m.c, m.rho, bc, flux)
     ops = dg.build_operators(om, N)
     source = dg.make_point_source(om, N, *SRC)
@@ -69,5 +81,5 @@ def test_layer_march_100_steps_against_oracle(N, bits, bc, flux):
         return out
 
     ref, _ = lsrk.integrate(f, U0, dt, 100)
-    err, emax = check(got, ref, TOL[bits], f"layer march N={N} {bits}")
-    _say("layer march", N, bits, bc, flux, "rel err", err, "worst element", emax)
+    err, emax = check(got, ref, TOL[bits], f"layer march {mode} N={N} {bits}")
+    _say("layer march", mode, N, bits, bc, flux, "rel err", err, "worst element", emax)

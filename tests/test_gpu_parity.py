@@ -37,8 +37,8 @@ def _solver(m, N, bits, bc="rigid", flux="upwind", wedge="auto"):
 
 def _wedge_kernels(N, bits):
     """Wedge stage kernels of an order: the level-lane kernel runs at every
-    order, the node-lane kernel (the default) from order 4 on in FP32."""
-    return ("auto", "level") if N >= 4 and bits == 32 else ("auto",)
+    order, the node-lane kernel at orders 4 and 5 in FP32."""
+    return ("level", "node") if N >= 4 and bits == 32 else ("auto",)
 
 
 def _omesh(m, bc="rigid", flux="upwind"):
