@@ -488,7 +488,7 @@ def forward_leg(config: str, bits: int, steps: int, warmup: int, layer_march: st
     if Kw:
         avg = w_ms * 1e3 / nlaunch
         rec_bytes = Kw * (stage_bytes(N, bits, False) + 4 * stage_bytes(N, bits, True)) / 5
-        node = N >= 4 and bits == 32 and (wedge_kernel == "node" or (wedge_kernel == "auto" and N == 5))
+        node = N >= 4 and bits == 32 and (wedge_kernel == "node" or (wedge_kernel == "auto" and (N == 5 or Kt > 0)))
         kernels["wedge_stage"] = {"avg_us": avg, "variant": "node-lane" if node else "level-lane",
                                   "bytes_per_launch": Kw * survey_stage_bytes(N, bits),
                                   "GBs": Kw * survey_stage_bytes(N, bits) / avg / 1e3,
@@ -607,7 +607,7 @@ def main():
     if default_run and not args.no_legs:
         legs = {}
         for name, cfg, b, tk, wk in (("cfg3", "cfg3", 32, "mfma", "auto"), ("cfg3_tet_valu", "cfg3", 32, "valu", "auto"),
-                                     ("cfg3_wedge_node", "cfg3", 32, "mfma", "node"),
+                                     ("cfg3_wedge_level", "cfg3", 32, "mfma", "level"),
                                      ("cfg5_forward", "cfg5", 32, "mfma", "auto"), ("order4", "order4", 32, "mfma", "auto"),
                                      ("order4_wedge_node", "order4", 32, "mfma", "node"),
                                      ("order5", "order5", 32, "mfma", "auto"),

@@ -147,7 +147,8 @@ int wdg_set_tet_kernel(wdg_ctx* ctx, int variant);
  * node-lane kernel, which exists for orders 4 and 5 in FP32, gives each lane
  * one triangle node (the node's vertical line of GLL levels).  Layer
  * marching and the adjoint sweep always use the level-lane kernel.
- * WDG_WEDGE_AUTO (default): node-lane at order 5 in FP32, else level-lane.
+ * WDG_WEDGE_AUTO (default): node-lane in FP32 at order 5, and at order 4 on
+ * meshes with tetrahedra; else level-lane.
  * WDG_WEDGE_LEVEL: level-lane everywhere.  WDG_WEDGE_NODE: node-lane
  * wherever it exists.  Other values: WDG_ERR_ARG. */
 enum { WDG_WEDGE_AUTO = 0, WDG_WEDGE_LEVEL = 1, WDG_WEDGE_NODE = 2 };

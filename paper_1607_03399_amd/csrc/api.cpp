@@ -397,10 +397,13 @@ int upload_sources(wdg_ctx* ctx) {
 // Whether the wedges of a stage with these flags run on the node-lane kernel:
 // it exists for orders 4 and 5 in FP32, without layer marching and outside
 // the adjoint sweep (which only the level-lane kernel implements); by default
-// it runs at order 5 only (at order 4 the level-lane kernel measured faster).
+// it runs at order 5, and at order 4 on meshes with tetrahedra (measured:
+// on wedges alone the level-lane kernel is faster at order 4, beside
+// tetrahedra and mortar faces the node-lane one).
 bool node_kernel(const wdg_ctx* ctx, int flags) {
   if (ctx->N < 4 || ctx->bits != 32 || (flags & (wdg::kLayerMarch | wdg::kGrad))) return false;
-  return ctx->wedge_kernel == WDG_WEDGE_NODE || (ctx->wedge_kernel == WDG_WEDGE_AUTO && ctx->N == 5);
+  if (ctx->wedge_kernel == WDG_WEDGE_NODE) return true;
+  return ctx->wedge_kernel == WDG_WEDGE_AUTO && (ctx->N == 5 || ctx->Kt > 0);
 }
 
 hipError_t launch_wedges(const wdg_ctx* ctx, const wdg::StageLaunch& L) {

@@ -219,7 +219,8 @@ class Solver:
         self._check(self._lib.wdg_set_tet_kernel(self._h, {"mfma": 0, "valu": 1}[variant]), "set_tet_kernel")
 
     def set_wedge_kernel(self, variant: str):
-        """'auto' (default: one lane per triangle node at order 5 in FP32, else one lane per GLL level),
+        """'auto' (default: one lane per triangle node in FP32 at order 5, and at order 4 with
+        tetrahedra; else one lane per GLL level),
         'level' (one lane per GLL level) or 'node' (one lane per triangle node wherever it exists)."""
         self._check(self._lib.wdg_set_wedge_kernel(self._h, {"auto": 0, "level": 1, "node": 2}[variant]),
                     "set_wedge_kernel")
