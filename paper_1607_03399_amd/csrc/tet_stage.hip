@@ -310,7 +310,7 @@ __global__ void __launch_bounds__((MCfg<N, T>::BS)) tet_stage_mfma(StageLaunch A
   __shared__ V4<T> sF[C::NF];
   __shared__ V4<T> sD[2 * C::NN];  // per node: D_r p, D_s p, D_t p, div u; lifted F_p, F_u n_x, F_u n_y, F_u n_z
   __shared__ T sG[EPB * kTetGeoStride];
-  __shared__ int sC[EPB * kTetConnStride];
+  __shared__ int sC[2][EPB * kTetConnStride];  // connectivity of this chunk and of the next one
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -346,13 +346,14 @@ __global__ void __launch_bounds__((MCfg<N, T>::BS)) tet_stage_mfma(StageLaunch A
   const bool rd = (A.flags & kReadRes) != 0, wu = (A.flags & kWriteU) != 0;
   const int64_t nchunks = (A.Kt + EPB - 1) / EPB;
 
-  // the next chunk's state (through the buffer's range check: zeros past the
-  // last tetrahedron), geometry and connectivity (indices past the chunk read
-  // its first value; never stored)
+  // Loads run ahead of their use: a chunk's state and geometry one chunk
+  // ahead (through the buffer's range check: zeros past the last
+  // tetrahedron; geometry indices past the chunk read its first value, never
+  // stored), its connectivity two chunks ahead, so that its neighbour states
+  // and mortar fluxes can be gathered during the previous chunk.
   struct Pre {
     V4<T> u[C::NPL];
     T g[C::GL];
-    int c[C::CL];
   };
   auto fetch = [&](int64_t ch) -> Pre {
     const int64_t f0 = ch * EPB;
@@ -366,6 +367,15 @@ __global__ void __launch_bounds__((MCfg<N, T>::BS)) tet_stage_mfma(StageLaunch A
       const int idx = tid + BS * l;
       p.g[l] = geo[f0 * kTetGeoStride + (idx < n * kTetGeoStride ? idx : 0)];
     }
+    return p;
+  };
+  struct PreC {
+    int c[C::CL];
+  };
+  auto fetch_conn = [&](int64_t ch) -> PreC {
+    PreC p;
+    const int64_t f0 = ch < nchunks ? ch * EPB : 0;
+    const int n = int(A.Kt - f0 < EPB ? A.Kt - f0 : EPB);
 #pragma unroll
     for (int l = 0; l < C::CL; ++l) {
       const int idx = tid + BS * l;
@@ -373,12 +383,65 @@ __global__ void __launch_bounds__((MCfg<N, T>::BS)) tet_stage_mfma(StageLaunch A
     }
     return p;
   };
-  Pre pre{};
-  if (int64_t(blockIdx.x) < nchunks) pre = fetch(blockIdx.x);
+  auto put_conn = [&](int buf, const PreC& p) {
+#pragma unroll
+    for (int l = 0; l < C::CL; ++l)
+      if (tid + BS * l < EPB * kTetConnStride) sC[buf][tid + BS * l] = p.c[l];
+  };
+  // Neighbour state at every face node of chunk ch (connectivity in sC[buf])
+  // and, on mortar faces, the mortar's nodal flux: issued without branches
+  // (lanes past the chunk read node 0 and the state as a stand-in flux).
+  V4<T> nbg[C::FPL];
+  T mfp[C::FPL], mfu[C::FPL];
+  const T* __restrict__ mortF = static_cast<const T*>(A.mortF);
+  auto gather = [&](int64_t ch, int buf) {
+    const int64_t f0 = ch * EPB;
+    const int n = int(A.Kt - f0 < EPB ? A.Kt - f0 : EPB);
+#pragma unroll
+    for (int l = 0; l < C::FPL; ++l) {
+      const int q0 = tid + BS * l;
+      const bool ok = q0 < C::NF && q0 / FN < n;
+      const int q = ok ? q0 : 0;
+      const int le = q / FN, qq = q - le * FN;
+      const int f = qq / NT, m = qq - f * NT;
+      const int* cn = sC[buf] + le * kTetConnStride;
+      const int code = cn[4];
+      const int nbr = cn[f];
+      const int pc = (code >> (5 * f)) & 7, nf = (code >> (5 * f + 3)) & 3;
+      const int fn = face_perm<N>(pc, m);
+      const int64_t src = nbr >= 0 ? int64_t(nbr) : A.Kw + f0 + le;
+      const int64_t gi = src >= A.Kw ? tb + (src - A.Kw) * NP + tet_face_node<N>(nf, fn)
+                                     : src * NPW + (nf == 1 ? N * NT : 0) + fn;
+      nbg[l] = Uin[ok ? gi : 0];
+      const bool mort = ok && nbr <= -2;
+      const T* mf = mort ? mortF + int64_t(-2 - nbr) * 2 * NT + m : reinterpret_cast<const T*>(Uin);
+      mfp[l] = mf[0];
+      mfu[l] = mf[mort ? NT : 0];
+    }
+  };
+  // the sources in this launch's elements (applied in the update of the chunks that hold them)
+  int64_t src_lo = INT64_MAX, src_hi = -1;
+  for (int s = 0; s < A.nsrc; ++s) {
+    const int64_t se = A.src_elem[s];
+    src_lo = se < src_lo ? se : src_lo;
+    src_hi = se > src_hi ? se : src_hi;
+  }
 
-  for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+  Pre pre{};
+  PreC prec{};
+  if (int64_t(blockIdx.x) < nchunks) {
+    pre = fetch(blockIdx.x);
+    put_conn(0, fetch_conn(blockIdx.x));
+    prec = fetch_conn(int64_t(blockIdx.x) + gridDim.x);
+    __syncthreads();
+    gather(blockIdx.x, 0);
+  }
+
+  int buf = 0;
+  for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x, buf ^= 1) {
     const int64_t e0 = chunk * EPB;
     const int nE = int(A.Kt - e0 < EPB ? A.Kt - e0 : EPB);
+    const int64_t next = chunk + gridDim.x;
     const int nn = nE * NP;
     V4<T>* const res_chunk = static_cast<V4<T>*>(A.res) + tb + e0 * NP;
     const auto bres_in = chunk_rsrc(res_chunk, rd ? int64_t(nn) * V4B : 0);
@@ -395,10 +458,12 @@ __global__ void __launch_bounds__((MCfg<N, T>::BS)) tet_stage_mfma(StageLaunch A
 #pragma unroll
     for (int l = 0; l < C::GL; ++l)
       if (tid + BS * l < EPB * kTetGeoStride) sG[tid + BS * l] = pre.g[l];
-#pragma unroll
-    for (int l = 0; l < C::CL; ++l)
-      if (tid + BS * l < EPB * kTetConnStride) sC[tid + BS * l] = pre.c[l];
-    if (chunk + gridDim.x < nchunks) pre = fetch(chunk + gridDim.x);
+    // the next chunk's connectivity, loaded one chunk ago
+    put_conn(buf ^ 1, prec);
+    if (next < nchunks) {
+      pre = fetch(next);
+      prec = fetch_conn(next + gridDim.x);
+    }
     __syncthreads();
 
     // (p, r.u, s.u, t.u) per node: div u = D_r (r.u) + D_s (s.u) + D_t (t.u)
@@ -421,19 +486,11 @@ __global__ void __launch_bounds__((MCfg<N, T>::BS)) tet_stage_mfma(StageLaunch A
         const int f = qq / NT, m = qq - f * NT;
         V4<T> out{T(0), T(0), T(0), T(0)};
         if (le < nE) {
-          const int64_t e = e0 + le;
           const T* g = sG + le * kTetGeoStride;
-          const int* cn = sC + le * kTetConnStride;
-          const int code = cn[4];
-          const int nbr = cn[f];
+          const int nbr = sC[buf][le * kTetConnStride + f];
           const T w_in = nbr >= 0 ? T(1) : T(0);
-          const int pc = (code >> (5 * f)) & 7, nf = (code >> (5 * f + 3)) & 3;
-          const int fn = face_perm<N>(pc, m);
-          const int64_t src = nbr >= 0 ? int64_t(nbr) : A.Kw + e;
-          const int64_t gi = src >= A.Kw ? tb + (src - A.Kw) * NP + tet_face_node<N>(nf, fn)
-                                         : src * NPW + (nf == 1 ? N * NT : 0) + fn;
           const V4<T> own = sU[le * NP + tet_face_node<N>(f, m)];
-          const V4<T> nb = Uin[gi];
+          const V4<T> nb = nbg[l];
           const T Fs = g[12 + 4 * f], nx = g[13 + 4 * f], ny = g[14 + 4 * f], nz = g[15 + 4 * f];
           const T zs = g[28 + f];
           const T taup = tau_on * T(2) / zs;
@@ -447,9 +504,8 @@ __global__ void __launch_bounds__((MCfg<N, T>::BS)) tet_stage_mfma(StageLaunch A
           T Fp = T(0.5) * (taup * jp - jun), Fu = T(0.5) * (tauu * jun - jp);
           if (nbr <= -2) {
             // mortar side: the equivalent nodal flux of the common refinement
-            const T* mf = static_cast<const T*>(A.mortF) + int64_t(-2 - nbr) * 2 * NT;
-            Fp = mf[m];
-            Fu = mf[NT + m];
+            Fp = mfp[l];
+            Fu = mfu[l];
           }
           const T su = Fs * Fu;
           out = V4<T>{Fs * Fp, su * nx, su * ny, su * nz};
@@ -512,10 +568,15 @@ __global__ void __launch_bounds__((MCfg<N, T>::BS)) tet_stage_mfma(StageLaunch A
         }
       }
     }
+    // the next chunk's neighbour gathers, in flight during this update and
+    // the next chunk's staging (its connectivity went to LDS before the
+    // barrier ahead of the flux phase)
+    if (next < nchunks) gather(next, buf ^ 1);
     __syncthreads();
 
     // right-hand side, sources and the low-storage update, node-contiguous
     const T ca = T(A.a), cb = T(A.b), dtt = T(A.dt), cg = (A.flags & kGamma) ? T(A.g) : T(1);
+    const bool src_here = src_hi >= A.Kw + e0 && src_lo < A.Kw + e0 + nE;
 #pragma unroll
     for (int l = 0; l < C::NPL; ++l) {
       const int n = tid + BS * l;
@@ -529,8 +590,9 @@ __global__ void __launch_bounds__((MCfg<N, T>::BS)) tet_stage_mfma(StageLaunch A
         const T Rx = irho * (d[5] - (g[0] * d[0] + g[3] * d[1] + g[6] * d[2]));
         const T Ry = irho * (d[6] - (g[1] * d[0] + g[4] * d[1] + g[7] * d[2]));
         const T Rz = irho * (d[7] - (g[2] * d[0] + g[5] * d[1] + g[8] * d[2]));
-        for (int s = 0; s < A.nsrc; ++s)
-          if (A.src_elem[s] == A.Kw + e) Rp += T(A.src_amp[s]) * static_cast<const T*>(A.srcvec)[s * NPW + i];
+        if (src_here)
+          for (int s = 0; s < A.nsrc; ++s)
+            if (A.src_elem[s] == A.Kw + e) Rp += T(A.src_amp[s]) * static_cast<const T*>(A.srcvec)[s * NPW + i];
         const V4<T> q = rprev[l];
         const V4<T> r{ca * q.p + dtt * Rp, ca * q.uz + dtt * Rz, ca * q.ux + dtt * Rx, ca * q.uy + dtt * Ry};
         bstore<T>(bres, n, r);
