@@ -83,6 +83,12 @@ struct wdg_ctx {
   int tet_blocks = 0;  // persistent blocks of the tetrahedron kernel (0: default)
   bool tet_valu = false;  // tetrahedron products as per-node dot products (else MFMA)
   int wedge_kernel = WDG_WEDGE_AUTO;  // which wedge stage kernel (wdg_set_wedge_kernel)
+  // Hybrid meshes: after the mortar kernel the tetrahedron kernel runs on a
+  // second stream beside the wedge kernel (they read the same input and write
+  // disjoint nodes), joined back before the stage ends (wdg_set_overlap).
+  bool overlap = true;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double time = 0.0;
 
   hipStream_t stream = nullptr;
@@ -215,6 +221,14 @@ void release_device(wdg_ctx* ctx) {
     for (auto& e : ev) (void)hipEventDestroy(e);
   ctx->events.clear();
   ctx->events_used = 0;
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipStreamDestroy(ctx->side);
+  }
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  ctx->side = nullptr;
+  ctx->ev_fork = ctx->ev_join = nullptr;
 }
 
 // reference coordinates of physical point x in wedge k (closed form for a
@@ -478,6 +492,17 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
     return WDG_OK;
   }
   HIPCHK(wdg::launch_mortar_stage(ctx->N, ctx->bits, L, ctx->stream));
+  if (ctx->overlap && ctx->side && ctx->Kw > 0 && ctx->Kt > 0) {
+    // fork: the tetrahedra on the side stream once the mortar fluxes are
+    // written, the wedges on the solver stream; join before the next stage
+    HIPCHK(hipEventRecord(ctx->ev_fork, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+    HIPCHK(wdg::launch_tet_stage(ctx->N, ctx->bits, L, ctx->side));
+    HIPCHK(launch_wedges(ctx, L));
+    HIPCHK(hipEventRecord(ctx->ev_join, ctx->side));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
+    return WDG_OK;
+  }
   HIPCHK(launch_wedges(ctx, L));
   HIPCHK(wdg::launch_tet_stage(ctx->N, ctx->bits, L, ctx->stream));
   return WDG_OK;
@@ -1137,6 +1162,13 @@ int wdg_set_mesh(wdg_ctx* ctx, int64_t nv, const double* vxyz, int64_t nw, const
     HIPCHK(hipMemcpyAsync(ctx->dOpsW, buf.data(), buf.size(), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
   }
+  if (Kt > 0 && Kw > 0) {
+    // the second stream of the hybrid stage (non-blocking: ordered with the
+    // solver stream only through the fork and join events)
+    HIPCHK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+  }
   if (Kt > 0) {
     const TetOps& Tt = *ctx->tref;
     const int NPt = Tt.NP, NT = R.NT;
@@ -1293,6 +1325,12 @@ int wdg_set_layer_march(wdg_ctx* ctx, int mode) {
   if (mode != WDG_MARCH_OFF && mode != WDG_MARCH_CHUNK && mode != WDG_MARCH_COLUMN)
     return fail(ctx, WDG_ERR_ARG, "unknown layer marching mode");
   ctx->layer_march = mode;
+  return WDG_OK;
+}
+
+int wdg_set_overlap(wdg_ctx* ctx, int enable) {
+  if (!ctx) return WDG_ERR_ARG;
+  ctx->overlap = enable != 0;
   return WDG_OK;
 }
 

@@ -62,6 +62,7 @@ def load_library() -> C.CDLL:
         "wdg_set_mass": (C.c_int, [vp, C.c_int]),
         "wdg_set_layer_march": (C.c_int, [vp, C.c_int]),
         "wdg_set_tet_blocks": (C.c_int, [vp, C.c_int]),
+        "wdg_set_overlap": (C.c_int, [vp, C.c_int]),
         "wdg_set_tet_kernel": (C.c_int, [vp, C.c_int]),
         "wdg_set_wedge_kernel": (C.c_int, [vp, C.c_int]),
         "wdg_num_nodes": (C.c_int, [vp, _i64p]),
@@ -209,6 +210,11 @@ class Solver:
         (one block marches each column, carrying a chunk's top level to the next)."""
         code = {False: 0, True: 1, "off": 0, "chunk": 1, "column": 2}[mode]
         self._check(self._lib.wdg_set_layer_march(self._h, code), "set_layer_march")
+
+    def set_overlap(self, enable: bool):
+        """Hybrid stages: run the tetrahedron kernel on a second stream beside the wedge kernel
+        (default True) or all kernels in order on the solver stream."""
+        self._check(self._lib.wdg_set_overlap(self._h, int(bool(enable))), "set_overlap")
 
     def set_tet_blocks(self, blocks: int):
         """Cap on the persistent blocks of the tetrahedron kernel (0: default)."""
