@@ -83,27 +83,44 @@ __device__ __forceinline__ void wedge_node_chunk(const StageLaunch& A, int chunk
   const T bsign = (A.flags & kDirichlet) ? T(-1) : T(1);
   const T tau_on = (A.flags & kCentral) ? T(0) : T(1);
 
-  // ---- 1. loads: connectivity first, then gathers, then the coalesced staging
-  int cn[6];
+  // ---- 1. loads: connectivity first, then the coalesced staging, then the gathers
+  // (named values, not an array: a lane-dependent selection from a private
+  // array becomes a scratch load, whose wait also waits for every gather
+  // issued before it)
+  const int4* cp = reinterpret_cast<const int4*>(A.conn + e * kConnStride);
+  const int4 c0 = cp[0], c1 = cp[1];
+  // the chunk's coalesced staging loads, issued before the connectivity is
+  // waited for (the vector-memory counter completes in order: waiting for
+  // the connectivity does not wait for these)
+  V4<T> rU[C::SU], rG[C::SG], rL[C::SL];
+  T rO[C::SO];
   {
-    const int4* cp = reinterpret_cast<const int4*>(A.conn + e * kConnStride);
-    const int4 c0 = cp[0], c1 = cp[1];
-    cn[0] = c0.x;
-    cn[1] = c0.y;
-    cn[2] = c0.z;
-    cn[3] = c0.w;
-    cn[4] = c1.x;
-    cn[5] = c1.y;
+    const auto bu = chunk_rsrc(Uin + e0 * NP, int64_t(nE) * NP * V4B);
+    const auto bl = chunk_rsrc(static_cast<const T*>(A.L) + e0 * C::LS, int64_t(nE) * C::LV * V4B);
+    const auto bg = chunk_rsrc(static_cast<const T*>(A.geo) + e0 * kGeoStride, int64_t(nE) * C::SGV * V4B);
+#pragma unroll
+    for (int k = 0; k < C::SU; ++k) rU[k] = bload<T>(bu, tid + BS * k);
+#pragma unroll
+    for (int k = 0; k < C::SL; ++k) rL[k] = bload<T>(bl, tid + BS * k);
+#pragma unroll
+    for (int k = 0; k < C::SG; ++k) rG[k] = bload<T>(bg, tid + BS * k);
+    const T* ops = static_cast<const T*>(A.opsW);
+#pragma unroll
+    for (int k = 0; k < C::SO; ++k) {
+      const int idx = tid + BS * k;
+      rO[k] = ops[idx < C::NOPS ? idx : 0];
+    }
   }
-  const int code = cn[5];
-  // neighbour across quadrilateral face ed (a selection: the register array
-  // is not indexed at run time)
-  auto quad_nbr = [&](int ed) { return ed == 0 ? cn[2] : (ed == 1 ? cn[3] : cn[4]); };
+  const int tri_nb0 = c0.x, tri_nb1 = c0.y, quad_nb0 = c0.z, quad_nb1 = c0.w, quad_nb2 = c1.x;
+  const int code = c1.y;
+  // neighbour across triangular face (0 bottom, 1 top) and quadrilateral face ed
+  auto tri_nbr = [&](int face) { return face == 0 ? tri_nb0 : tri_nb1; };
+  auto quad_nbr = [&](int ed) { return ed == 0 ? quad_nb0 : (ed == 1 ? quad_nb1 : quad_nb2); };
   // the node's traces on the neighbours across the bottom and top triangles
   V4<T> gt[2];
 #pragma unroll
   for (int face = 0; face < 2; ++face) {
-    const int nbr = cn[face];
+    const int nbr = tri_nbr(face);
     const int pc = (code >> (3 * face)) & 7;
     const int nlev = ((code >> (6 + face)) & 1) ? N : 0;
     const int64_t src = nbr >= 0 ? int64_t(nbr) : e;
@@ -128,25 +145,6 @@ __device__ __forceinline__ void wedge_node_chunk(const StageLaunch& A, int chunk
     const int ned = (code >> (8 + 2 * ed)) & 3;
     const int ni = ned == 0 ? edge_node(N, 0, N - q) : (ned == 1 ? edge_node(N, 1, N - q) : edge_node(N, 2, N - q));
     gq[s] = Uin[(nbr >= 0 ? int64_t(nbr) : e) * NP + j * NT + ni];
-  }
-  V4<T> rU[C::SU], rG[C::SG], rL[C::SL];
-  T rO[C::SO];
-  {
-    const auto bu = chunk_rsrc(Uin + e0 * NP, int64_t(nE) * NP * V4B);
-    const auto bl = chunk_rsrc(static_cast<const T*>(A.L) + e0 * C::LS, int64_t(nE) * C::LV * V4B);
-    const auto bg = chunk_rsrc(static_cast<const T*>(A.geo) + e0 * kGeoStride, int64_t(nE) * C::SGV * V4B);
-#pragma unroll
-    for (int k = 0; k < C::SU; ++k) rU[k] = bload<T>(bu, tid + BS * k);
-#pragma unroll
-    for (int k = 0; k < C::SL; ++k) rL[k] = bload<T>(bl, tid + BS * k);
-#pragma unroll
-    for (int k = 0; k < C::SG; ++k) rG[k] = bload<T>(bg, tid + BS * k);
-    const T* ops = static_cast<const T*>(A.opsW);
-#pragma unroll
-    for (int k = 0; k < C::SO; ++k) {
-      const int idx = tid + BS * k;
-      rO[k] = ops[idx < C::NOPS ? idx : 0];
-    }
   }
 #pragma unroll
   for (int k = 0; k < C::SU; ++k) {
@@ -235,7 +233,7 @@ __device__ __forceinline__ void wedge_node_chunk(const StageLaunch& A, int chunk
     const bool lumped = (A.flags & kLumped) != 0;
 #pragma unroll
     for (int face = 0; face < 2; ++face) {
-      const T w_in = cn[face] >= 0 ? T(1) : T(0);
+      const T w_in = tri_nbr(face) >= 0 ? T(1) : T(0);
       const T* gf = g + 12 + 4 * face;
       const T Jf = gf[0], nx = gf[1], ny = gf[2], nz = gf[3];
       const T zs = g[32 + face];
@@ -299,7 +297,7 @@ __device__ __forceinline__ void wedge_node_chunk(const StageLaunch& A, int chunk
     const T* mb = static_cast<const T*>(A.mortB);
 #pragma unroll
     for (int ed = 0; ed < 3; ++ed) {
-      const int nbr = cn[2 + ed];
+      const int nbr = quad_nbr(ed);
       if (nbr <= -2) {
         const int64_t mo = int64_t(-2 - nbr);
         const T nxe = g[22 + 4 * ed], nye = g[23 + 4 * ed];
