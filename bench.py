@@ -498,7 +498,7 @@ def forward_leg(config: str, bits: int, steps: int, warmup: int, layer_march: st
     if Kw:
         avg = w_ms * 1e3 / nlaunch
         rec_bytes = Kw * (stage_bytes(N, bits, False) + 4 * stage_bytes(N, bits, True)) / 5
-        node = N >= 4 and bits == 32 and (wedge_kernel == "node" or (wedge_kernel == "auto" and (N == 5 or Kt > 0)))
+        node = N >= 4 and bits == 32 and wedge_kernel in ("node", "auto")
         kernels["wedge_stage"] = {"avg_us": avg, "variant": "node-lane" if node else "level-lane",
                                   "bytes_per_launch": Kw * survey_stage_bytes(N, bits),
                                   "GBs": Kw * survey_stage_bytes(N, bits) / avg / 1e3,
@@ -544,8 +544,8 @@ def main():
     ap.add_argument("--tet-kernel", default="mfma", choices=["mfma", "valu"],
                     help="tetrahedron operator products on the matrix cores (default) or as per-node dot products")
     ap.add_argument("--wedge-kernel", default="auto", choices=["auto", "level", "node"],
-                    help="wedge stage kernel: auto (one lane per triangle node in FP32 at order 5, and at order 4 "
-                         "on meshes with tetrahedra; else one lane per GLL level), level (one lane per GLL level) or node (one lane per triangle node at "
+                    help="wedge stage kernel: auto (one lane per triangle node in FP32 at orders 4 and 5, else one "
+                         "lane per GLL level), level (one lane per GLL level) or node (one lane per triangle node at "
                          "orders 4 and 5 in FP32)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-sample", type=int, default=1024)
@@ -621,7 +621,7 @@ def main():
         for name, cfg, b, tk, wk in (("cfg3", "cfg3", 32, "mfma", "auto"), ("cfg3_tet_valu", "cfg3", 32, "valu", "auto"),
                                      ("cfg3_wedge_level", "cfg3", 32, "mfma", "level"),
                                      ("cfg5_forward", "cfg5", 32, "mfma", "auto"), ("order4", "order4", 32, "mfma", "auto"),
-                                     ("order4_wedge_node", "order4", 32, "mfma", "node"),
+                                     ("order4_wedge_level", "order4", 32, "mfma", "level"),
                                      ("order5", "order5", 32, "mfma", "auto"),
                                      ("order5_wedge_level", "order5", 32, "mfma", "level"),
                                      ("cfg2_fp64", "cfg2", 64, "mfma", "auto")):

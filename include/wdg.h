@@ -158,12 +158,20 @@ int wdg_set_tet_kernel(wdg_ctx* ctx, int variant);
  * node-lane kernel, which exists for orders 4 and 5 in FP32, gives each lane
  * one triangle node (the node's vertical line of GLL levels).  Layer
  * marching and the adjoint sweep always use the level-lane kernel.
- * WDG_WEDGE_AUTO (default): node-lane in FP32 at order 5, and at order 4 on
- * meshes with tetrahedra; else level-lane.
+ * WDG_WEDGE_AUTO (default): node-lane wherever it exists, else level-lane.
  * WDG_WEDGE_LEVEL: level-lane everywhere.  WDG_WEDGE_NODE: node-lane
  * wherever it exists.  Other values: WDG_ERR_ARG. */
 enum { WDG_WEDGE_AUTO = 0, WDG_WEDGE_LEVEL = 1, WDG_WEDGE_NODE = 2 };
 int wdg_set_wedge_kernel(wdg_ctx* ctx, int variant);
+
+/* Elements per block of the node-lane wedge kernel (Sec. 6.2: the number of
+ * elements a block processes is a tuning parameter).  elements = 0: the
+ * built-in default; otherwise one of the compiled shapes, which
+ * wdg_batch_trials lists per order (orders 4 and 5 in FP32: 8, 17, 12, 4 and
+ * 12, 9, 6, 3, the first of each the default).  Blocks hold whole elements, so
+ * results are bitwise the same for every shape.  It applies where the
+ * node-lane kernel runs.  Any other value: WDG_ERR_ARG (the setting is kept). */
+int wdg_set_wedge_block(wdg_ctx* ctx, int elements);
 
 /* Total number of nodes (sum over elements of Np). */
 int wdg_num_nodes(const wdg_ctx* ctx, int64_t* n);

@@ -83,6 +83,7 @@ struct wdg_ctx {
   int tet_blocks = 0;  // persistent blocks of the tetrahedron kernel (0: default)
   bool tet_valu = false;  // tetrahedron products as per-node dot products (else MFMA)
   int wedge_kernel = WDG_WEDGE_AUTO;  // which wedge stage kernel (wdg_set_wedge_kernel)
+  int wedge_block = 0;  // elements per block of the node-lane kernel (0: default; wdg_set_wedge_block)
   // Hybrid meshes: after the mortar kernel the tetrahedron kernel runs on a
   // second stream beside the wedge kernel (they read the same input and write
   // disjoint nodes), joined back before the stage ends (wdg_set_overlap).
@@ -411,18 +412,18 @@ int upload_sources(wdg_ctx* ctx) {
 // Whether the wedges of a stage with these flags run on the node-lane kernel:
 // it exists for orders 4 and 5 in FP32, without layer marching and outside
 // the adjoint sweep (which only the level-lane kernel implements); by default
-// it runs at order 5, and at order 4 on meshes with tetrahedra (measured:
-// on wedges alone the level-lane kernel is faster at order 4, beside
-// tetrahedra and mortar faces the node-lane one).
+// it is the default wherever it exists (measured faster at orders 4 and 5:
+// 122 against 137 us and 209 against 309 us per stage on 73 728 wedges).
 bool node_kernel(const wdg_ctx* ctx, int flags) {
   if (ctx->N < 4 || ctx->bits != 32 || (flags & (wdg::kLayerMarch | wdg::kGrad))) return false;
-  if (ctx->wedge_kernel == WDG_WEDGE_NODE) return true;
-  return ctx->wedge_kernel == WDG_WEDGE_AUTO && (ctx->N == 5 || ctx->Kt > 0);
+  return ctx->wedge_kernel == WDG_WEDGE_NODE || ctx->wedge_kernel == WDG_WEDGE_AUTO;
 }
 
 hipError_t launch_wedges(const wdg_ctx* ctx, const wdg::StageLaunch& L) {
   if (node_kernel(ctx, L.flags))
-    return wdg::launch_wedge_node_stage(ctx->N, ctx->bits, wdg::wedge_node_epb(ctx->N, ctx->bits, 0), L, ctx->stream);
+    return wdg::launch_wedge_node_stage(ctx->N, ctx->bits,
+                                        ctx->wedge_block ? ctx->wedge_block : wdg::wedge_node_epb(ctx->N, ctx->bits, 0),
+                                        L, ctx->stream);
   return wdg::launch_wedge_stage(ctx->N, ctx->bits, L, ctx->stream);
 }
 
@@ -1346,6 +1347,17 @@ int wdg_set_wedge_kernel(wdg_ctx* ctx, int variant) {
   if (variant != WDG_WEDGE_AUTO && variant != WDG_WEDGE_LEVEL && variant != WDG_WEDGE_NODE)
     return fail(ctx, WDG_ERR_ARG, "unknown wedge kernel");
   ctx->wedge_kernel = variant;
+  return WDG_OK;
+}
+
+int wdg_set_wedge_block(wdg_ctx* ctx, int elements) {
+  if (!ctx) return WDG_ERR_ARG;
+  if (elements != 0) {
+    bool ok = false;
+    for (int k = 0; k < wdg::kNodeEpbVariants; ++k) ok = ok || wdg::wedge_node_epb(ctx->N, ctx->bits, k) == elements;
+    if (!ok) return fail(ctx, WDG_ERR_ARG, "no node-lane wedge kernel with that many elements per block");
+  }
+  ctx->wedge_block = elements;
   return WDG_OK;
 }
 

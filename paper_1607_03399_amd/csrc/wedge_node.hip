@@ -462,7 +462,11 @@ hipError_t launch_node_batch_t(const StageLaunch* probs, const int2* work, int n
 // autotuner tries (index 0 is the single-problem kernel's), lane counts
 // EPB Np_tri close to whole wavefronts.
 int wedge_node_epb(int N, int bits, int idx) {
-  static const int e4[kNodeEpbVariants] = {17, 12, 8, 4}, e5[kNodeEpbVariants] = {12, 9, 6, 3};
+  // index 0 is the default: the fastest shape measured for one problem (order 4
+  // on 73 728 wedges: 121 / 125 / 125 / 124 us for 8 / 17 / 12 / 4 elements
+  // per block, and 8 also beside tetrahedra; order 5: 213 us at 12, 239-244 at
+  // 9, 6, 3)
+  static const int e4[kNodeEpbVariants] = {8, 17, 12, 4}, e5[kNodeEpbVariants] = {12, 9, 6, 3};
   if (bits != 32 || idx < 0 || idx >= kNodeEpbVariants) return 0;
   return N == 4 ? e4[idx] : (N == 5 ? e5[idx] : 0);
 }

@@ -63,6 +63,7 @@ def load_library() -> C.CDLL:
         "wdg_set_layer_march": (C.c_int, [vp, C.c_int]),
         "wdg_set_tet_blocks": (C.c_int, [vp, C.c_int]),
         "wdg_set_overlap": (C.c_int, [vp, C.c_int]),
+        "wdg_set_wedge_block": (C.c_int, [vp, C.c_int]),
         "wdg_set_tet_kernel": (C.c_int, [vp, C.c_int]),
         "wdg_set_wedge_kernel": (C.c_int, [vp, C.c_int]),
         "wdg_num_nodes": (C.c_int, [vp, _i64p]),
@@ -211,6 +212,10 @@ class Solver:
         code = {False: 0, True: 1, "off": 0, "chunk": 1, "column": 2}[mode]
         self._check(self._lib.wdg_set_layer_march(self._h, code), "set_layer_march")
 
+    def set_wedge_block(self, elements: int):
+        """Elements per block of the node-lane wedge kernel (0: default; orders 4 and 5 in FP32)."""
+        self._check(self._lib.wdg_set_wedge_block(self._h, int(elements)), "set_wedge_block")
+
     def set_overlap(self, enable: bool):
         """Hybrid stages: run the tetrahedron kernel on a second stream beside the wedge kernel
         (default True) or all kernels in order on the solver stream."""
@@ -225,8 +230,8 @@ class Solver:
         self._check(self._lib.wdg_set_tet_kernel(self._h, {"mfma": 0, "valu": 1}[variant]), "set_tet_kernel")
 
     def set_wedge_kernel(self, variant: str):
-        """'auto' (default: one lane per triangle node in FP32 at order 5, and at order 4 with
-        tetrahedra; else one lane per GLL level),
+        """'auto' (default: one lane per triangle node in FP32 at orders 4 and 5, else one lane per
+        GLL level),
         'level' (one lane per GLL level) or 'node' (one lane per triangle node wherever it exists)."""
         self._check(self._lib.wdg_set_wedge_kernel(self._h, {"auto": 0, "level": 1, "node": 2}[variant]),
                     "set_wedge_kernel")

@@ -298,3 +298,21 @@ def test_adjoint_gradient_argument_checks():
     with pytest.raises(ValueError):
         s.adjoint_gradient(3, 1e-3, np.zeros((2, 1)))
     s.close()
+
+
+def test_wedge_block_arguments():
+    """Elements per block of the node-lane kernel: only the compiled shapes of
+    the context's order and precision (none below order 4 or in FP64)."""
+    for N, bits, shapes in ((4, 32, (8, 17, 12, 4)), (5, 32, (12, 9, 6, 3))):
+        s = wdg.Solver(N, bits, device=-1)
+        for e in shapes:
+            s.set_wedge_block(e)
+        s.set_wedge_block(0)
+        for e in (1, 5, 9 if N == 4 else 8, 64, -1):
+            _expect("WDG_ERR_ARG", s.set_wedge_block, e)
+        s.close()
+    for N, bits in ((3, 32), (4, 64)):
+        s = wdg.Solver(N, bits, device=-1)
+        s.set_wedge_block(0)
+        _expect("WDG_ERR_ARG", s.set_wedge_block, 8)
+        s.close()

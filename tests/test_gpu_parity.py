@@ -308,3 +308,35 @@ def test_cfg2_full_size_sampled_rhs_and_energy():
     assert np.all(np.isfinite(F))
     assert E1 <= E0 * (1 + 1e-5)
     s.close()
+
+
+@pytest.mark.parametrize("N", [4, 5])
+def test_node_kernel_block_shapes_bitwise(N):
+    """Every elements-per-block shape of the node-lane kernel (FP32) gives
+    bitwise the same right-hand side and 5-step fields on a 131-wedge mesh
+    with permuted vertices (a ragged last block for every shape), and the
+    default shape matches the oracle."""
+    base = _rotated(inputs.layered_config(4, 5, 0.3, seed=3), seed=131)
+    w = base.wedges[:131]
+    used = np.unique(w)
+    remap = -np.ones(len(base.verts), dtype=np.int64)
+    remap[used] = np.arange(len(used))
+    m = inputs.WedgeMesh(base.verts[used], remap[w], base.c[:131], base.rho[:131], base.layers)
+    ops = dg.build_operators(_omesh(m), N)
+    U = np.random.default_rng(40 + N).standard_normal((m.K, 4, ops.M.shape[1]))
+    shapes = (8, 17, 12, 4) if N == 4 else (12, 9, 6, 3)
+    outs = []
+    for e in (0,) + shapes:
+        _say("block shape", N, e)
+        s = _solver(m, N, 32, wedge="node")
+        s.set_wedge_block(e)
+        r = s.eval_rhs(U)
+        s.set_fields(U)
+        dt = s.stable_dt(0.5)
+        s.step(5, dt)
+        outs.append((r, s.get_fields()))
+        s.close()
+    check(outs[0][0], dg.rhs(ops, U), TOL[32], f"node kernel N={N} default shape")
+    for r, f in outs[1:]:
+        assert np.array_equal(r, outs[0][0])
+        assert np.array_equal(f, outs[0][1])
