@@ -84,10 +84,11 @@ struct wdg_ctx {
   bool tet_valu = false;  // tetrahedron products as per-node dot products (else MFMA)
   int wedge_kernel = WDG_WEDGE_AUTO;  // which wedge stage kernel (wdg_set_wedge_kernel)
   int wedge_block = 0;  // elements per block of the node-lane kernel (0: default; wdg_set_wedge_block)
-  // Hybrid meshes: after the mortar kernel the tetrahedron kernel runs on a
-  // second stream beside the wedge kernel (they read the same input and write
-  // disjoint nodes), joined back before the stage ends (wdg_set_overlap).
-  bool overlap = true;
+  // Hybrid meshes, optionally: after the mortar kernel the tetrahedron kernel
+  // runs on a second stream beside the wedge kernel (they read the same input
+  // and write disjoint nodes), joined back before the stage ends
+  // (wdg_set_overlap; off by default: measured slower with the current kernels).
+  bool overlap = false;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double time = 0.0;

@@ -218,7 +218,7 @@ class Solver:
 
     def set_overlap(self, enable: bool):
         """Hybrid stages: run the tetrahedron kernel on a second stream beside the wedge kernel
-        (default True) or all kernels in order on the solver stream."""
+        (True) or all kernels in order on the solver stream (False, the default)."""
         self._check(self._lib.wdg_set_overlap(self._h, int(bool(enable))), "set_overlap")
 
     def set_tet_blocks(self, blocks: int):
