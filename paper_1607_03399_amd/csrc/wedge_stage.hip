@@ -70,6 +70,31 @@ __device__ __forceinline__ T pick(const double* tab, int j, int stride, int col)
   return v;
 }
 
+// The same selection where it is needed late in a kernel: the compiler turns
+// the selection above into one load at a selected address in global memory,
+// which is harmless next to the chunk's first loads but, issued late, comes
+// with a wait for every load still in flight.  Here the entry is the sum of the
+// entries times 0/1 masks of the lane's level (exact: one term is non-zero),
+// the masks hidden from the compiler by an empty asm statement, so that every
+// entry is read at a constant address (a scalar load).
+template <int Nq, typename T>
+struct LevelMask {
+  T m[Nq];
+  __device__ __forceinline__ explicit LevelMask(int j) {
+#pragma unroll
+    for (int jj = 0; jj < Nq; ++jj) {
+      m[jj] = j == jj ? T(1) : T(0);
+      asm volatile("" : "+v"(m[jj]));
+    }
+  }
+  __device__ __forceinline__ T pick(const double* tab, int stride, int col) const {
+    T v = T(0);
+#pragma unroll
+    for (int jj = 0; jj < Nq; ++jj) v += m[jj] * T(tab[jj * stride + col]);
+    return v;
+  }
+};
+
 
 // Adds one stage's gradient terms x[kGradStride] of wedge e to its
 // accumulators across the reverse sweep: FP64 in place; FP32 as Kahan
@@ -101,9 +126,28 @@ __device__ __forceinline__ void grad_accumulate(void* gacc, int64_t e, const T* 
 // (gacc slots 2..6 and 7..11), which the combine kernel turns into the
 // penalty derivatives.  M^k = (sum_v w_v M_v) (x) M^1D and the face masses
 // are literals (reference triangle, 1D, edge masses).
+// FP32 up to N = 3 the gradient epilogue takes the element's connectivity
+// and geometry from the stage's registers and issues its gathers first and its
+// chunk loads before its first barrier: reloading them from memory after the
+// update's stores would wait for the stores.  Beyond, the extra live registers
+// spill, and it reads them from memory where they are used.
+template <int N, typename T>
+constexpr bool grad_early() {
+  return sizeof(T) == 4 && N <= 3;
+}
+// the geometry the epilogue uses, copied out of the stage's LDS before the
+// right-hand side overwrites it: the lane's triangular face (bottom for level
+// 0, else top), the three quadrilateral faces, kappa, 1/rho, the vertex weights
+template <typename T>
+struct EpiGeo {
+  T tJf, tnx, tny, tnz, kap, irho, w0, w1, w2;
+  T qg[3][4];
+};
+
 template <int N, typename T>
 __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, int nE, int tid, int le, int j,
-                                              bool active, int64_t e, V4<T>* sU, V4<T>* sX) {
+                                              bool active, int64_t e, V4<T>* sU, V4<T>* sX, const int* cn,
+                                              const EpiGeo<T>& eg) {
   using C = Cfg<N, T>;
   using RT = gen::RefTables<N>;
   constexpr int NT = C::NT, Nq = C::Nq, NP = C::NP, NPP = C::NPP, EPB = C::EPB;
@@ -116,18 +160,19 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
   const T bsign = (A.flags & kDirichlet) ? T(-1) : T(1);
   const int lb = (lane_ok ? le : 0) * NPP + j * NT;
   const V4<T>* __restrict__ Us = static_cast<const V4<T>*>(A.gUs);
-  const T* __restrict__ g = static_cast<const T*>(A.geo) + e * kGeoStride;
-  const int* __restrict__ cn = A.conn + e * kConnStride;
-  const int code = cn[5];
-
-  V4<T> sg[NT];
+  constexpr bool early = grad_early<N, T>();
+  const int* __restrict__ gcn = A.conn + e * kConnStride;
+  const T* __restrict__ gm = static_cast<const T*>(A.geo) + e * kGeoStride;
+  int cv[6];
 #pragma unroll
-  for (int i = 0; i < NT; ++i) sg[i] = sU[lb + i];
-  // neighbour nodes of the forward stage input on the quadrilateral faces (this level)
+  for (int k = 0; k < 6; ++k) cv[k] = early ? cn[k] : gcn[k];
+  const int code = cv[5];
+  // neighbour nodes of the forward stage input on the quadrilateral faces (this
+  // level)
   V4<T> gq[3][Nq];
 #pragma unroll
   for (int ed = 0; ed < 3; ++ed) {
-    const int nbr = cn[2 + ed];
+    const int nbr = cv[2 + ed];
     const int ned = (code >> (8 + 2 * ed)) & 3;
     const V4<T>* nb_el = Us + (nbr >= 0 ? int64_t(nbr) : e) * NP + j * NT;
 #pragma unroll
@@ -136,17 +181,29 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
       gq[ed][q] = nb_el[ni];
     }
   }
-  __syncthreads();  // the update and the reads of sig are done
-  {
-    const int64_t bytes = int64_t(nE) * NP * V4B;
-    const auto bu = chunk_rsrc(Us + e0 * NP, bytes);
-    const auto br = chunk_rsrc(static_cast<const V4<T>*>(A.gRs) + e0 * NP, bytes);
-    V4<T> a[SU], b[SU];
+
+  // the chunk's forward stage input and right-hand side, coalesced; they go
+  // to LDS once the barrier below has freed it.  Issued before that barrier
+  // where the registers allow it (FP32 up to N = 3; beyond, holding them
+  // across the barrier spills)
+  V4<T> a[SU], b[SU];
+  const int64_t bytes = int64_t(nE) * NP * V4B;
+  const auto bu = chunk_rsrc(Us + e0 * NP, bytes);
+  const auto br = chunk_rsrc(static_cast<const V4<T>*>(A.gRs) + e0 * NP, bytes);
+  auto load_ab = [&]() {
 #pragma unroll
     for (int k = 0; k < SU; ++k) {
       a[k] = bload<T>(bu, tid + 64 * k);
       b[k] = bload<T>(br, tid + 64 * k);
     }
+  };
+  if constexpr (early) load_ab();
+  V4<T> sg[NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) sg[i] = sU[lb + i];
+  __syncthreads();  // the update and the reads of sig are done
+  if constexpr (!early) load_ab();
+  {
 #pragma unroll
     for (int k = 0; k < SU; ++k) {
       const int idx = tid + 64 * k;
@@ -165,21 +222,25 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
   // triangular faces: lane 0 the bottom, lane N the top (own level)
   if (lane_ok && (j == 0 || j == N)) {
     const int face = j == 0 ? 0 : 1;
-    const int nbr = cn[face];
+    const int nbr = face ? cv[1] : cv[0];
     const int pc = (code >> (3 * face)) & 7;
     const int nlev = ((code >> (6 + face)) & 1) ? N : 0;
-    const T Jf = g[12 + 4 * face], nx = g[13 + 4 * face], ny = g[14 + 4 * face], nz = g[15 + 4 * face];
+    const T Jf = early ? eg.tJf : gm[12 + 4 * face], nx = early ? eg.tnx : gm[13 + 4 * face];
+    const T ny = early ? eg.tny : gm[14 + 4 * face], nz = early ? eg.tnz : gm[15 + 4 * face];
     T jp[NT], jn[NT];
+    // the neighbour's face nodes, all issued before any is used (a boundary
+    // face reads the own element, a valid address, and uses the mirror state)
+    const bool inner = nbr >= 0;
+    const int64_t src = inner ? int64_t(nbr) : e;
+    V4<T> vn[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) vn[i] = Us[src * NP + nlev * NT + face_perm<N>(pc, i)];
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
       const V4<T> own = sUs[lb + i];
       const T pm = own.p, unm = nx * own.ux + ny * own.uy + nz * own.uz;
-      T pp = bsign * pm, unp = -bsign * unm;  // mirror state
-      if (nbr >= 0) {
-        const V4<T> v = Us[int64_t(nbr) * NP + nlev * NT + face_perm<N>(pc, i)];
-        pp = v.p;
-        unp = nx * v.ux + ny * v.uy + nz * v.uz;
-      }
+      const T pp = inner ? vn[i].p : bsign * pm;  // else the mirror state
+      const T unp = inner ? nx * vn[i].ux + ny * vn[i].uy + nz * vn[i].uz : -bsign * unm;
       jp[i] = pp - pm;
       jn[i] = unp - unm;
     }
@@ -204,8 +265,9 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
   T jq[3][Nq][2], ap[3][Nq], an[3][Nq];
 #pragma unroll
   for (int ed = 0; ed < 3; ++ed) {
-    const int nbr = cn[2 + ed];
-    const T Ja = g[20 + 4 * ed], Jb = g[21 + 4 * ed], nx = g[22 + 4 * ed], ny = g[23 + 4 * ed];
+    const int nbr = cv[2 + ed];
+    const T Ja = early ? eg.qg[ed][0] : gm[20 + 4 * ed], Jb = early ? eg.qg[ed][1] : gm[21 + 4 * ed];
+    const T nx = early ? eg.qg[ed][2] : gm[22 + 4 * ed], ny = early ? eg.qg[ed][3] : gm[23 + 4 * ed];
     T sp[Nq], sn[Nq];
 #pragma unroll
     for (int q = 0; q < Nq; ++q) {
@@ -238,11 +300,14 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
   }
 
   T m1[Nq];
+  {
+    const LevelMask<Nq, T> lm(j);
 #pragma unroll
-  for (int m = 0; m < Nq; ++m) m1[m] = pick<Nq, T>(RT::M1, j, Nq, m);
+    for (int m = 0; m < Nq; ++m) m1[m] = lm.pick(RT::M1, Nq, m);
+  }
   if (lane_ok) {
     // mass terms on this level: sig^T (M^{tri,k} (x) M^1D) R, M^{tri,k} = sum_v w_v M_v
-    const T w0 = g[37], w1 = g[38], w2 = g[39];
+    const T w0 = early ? eg.w0 : gm[37], w1 = early ? eg.w1 : gm[38], w2 = early ? eg.w2 : gm[39];
     T y[4][NT];
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
@@ -328,7 +393,7 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
       for (int l = 0; l < Nq; ++l) s += sPart[(le * Nq + l) * GS + k];
       tot[k] = s;
     }
-    const T kap = g[9], irho = g[10];
+    const T kap = early ? eg.kap : gm[9], irho = early ? eg.irho : gm[10];
     const T c = std::sqrt(kap * irho);
     const T dt = T(A.dt);
     T x[kGradStride];
@@ -661,8 +726,9 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int64_t 
       // exact mass: (M^1D)^-1 e_{0,N}; lumped mass (Gauss-Lobatto weights w): e_{0,N} / w_{0,N}
       const T wend = T(0.5 * N * (N + 1));  // 1 / w_0 = 1 / w_N
       const bool lumped = (A.flags & kLumped) != 0;
-      const T g0j = lumped ? (j == 0 ? wend : T(0)) : pick<Nq, T>(RT::g0, j, 1, 0);
-      const T gNj = lumped ? (j == N ? wend : T(0)) : pick<Nq, T>(RT::gN, j, 1, 0);
+      const LevelMask<Nq, T> lm(j);
+      const T g0j = lumped ? (j == 0 ? wend : T(0)) : lm.pick(RT::g0, 1, 0);
+      const T gNj = lumped ? (j == N ? wend : T(0)) : lm.pick(RT::gN, 1, 0);
       const T* fbt = sF + (le * 2 + 0) * NT * 2;
       const T* ftp = sF + (le * 2 + 1) * NT * 2;
       const T bx = g[13], by = g[14], bz = g[15], tx = g[17], ty = g[18], tz = g[19];
@@ -856,6 +922,25 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int64_t 
       }
     }
   }
+  // the gradient epilogue's geometry, before the right-hand side replaces it
+  [[maybe_unused]] EpiGeo<T> eg{};
+  if constexpr (MODE == 4 && grad_early<N, T>()) {
+    const T* gl = reinterpret_cast<const T*>(sG) + (le < EPB ? le : 0) * kGeoStride;
+    const int tf = j == 0 ? 0 : 1;
+    eg.tJf = gl[12 + 4 * tf];
+    eg.tnx = gl[13 + 4 * tf];
+    eg.tny = gl[14 + 4 * tf];
+    eg.tnz = gl[15 + 4 * tf];
+#pragma unroll
+    for (int ed = 0; ed < 3; ++ed)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) eg.qg[ed][k] = gl[20 + 4 * ed + k];
+    eg.kap = gl[9];
+    eg.irho = gl[10];
+    eg.w0 = gl[37];
+    eg.w1 = gl[38];
+    eg.w2 = gl[39];
+  }
   // the right-hand side replaces lifts, geometry and fluxes in LDS
   __syncthreads();
   if (active) {
@@ -896,7 +981,7 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int64_t 
     update(std::true_type{});
   else
     update(std::false_type{});
-  if constexpr (MODE == 4) grad_epilogue<N, T>(A, e0, nE, tid, le, j, active, e, sU, sX);
+  if constexpr (MODE == 4) grad_epilogue<N, T>(A, e0, nE, tid, le, j, active, e, sU, sX, cn, eg);
   if constexpr (MODE == 5) {
     __syncthreads();  // the update's reads of the staged state are done
     if (tid < NT) carry[tid] = sU[(nE - 1) * NPP + N * NT + tid];
