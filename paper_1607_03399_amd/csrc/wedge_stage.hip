@@ -592,13 +592,15 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int64_t 
 
   if (active) {
     const T tzJ = g[4];
-    const T tl = T(0.5) * (T(1) - pick<Nq, T>(RT::t, j, 1, 0));
-    const T th = T(0.5) * (T(1) + pick<Nq, T>(RT::t, j, 1, 0));
+    const LevelMask<Nq, T> lm(j);
+    const T tj = lm.pick(RT::t, 1, 0);
+    const T tl = T(0.5) * (T(1) - tj);
+    const T th = T(0.5) * (T(1) + tj);
     const T txJ = g[5] * tl + g[6] * th;
     const T tyJ = g[7] * tl + g[8] * th;
     T dtr[Nq];
 #pragma unroll
-    for (int m = 0; m < Nq; ++m) dtr[m] = pick<Nq, T>(RT::Dt, j, Nq, m);
+    for (int m = 0; m < Nq; ++m) dtr[m] = lm.pick(RT::Dt, Nq, m);
 
     // vertical part: W = t_dJ(t_j) (D_t U)(level j)
 #pragma unroll
