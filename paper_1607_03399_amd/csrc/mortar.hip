@@ -80,29 +80,34 @@ __global__ void __launch_bounds__(64) mortar_kernel(StageLaunch A) {
   const int64_t mo = blockIdx.x;
   const int* mi = A.mortI + mo * kMortIntStride;
   const double* mg = static_cast<const double*>(A.mortG) + mo * kMortGeoStride;
-  const int e = mi[1];
-
-  // node values: the wedge face (Nq x Nq, level-major), then both tetrahedron faces
-  V4<T> nv[NSL];
-#pragma unroll
-  for (int l = 0; l < NSL; ++l) {
-    const int idx = tid + 64 * l;
-    nv[l] = V4<T>{T(0), T(0), T(0), T(0)};
-    if (idx < NW) {
-      const int lev = idx / Nq, q = idx - lev * Nq;
-      nv[l] = Uin[int64_t(mi[0]) * NPW + lev * NT + edge_node(N, e, q)];
-    } else if (idx < NST) {
-      const int r = idx - NW, side = r / NT, i = r - side * NT;
-      nv[l] = Uin[A.Kw * NPW + (int64_t(mi[3 + 2 * side]) - A.Kw) * NPT + tet_face_node<N>(mi[4 + 2 * side], i)];
-    }
-  }
+  // Loads in the order their results are needed, each issued before any
+  // wait: the mortar's record, its coupling matrices (which do not depend on
+  // the record), then the node gathers addressed from the record.  The
+  // vector-memory counter completes in order, so waiting for the record does
+  // not wait for the matrices.
+  const int wel = mi[0], e = mi[1], t0 = mi[3], f0 = mi[4], t1 = mi[5], f1 = mi[6];
+  const double mgx = mg[5], mgy = mg[6], mz0 = mg[27], mz1 = mg[28], ms0 = mg[25], ms1 = mg[26];
   V4<T> cv[CVL];
   {
     const auto rc = chunk_rsrc(static_cast<const V4<T>*>(A.mortC) + mo * CV, int64_t(CV) * 4 * int64_t(sizeof(T)));
 #pragma unroll
     for (int l = 0; l < CVL; ++l) cv[l] = core_load<T>(rc, tid + 64 * l);
   }
-  const T nx = T(mg[5]), ny = T(mg[6]);
+
+  // node values: the wedge face (Nq x Nq, level-major), then both tetrahedron
+  // faces; lanes past them read node 0 (a valid address, never used)
+  V4<T> nv[NSL];
+#pragma unroll
+  for (int l = 0; l < NSL; ++l) {
+    const int idx = tid + 64 * l;
+    const int lev = idx / Nq, q = idx - lev * Nq;
+    const int r = idx - NW, side = r >= NT ? 1 : 0, i = r - side * NT;
+    const int64_t aw = int64_t(wel) * NPW + lev * NT + edge_node(N, e, q < Nq ? q : 0);
+    const int64_t at = A.Kw * NPW + (int64_t(side ? t1 : t0) - A.Kw) * NPT +
+                       tet_face_node<N>(side ? f1 : f0, i >= 0 && i < NT ? i : 0);
+    nv[l] = Uin[idx < NW ? aw : (idx < NST ? at : 0)];
+  }
+  const T nx = T(mgx), ny = T(mgy);
 #pragma unroll
   for (int l = 0; l < NSL; ++l) {
     const int idx = tid + 64 * l;
@@ -143,7 +148,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(StageLaunch A) {
         dp += cc * zp[c];
         dn += cc * zn[c];
       }
-      const T zs = T(mg[27 + s]);
+      const T zs = T(s == 0 ? mz0 : mz1);
       const T taup = tau_on * T(2) / zs, tauu = tau_on * zs * T(0.5);
       if (tid < NW) {
         wp += T(0.5) * (taup * dp - dn);
@@ -189,7 +194,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(StageLaunch A) {
     T acc = 0;
 #pragma unroll
     for (int k = 0; k < NT; ++k) acc += tab[TB::MTI + i * NT + k] * sMT[(2 * side + f) * NT + k];
-    static_cast<T*>(A.mortF)[(mo * 2 + side) * 2 * NT + f * NT + i] = acc * T(mg[25 + side]);
+    static_cast<T*>(A.mortF)[(mo * 2 + side) * 2 * NT + f * NT + i] = acc * T(side ? ms1 : ms0);
   }
 }
 
