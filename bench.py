@@ -538,13 +538,61 @@ def forward_leg(config: str, bits: int, steps: int, warmup: int, layer_march: st
     return leg, dt, mesh
 
 
+def ab_passes(kind: str, config: str, steps: int, warmup: int, reps: int = 3):
+    """Alternate two settings on one solver and print one JSON line per timed
+    pass: 'wedge-kernel' (level-lane vs node-lane wedge kernel, per-kernel HIP
+    events) or 'overlap' (hybrid meshes: the three kernels in order vs the
+    tetrahedron kernel beside the wedge kernel, wall time per step without
+    events)."""
+    import torch
+
+    from paper_1607_03399_amd import wdg
+
+    N, verts, wedges, tets, c, rho, mesh, desc = workload(config)
+    s = wdg.Solver(N, 32, device=0)
+    s.set_mesh(verts, wedges, tets)
+    s.set_material(c, rho)
+    s.set_boundary("rigid")
+    s.set_flux("upwind")
+    s.add_ricker_source([0.5, 0.5, 0.5], 10.0, 0.1, 1.0)
+    s.set_fields(initial_state(s))
+    s.bind_torch()
+    dt = s.stable_dt(0.5)
+    s.step(warmup, dt)
+    s.synchronize()
+    settings = ("level", "node") if kind == "wedge-kernel" else (False, True)
+    for rep in range(reps):
+        for v in settings:
+            if kind == "wedge-kernel":
+                s.set_wedge_kernel(v)
+            else:
+                s.set_overlap(v)
+            s.step(2, dt)
+            s.synchronize()
+            torch.cuda.synchronize()
+            if kind == "wedge-kernel":
+                s.kernel_timing(True)
+            t0 = time.perf_counter()
+            s.step(steps, dt)
+            s.synchronize()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            line = {"ab": kind, "config": config, "setting": v, "pass": rep, "ms_per_step": wall * 1e3 / steps}
+            if kind == "wedge-kernel":
+                w_ms, t_ms, m_ms, n = s.read_kernel_timing_split()
+                s.kernel_timing(False)
+                line["wedge_stage_us"] = w_ms * 1e3 / n
+            print(json.dumps(line), flush=True)
+    s.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="cfg2", choices=sorted(CONFIGS),
-                    help="; ".join(f"{k}: {v}" for k, v in CONFIGS.items()) + " (default cfg2)")
+                    help=("; ".join(f"{k}: {v}" for k, v in CONFIGS.items()) + " (default cfg2)").replace("%", "%%"))
     ap.add_argument("--precision", type=int, default=32, choices=[32, 64])
     ap.add_argument("--layer-march", default="off", choices=["off", "chunk", "column"],
                     help="layer marching of the level-lane wedge kernel: vertical neighbours inside a chunk from "
@@ -572,6 +620,10 @@ def main():
     ap.add_argument("--leg-steps", type=int, default=20)
     ap.add_argument("--no-copy-calibration", action="store_true",
                     help="skip the plain 512 MiB device copy (the measured HBM reference of the roofline)")
+    ap.add_argument("--ab", choices=["wedge-kernel", "overlap"],
+                    help="instead of the bench line: alternate the two wedge kernels (FP32, orders 4 and 5) or the "
+                         "in-order and side-by-side hybrid stage on the chosen --config, three times each, and print "
+                         "one JSON line per pass of --steps steps")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -583,6 +635,10 @@ def main():
 
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
     import torch  # noqa: F401  (device memory and streams of the bound state)
+
+    if args.ab:
+        ab_passes(args.ab, args.config, args.steps, args.warmup)
+        return
 
     copy_gbs = None if args.no_copy_calibration else copy_bandwidth()
     bits = args.precision

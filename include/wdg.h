@@ -141,7 +141,7 @@ int wdg_set_tet_blocks(wdg_ctx* ctx, int blocks);
  * solver stream waits for it before the stage ends; 0 (default): all three
  * kernels in order on the solver stream (side by side the two kernels slow
  * each other down: on the 39 312-wedge + 29 520-tetrahedron N = 4 mesh the
- * step measured 0.84 ms against 0.77 ms in order).  Results are bitwise the
+ * step measured 0.83 ms against 0.76 ms in order).  Results are bitwise the
  * same either way.  Stages timed with wdg_kernel_timing always run in order. */
 int wdg_set_overlap(wdg_ctx* ctx, int enable);
 
