@@ -617,7 +617,7 @@ def main():
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the other forward configurations (cfg2 runs cfg3 with both tetrahedron kernels, "
                          "cfg5, order 4 and 5 and FP64 cfg2 for 20 steps each)")
-    ap.add_argument("--leg-steps", type=int, default=20)
+    ap.add_argument("--leg-steps", type=int, default=40)
     ap.add_argument("--no-copy-calibration", action="store_true",
                     help="skip the plain 512 MiB device copy (the measured HBM reference of the roofline)")
     ap.add_argument("--ab", choices=["wedge-kernel", "overlap"],
@@ -689,10 +689,10 @@ def main():
                                      ("order5", "order5", 32, "mfma", "auto"),
                                      ("order5_wedge_level", "order5", 32, "mfma", "level"),
                                      ("cfg2_fp64", "cfg2", 64, "mfma", "auto")):
-            legs[name], _, _ = forward_leg(cfg, b, args.leg_steps, 3, tet_kernel=tk, wedge_kernel=wk)
+            legs[name], _, _ = forward_leg(cfg, b, args.leg_steps, 10, tet_kernel=tk, wedge_kernel=wk)
         # layer marching (the paper's future work) against the gathers, same kernel
         for name, mode in (("cfg2_chunk_march", "chunk"), ("cfg2_column_march", "column")):
-            legs[name], _, _ = forward_leg("cfg2", 32, args.leg_steps, 3, layer_march=mode)
+            legs[name], _, _ = forward_leg("cfg2", 32, args.leg_steps, 10, layer_march=mode)
         out["legs"] = legs
     if default_run and not args.no_adjoint:
         out["adjoint"] = adjoint_benchmark(args.adjoint_steps, 50)

@@ -209,6 +209,61 @@ def test_fp32_100_steps_n3():
     _say("   rel err", err, "worst element", emax)
 
 
+@pytest.mark.parametrize("N", [4, 5])
+def test_fp32_100_steps_high_order(N):
+    """FP32 at orders 4 and 5 (the node-lane wedge kernel, the default there)
+    after 100 steps with a Ricker source and receivers, against the FP64
+    oracle: fields element by element, traces and energy at the FP32
+    tolerance."""
+    m = inputs.layered_config(3, 3, 0.3, seed=11)  # 54 wedges, curved, banded c and rho
+    om = _omesh(m)
+    x = dg.node_coords(om, N)
+    U0 = np.zeros((m.K, 4, x.shape[1]))
+    U0[:, 0] = inputs.gaussian_pulse(x, width=0.25)
+    U0[:, 2] = 0.5 * inputs.gaussian_pulse(x, centre=(0.6, 0.4, 0.5), width=0.3)
+    dt = dg.stable_dt(om, N, 0.5)
+    src = ([0.4, 0.45, 0.55], 5.0, 0.2, 1.0)
+    rec = np.array([[0.5, 0.5, 0.5], [0.25, 0.7, 0.8]])
+    _say("fp32 high order library", N)
+    got, gtr, gE = _run_library(m, N, 32, U0, dt, 100, src=src, rec=rec)
+    _say("fp32 high order oracle", N)
+    ref, rtr, rE = _run_oracle(m, N, U0, dt, 100, src=src, rec=rec)
+    err, emax = check(got, ref, 1e-5, f"fp32 100 steps N={N}")
+    _say("   rel err", err, "worst element", emax)
+    assert np.abs(gtr - rtr).max() <= 1e-5 * np.abs(rtr).max()
+    assert abs(gE - rE) <= 1e-5 * rE
+
+
+def test_cfg2_full_size_100_steps_fp32_against_fp64():
+    """cfg2 at full size (262144 wedges, N=3): 100 FP32 steps against 100 FP64
+    steps of the device path (the FP64 path is held to the oracle at 1e-12 on
+    the smaller meshes above), element by element at the FP32 tolerance, and
+    the upwind scheme's energy does not increase over any 10 of the steps in
+    either precision."""
+    m = inputs.cfg2_mesh()
+    N = 3
+    out = {}
+    for bits in (64, 32):
+        _say("cfg2 100 steps", bits)
+        s = _solver(m, N, bits)
+        U0 = np.zeros((m.K, 4, 40))
+        U0[:, 0] = inputs.gaussian_pulse(s.node_coords(), width=0.2)
+        s.set_fields(U0)
+        dt = s.stable_dt(0.5) if bits == 64 else out[64][1]
+        E = [s.energy()]
+        for _ in range(10):
+            s.step(10, dt)
+            E.append(s.energy())
+        F = s.get_fields()
+        s.close()
+        assert np.all(np.isfinite(F))
+        assert all(E[k + 1] <= E[k] * (1 + 1e-6) for k in range(10)), E
+        assert E[-1] < E[0]
+        out[bits] = (F, dt)
+    err, emax = check(out[32][0], out[64][0], 1e-5, "cfg2 100 steps FP32 vs FP64")
+    _say("   rel err", err, "worst element", emax)
+
+
 def test_dirichlet_steps_fp64_and_energy_decay():
     m = inputs.cube_mesh(2, z_jitter=0.3, seed=2)
     N = 3
