@@ -330,12 +330,13 @@ __device__ __forceinline__ void wedge_node_chunk(const StageLaunch& A, int chunk
 #pragma unroll
   for (int j = 0; j < Nq; ++j) Rp[j] = Rz[j] = Rx[j] = Ry[j] = T(0);
   {
-    // rolled over the columns m: each step reads L[i][m] and the element's
-    // column m of B at all levels (a broadcast), unrolled the scheduler would
-    // hoist every column's reads at once
+    // over the columns m, unrolled three times (NT is a multiple of 3 at
+    // orders 4 and 5): each step reads L[i][m] and the element's column m of
+    // B at all levels (a broadcast); fully unrolled, the scheduler would hoist
+    // every column's reads at once and spill
     const V4<T>* bl = sB + le * C::XV;
     const T* lc = reinterpret_cast<const T*>(sL4) + le * C::LS + i;
-#pragma unroll 1
+#pragma unroll 3
     for (int m = 0; m < NT; ++m) {
       const T l = lc[m * NT];
 #pragma unroll
@@ -354,7 +355,7 @@ __device__ __forceinline__ void wedge_node_chunk(const StageLaunch& A, int chunk
     T aPr[Nq], aPs[Nq], aXr[Nq], aXs[Nq], aYr[Nq], aYs[Nq];
 #pragma unroll
     for (int j = 0; j < Nq; ++j) aPr[j] = aPs[j] = aXr[j] = aXs[j] = aYr[j] = aYs[j] = T(0);
-#pragma unroll 1
+#pragma unroll 3
     for (int m = 0; m < NT; ++m) {
       const T dr = sDr[i * NT + m], ds = sDs[i * NT + m];
 #pragma unroll
