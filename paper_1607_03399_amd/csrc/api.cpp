@@ -124,7 +124,7 @@ struct wdg_ctx {
   std::vector<double> rec_xyz;  // nrec x 3
   int64_t* dRecBase = nullptr;
   int* dRecNN = nullptr;
-  double* dRecRows = nullptr;
+  void* dRecRows = nullptr;  // receiver interpolation rows, in the state precision
   double* dRecBuf = nullptr;
   int64_t rec_cap = 0, rec_steps = 0;
   bool timing = false;
@@ -1528,11 +1528,17 @@ int wdg_set_receivers(wdg_ctx* ctx, int64_t n, const double* xyz) {
   if (n == 0) return WDG_OK;
   HIPCHK(hipMalloc(&ctx->dRecBase, base.size() * sizeof(int64_t)));
   HIPCHK(hipMalloc(&ctx->dRecNN, nn.size() * sizeof(int)));
-  HIPCHK(hipMalloc(&ctx->dRecRows, rows.size() * sizeof(double)));
+  HIPCHK(hipMalloc(&ctx->dRecRows, rows.size() * ctx->tsize()));
   HIPCHK(hipMemcpyAsync(ctx->dRecBase, base.data(), base.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->dRecNN, nn.data(), nn.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipMemcpyAsync(ctx->dRecRows, rows.data(), rows.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ctx->bits == 32) {
+    const std::vector<float> rf(rows.begin(), rows.end());
+    HIPCHK(hipMemcpyAsync(ctx->dRecRows, rf.data(), rf.size() * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  } else {
+    HIPCHK(hipMemcpyAsync(ctx->dRecRows, rows.data(), rows.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
   return WDG_OK;
 }
 

@@ -186,7 +186,7 @@ hipError_t launch_inject(int bits, int NP, int nrec, const int64_t* base, const 
                          double sb, void* U, void* S, hipStream_t st);
 // Pressure at receivers: receiver r reads nn[r] nodes from 4-vector index base[r] with row stride ld.
 hipError_t launch_receivers(int bits, int ld, int nrec, const void* U, const int64_t* base, const int* nn,
-                            const double* rows, double* out, hipStream_t st);
+                            const void* rows, double* out, hipStream_t st);
 // Per-block partial energies; returns the number of partials written.
 hipError_t launch_energy(int N, int bits, int64_t K, const void* U, const double* aux, const double* Mv,
                          const double* M1, double* partial, int* nblocks, hipStream_t st);

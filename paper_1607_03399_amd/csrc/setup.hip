@@ -152,15 +152,17 @@ __global__ void material_kernel(int64_t K, const double* __restrict__ c, const d
   aux[k * kAuxStride + 5] = rho[k];
 }
 
+// receiver traces: p at each receiver by its element's interpolation row, in
+// the state precision (the trace buffer holds them widened to double)
 template <typename T>
 __global__ void sample_receivers(int ld, int nrec, const T* __restrict__ U, const int64_t* __restrict__ base,
-                                 const int* __restrict__ nn, const double* __restrict__ rows, double* __restrict__ out) {
+                                 const int* __restrict__ nn, const T* __restrict__ rows, double* __restrict__ out) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrec) return;
   const T* Ue = U + base[r] * 4;
-  double acc = 0.0;
-  for (int n = 0; n < nn[r]; ++n) acc += rows[int64_t(r) * ld + n] * double(Ue[4 * n]);
-  out[r] = acc;
+  T acc = T(0);
+  for (int n = 0; n < nn[r]; ++n) acc += rows[int64_t(r) * ld + n] * Ue[4 * n];
+  out[r] = double(acc);
 }
 
 template <int N, typename T>
@@ -296,15 +298,15 @@ hipError_t launch_material(int bits, int64_t K, const double* dc, const double* 
 }
 
 hipError_t launch_receivers(int bits, int ld, int nrec, const void* U, const int64_t* base, const int* nn,
-                            const double* rows, double* out, hipStream_t st) {
+                            const void* rows, double* out, hipStream_t st) {
   if (nrec <= 0) return hipSuccess;
   const unsigned nb = unsigned((nrec + 63) / 64);
   if (bits == 32)
     hipLaunchKernelGGL(sample_receivers<float>, dim3(nb), dim3(64), 0, st, ld, nrec, static_cast<const float*>(U), base,
-                       nn, rows, out);
+                       nn, static_cast<const float*>(rows), out);
   else
     hipLaunchKernelGGL(sample_receivers<double>, dim3(nb), dim3(64), 0, st, ld, nrec, static_cast<const double*>(U),
-                       base, nn, rows, out);
+                       base, nn, static_cast<const double*>(rows), out);
   return hipGetLastError();
 }
 
