@@ -62,7 +62,7 @@ def stage_bytes(N: int, bits: int, reads_res: bool) -> int:
     return state * (3 + int(reads_res)) + 40 * ts + LS * ts + 8 * 4
 
 
-def survey_stage_bytes(N: int, bits: int) -> int:
+def table_stage_bytes(N: int, bits: int) -> int:
     """Algorithmic HBM bytes of one stage for one wedge as the hot-path scope
     table counts them (the roofline's reference figure): state read, residual
     read and written, state written (4 fields x Np values each, the residual
@@ -167,7 +167,7 @@ def _host_cpu():
 
 
 def cpu_baseline(config: str, N: int, dt: float, seconds: float, sample: int, workers: int):
-    """The FP64 oracle as it stands, on the GPU machine's host: one process on the
+    """The FP64 oracle as it stands, on the host of the GPU machine: one process on the
     first ``sample`` wedges (whole columns), then ``workers`` processes at
     once, each on its own block of ``sample`` wedges, for the same time
     (every process single-threaded: the oracle's einsums run on one core).
@@ -507,8 +507,8 @@ def forward_leg(config: str, bits: int, steps: int, warmup: int, layer_march: st
         rec_bytes = Kw * (stage_bytes(N, bits, False) + 4 * stage_bytes(N, bits, True)) / 5
         node = N >= 4 and bits == 32 and wedge_kernel in ("node", "auto")
         kernels["wedge_stage"] = {"avg_us": avg, "variant": "node-lane" if node else "level-lane",
-                                  "bytes_per_launch": Kw * survey_stage_bytes(N, bits),
-                                  "GBs": Kw * survey_stage_bytes(N, bits) / avg / 1e3,
+                                  "bytes_per_launch": Kw * table_stage_bytes(N, bits),
+                                  "GBs": Kw * table_stage_bytes(N, bits) / avg / 1e3,
                                   "record_bytes_per_launch": rec_bytes, "record_GBs": rec_bytes / avg / 1e3}
     if Kt:
         avg = t_ms * 1e3 / nlaunch
