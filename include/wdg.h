@@ -270,7 +270,16 @@ int wdg_adjoint_gradient(wdg_ctx* ctx, int64_t nsteps, double dt, const double* 
  * size runs, max_steps is exceeded, or the fields, time, material, boundary,
  * flux, mass or receivers are set.  weights: recorded steps x nrec (row n:
  * the traces after recorded step n); nsteps (may be NULL) receives the number
- * of recorded steps.  Fields and time are unchanged by the gradient call. */
+ * of recorded steps.  Fields and time are unchanged by the gradient call.
+ * While recording, step n's time is t_record + n dt (as the gradient call
+ * recomputes it), whatever the split of the steps over wdg_step calls.  When
+ * the reverse sweep's buffers are already kept whole-segment (an earlier
+ * gradient call with the same checkpoint_every, see
+ * wdg_set_adjoint_memory_limit), the recorded steps write their stage inputs
+ * and residuals into them, the same bytes as a plain step, and the next
+ * gradient call takes its last segment from there instead of recomputing it;
+ * a second gradient call of one recording recomputes everything.  Results are
+ * identical either way. */
 int wdg_adjoint_record(wdg_ctx* ctx, int64_t checkpoint_every, int64_t max_steps);
 int wdg_adjoint_gradient_recorded(wdg_ctx* ctx, const double* weights, double* grad_c, double* grad_rho,
                                   int64_t* nsteps);

@@ -9,7 +9,10 @@
 // of one stage with respect to an element's material is
 //   dt sig^T T (dG/dtheta Us - dE/dtheta Rs)
 // with Us the forward stage input and Rs its right-hand side (sources
-// included: E Rs = G Us + b with b independent of the material).
+// included: E Rs = G Us + b with b independent of the material).  The mass
+// terms are summed over a step's stages through the forward residuals
+// (dt Rs = res_s - a_s res_{s-1}), so the forward keeps those and never
+// stores Rs.
 //   dE/dc:   pressure block -2/(c kappa) M
 //   dE/drho: pressure block -1/(rho kappa) M, velocity blocks M
 //   dG/dZ:   the penalties tau_p = 2/(Z- + Z+), tau_u = (Z- + Z+)/2 of every
@@ -28,16 +31,17 @@ namespace wdg {
 namespace {
 
 // Per-wedge accumulator slots (state precision): 0 dJ/dc and 1 dJ/drho of
-// the mass terms; 2..6 sum dt 1/2 int sig_p [p], 7..11 sum dt 1/2 int sig_un
-// [u_n] over the faces (bottom, top, quadrilaterals 0..2); FP32 records then
-// hold the Kahan compensations of the same slots (the sums are read as they
-// are: the compensation is below their last bit).
-static_assert(kGradStride == 12, "gradient record layout");
+// the mass terms; 2..6 per face (bottom, top, quadrilaterals 0..2) the sum of
+// dt (-tau_p^2/2 1/2 int sig_p [p] - 1/2 1/2 int sig_un [u_n]), the own side's
+// share of dJ/dZ; FP32 records then hold the Kahan compensations of the same
+// slots (the sums are read as they are: the compensation is below their last
+// bit).
+static_assert(kGradStride == 7, "gradient record layout");
 
 // dJ/dZ of a wedge: every face's penalties depend on the impedances of both
-// sides (both are the own one on the boundary), with dtau_p/dZ = -tau_p^2/2
-// and dtau_u/dZ = 1/2; Z = rho c gives dZ/dc = rho, dZ/drho = c.  Arithmetic
-// in the state precision; the results are stored as FP64.
+// sides (both are the own one on the boundary) alike, so the face's share
+// from both sides adds up; Z = rho c gives dZ/dc = rho, dZ/drho = c.
+// Arithmetic in the state precision; the results are stored as FP64.
 template <typename T>
 __global__ void __launch_bounds__(256) grad_combine_kernel(int64_t K, const T* __restrict__ gacc,
                                                            const T* __restrict__ geo, const int* __restrict__ conn,
@@ -52,14 +56,12 @@ __global__ void __launch_bounds__(256) grad_combine_kernel(int64_t K, const T* _
     const int* cn = conn + k * kConnStride;
     const int code = cn[5];
     for (int f = 0; f < 5; ++f) {
-      const T tp = T(2) / g[32 + f];
-      const T own = -T(0.5) * tp * tp * ga[2 + f] - T(0.5) * ga[7 + f];
+      const T own = ga[2 + f];
       T other = own;
       const int nbr = cn[f];
       if (nbr >= 0) {
         const int nf = f < 2 ? ((code >> (6 + f)) & 1) : 2 + ((code >> (8 + 2 * (f - 2))) & 3);
-        const T* gn = gacc + int64_t(nbr) * kGradRecord<T>;
-        other = -T(0.5) * tp * tp * gn[2 + nf] - T(0.5) * gn[7 + nf];
+        other = gacc[int64_t(nbr) * kGradRecord<T> + 2 + nf];
       }
       gZ += own + other;
     }

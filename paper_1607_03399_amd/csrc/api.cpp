@@ -140,6 +140,10 @@ struct wdg_ctx {
   // fresh allocation of this size costs more than the sweep on some drivers)
   void* dAdjStore = nullptr;
   size_t adj_store_bytes = 0;
+  // the recorded forward writes each segment's stage inputs and residuals
+  // into the store (set when a recording starts with the store already kept
+  // in the whole-segment layout; cleared once a sweep overwrites it)
+  bool adj_tail = false;
   // per stage: start, after the mortar kernel, after the wedge kernel, after the tet kernel
   std::vector<std::array<hipEvent_t, 4>> events;
   size_t events_used = 0;
@@ -193,6 +197,7 @@ void release_device(wdg_ctx* ctx) {
   dfree(ctx->dAdjCp);
   dfree(ctx->dAdjStore);
   ctx->adj_store_bytes = 0;
+  ctx->adj_tail = false;
   ctx->adj_cp_bytes = 0;
   dfree(ctx->dSrcVec);
   dfree(ctx->dAux);
@@ -430,7 +435,7 @@ hipError_t launch_wedges(const wdg_ctx* ctx, const wdg::StageLaunch& L) {
 
 int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a, double b, double dt, double tstage,
                  int flags, double g = 1.0, void* rout = nullptr, bool sources = true, const void* gUs = nullptr,
-                 const void* gRs = nullptr, void* gacc = nullptr) {
+                 const void* gRs = nullptr, void* gacc = nullptr, double gb = 0.0) {
   wdg::StageLaunch L{};
   L.Uin = Uin;
   L.Uout = Uout;
@@ -462,6 +467,7 @@ int launch_stage(wdg_ctx* ctx, const void* Uin, void* Uout, void* res, double a,
   L.rout = rout;
   L.gUs = gUs;
   L.gRs = gRs;
+  L.gb = gb;
   L.gacc = gacc;
   L.Kw = ctx->Kw;
   L.Kt = ctx->Kt;
@@ -1602,8 +1608,21 @@ int wdg_step(wdg_ctx* ctx, int64_t nsteps, double dt) {
   if (rc) return rc;
   const double t0 = ctx->time;
   const size_t SB = size_t(ctx->nodes()) * 4 * ctx->tsize();
+  // X: the current state.  A recorded forward with the reverse sweep's store
+  // kept writes step i of each segment into its slots as the sweep lays them
+  // out (start state 10 i, stage inputs 10 i + 1..4, residuals 10 i + 5..9),
+  // the next step's start into the next step's slot (the segment's first
+  // slot after its last step: the sweep starts a segment from its checkpoint); the
+  // state returns to the solver's buffers when that stops and at the end.
+  void* X = ctx->dU[ctx->cur];
+  auto settle = [&]() -> int {
+    if (X != ctx->dU[ctx->cur]) {
+      HIPCHK(hipMemcpyAsync(ctx->dU[ctx->cur], X, SB, hipMemcpyDeviceToDevice, ctx->stream));
+      X = ctx->dU[ctx->cur];
+    }
+    return WDG_OK;
+  };
   for (int64_t n = 0; n < nsteps; ++n) {
-    const double tn = t0 + double(n) * dt;
     if (ctx->recording) {
       // checkpoint at the start of every adj_every-th recorded step
       if (ctx->adj_steps == 0) ctx->adj_dt = dt;
@@ -1611,24 +1630,49 @@ int wdg_step(wdg_ctx* ctx, int64_t nsteps, double dt) {
       if (dt != ctx->adj_dt || ctx->adj_steps >= ctx->adj_ncap * ctx->adj_every) {
         ctx->recording = false;
       } else if (g > 0 && ctx->adj_steps % ctx->adj_every == 0) {
-        HIPCHK(hipMemcpyAsync(static_cast<unsigned char*>(ctx->dAdjCp) + size_t(g) * SB, ctx->dU[ctx->cur], SB,
+        HIPCHK(hipMemcpyAsync(static_cast<unsigned char*>(ctx->dAdjCp) + size_t(g) * SB, X, SB,
                               hipMemcpyDeviceToDevice, ctx->stream));
       }
     }
-    for (int s = 0; s < 5; ++s) {
-      const int flags = (s == 0 ? 0 : wdg::kReadRes) | wdg::kWriteU;
-      rc = launch_stage(ctx, ctx->dU[ctx->cur], ctx->dU[1 - ctx->cur], ctx->dRes, kRkA[s], kRkB[s], dt,
-                        tn + kRkC[s] * dt, flags);
+    // a recorded step's time as the reverse sweep computes it when it
+    // recomputes the step (the same bits whichever calls the steps came in)
+    const double tn = ctx->recording ? ctx->adj_t0 + double(ctx->adj_steps) * dt : t0 + double(n) * dt;
+    if (ctx->recording && ctx->adj_tail) {
+      const int64_t i = ctx->adj_steps % ctx->adj_every;
+      auto slot = [&](int64_t ii, int k) -> void* {
+        return static_cast<unsigned char*>(ctx->dAdjStore) + size_t(10 * ii + k) * SB;
+      };
+      void* outs[5] = {slot(i, 1), slot(i, 2), slot(i, 3), slot(i, 4), slot((i + 1) % ctx->adj_every, 0)};
+      const void* in = X;
+      for (int s = 0; s < 5; ++s) {
+        const int flags = (s == 0 ? 0 : wdg::kReadRes) | wdg::kWriteU | wdg::kResOut;
+        rc = launch_stage(ctx, in, outs[s], slot(i, s > 0 ? 4 + s : 5), kRkA[s], kRkB[s], dt, tn + kRkC[s] * dt,
+                          flags, 1.0, slot(i, 5 + s));
+        if (rc) return rc;
+        in = outs[s];
+      }
+      X = outs[4];
+    } else {
+      rc = settle();
       if (rc) return rc;
-      ctx->cur = 1 - ctx->cur;
+      for (int s = 0; s < 5; ++s) {
+        const int flags = (s == 0 ? 0 : wdg::kReadRes) | wdg::kWriteU;
+        rc = launch_stage(ctx, ctx->dU[ctx->cur], ctx->dU[1 - ctx->cur], ctx->dRes, kRkA[s], kRkB[s], dt,
+                          tn + kRkC[s] * dt, flags);
+        if (rc) return rc;
+        ctx->cur = 1 - ctx->cur;
+      }
+      X = ctx->dU[ctx->cur];
     }
     if (ctx->nrec > 0) {
-      HIPCHK(wdg::launch_receivers(ctx->bits, ctx->NP(), int(ctx->nrec), ctx->dU[ctx->cur], ctx->dRecBase,
-                                   ctx->dRecNN, ctx->dRecRows, ctx->dRecBuf + ctx->rec_steps * ctx->nrec, ctx->stream));
+      HIPCHK(wdg::launch_receivers(ctx->bits, ctx->NP(), int(ctx->nrec), X, ctx->dRecBase, ctx->dRecNN,
+                                   ctx->dRecRows, ctx->dRecBuf + ctx->rec_steps * ctx->nrec, ctx->stream));
       ctx->rec_steps += 1;
     }
     if (ctx->recording) ctx->adj_steps += 1;
   }
+  rc = settle();
+  if (rc) return rc;
   ctx->time = t0 + double(nsteps) * dt;
   return WDG_OK;
 }
@@ -1667,8 +1711,37 @@ int adjoint_supported(wdg_ctx* ctx) {
 // budget allows, that pass keeps every stage input and stage right-hand side
 // of the segment, otherwise it keeps the step-start states and every step
 // recomputes its stages before its reverse stages.
+// Memory plan of the reverse sweep's store: the stage store (keep: a whole
+// segment's stage inputs and residuals, 10 states per step; else the
+// step-start states and one step's stage data, C + 9), then the forward
+// ping-pong pair and residual (3), then the adjoint state and the ping-pong
+// pair of stage vectors (3).  Keep if it fits 85 % of the free memory (the
+// kept store counts as free) or the set limit.
+struct StorePlan {
+  bool keep = false, reusable = false;
+  size_t nstore = 0, need = 0;
+};
+int store_plan(wdg_ctx* ctx, int64_t C, int64_t nsteps, StorePlan& plan) {
+  const size_t SB = size_t(ctx->nodes()) * 4 * ctx->tsize();
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(hipMemGetInfo(&free_b, &total_b));
+  const size_t small = size_t(ctx->Kw) * (wdg::kGradStride + 2) * sizeof(double) +
+                       (size_t(nsteps) * ctx->nrec + size_t(ctx->nrec) * ctx->NP()) * sizeof(double) +
+                       size_t(ctx->nrec) * sizeof(int64_t);
+  const size_t fixed = small + (size_t(256) << 20);
+  const size_t avail = free_b + ctx->adj_store_bytes;
+  const size_t budget = ctx->adj_mem_limit ? ctx->adj_mem_limit : size_t(0.85 * double(avail));
+  plan.keep = fixed + size_t(10 * C + 6) * SB <= budget;
+  plan.nstore = size_t(plan.keep ? 10 * C : C + 9);
+  plan.need = (plan.nstore + 6) * SB;
+  plan.reusable = ctx->dAdjStore && ctx->adj_store_bytes >= plan.need && ctx->adj_store_bytes <= plan.need + plan.need / 2;
+  return WDG_OK;
+}
+
+// tail: the recorded forward kept its last segment's stage inputs and
+// residuals in the store (valid only if the store is kept as it is)
 int adjoint_backward(wdg_ctx* ctx, const void* cp, int64_t C, int64_t nsteps, double dt, double t0,
-                     const double* weights, double* grad_c, double* grad_rho) {
+                     const double* weights, double* grad_c, double* grad_rho, bool tail) {
   const int N = ctx->N, NP = ctx->NP(), nrec = int(ctx->nrec);
   const int64_t K = ctx->Kw;
   const size_t SB = size_t(ctx->nodes()) * 4 * ctx->tsize();
@@ -1689,25 +1762,22 @@ int adjoint_backward(wdg_ctx* ctx, const void* cp, int64_t C, int64_t nsteps, do
     std::copy(v.begin(), v.end(), rvec.begin() + size_t(r) * NP);
   }
   // memory: keep the whole segment's stage data (10 states per step) if it fits
-  size_t free_b = 0, total_b = 0;
-  HIPCHK(hipMemGetInfo(&free_b, &total_b));
-  const size_t small = size_t(K) * (wdg::kGradStride + 2) * sizeof(double) + (size_t(nsteps) * nrec + rvec.size()) *
-                        sizeof(double) + rbase.size() * sizeof(int64_t);
-  const size_t fixed = small + (size_t(256) << 20);
-  const size_t avail = free_b + ctx->adj_store_bytes;  // the kept buffers count as available
-  const size_t budget = ctx->adj_mem_limit ? ctx->adj_mem_limit : size_t(0.85 * double(avail));
-  const bool keep = fixed + size_t(10 * C + 6) * SB <= budget;
-  // stage store, then the forward ping-pong pair and residual (3), then the
-  // adjoint state and the ping-pong pair of stage vectors (3)
-  const size_t nstore = size_t(keep ? 10 * C : C + 9);
-  const size_t need = (nstore + 6) * SB;
-  if (ctx->adj_store_bytes < need || ctx->adj_store_bytes > need + need / 2) {
+  StorePlan plan;
+  int rc0 = store_plan(ctx, C, nsteps, plan);
+  if (rc0) return rc0;
+  const bool keep = plan.keep;
+  const size_t nstore = plan.nstore;
+  const bool fresh = !plan.reusable;
+  if (fresh) {
     HIPCHK(hipStreamSynchronize(st));
     dfree(ctx->dAdjStore);
     ctx->adj_store_bytes = 0;
-    HIPCHK(hipMalloc(&ctx->dAdjStore, need));
-    ctx->adj_store_bytes = need;
+    HIPCHK(hipMalloc(&ctx->dAdjStore, plan.need));
+    ctx->adj_store_bytes = plan.need;
   }
+  // the recorded forward left the last segment's stage data in the store
+  const bool use_tail = tail && keep && !fresh;
+  ctx->adj_tail = false;  // the sweep overwrites the store
 
   DeviceScratch ds;
   void *pg, *pw, *pv, *pb;
@@ -1732,20 +1802,23 @@ int adjoint_backward(wdg_ctx* ctx, const void* cp, int64_t C, int64_t nsteps, do
   HIPCHK(hipMemsetAsync(gacc, 0, size_t(K) * wdg::kGradStride * sizeof(double), st));
   HIPCHK(hipMemsetAsync(adj, 0, SB * 3, st));
 
-  // store slots: keep: step i of the segment holds its start state (0), stage
-  // inputs 1..4 (1..4) and stage right-hand sides (5..9); otherwise the
-  // step-start states (0..C-1), then one step's stage inputs and right-hand sides
+  // store slots: keep: step i of the segment holds its start state (0; unused
+  // for the first step), stage inputs 1..4 (1..4) and the residuals after
+  // stages 0..4 (5..9); otherwise the step-start states (0..C-1), then one
+  // step's stage inputs and residuals
   auto slot = [&](int64_t i, int k) -> void* {
     if (keep) return at(store, 10 * i + k);
     return k == 0 ? at(store, i) : at(store, C + k - 1);
   };
   // one forward step from X; stage s writes outs[s] (null: no state output)
-  // and, if routs, its right-hand side to routs[s]
+  // and, if routs, keeps its residual in routs[s] (read back by stage s + 1)
+  // instead of updating one residual in place
   auto forward_step = [&](const void* X, void* const* outs, void* const* routs, double tn) -> int {
     const void* in = X;
     for (int s = 0; s < 5; ++s) {
-      const int flags = (s == 0 ? 0 : wdg::kReadRes) | (outs[s] ? wdg::kWriteU : 0) | (routs ? wdg::kWriteR : 0);
-      const int rc = launch_stage(ctx, in, outs[s], at(tmp, 2), kRkA[s], kRkB[s], dt, tn + kRkC[s] * dt, flags, 1.0,
+      const int flags = (s == 0 ? 0 : wdg::kReadRes) | (outs[s] ? wdg::kWriteU : 0) | (routs ? wdg::kResOut : 0);
+      void* res = routs ? (s > 0 ? routs[s - 1] : routs[0]) : at(tmp, 2);
+      const int rc = launch_stage(ctx, in, outs[s], res, kRkA[s], kRkB[s], dt, tn + kRkC[s] * dt, flags, 1.0,
                                   routs ? routs[s] : nullptr, true);
       if (rc) return rc;
       in = outs[s];
@@ -1759,19 +1832,20 @@ int adjoint_backward(wdg_ctx* ctx, const void* cp, int64_t C, int64_t nsteps, do
                             dw + (nsteps - 1) * nrec, kRkB[4], Ua, at(adj, sc), st));
   for (int64_t g = ncp - 1; g >= 0; --g) {
     const int64_t n0 = g * C, n1 = std::min(n0 + C, nsteps);
-    HIPCHK(hipMemcpyAsync(slot(0, 0), at(cp, g), SB, hipMemcpyDeviceToDevice, st));
-    for (int64_t n = n0; n < n1; ++n) {
+    // step-start states: the segment's first is its checkpoint, read in place
+    auto start = [&](int64_t i) -> void* { return i == 0 ? at(cp, g) : slot(i, 0); };
+    for (int64_t n = n0; n < n1 && !(use_tail && g == ncp - 1); ++n) {
       const int64_t i = n - n0;
       void* next = n + 1 < n1 ? slot(i + 1, 0) : nullptr;
       int rc;
       if (keep) {
         void* outs[5] = {slot(i, 1), slot(i, 2), slot(i, 3), slot(i, 4), next};
         void* routs[5] = {slot(i, 5), slot(i, 6), slot(i, 7), slot(i, 8), slot(i, 9)};
-        rc = forward_step(slot(i, 0), outs, routs, t0 + double(n) * dt);
+        rc = forward_step(start(i), outs, routs, t0 + double(n) * dt);
       } else {
         if (!next) break;
         void* outs[5] = {at(tmp, 0), at(tmp, 1), at(tmp, 0), at(tmp, 1), next};
-        rc = forward_step(slot(i, 0), outs, nullptr, t0 + double(n) * dt);
+        rc = forward_step(start(i), outs, nullptr, t0 + double(n) * dt);
       }
       if (rc) return rc;
     }
@@ -1781,26 +1855,27 @@ int adjoint_backward(wdg_ctx* ctx, const void* cp, int64_t C, int64_t nsteps, do
       void* Rs[5];
       if (keep) {
         for (int s = 0; s < 5; ++s) {
-          Us[s] = slot(i, s);
+          Us[s] = s ? slot(i, s) : start(i);
           Rs[s] = slot(i, 5 + s);
         }
       } else {
         // the stage data of this step go to the shared slots 1..9
         void* outs[5] = {slot(0, 1), slot(0, 2), slot(0, 3), slot(0, 4), nullptr};
         void* routs[5] = {slot(0, 5), slot(0, 6), slot(0, 7), slot(0, 8), slot(0, 9)};
-        const int rc = forward_step(slot(i, 0), outs, routs, t0 + double(n) * dt);
+        const int rc = forward_step(start(i), outs, routs, t0 + double(n) * dt);
         if (rc) return rc;
-        Us[0] = slot(i, 0);
+        Us[0] = start(i);
         for (int s = 1; s < 5; ++s) Us[s] = outs[s - 1];
         for (int s = 0; s < 5; ++s) Rs[s] = routs[s];
       }
       for (int s = 4; s >= 0; --s) {
         void* sig = at(adj, sc);
         // U~ += dt A sig;  sig <- a_s sig + b_{s-1} U~  (b of the previous step's last stage at s = 0);
-        // the same kernel accumulates the stage's gradient terms from Us[s], Rs[s]
+        // the same kernel accumulates the stage's gradient terms from Us[s] and the
+        // forward residual Rs[s] (mass terms weighted by b_s)
         const int rc = launch_stage(ctx, sig, at(adj, 3 - sc), Ua, 1.0, s > 0 ? kRkB[s - 1] : kRkB[4], dt, 0.0,
                                     wdg::kReadRes | wdg::kWriteU | wdg::kGrad, kRkA[s], nullptr, false, Us[s], Rs[s],
-                                    gacc);
+                                    gacc, kRkB[s]);
         if (rc) return rc;
         sc = 3 - sc;
       }
@@ -1861,7 +1936,7 @@ int wdg_adjoint_gradient(wdg_ctx* ctx, int64_t nsteps, double dt, const double* 
     }
     x = outs[4];
   }
-  return adjoint_backward(ctx, cp, C, nsteps, dt, t0, weights, grad_c, grad_rho);
+  return adjoint_backward(ctx, cp, C, nsteps, dt, t0, weights, grad_c, grad_rho, false);
 }
 
 int wdg_adjoint_record(wdg_ctx* ctx, int64_t checkpoint_every, int64_t max_steps) {
@@ -1886,6 +1961,13 @@ int wdg_adjoint_record(wdg_ctx* ctx, int64_t checkpoint_every, int64_t max_steps
   ctx->adj_steps = 0;
   ctx->adj_t0 = ctx->time;
   ctx->adj_dt = 0.0;
+  // with the reverse sweep's store already kept in the whole-segment layout
+  // (an earlier gradient call), the forward writes into it what the sweep
+  // would recompute for the last segment
+  StorePlan plan;
+  rc = store_plan(ctx, checkpoint_every, max_steps, plan);
+  if (rc) return rc;
+  ctx->adj_tail = plan.keep && plan.reusable;
   ctx->recording = true;
   return WDG_OK;
 }
@@ -1902,12 +1984,13 @@ int wdg_adjoint_gradient_recorded(wdg_ctx* ctx, const double* weights, double* g
   HIPCHK(hipSetDevice(ctx->device));
   TimingOff off(ctx);
   return adjoint_backward(ctx, ctx->dAdjCp, ctx->adj_every, ctx->adj_steps, ctx->adj_dt, ctx->adj_t0, weights,
-                          grad_c, grad_rho);
+                          grad_c, grad_rho, ctx->adj_tail);
 }
 
 int wdg_set_adjoint_memory_limit(wdg_ctx* ctx, int64_t bytes) {
   if (!ctx || bytes < 0) return WDG_ERR_ARG;
   ctx->adj_mem_limit = size_t(bytes);
+  ctx->adj_tail = false;
   if (ctx->dAdjStore) {
     HIPCHK(hipSetDevice(ctx->device));
     HIPCHK(hipStreamSynchronize(ctx->stream));

@@ -66,7 +66,7 @@ enum StageFlags : int {
   kDirichlet = 4,  // else rigid wall
   kCentral = 8,    // else upwind flux
   kLumped = 16,    // Gauss-Lobatto mass in t: (M^1D)^-1 e_{0,N} becomes e_{0,N} / w_{0,N}
-  kWriteR = 32,    // also store the stage right-hand side (sources included) to rout (wedges)
+  kResOut = 32,    // res' goes to rout instead of back into res, which is then only read (wedges)
   kGamma = 64,     // U_out = g U_in + b res' (else g = 1)
   kLayerMarch = 128,  // wedge meshes: vertical neighbours inside a chunk from LDS
   kGrad = 256,        // wedge meshes, adjoint sweep: also accumulate the stage's gradient terms
@@ -100,10 +100,12 @@ struct StageLaunch {
   int nsrc;
   // res' = a res + dt rhs;  U_out = g U_in + b res'  (the forward stages use g = 1)
   double a, b, dt, g;
-  void* rout;  // kWriteR: the right-hand side, same layout as res
-  // kGrad: forward stage input and its right-hand side, gradient accumulators
+  void* rout;  // kResOut: the updated residual, same layout as res
+  // kGrad: the forward stage input U_s and the forward residual res_s after that
+  // stage, the forward stage's coefficient b_s, gradient accumulators
   const void* gUs;
   const void* gRs;
+  double gb;
   void* gacc;  // kGrad: gradient accumulators (kGradRecord values of the state precision per wedge)
   int64_t Kw, Kt;
   int flags;
@@ -170,10 +172,13 @@ hipError_t launch_batch_advance(int64_t* counter, hipStream_t st);
 
 // Adjoint gradient (wedge meshes).  Per reverse stage the stage kernel (kGrad)
 // accumulates into gacc (per wedge: kGradStride values of the state precision;
-// FP32 also their kGradStride Kahan compensations) dt times the mass terms
-// sig^T M R of the pressure and of the velocity and the face integrals
-// 1/2 int sig_p [p], 1/2 int sig_un [u_n] of the forward stage input Us.
-constexpr int kGradStride = 12;
+// FP32 also their kGradStride Kahan compensations): the mass terms' dJ/dc and
+// dJ/drho, and per face (bottom, top, quadrilaterals 0..2) the own side's
+// share of dJ/dZ, dt (dtau_p/dZ 1/2 int sig_p [p] + dtau_u/dZ 1/2 int sig_un
+// [u_n]) of the forward stage input Us (the penalties' derivatives are fixed
+// during the sweep).  kGradTerms: the partial sums behind them.
+constexpr int kGradStride = 7;
+constexpr int kGradTerms = 12;
 template <typename T>
 constexpr int kGradRecord = sizeof(T) == 4 ? 2 * kGradStride : kGradStride;  // values per wedge
 // Gradient with respect to c and rho from the accumulated terms and the penalty

@@ -313,7 +313,7 @@ __device__ __forceinline__ void wedge_node_chunk(const StageLaunch& A, int chunk
     }
   }
   // previous residual of the node's line, read while the lifts are applied
-  const bool rd = (A.flags & kReadRes) != 0, wu = (A.flags & kWriteU) != 0, wr = (A.flags & kWriteR) != 0;
+  const bool rd = (A.flags & kReadRes) != 0, wu = (A.flags & kWriteU) != 0;
   V4<T>* const res_el = static_cast<V4<T>*>(A.res) + e * NP;
   V4<T> rprev[Nq];
 #pragma unroll
@@ -398,13 +398,12 @@ __device__ __forceinline__ void wedge_node_chunk(const StageLaunch& A, int chunk
   }
   const T ca = T(A.a), cb = T(A.b), dt = T(A.dt), cg = (A.flags & kGamma) ? T(A.g) : T(1);
   V4<T>* const out_el = static_cast<V4<T>*>(A.Uout) + e * NP;
-  V4<T>* const rout_el = static_cast<V4<T>*>(A.rout) + e * NP;
+  V4<T>* const rout_el = ((A.flags & kResOut) ? static_cast<V4<T>*>(A.rout) : static_cast<V4<T>*>(A.res)) + e * NP;
 #pragma unroll
   for (int j = 0; j < Nq; ++j) {
     const V4<T> q = rprev[j];
     const V4<T> r{ca * q.p + dt * Rp[j], ca * q.uz + dt * Rz[j], ca * q.ux + dt * Rx[j], ca * q.uy + dt * Ry[j]};
-    res_el[j * NT + i] = r;
-    if (wr) rout_el[j * NT + i] = V4<T>{Rp[j], Rz[j], Rx[j], Ry[j]};
+    rout_el[j * NT + i] = r;
     if (wu) {
       const V4<T> u = el[j * NT + i];
       out_el[j * NT + i] =

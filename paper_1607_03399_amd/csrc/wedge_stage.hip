@@ -96,21 +96,32 @@ struct LevelMask {
 };
 
 
-// Adds one stage's gradient terms x[kGradStride] of wedge e to its
-// accumulators across the reverse sweep: FP64 in place; FP32 as Kahan
+// A wedge's accumulators across the reverse sweep: FP64 sums; FP32 Kahan
 // (compensated) sums, the record holding the sums, then their compensations.
+// Read early (grad_record_load), then one stage's terms x[kGradStride] added
+// and written back (grad_record_add).
 template <typename T>
-__device__ __forceinline__ void grad_accumulate(void* gacc, int64_t e, const T* x) {
+struct GradRecord {
+  T v[kGradRecord<T>];
+};
+template <typename T>
+__device__ __forceinline__ void grad_record_load(const void* gacc, int64_t e, GradRecord<T>& r) {
+  const T* ga = static_cast<const T*>(gacc) + e * kGradRecord<T>;
+#pragma unroll
+  for (int k = 0; k < kGradRecord<T>; ++k) r.v[k] = ga[k];
+}
+template <typename T>
+__device__ __forceinline__ void grad_record_add(void* gacc, int64_t e, const GradRecord<T>& r, const T* x) {
   T* ga = static_cast<T*>(gacc) + e * kGradRecord<T>;
   if constexpr (sizeof(T) == 8) {
 #pragma unroll
-    for (int k = 0; k < kGradStride; ++k) ga[k] += x[k];
+    for (int k = 0; k < kGradStride; ++k) ga[k] = r.v[k] + x[k];
   } else {
 #pragma unroll
     for (int k = 0; k < kGradStride; ++k) {
-      const T y = x[k] - ga[kGradStride + k];
-      const T t = ga[k] + y;
-      ga[kGradStride + k] = (t - ga[k]) - y;
+      const T y = x[k] - r.v[kGradStride + k];
+      const T t = r.v[k] + y;
+      ga[kGradStride + k] = (t - r.v[k]) - y;
       ga[k] = t;
     }
   }
@@ -118,13 +129,16 @@ __device__ __forceinline__ void grad_accumulate(void* gacc, int64_t e, const T* 
 
 // Gradient terms of one reverse stage of the adjoint sweep (MODE 4), run by
 // the stage kernel after its update.  The stage input (the adjoint stage
-// vector sig) is still staged in sU; the forward stage input Us and its
-// right-hand side Rs are staged into the freed LDS regions.  Per wedge it
-// accumulates dt times the mass terms sig_p^T M R_p, sig_u^T M R_u (as
-// dJ/dc = 2/(c kappa) m_p, dJ/drho = m_p/(rho kappa) + m_u) and the face
-// integrals 1/2 int sig_p [p], 1/2 int sig_un [u_n] of Us per face
-// (gacc slots 2..6 and 7..11), which the combine kernel turns into the
-// penalty derivatives.  M^k = (sum_v w_v M_v) (x) M^1D and the face masses
+// vector sig) is still staged in sU and the incoming adjoint state U~ in the
+// second region; the forward residual res_s after stage s, then the forward
+// stage input Us, are staged into them as they free up.  Per wedge it
+// accumulates the mass terms b_s U~_p^T M res_p, b_s U~_u^T M res_u (their sum
+// over a step's stages is that of dt sig_p^T M R_p, dt sig_u^T M R_u with R_s
+// the stage's right-hand side; as dJ/dc = 2/(c kappa) m_p, dJ/drho =
+// m_p/(rho kappa) + m_u) and per face dt times the face integrals 1/2 int
+// sig_p [p], 1/2 int sig_un [u_n] of Us weighted by the penalties'
+// derivatives (gacc slots 2..6), which the combine kernel adds up over both
+// sides of every face.  M^k = (sum_v w_v M_v) (x) M^1D and the face masses
 // are literals (reference triangle, 1D, edge masses).
 // FP32 up to N = 3 the gradient epilogue takes the element's connectivity
 // and geometry from the stage's registers and issues its gathers first and its
@@ -144,6 +158,39 @@ struct EpiGeo {
   T qg[3][4];
 };
 
+// the epilogue's global loads: the quadrilateral-face neighbour nodes of Us
+// on this level, the chunk's Us (a) and forward residual (b), coalesced
+template <int N, typename T>
+struct EpiLoads {
+  static constexpr int SU = (Cfg<N, T>::EPB * Cfg<N, T>::NP + 63) / 64;
+  V4<T> gq[3][Cfg<N, T>::Nq];
+  V4<T> a[SU], b[SU];
+};
+template <int N, typename T>
+__device__ __forceinline__ void grad_load_q(const StageLaunch& A, int j, int64_t e, const int* cv, EpiLoads<N, T>& L) {
+  constexpr int NT = Cfg<N, T>::NT, Nq = Cfg<N, T>::Nq, NP = Cfg<N, T>::NP;
+  const V4<T>* __restrict__ Us = static_cast<const V4<T>*>(A.gUs);
+  const int code = cv[5];
+#pragma unroll
+  for (int ed = 0; ed < 3; ++ed) {
+    const int nbr = cv[2 + ed];
+    const int ned = (code >> (8 + 2 * ed)) & 3;
+    const V4<T>* nb_el = Us + (nbr >= 0 ? int64_t(nbr) : e) * NP + j * NT;
+#pragma unroll
+    for (int q = 0; q < Nq; ++q) {
+      const int ni = ned == 0 ? edge_node(N, 0, N - q) : (ned == 1 ? edge_node(N, 1, N - q) : edge_node(N, 2, N - q));
+      L.gq[ed][q] = nb_el[ni];
+    }
+  }
+}
+template <int N, typename T>
+__device__ __forceinline__ void grad_load_chunk(const void* src, int64_t e0, int nE, int tid, V4<T>* out) {
+  constexpr int NP = Cfg<N, T>::NP, V4B = 4 * int(sizeof(T));
+  const auto br = chunk_rsrc(static_cast<const V4<T>*>(src) + e0 * NP, int64_t(nE) * NP * V4B);
+#pragma unroll
+  for (int k = 0; k < EpiLoads<N, T>::SU; ++k) out[k] = bload<T>(br, tid + 64 * k);
+}
+
 template <int N, typename T>
 __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, int nE, int tid, int le, int j,
                                               bool active, int64_t e, V4<T>* sU, V4<T>* sX, const int* cn,
@@ -151,9 +198,8 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
   using C = Cfg<N, T>;
   using RT = gen::RefTables<N>;
   constexpr int NT = C::NT, Nq = C::Nq, NP = C::NP, NPP = C::NPP, EPB = C::EPB;
-  constexpr int V4B = 4 * int(sizeof(T));
-  constexpr int SU = (EPB * NP + 63) / 64;
-  constexpr int GS = kGradStride + 1;  // partial sums per lane (odd: fewer bank conflicts)
+  constexpr int SU = EpiLoads<N, T>::SU;
+  constexpr int GS = kGradTerms + 1;  // partial sums per lane (odd: fewer bank conflicts)
   static_assert(EPB * 3 * Nq * Nq * 2 <= EPB * NPP * 4, "jump scratch fits the state region");
   static_assert(EPB * Nq * GS <= EPB * C::XPE * 4, "partial sums fit the second region");
   const bool lane_ok = le < EPB;
@@ -167,138 +213,40 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
 #pragma unroll
   for (int k = 0; k < 6; ++k) cv[k] = early ? cn[k] : gcn[k];
   const int code = cv[5];
-  // neighbour nodes of the forward stage input on the quadrilateral faces (this
-  // level)
-  V4<T> gq[3][Nq];
-#pragma unroll
-  for (int ed = 0; ed < 3; ++ed) {
-    const int nbr = cv[2 + ed];
-    const int ned = (code >> (8 + 2 * ed)) & 3;
-    const V4<T>* nb_el = Us + (nbr >= 0 ? int64_t(nbr) : e) * NP + j * NT;
-#pragma unroll
-    for (int q = 0; q < Nq; ++q) {
-      const int ni = ned == 0 ? edge_node(N, 0, N - q) : (ned == 1 ? edge_node(N, 1, N - q) : edge_node(N, 2, N - q));
-      gq[ed][q] = nb_el[ni];
-    }
+  // the quadrilateral-face gathers first; FP32 up to N = 3 the chunk loads
+  // too, before the first barrier (beyond, holding them across it spills).
+  // Issuing them before the update's stores instead, so that waiting for them
+  // would not wait for the stores, measured slower (522 against 492 us per
+  // stage on 524 288 wedges)
+  EpiLoads<N, T> L;
+  grad_load_q<N, T>(A, j, e, cv, L);
+  if constexpr (early) {
+    grad_load_chunk<N, T>(A.gUs, e0, nE, tid, L.a);
+    grad_load_chunk<N, T>(A.gRs, e0, nE, tid, L.b);
   }
-
-  // the chunk's forward stage input and right-hand side, coalesced; they go
-  // to LDS once the barrier below has freed it.  Issued before that barrier
-  // where the registers allow it (FP32 up to N = 3; beyond, holding them
-  // across the barrier spills)
-  V4<T> a[SU], b[SU];
-  const int64_t bytes = int64_t(nE) * NP * V4B;
-  const auto bu = chunk_rsrc(Us + e0 * NP, bytes);
-  const auto br = chunk_rsrc(static_cast<const V4<T>*>(A.gRs) + e0 * NP, bytes);
-  auto load_ab = [&]() {
-#pragma unroll
-    for (int k = 0; k < SU; ++k) {
-      a[k] = bload<T>(bu, tid + 64 * k);
-      b[k] = bload<T>(br, tid + 64 * k);
-    }
+  auto slot = [&](int k) {
+    const int idx = tid + 64 * k;
+    return idx < EPB * NP ? idx + (idx / NP) * (NPP - NP) : EPB * NPP;
   };
-  if constexpr (early) load_ab();
   V4<T> sg[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) sg[i] = sU[lb + i];
   __syncthreads();  // the update and the reads of sig are done
-  if constexpr (!early) load_ab();
-  {
+  if constexpr (!early) grad_load_chunk<N, T>(A.gRs, e0, nE, tid, L.b);
 #pragma unroll
-    for (int k = 0; k < SU; ++k) {
-      const int idx = tid + 64 * k;
-      const int l = idx < EPB * NP ? idx + (idx / NP) * (NPP - NP) : EPB * NPP;
-      sX[l] = a[k];  // Us
-      sU[l] = b[k];  // Rs
-    }
-  }
+  for (int k = 0; k < SU; ++k) sU[slot(k)] = L.b[k];  // res_s over sig
   __syncthreads();
-  T part[kGradStride];
+  T part[kGradTerms];
 #pragma unroll
-  for (int k = 0; k < kGradStride; ++k) part[k] = T(0);
-  const V4<T>* sUs = sX;
-  const V4<T>* sRs = sU;
+  for (int k = 0; k < kGradTerms; ++k) part[k] = T(0);
 
-  // triangular faces: lane 0 the bottom, lane N the top (own level)
-  if (lane_ok && (j == 0 || j == N)) {
-    const int face = j == 0 ? 0 : 1;
-    const int nbr = face ? cv[1] : cv[0];
-    const int pc = (code >> (3 * face)) & 7;
-    const int nlev = ((code >> (6 + face)) & 1) ? N : 0;
-    const T Jf = early ? eg.tJf : gm[12 + 4 * face], nx = early ? eg.tnx : gm[13 + 4 * face];
-    const T ny = early ? eg.tny : gm[14 + 4 * face], nz = early ? eg.tnz : gm[15 + 4 * face];
-    T jp[NT], jn[NT];
-    // the neighbour's face nodes, all issued before any is used (a boundary
-    // face reads the own element, a valid address, and uses the mirror state)
-    const bool inner = nbr >= 0;
-    const int64_t src = inner ? int64_t(nbr) : e;
-    V4<T> vn[NT];
-#pragma unroll
-    for (int i = 0; i < NT; ++i) vn[i] = Us[src * NP + nlev * NT + face_perm<N>(pc, i)];
-#pragma unroll
-    for (int i = 0; i < NT; ++i) {
-      const V4<T> own = sUs[lb + i];
-      const T pm = own.p, unm = nx * own.ux + ny * own.uy + nz * own.uz;
-      const T pp = inner ? vn[i].p : bsign * pm;  // else the mirror state
-      const T unp = inner ? nx * vn[i].ux + ny * vn[i].uy + nz * vn[i].uz : -bsign * unm;
-      jp[i] = pp - pm;
-      jn[i] = unp - unm;
-    }
-    T sp = 0, sn = 0;
-#pragma unroll
-    for (int i = 0; i < NT; ++i) {
-      T mp = 0, mn = 0;
-#pragma unroll
-      for (int k = 0; k < NT; ++k) {
-        constexpr_or_skip(RT::Mtri[i * NT + k], mp, jp[k]);
-        constexpr_or_skip(RT::Mtri[i * NT + k], mn, jn[k]);
-      }
-      sp += sg[i].p * mp;
-      sn += (nx * sg[i].ux + ny * sg[i].uy + nz * sg[i].uz) * mn;
-    }
-    part[2 + face] = T(0.5) * Jf * sp;
-    part[7 + face] = T(0.5) * Jf * sn;
-  }
-
-  // quadrilateral faces: jumps of this level (to LDS below); the adjoint
-  // trace times the edge mass stays in registers
-  T jq[3][Nq][2], ap[3][Nq], an[3][Nq];
-#pragma unroll
-  for (int ed = 0; ed < 3; ++ed) {
-    const int nbr = cv[2 + ed];
-    const T Ja = early ? eg.qg[ed][0] : gm[20 + 4 * ed], Jb = early ? eg.qg[ed][1] : gm[21 + 4 * ed];
-    const T nx = early ? eg.qg[ed][2] : gm[22 + 4 * ed], ny = early ? eg.qg[ed][3] : gm[23 + 4 * ed];
-    T sp[Nq], sn[Nq];
-#pragma unroll
-    for (int q = 0; q < Nq; ++q) {
-      const int i = edge_node(N, ed, q);
-      const V4<T> own = sUs[lb + i];
-      const T pm = own.p, unm = nx * own.ux + ny * own.uy;
-      T pp = bsign * pm, unp = -bsign * unm;
-      if (nbr >= 0) {
-        pp = gq[ed][q].p;
-        unp = nx * gq[ed][q].ux + ny * gq[ed][q].uy;
-      }
-      jq[ed][q][0] = pp - pm;
-      jq[ed][q][1] = unp - unm;
-      sp[q] = sg[i].p;
-      sn[q] = nx * sg[i].ux + ny * sg[i].uy;
-    }
-#pragma unroll
-    for (int qq = 0; qq < Nq; ++qq) {
-      T vpa = 0, vna = 0, vpb = 0, vnb = 0;
-#pragma unroll
-      for (int q = 0; q < Nq; ++q) {
-        constexpr_or_skip(RT::Ma[q * Nq + qq], vpa, sp[q]);
-        constexpr_or_skip(RT::Ma[q * Nq + qq], vna, sn[q]);
-        constexpr_or_skip(RT::Mb[q * Nq + qq], vpb, sp[q]);
-        constexpr_or_skip(RT::Mb[q * Nq + qq], vnb, sn[q]);
-      }
-      ap[ed][qq] = Ja * vpa + Jb * vpb;
-      an[ed][qq] = Ja * vna + Jb * vnb;
-    }
-  }
-
+  // Mass terms.  The stage's right-hand side R_s enters as sig_s^T M R_s; with
+  // dt R_s = res_s - a_s res_{s-1} (a_1 = 0) the sum over a step's stages equals
+  // the sum of (sig_s - a_{s+1} sig_{s+1})^T M res_s / dt, and the reverse sweep
+  // has sig_s - a_{s+1} sig_{s+1} = b_s U~, U~ the adjoint state this stage
+  // reads (left in the second LDS region by the update).  So the forward
+  // keeps its residuals instead of writing every right-hand side.
+  // On this level: U~^T (M^{tri,k} (x) M^1D) res_s, M^{tri,k} = sum_v w_v M_v.
   T m1[Nq];
   {
     const LevelMask<Nq, T> lm(j);
@@ -306,7 +254,8 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
     for (int m = 0; m < Nq; ++m) m1[m] = lm.pick(RT::M1, Nq, m);
   }
   if (lane_ok) {
-    // mass terms on this level: sig^T (M^{tri,k} (x) M^1D) R, M^{tri,k} = sum_v w_v M_v
+    const V4<T>* sRs = sU;
+    const V4<T>* sUa = sX;
     const T w0 = early ? eg.w0 : gm[37], w1 = early ? eg.w1 : gm[38], w2 = early ? eg.w2 : gm[39];
     T y[4][NT];
 #pragma unroll
@@ -340,13 +289,111 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
         z2 += m * y[2][k];
         z3 += m * y[3][k];
       }
-      mp += sg[i].p * z0;
-      mu += sg[i].ux * z1 + sg[i].uy * z2 + sg[i].uz * z3;
+      const V4<T> ua = sUa[lb + i];
+      mp += ua.p * z0;
+      mu += ua.ux * z1 + ua.uy * z2 + ua.uz * z3;
     }
     part[0] = mp;
     part[1] = mu;
   }
-  __syncthreads();  // Us and Rs in LDS are consumed
+  if constexpr (!early) grad_load_chunk<N, T>(A.gUs, e0, nE, tid, L.a);
+  __syncthreads();  // U~ and res_s in LDS are consumed
+#pragma unroll
+  for (int k = 0; k < SU; ++k) sX[slot(k)] = L.a[k];  // Us
+  __syncthreads();
+  const V4<T>* sUs = sX;
+
+  // triangular faces: lane 0 the bottom, lane N the top (own level).  The
+  // neighbour's face nodes are gathered here, unconditionally (the other
+  // lanes, and boundary faces, read the own element: a valid address), and
+  // used after the quadrilateral faces, which need no memory
+  const bool tri = lane_ok && (j == 0 || j == N);
+  const int face = j == 0 ? 0 : 1;
+  const int tnbr = face ? cv[1] : cv[0];
+  const bool inner = tnbr >= 0;
+  const int pc = (code >> (3 * face)) & 7;
+  const int nlev = ((code >> (6 + face)) & 1) ? N : 0;
+  const int64_t src = (tri && inner) ? int64_t(tnbr) : e;
+  V4<T> vn[NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) vn[i] = Us[src * NP + nlev * NT + face_perm<N>(pc, i)];
+
+  // quadrilateral faces: jumps of this level (to LDS below); the adjoint
+  // trace times the edge mass stays in registers
+  T jq[3][Nq][2], ap[3][Nq], an[3][Nq];
+#pragma unroll
+  for (int ed = 0; ed < 3; ++ed) {
+    const int nbr = cv[2 + ed];
+    const T Ja = early ? eg.qg[ed][0] : gm[20 + 4 * ed], Jb = early ? eg.qg[ed][1] : gm[21 + 4 * ed];
+    const T nx = early ? eg.qg[ed][2] : gm[22 + 4 * ed], ny = early ? eg.qg[ed][3] : gm[23 + 4 * ed];
+    T sp[Nq], sn[Nq];
+#pragma unroll
+    for (int q = 0; q < Nq; ++q) {
+      const int i = edge_node(N, ed, q);
+      const V4<T> own = sUs[lb + i];
+      const T pm = own.p, unm = nx * own.ux + ny * own.uy;
+      T pp = bsign * pm, unp = -bsign * unm;
+      if (nbr >= 0) {
+        pp = L.gq[ed][q].p;
+        unp = nx * L.gq[ed][q].ux + ny * L.gq[ed][q].uy;
+      }
+      jq[ed][q][0] = pp - pm;
+      jq[ed][q][1] = unp - unm;
+      sp[q] = sg[i].p;
+      sn[q] = nx * sg[i].ux + ny * sg[i].uy;
+    }
+#pragma unroll
+    for (int qq = 0; qq < Nq; ++qq) {
+      T vpa = 0, vna = 0, vpb = 0, vnb = 0;
+#pragma unroll
+      for (int q = 0; q < Nq; ++q) {
+        constexpr_or_skip(RT::Ma[q * Nq + qq], vpa, sp[q]);
+        constexpr_or_skip(RT::Ma[q * Nq + qq], vna, sn[q]);
+        constexpr_or_skip(RT::Mb[q * Nq + qq], vpb, sp[q]);
+        constexpr_or_skip(RT::Mb[q * Nq + qq], vnb, sn[q]);
+      }
+      ap[ed][qq] = Ja * vpa + Jb * vpb;
+      an[ed][qq] = Ja * vna + Jb * vnb;
+    }
+  }
+
+  if (tri) {
+    const T Jf = early ? eg.tJf : gm[12 + 4 * face], nx = early ? eg.tnx : gm[13 + 4 * face];
+    const T ny = early ? eg.tny : gm[14 + 4 * face], nz = early ? eg.tnz : gm[15 + 4 * face];
+    T jp[NT], jn[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const V4<T> own = sUs[lb + i];
+      const T pm = own.p, unm = nx * own.ux + ny * own.uy + nz * own.uz;
+      const T pp = inner ? vn[i].p : bsign * pm;  // else the mirror state
+      const T unp = inner ? nx * vn[i].ux + ny * vn[i].uy + nz * vn[i].uz : -bsign * unm;
+      jp[i] = pp - pm;
+      jn[i] = unp - unm;
+    }
+    T sp = 0, sn = 0;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      T mp = 0, mn = 0;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        constexpr_or_skip(RT::Mtri[i * NT + k], mp, jp[k]);
+        constexpr_or_skip(RT::Mtri[i * NT + k], mn, jn[k]);
+      }
+      sp += sg[i].p * mp;
+      sn += (nx * sg[i].ux + ny * sg[i].uy + nz * sg[i].uz) * mn;
+    }
+    part[2 + face] = T(0.5) * Jf * sp;
+    part[7 + face] = T(0.5) * Jf * sn;
+  }
+
+  // the wedge's accumulator record, read before the level coupling below
+  // (idle lanes read the wedge they shadow)
+  GradRecord<T> rec;
+  grad_record_load<T>(A.gacc, e, rec);
+  T zsum[5];  // Z- + Z+ per face
+#pragma unroll
+  for (int f = 0; f < 5; ++f) zsum[f] = gm[32 + f];
+  __syncthreads();  // Us in LDS is consumed
   T* const sJ = reinterpret_cast<T*>(sU);  // quadrilateral-face jumps [wedge][edge][level][node][p, u_n]
   if (lane_ok) {
 #pragma unroll
@@ -381,13 +428,13 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
       part[9 + ed] = T(0.5) * sn;
     }
 #pragma unroll
-    for (int k = 0; k < kGradStride; ++k) sPart[(le * Nq + j) * GS + k] = part[k];
+    for (int k = 0; k < kGradTerms; ++k) sPart[(le * Nq + j) * GS + k] = part[k];
   }
   __syncthreads();
   if (active && j == 0) {
-    T tot[kGradStride];
+    T tot[kGradTerms];
 #pragma unroll
-    for (int k = 0; k < kGradStride; ++k) {
+    for (int k = 0; k < kGradTerms; ++k) {
       T s = 0;
 #pragma unroll
       for (int l = 0; l < Nq; ++l) s += sPart[(le * Nq + l) * GS + k];
@@ -397,11 +444,18 @@ __device__ __forceinline__ void grad_epilogue(const StageLaunch& A, int64_t e0, 
     const T c = std::sqrt(kap * irho);
     const T dt = T(A.dt);
     T x[kGradStride];
-    x[0] = dt * T(2) / (c * kap) * tot[0];
-    x[1] = dt * (tot[0] * irho / kap + tot[1]);
+    const T gb = T(A.gb);  // dt times the mass terms' factor b_s / dt
+    x[0] = gb * T(2) / (c * kap) * tot[0];
+    x[1] = gb * (tot[0] * irho / kap + tot[1]);
+    // per face dtau_p/dZ = -tau_p^2 / 2, dtau_u/dZ = 1/2 (upwind, tau_p = 2 / (Z- + Z+);
+    // the central flux has no penalties)
+    const bool upwind = !(A.flags & kCentral);
 #pragma unroll
-    for (int k = 2; k < kGradStride; ++k) x[k] = dt * tot[k];
-    grad_accumulate<T>(A.gacc, e, x);
+    for (int f = 0; f < 5; ++f) {
+      const T tp = T(2) / zsum[f];
+      x[2 + f] = upwind ? dt * (-T(0.5) * tp * tp * tot[2 + f] - T(0.5) * tot[7 + f]) : T(0);
+    }
+    grad_record_add<T>(A.gacc, e, rec, x);
   }
 }
 
@@ -714,7 +768,8 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int64_t 
   // loads return zeros without touching memory and need no branch.
   V4<T>* const res_chunk = static_cast<V4<T>*>(A.res) + e0 * NP;
   const auto bres_in = chunk_rsrc(res_chunk, rd ? int64_t(nE) * NP * V4B : 0);
-  const auto bres = chunk_rsrc(res_chunk, int64_t(nE) * NP * V4B);
+  const auto bres = chunk_rsrc((A.flags & kResOut) ? static_cast<V4<T>*>(A.rout) + e0 * NP : res_chunk,
+                               int64_t(nE) * NP * V4B);
   V4<T> rprev[C::PREFETCH ? C::UPD : 1];
   if constexpr (C::PREFETCH) {
 #pragma unroll
@@ -953,9 +1008,7 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int64_t 
 
   // low-storage Runge-Kutta update, coalesced over the chunk
   const T ca = T(A.a), cb = T(A.b), dt = T(A.dt), cg = T(A.g);
-  const bool wr = (A.flags & kWriteR) != 0;
   const auto bout = chunk_rsrc(static_cast<V4<T>*>(A.Uout) + e0 * NP, int64_t(nE) * NP * V4B);
-  const auto brout = chunk_rsrc(static_cast<V4<T>*>(A.rout) + e0 * NP, wr ? int64_t(nE) * NP * V4B : 0);
   // U' = g U + b res' with g = 1 except in the adjoint sweep: two copies of the loop
   auto update = [&](auto with_g) {
     constexpr bool G = decltype(with_g)::value;
@@ -971,7 +1024,10 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int64_t 
         q = bload<T>(bres_in, idx);
       const V4<T> r{ca * q.p + dt * R.p, ca * q.uz + dt * R.uz, ca * q.ux + dt * R.ux, ca * q.uy + dt * R.uy};
       bstore<T>(bres, idx, r);
-      if (wr) bstore<T>(brout, idx, R);
+      // the adjoint sweep's mass terms take the incoming adjoint state from
+      // here (each slot is read above by the lane that writes it; the lanes
+      // past the chunk write the spare slot)
+      if constexpr (MODE == 4) sR[idx < nE * NP ? l : EPB * C::XPE] = q;
       if (wu) {
         V4<T> u = sU[l];
         if constexpr (G) u = V4<T>{cg * u.p, cg * u.uz, cg * u.ux, cg * u.uy};

@@ -128,6 +128,44 @@ def test_recorded_forward_and_memory_modes_give_the_same_gradient():
     s.close()
 
 
+@pytest.mark.parametrize("bits", [64, 32])
+@pytest.mark.parametrize("nsteps,every,split", [(11, 4, (6, 5)), (12, 4, (5, 7)), (5, 1, (2, 3)), (11, 13, (11,))])
+def test_recorded_forward_keeps_the_last_segment(bits, nsteps, every, split):
+    """With the reverse sweep's store kept from an earlier gradient call, the
+    recorded forward writes its segments' stage data into it and the sweep
+    skips recomputing the last segment: the final state, the receiver traces
+    and the gradient are bitwise those of the plain forward and of the
+    self-contained call; a second gradient of the same recording, and one
+    after further recorded steps, recompute everything and agree too."""
+    m, N, U0, src, rec = _problem()
+    s = _solver(m, N, bits, "rigid", "upwind", src, rec)
+    s.set_fields(U0)
+    dt = s.stable_dt(0.5)
+    rng = np.random.default_rng(17)
+    w = rng.standard_normal((nsteps, len(rec)))
+    w2 = rng.standard_normal((nsteps + 3, len(rec)))
+    _say(f"bits={bits} nsteps={nsteps} every={every} split={split}")
+    ref = s.adjoint_gradient(nsteps, dt, w, checkpoint_every=every)  # keeps the store
+    ref2 = s.adjoint_gradient(nsteps + 3, dt, w2, checkpoint_every=every)
+    s.step(nsteps, dt)
+    U_plain, tr_plain = s.get_fields(), s.read_receivers()
+    s.set_fields(U0)
+    s.time = 0.0
+    s.adjoint_record(every, nsteps + 3)
+    for k in split:
+        s.step(k, dt)
+    assert s.recorded_steps() == nsteps
+    assert np.array_equal(s.get_fields(), U_plain)
+    assert np.array_equal(s.read_receivers(), tr_plain)
+    for _ in range(2):
+        g = s.adjoint_gradient_recorded(w)
+        assert np.array_equal(g[0], ref[0]) and np.array_equal(g[1], ref[1])
+    s.step(3, dt)
+    g = s.adjoint_gradient_recorded(w2)
+    assert np.array_equal(g[0], ref2[0]) and np.array_equal(g[1], ref2[1])
+    s.close()
+
+
 def test_gradient_matches_central_differences():
     """Device-only check on a larger mesh (N=3): the adjoint gradient of the
     misfit against central differences of the device's own forward solve."""
