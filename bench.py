@@ -351,6 +351,15 @@ def batch_benchmark(steps: int):
     batch.step(steps)
     bat = time.perf_counter() - t0
     same = all(np.array_equal(s.get_fields(), f) for s, f in zip(solvers, seq_fields))
+    # the same batch with the orders of a stage one after another on one stream
+    batch.set_concurrent(False)
+    reset()
+    batch.step(1)  # captures that graph
+    reset()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    bat1 = time.perf_counter() - t0
+    same = same and all(np.array_equal(s.get_fields(), f) for s, f in zip(solvers, seq_fields))
     orders = sorted({N for N, _, _ in specs})
     tuned = {str(N): {"elements_per_block": batch.config(N)[0], "waves_per_simd": batch.config(N)[1],
                       "tuned_stage_us": batch.config(N)[2],
@@ -371,6 +380,7 @@ def batch_benchmark(steps: int):
         "steps": steps,
         "sequential_s": seq,
         "batched_s": bat,
+        "batched_one_stream_s": bat1,
         "speedup": seq / bat,
         "batched_node_updates_per_s": nodes * 5 * steps / bat,
         "sequential_node_updates_per_s": nodes * 5 * steps / seq,

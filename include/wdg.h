@@ -341,6 +341,12 @@ const char* wdg_batch_last_error(const wdg_batch* batch);
 int wdg_batch_add(wdg_batch* batch, wdg_ctx* problem, double dt, int* index);
 int wdg_batch_prepare(wdg_batch* batch, int autotune);
 int wdg_batch_step(wdg_batch* batch, int64_t nsteps);
+/* How a batch step runs the orders of one stage (performance only; results
+ * are identical): enable != 0 (the default) launches each order on its own
+ * stream, all at once; 0 launches them one after another on the batch's
+ * stream.  Takes effect at the next wdg_batch_step (the step graph is
+ * captured again). */
+int wdg_batch_set_concurrent(wdg_batch* batch, int enable);
 int wdg_batch_config(const wdg_batch* batch, int N, int* elems_per_block, int* waves_per_simd, double* tuned_us);
 int wdg_batch_trials(const wdg_batch* batch, int N, int64_t cap, int* kernel, int* elems_per_block,
                      int* waves_per_simd, double* stage_us, int64_t* count);

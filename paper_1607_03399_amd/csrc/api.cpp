@@ -2279,6 +2279,7 @@ struct wdg_batch {
   std::vector<hipStream_t> side;
   std::vector<hipEvent_t> events;
   bool ready = false;
+  bool concurrent = true;  // the orders of a stage on side streams, else one after another
   mutable std::string err;
 };
 
@@ -2565,6 +2566,10 @@ int batch_capture(wdg_batch* b) {
   };
   for (int s = 0; s < 5 && cap == hipSuccess; ++s) {
     ok(wdg::launch_batch_prepare(np, b->dProbs, b->dParam, b->dCounter, s, kRkA[s], kRkB[s], b->dAmp, b->stream));
+    if (!b->concurrent) {
+      for (const auto& g : b->groups) ok(launch_group(b, g, g.node, g.epb, g.wpe, g.dWork, g.nwork, b->stream));
+      continue;
+    }
     hipEvent_t fork = b->events[s * (ng + 1)];
     ok(hipEventRecord(fork, b->stream));
     // the orders are independent within a stage: all but the first on side streams
@@ -2591,6 +2596,20 @@ int batch_capture(wdg_batch* b) {
 }  // namespace
 
 extern "C" {
+
+int wdg_batch_set_concurrent(wdg_batch* b, int enable) {
+  if (!b) return WDG_ERR_ARG;
+  BHIPCHK(hipSetDevice(b->device));
+  if (b->concurrent == (enable != 0)) return WDG_OK;
+  BHIPCHK(hipStreamSynchronize(b->stream));
+  b->concurrent = enable != 0;
+  // the next step captures the graph again
+  if (b->exec) BHIPCHK(hipGraphExecDestroy(b->exec));
+  if (b->graph) BHIPCHK(hipGraphDestroy(b->graph));
+  b->exec = nullptr;
+  b->graph = nullptr;
+  return WDG_OK;
+}
 
 int wdg_batch_step(wdg_batch* b, int64_t nsteps) {
   if (!b) return WDG_ERR_ARG;

@@ -100,6 +100,7 @@ def load_library() -> C.CDLL:
         "wdg_batch_prepare": (C.c_int, [vp, C.c_int]),
         "wdg_batch_step": (C.c_int, [vp, C.c_int64]),
         "wdg_batch_config": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _dp]),
+        "wdg_batch_set_concurrent": (C.c_int, [vp, C.c_int]),
         "wdg_batch_trials": (C.c_int, [vp, C.c_int, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                        C.POINTER(C.c_int), _dp, _i64p]),
     }
@@ -473,6 +474,11 @@ class Batch:
 
     def step(self, nsteps: int):
         self._check(self._lib.wdg_batch_step(self._h, int(nsteps)), "batch_step")
+
+    def set_concurrent(self, enable: bool):
+        """Orders of a stage on their own streams at once (default), or one
+        after another on the batch's stream (wdg_batch_set_concurrent)."""
+        self._check(self._lib.wdg_batch_set_concurrent(self._h, int(bool(enable))), "batch_set_concurrent")
 
     def config(self, N: int):
         """(elements per block, waves per SIMD chosen by the autotuner, tuned stage microseconds)."""

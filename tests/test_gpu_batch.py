@@ -39,9 +39,10 @@ SPECS = [(2, 3, 2, 1, [0.4, 0.5, 0.5]), (3, 4, 3, 2, [0.5, 0.3, 0.6]), (4, 2, 3,
 
 
 @pytest.mark.parametrize("bits", [32, 64])
-@pytest.mark.parametrize("autotune", [True, False])
-def test_batch_equals_single_problem_steps(bits, autotune):
+@pytest.mark.parametrize("autotune,concurrent", [(True, True), (False, True), (True, False)])
+def test_batch_equals_single_problem_steps(bits, autotune, concurrent):
     batch = wdg.Batch(bits, device=0)
+    batch.set_concurrent(concurrent)
     probs = []
     for (N, nx, layers, seed, src) in SPECS:
         m, s, U, dt = _problem(N, nx, layers, seed, bits, src)
