@@ -48,16 +48,16 @@ def stage_bytes(N: int, bits: int, reads_res: bool) -> int:
 
     State U read and U' written, residual written (and read after the first
     stage): 4 fields x Np values each; per-element geometry and material
-    record (40 values), triangular operator (N <= 4: the lower triangle of
-    (M^{tri,k})^-1, Np_tri (Np_tri + 1) / 2 values; N = 5: L^{tri,k}, Np_tri^2
-    values; padded to a multiple of 4) and connectivity (8 int32).  Neighbour
-    traces are counted as cache hits.  At N = 3 in FP32 this is 2976 B (2336 B
+    record (40 values), triangular operator (N <= 3: none, the stage factors
+    M^{tri,k} from the record's vertex weights; N >= 4: L^{tri,k}, Np_tri^2
+    values padded to a multiple of 4) and connectivity (8 int32).  Neighbour
+    traces are counted as cache hits.  At N = 3 in FP32 this is 2752 B (2112 B
     in the first stage).
     """
     NT = (N + 1) * (N + 2) // 2
     NP = NT * (N + 1)
     ts = bits // 8
-    LS = ((NT * (NT + 1) // 2 if N <= 4 else NT * NT) + 3) // 4 * 4
+    LS = 0 if N <= 3 else (NT * NT + 3) // 4 * 4
     state = 4 * NP * ts
     return state * (3 + int(reads_res)) + 40 * ts + LS * ts + 8 * 4
 

@@ -19,10 +19,11 @@ struct Dim {
   static constexpr int Nq = N + 1;
   static constexpr int NP = NT * Nq;
   // Per-element triangular operator: for N <= 3 (M^{tri,k})^-1, stored as its
-  // lower triangle row by row (symmetric), applied after the literal M^tri;
-  // for N >= 4 the lift L^{tri,k} = (M^{tri,k})^-1 M^tri itself, column by
-  // column (the node-lane kernel reads a row per lane, coalesced across the
-  // element's lanes).  Padded to whole 4-vectors.
+  // lower triangle row by row (symmetric; the stage kernel does not read it:
+  // it factors M^{tri,k} itself into the same LDS slots and solves after the
+  // literal M^tri); for N >= 4 the lift L^{tri,k} = (M^{tri,k})^-1 M^tri
+  // itself, column by column (the node-lane kernel reads a row per lane,
+  // coalesced across the element's lanes).  Padded to whole 4-vectors.
   static constexpr bool PACKED = N <= 3;
   static constexpr int NPK = NT * (NT + 1) / 2;
   static constexpr int LS = ((PACKED ? NPK : NT * NT) + 3) / 4 * 4;

@@ -117,9 +117,11 @@ struct StageLaunch {
   int ncols;
 };
 
-// Whether order N stores (M^{tri,k})^-1 as its lower triangle (N <= 3) instead
-// of the lift L^{tri,k} = (M^{tri,k})^-1 M^tri (Np_tri^2 values, column by
-// column: entry (r, c) at c Np_tri + r).
+// Whether order N stores (M^{tri,k})^-1 as its lower triangle (N <= 3: kept
+// for wdg_element_data; the stage kernels factor M^{tri,k} from the geometry
+// record's vertex weights instead of reading it) instead of the lift
+// L^{tri,k} = (M^{tri,k})^-1 M^tri (Np_tri^2 values, column by column: entry
+// (r, c) at c Np_tri + r).
 constexpr bool lift_packed(int N) { return N <= 3; }
 // Per-element stride (values) of that record, padded to a multiple of 4.
 int lift_stride(int N);

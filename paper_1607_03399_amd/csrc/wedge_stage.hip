@@ -23,6 +23,10 @@ template <int N, typename T>
 struct Cfg {
   static constexpr int NT = Dim<N>::NT, Nq = Dim<N>::Nq, NP = Dim<N>::NP;
   static constexpr int NPP = NP | 1;
+  // N <= 3: the element's triangular mass M^{tri,k} = sum_v w_v M_v is factored
+  // (Cholesky) in the block from the vertex weights of the geometry record
+  // instead of reading a stored inverse
+  static constexpr bool CHOL = Dim<N>::PACKED;
   static constexpr int VL = Dim<N>::LS / 4, VG = kGeoStride / 4, VF = NT;  // 4-vectors per element
   static constexpr int XPE = (VL + VG + VF) > NPP ? (VL + VG + VF) : NPP;
   static constexpr int per_elem = (NPP + XPE) * 4 * int(sizeof(T));
@@ -538,9 +542,9 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int64_t 
     cn[4] = c1.x;
     cn[5] = c1.y;
   }
-  constexpr int SU = (EPB * NP + 63) / 64, SL = (EPB * VL + 63) / 64, SG = (EPB * VG + 63) / 64;
+  constexpr int SU = (EPB * NP + 63) / 64, SL = C::CHOL ? 0 : (EPB * VL + 63) / 64, SG = (EPB * VG + 63) / 64;
   constexpr int V4B = 4 * int(sizeof(T));
-  V4<T> rU[SU], rL[SL], rG[SG];
+  V4<T> rU[SU], rL[SL > 0 ? SL : 1], rG[SG];
   {
     const auto bu = chunk_rsrc(Uin + e0 * NP, int64_t(nE) * NP * V4B);
     const auto bl = chunk_rsrc(Lm + e0 * Dim<N>::LS, int64_t(nE) * VL * V4B);
@@ -613,6 +617,37 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int64_t 
     sX[idx < EPB * VG ? EPB * VL + idx : EPB * C::XPE] = rG[k];
   }
   __syncthreads();
+  if constexpr (C::CHOL) {
+    // M^{tri,k} = L L^T, row by row into the element's triangular-operator
+    // slots (entry (i, m) at i (i + 1) / 2 + m, the diagonal holding 1 / L_ii);
+    // read after the barrier that follows the triangular-face fluxes
+    if (active && j == 0) {
+      constexpr int NK = Dim<N>::NPK;
+      const T* gw = reinterpret_cast<const T*>(sG) + le * kGeoStride;
+      const T w0 = gw[37], w1 = gw[38], w2 = gw[39];
+      T a[NK];
+#pragma unroll
+      for (int f = 0; f < NK; ++f) {
+        const int i = tri_row(f), m = f - i * (i + 1) / 2;
+        T v = 0;
+        constexpr_or_skip(RT::Mv[i * NT + m], v, w0);
+        constexpr_or_skip(RT::Mv[NT * NT + i * NT + m], v, w1);
+        constexpr_or_skip(RT::Mv[2 * NT * NT + i * NT + m], v, w2);
+        a[f] = v;
+      }
+#pragma unroll
+      for (int f = 0; f < NK; ++f) {
+        const int i = tri_row(f), m = f - i * (i + 1) / 2;
+        T sm = a[f];
+#pragma unroll
+        for (int k = 0; k < m; ++k) sm -= a[i * (i + 1) / 2 + k] * a[m * (m + 1) / 2 + k];
+        a[f] = m < i ? sm * a[m * (m + 1) / 2 + m] : T(1) / std::sqrt(sm);
+      }
+      T* lo = reinterpret_cast<T*>(sL + le * VL);
+#pragma unroll
+      for (int f = 0; f < NK; ++f) lo[f] = a[f];
+    }
+  }
   if constexpr (MARCH) {
 #pragma unroll
     for (int t = 0; t < per; ++t) {
@@ -875,15 +910,10 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int64_t 
           }
         }
       }
-#pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        Bp[i] = Rp[i];
-        Bz[i] = Rz[i];
-        Bx[i] = Rx[i];
-        By[i] = Ry[i];
-        Rp[i] = Rz[i] = Rx[i] = Ry[i] = T(0);
-      }
       {
+        static_assert(C::CHOL, "the packed orders factor the triangular mass");
+        // R = L^-T L^-1 R: forward substitution row by row, then the
+        // transposed solve column by column (the factor's entries in reverse)
         const V4<T>* Lv = sL + le * VL;
 #pragma unroll
         for (int c = 0; c < VL; ++c) {
@@ -894,15 +924,39 @@ __device__ __forceinline__ void wedge_stage_chunk(const StageLaunch& A, int64_t 
             const int f = 4 * c + k;
             if (f < Dim<N>::NPK) {
               const int i = tri_row(f), m = f - i * (i + 1) / 2;
-              Rp[i] += lv[k] * Bp[m];
-              Rz[i] += lv[k] * Bz[m];
-              Rx[i] += lv[k] * Bx[m];
-              Ry[i] += lv[k] * By[m];
-              if (m != i) {
-                Rp[m] += lv[k] * Bp[i];
-                Rz[m] += lv[k] * Bz[i];
-                Rx[m] += lv[k] * Bx[i];
-                Ry[m] += lv[k] * By[i];
+              if (m < i) {
+                Rp[i] -= lv[k] * Rp[m];
+                Rz[i] -= lv[k] * Rz[m];
+                Rx[i] -= lv[k] * Rx[m];
+                Ry[i] -= lv[k] * Ry[m];
+              } else {
+                Rp[i] *= lv[k];
+                Rz[i] *= lv[k];
+                Rx[i] *= lv[k];
+                Ry[i] *= lv[k];
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int c = VL - 1; c >= 0; --c) {
+          const V4<T> l4 = Lv[c];
+          const T lv[4] = {l4.p, l4.uz, l4.ux, l4.uy};
+#pragma unroll
+          for (int k = 3; k >= 0; --k) {
+            const int f = 4 * c + k;
+            if (f < Dim<N>::NPK) {
+              const int i = tri_row(f), m = f - i * (i + 1) / 2;
+              if (m < i) {
+                Rp[m] -= lv[k] * Rp[i];
+                Rz[m] -= lv[k] * Rz[i];
+                Rx[m] -= lv[k] * Rx[i];
+                Ry[m] -= lv[k] * Ry[i];
+              } else {
+                Rp[i] *= lv[k];
+                Rz[i] *= lv[k];
+                Rx[i] *= lv[k];
+                Ry[i] *= lv[k];
               }
             }
           }

@@ -239,7 +239,11 @@ def test_cfg2_full_size_100_steps_fp32_against_fp64():
     steps of the device path (the FP64 path is held to the oracle at 1e-12 on
     the smaller meshes above), element by element at the FP32 tolerance, and
     the upwind scheme's energy does not increase over any 10 of the steps in
-    either precision."""
+    either precision.  Over the whole run FP64 dissipates 4.3e-9 of the energy;
+    FP32 rounding moves the energy by up to 7e-9 per 10 steps (measured alike
+    with the stored inverse triangular mass and with the factored one), so the
+    sign of the FP32 total is rounding: FP64 must decrease, FP32 must stay
+    within twice FP32's unit roundoff of the start."""
     m = inputs.cfg2_mesh()
     N = 3
     out = {}
@@ -258,7 +262,10 @@ def test_cfg2_full_size_100_steps_fp32_against_fp64():
         s.close()
         assert np.all(np.isfinite(F))
         assert all(E[k + 1] <= E[k] * (1 + 1e-6) for k in range(10)), E
-        assert E[-1] < E[0]
+        if bits == 64:
+            assert E[-1] < E[0]
+        else:
+            assert E[-1] <= E[0] * (1 + 2.0 ** -23), E
         out[bits] = (F, dt)
     err, emax = check(out[32][0], out[64][0], 1e-5, "cfg2 100 steps FP32 vs FP64")
     _say("   rel err", err, "worst element", emax)
