@@ -67,3 +67,34 @@ def test_gradient_vanishes_at_the_data_and_is_linear():
     tr = adjoint.solve_traces(m, N, U0, dt, nsteps, src, rec)
     d = float(np.sum((tr.real - data) * tr.imag)) / 1e-30
     assert abs(d - np.dot(v, gc)) <= 1e-12 * max(abs(d), 1e-300)
+
+
+def test_stage_mass_terms_sum_by_parts():
+    """The reverse sweep on the device pairs each stage's forward residual
+    with b_s times the adjoint state the stage reads instead of pairing the
+    stage right-hand side with the stage's adjoint vector.  Over one
+    low-storage Runge-Kutta step the two sums agree because the first stage
+    discards the residual (a_1 = 0), res_s = a_s res_{s-1} + dt R_s, and the
+    sweep's recurrence sig_s = a_{s+1} sig_{s+1} + b_s U~_s (sig_6 = 0)."""
+    from oracle import lsrk
+
+    a, b = lsrk.A, lsrk.B
+    assert a[0] == 0.0
+    rng = np.random.default_rng(5)
+    n, dt = 37, 0.013
+    R = rng.standard_normal((5, n))  # stage right-hand sides
+    Ua = rng.standard_normal((5, n))  # adjoint state read by each reverse stage
+    res = np.zeros((5, n))
+    prev = rng.standard_normal(n)  # last step's residual, discarded by stage 1
+    for s in range(5):
+        prev = a[s] * prev + dt * R[s]
+        res[s] = prev
+    sig = np.zeros((6, n))
+    for s in range(4, -1, -1):
+        sig[s] = (a[s + 1] * sig[s + 1] if s < 4 else 0.0) + b[s] * Ua[s]
+    lhs = sum(sig[s] @ (dt * R[s]) for s in range(5))
+    rhs = sum(b[s] * (Ua[s] @ res[s]) for s in range(5))
+    assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + 1.0)
+    # a plausible slip, pairing each residual with sig_s itself, does not agree
+    wrong = sum(sig[s] @ res[s] for s in range(5))
+    assert abs(wrong - lhs) > 1e-3 * abs(lhs)
